@@ -1,0 +1,256 @@
+"""FP64 oracle: orthogonalization sweeps, sparse tangent projection, TT rounding.
+
+Test infrastructure only (see the package docstring).
+
+The paper names these operations (Implementation Details: ``t3f.round`` with
+``max_tt_rank``; Riemannian Geometry Operations: the projection P_B A onto the
+tangent space of the fixed-rank manifold, ``project_sum``, Riemannian
+gradients P_X df/dX) but gives no algorithm for them.  They follow the
+standard TT algorithms of the literature the paper cites: QR sweeps and
+TT-SVD rounding from the TT-format paper (Oseledets 2011), the tangent-space
+parametrisation with left/right orthonormal cores and the gauge condition
+from the Riemannian TT paper (Steinlechner 2016).  Readings that the paper
+leaves open (sign conventions, rank feasibility, rounding direction) are fixed
+as documented in each function.
+"""
+import numpy as np
+
+from .core import sparse_adjoint
+
+
+def qr_pos(A):
+    """Reduced Householder QR (LAPACK) with the sign fixed so diag(R) >= 0.
+
+    The sign reading (diag(R) >= 0, sign(0) taken as +1) makes Q and R unique
+    for a matrix of full column rank.
+    """
+    Q, R = np.linalg.qr(np.asarray(A, dtype=np.float64), mode="reduced")
+    s = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return Q * s[None, :], R * s[:, None]
+
+
+def orthogonalize_lr(cores):
+    """Left-to-right orthogonalization sweep.
+
+    For k = 1..d-1: QR of the left unfolding reshape(G^k, r_{k-1} n_k x r_k),
+    G^k <- Q (left-orthonormal, rank min(r_{k-1} n_k, r_k)), and the R factor
+    is multiplied into G^{k+1}.  The tensor is unchanged; the last core
+    carries it (its norm is the tensor's Frobenius norm).
+    """
+    G = [np.array(c, dtype=np.float64) for c in cores]
+    d = len(G)
+    for k in range(d - 1):
+        r0, n, r1 = G[k].shape
+        Q, R = qr_pos(G[k].reshape(r0 * n, r1))
+        G[k] = Q.reshape(r0, n, Q.shape[1])
+        G[k + 1] = np.tensordot(R, G[k + 1], axes=([1], [0]))
+    return G
+
+
+def orthogonalize_rl(cores):
+    """Right-to-left orthogonalization sweep (mirror of ``orthogonalize_lr``).
+
+    For k = d..2: LQ of the right unfolding reshape(G^k, r_{k-1} x n_k r_k),
+    computed as the QR of its transpose, A = L Q with diag(L) >= 0;
+    G^k <- Q (right-orthonormal rows) and G^{k-1} <- G^{k-1} L.
+    """
+    G = [np.array(c, dtype=np.float64) for c in cores]
+    d = len(G)
+    for k in range(d - 1, 0, -1):
+        r0, n, r1 = G[k].shape
+        Q, R = qr_pos(G[k].reshape(r0, n * r1).T)  # A^T = Q R  =>  A = R^T Q^T
+        G[k] = Q.T.reshape(Q.shape[1], n, r1)
+        G[k - 1] = np.tensordot(G[k - 1], R.T, axes=([2], [0]))
+    return G
+
+
+def project_sparse_cores(U, V, idx, z):
+    """Core contractions Zhat_k of a sparse tensor with the tangent-space
+    interfaces of X.
+
+    Zhat_k[a, i, b] = sum over m with i_k^m = i of
+        z_m (U^1[i_1]..U^{k-1}[i_{k-1}])[a] (V^{k+1}[i_{k+1}]..V^d[i_d])[b],
+    i.e. the adjoint of the gather taken with the left-orthonormal cores U on
+    the left and the right-orthonormal cores V on the right.  By the linearity
+    used by ``project_sum`` (Riemannian Geometry Operations section) this is
+    the projection of sum_m z_m e_{i^m}, a weighted sum of M one-hot rank-1 TT
+    tensors, computed one observed entry at a time.
+    """
+    return sparse_adjoint(U, V, idx, z)
+
+
+def tangent_cores(U, Zhat):
+    """Gauge-fixed tangent cores dG from the core contractions Zhat.
+
+    dG_k = Zhat_k - U_k (U_k^L^T Zhat_k^L) for k < d (left unfoldings), which
+    imposes the gauge U_k^L^T dG_k^L = 0; dG_d = Zhat_d.  These are the
+    parameters of the orthogonal projection onto the tangent space of the
+    fixed-rank manifold at X.
+    """
+    d = len(U)
+    out = []
+    for k in range(d):
+        Z = np.asarray(Zhat[k], dtype=np.float64)
+        if k < d - 1:
+            r0, n, r1 = U[k].shape
+            UL = U[k].reshape(r0 * n, r1)
+            ZL = Z.reshape(r0 * n, r1)
+            out.append((ZL - UL @ (UL.T @ ZL)).reshape(r0, n, r1))
+        else:
+            out.append(Z.copy())
+    return out
+
+
+def tangent_tt(U, V, dG, alpha=1.0, beta=0.0):
+    """The tangent vector beta*X + alpha*sum_k U_<k dG_k V_>k as a TT of rank 2r.
+
+    Cores: W_1 = [alpha dG_1, U_1]; W_k = [[V_k, 0], [alpha dG_k, U_k]];
+    W_d = [[V_d], [beta S_d + alpha dG_d]], where S_d is the last core of the
+    left-orthogonalized X (U[-1]).  Elements of one tangent space add by this
+    block structure, the fact ``project_sum`` relies on (Riemannian Geometry
+    Operations section).  beta = 1 gives the retraction input X + alpha P_X(Z).
+    """
+    d = len(U)
+    assert d >= 2
+    W = []
+    for k in range(d):
+        if k == 0:
+            W.append(np.concatenate([alpha * dG[0], U[0]], axis=2))
+        elif k == d - 1:
+            W.append(np.concatenate([V[k], beta * U[k] + alpha * dG[k]], axis=0))
+        else:
+            r0, n, r1 = U[k].shape
+            c = np.zeros((2 * r0, n, 2 * r1))
+            c[:r0, :, :r1] = V[k]
+            c[r0:, :, :r1] = alpha * dG[k]
+            c[r0:, :, r1:] = U[k]
+            W.append(c)
+    return W
+
+
+def _check_interfaces(U, V):
+    for k in range(len(U) - 1):
+        if U[k].shape[2] != V[k + 1].shape[0]:
+            raise ValueError(
+                "left- and right-orthogonalized ranks differ at bond %d (%d vs %d):"
+                " X is not at feasible ranks" % (k + 1, U[k].shape[2], V[k + 1].shape[0]))
+
+
+def project_sparse(X, idx, z, alpha=1.0, beta=0.0):
+    """Projection of the sparse tensor Z = sum_m z_m e_{i^m} onto the tangent
+    space of X, returned as the rank-2r TT  beta*X + alpha*P_X(Z).
+
+    Riemannian Geometry Operations section: P_X Z, computed as project_sum of
+    one-hot rank-1 tensors.  Steps: orthogonalize X both ways, contract Z with
+    the interfaces (``project_sparse_cores``), fix the gauge
+    (``tangent_cores``), assemble (``tangent_tt``).  Returns (W, U, V, dG).
+    """
+    U = orthogonalize_lr(X)
+    V = orthogonalize_rl(X)
+    _check_interfaces(U, V)
+    Zhat = project_sparse_cores(U, V, idx, z)
+    dG = tangent_cores(U, Zhat)
+    return tangent_tt(U, V, dG, alpha, beta), U, V, dG
+
+
+def round_tt(cores, max_rank):
+    """TT rounding to ranks <= max_rank (``t3f.round``, Implementation Details).
+
+    TT-SVD rounding of the cited TT-format paper: a right-to-left
+    orthogonalization sweep, then for k = 1..d-1 the SVD of the left unfolding
+    reshape(G^k, r_{k-1} n_k x r_k); the leading min(max_rank, r_{k-1} n_k, r_k)
+    singular triplets are kept (singular values in descending order), G^k <- U,
+    and Sigma V^T is multiplied into G^{k+1}.  Each kept left singular vector
+    is sign-fixed so that its largest-magnitude component is positive.
+    Returns (cores, disc_sq) with disc_sq[k] the sum of the discarded squared
+    singular values at bond k+1; their total equals ||Y - round(Y)||_F^2.
+    """
+    G = orthogonalize_rl(cores)
+    d = len(G)
+    disc = []
+    for k in range(d - 1):
+        r0, n, r1 = G[k].shape
+        Uf, s, Vt = np.linalg.svd(G[k].reshape(r0 * n, r1), full_matrices=False)
+        rk = min(max_rank, s.shape[0])
+        disc.append(float(np.sum(s[rk:] ** 2)))
+        Uk = Uf[:, :rk]
+        SVt = s[:rk, None] * Vt[:rk]
+        j = np.argmax(np.abs(Uk), axis=0)
+        sgn = np.where(Uk[j, np.arange(rk)] < 0, -1.0, 1.0)
+        Uk = Uk * sgn[None, :]
+        SVt = SVt * sgn[:, None]
+        G[k] = Uk.reshape(r0, n, rk)
+        G[k + 1] = np.tensordot(SVt, G[k + 1], axes=([1], [0]))
+    return G, np.array(disc)
+
+
+def completion_step(X, idx, t, alpha=-0.1, max_rank=None):
+    """One Riemannian tensor-completion step on the observed set.
+
+    Introduction (the completion example: fit a low-TT-rank tensor to known
+    entries by Riemannian optimization) with the Riemannian gradient
+    P_X(df/dX) of the Riemannian Geometry Operations section:
+      y = gather(X), L = mean((y - t)^2), g = 2 (y - t) / M,
+      core gradients = gather_backward(g),
+      W = X + alpha * P_X(sum_m g_m e_{i^m}),  Y = round(W, max_rank).
+    """
+    from .core import gather, gather_backward, mse_loss_and_grad
+
+    if max_rank is None:
+        max_rank = max(c.shape[2] for c in X)
+    y = gather(X, idx)
+    loss, g = mse_loss_and_grad(y, t)
+    grads = gather_backward(X, idx, g)
+    W, U, V, dG = project_sparse(X, idx, g, alpha=alpha, beta=1.0)
+    Y, disc = round_tt(W, max_rank)
+    return dict(y=y, loss=loss, g=g, grads=grads, U=U, V=V, dG=dG, W=W, Y=Y, disc_sq=disc)
+
+
+def left_interface(U, k):
+    """Left interface matrix U_{<=k} (prod n_1..n_k x r_k) of the first k cores."""
+    if k == 0:
+        return np.ones((1, 1))
+    t = U[0]
+    for c in U[1:k]:
+        t = np.tensordot(t, c, axes=([t.ndim - 1], [0]))
+    return t.reshape(-1, t.shape[-1])
+
+
+def right_interface(V, k):
+    """Right interface matrix V_{>=k} (r_{k-1} x prod n_k..n_d), 1-based k."""
+    d = len(V)
+    if k > d:
+        return np.ones((1, 1))
+    t = V[k - 1]
+    for c in V[k:]:
+        t = np.tensordot(t, c, axes=([t.ndim - 1], [0]))
+    return t.reshape(t.shape[0], -1)
+
+
+def dense_projector(U, V):
+    """Dense matrix of the tangent-space projector at X (tiny sizes only).
+
+    P = sum_{k=1}^{d} P_<=k-1 (x) I_{n_k} (x) P_>=k+1
+        - sum_{k=1}^{d-1} P_<=k (x) P_>=k+1,
+    with P_<=k = U_<=k U_<=k^T from the left-orthonormal cores and
+    P_>=k = V_>=k^T V_>=k from the right-orthonormal cores (P_<=0 = P_>=d+1 = 1);
+    C-ordered Kronecker products match the C-ordered multi-index.
+    """
+    d = len(U)
+    ns = [c.shape[1] for c in U]
+    N = int(np.prod(ns))
+
+    def PL(k):
+        Ul = left_interface(U, k)
+        return Ul @ Ul.T
+
+    def PR(k):
+        Vr = right_interface(V, k)
+        return Vr.T @ Vr
+
+    P = np.zeros((N, N))
+    for k in range(1, d + 1):
+        P += np.kron(np.kron(PL(k - 1), np.eye(ns[k - 1])), PR(k + 1))
+    for k in range(1, d):
+        P -= np.kron(PL(k), PR(k + 1))
+    return P

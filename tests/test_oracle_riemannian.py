@@ -1,0 +1,292 @@
+"""Pins of the FP64 oracle's Riemannian step: QR sweeps, sparse tangent
+projection, tangent assembly and TT rounding.
+
+The tangent-space projector is pinned against the range of the Jacobian of
+the TT parametrisation (an independent construction of the tangent space),
+rounding against a dense TT-SVD of the full tensor and against Eckart-Young,
+and the sweeps against orthonormality and tensor invariance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import random_tt, random_indices, canonical_ranks, small_step
+
+
+def _rng(s):
+    return np.random.default_rng(2000 + s)
+
+
+def _X(seed, ns, r):
+    return [c.astype(np.float64) for c in random_tt(seed, ns, canonical_ranks(ns, r))]
+
+
+# ----------------------------------------------------------------------- QR
+
+def test_qr_pos():
+    A = _rng(0).standard_normal((12, 5))
+    Q, R = oracle.qr_pos(A)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(5), atol=1e-14)
+    assert np.all(np.diag(R) >= 0)
+    np.testing.assert_allclose(np.tril(R, -1), 0, atol=0)
+    np.testing.assert_allclose(Q @ R, A, atol=1e-13)
+
+
+@pytest.mark.parametrize("ns,r", [([3, 4, 3, 5], 3), ([4, 4, 4, 4, 4], 6), ([5, 2, 6], 4)])
+def test_orthogonalize_sweeps(ns, r):
+    X = _X(1, ns, r)
+    F = oracle.full(X)
+    U = oracle.orthogonalize_lr(X)
+    V = oracle.orthogonalize_rl(X)
+    np.testing.assert_allclose(oracle.full(U), F, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(oracle.full(V), F, rtol=1e-12, atol=1e-13)
+    for k in range(len(ns) - 1):
+        UL = U[k].reshape(-1, U[k].shape[2])
+        np.testing.assert_allclose(UL.T @ UL, np.eye(UL.shape[1]), atol=1e-13)
+        VR = V[k + 1].reshape(V[k + 1].shape[0], -1)
+        np.testing.assert_allclose(VR @ VR.T, np.eye(VR.shape[0]), atol=1e-13)
+    nrm = np.linalg.norm(F)
+    assert np.linalg.norm(U[-1]) == pytest.approx(nrm, rel=1e-12)
+    assert np.linalg.norm(V[0]) == pytest.approx(nrm, rel=1e-12)
+    # the first QR of the sweep is LAPACK's after the sign fix (uniqueness)
+    Q, _ = np.linalg.qr(X[0].reshape(-1, X[0].shape[2]))
+    Q = Q * np.sign(np.diag(np.linalg.qr(X[0].reshape(-1, X[0].shape[2]))[1]))[None, :]
+    np.testing.assert_allclose(U[0].reshape(Q.shape), Q, atol=1e-13)
+
+
+def test_orthogonalize_reduces_infeasible_ranks():
+    """Ranks above min(r_{k-1} n_k, r_k) shrink to it."""
+    ns = [2, 3, 2]
+    X = [c.astype(np.float64) for c in random_tt(3, ns, [1, 5, 5, 1])]
+    U = oracle.orthogonalize_lr(X)
+    assert [c.shape[2] for c in U] == [2, 5, 1]
+    V = oracle.orthogonalize_rl(X)
+    assert [c.shape[0] for c in V] == [1, 5, 2]
+    np.testing.assert_allclose(oracle.full(U), oracle.full(X), atol=1e-13)
+    np.testing.assert_allclose(oracle.full(V), oracle.full(X), atol=1e-13)
+
+
+# --------------------------------------------------------------- projection
+
+def _jacobian_projector(X):
+    """Orthogonal projector onto the range of d vec(full(X)) / d(cores): the
+    tangent space of the fixed-rank manifold, built without any of the
+    projection formulas.  full() is multilinear, so each Jacobian column is
+    full() with one core replaced by a unit tensor."""
+    cols = []
+    for k in range(len(X)):
+        for j in range(X[k].size):
+            E = np.zeros(X[k].size); E[j] = 1
+            Xk = list(X); Xk[k] = E.reshape(X[k].shape)
+            cols.append(oracle.full(Xk).reshape(-1))
+    J = np.stack(cols, axis=1)
+    Uj, s, _ = np.linalg.svd(J, full_matrices=False)
+    rank = int(np.sum(s > 1e-10 * s[0]))
+    B = Uj[:, :rank]
+    return B @ B.T, rank
+
+
+def _manifold_dim(ns, rk):
+    return sum(rk[k] * ns[k] * rk[k + 1] for k in range(len(ns))) - sum(r * r for r in rk[1:-1])
+
+
+@pytest.mark.parametrize("ns,r", [([3, 3, 3], 2), ([2, 3, 2, 3], 2), ([3, 4, 3], 3)])
+def test_dense_projector_is_jacobian_range(ns, r):
+    X = _X(4, ns, r)
+    U = oracle.orthogonalize_lr(X)
+    V = oracle.orthogonalize_rl(X)
+    P = oracle.dense_projector(U, V)
+    PJ, rank = _jacobian_projector(X)
+    rk = canonical_ranks(ns, r)
+    assert rank == _manifold_dim(ns, rk)
+    np.testing.assert_allclose(P, PJ, atol=1e-10)
+    np.testing.assert_allclose(P @ P, P, atol=1e-12)
+    np.testing.assert_allclose(P, P.T, atol=1e-12)
+    assert np.trace(P) == pytest.approx(rank, abs=1e-9)
+
+
+def _dense_sparse(ns, idx, z):
+    Z = np.zeros(ns)
+    np.add.at(Z, tuple(idx), z)
+    return Z
+
+
+@pytest.mark.parametrize("ns,r", [([3, 3, 3], 2), ([3, 4, 3, 2], 3), ([4, 4, 4, 4], 4)])
+def test_project_sparse_equals_dense_projector(ns, r):
+    rng = _rng(5)
+    X = _X(5, ns, r)
+    idx = random_indices(rng, ns, 60)
+    z = rng.standard_normal(60)
+    W, U, V, dG = oracle.project_sparse(X, idx, z, alpha=1.0, beta=0.0)
+    P = oracle.dense_projector(U, V)
+    Z = _dense_sparse(ns, idx, z)
+    np.testing.assert_allclose(oracle.full(W).reshape(-1), P @ Z.reshape(-1), atol=1e-12)
+    # gauge condition on the tangent cores
+    for k in range(len(ns) - 1):
+        UL = U[k].reshape(-1, U[k].shape[2])
+        np.testing.assert_allclose(UL.T @ dG[k].reshape(UL.shape[0], -1), 0, atol=1e-12)
+    # rank of the tangent TT is 2r in the interior
+    assert [c.shape[2] for c in W][:-1] == [2 * c.shape[2] for c in U][:-1]
+
+
+def _all_entries(ns):
+    return np.indices(ns).reshape(len(ns), -1)
+
+
+def test_projection_idempotent_identity_and_symmetric():
+    rng = _rng(6)
+    ns, r = [3, 4, 3, 3], 3
+    X = _X(6, ns, r)
+    grid = _all_entries(ns)
+    idx = random_indices(rng, ns, 80)
+    z = rng.standard_normal(80)
+    W1 = oracle.project_sparse(X, idx, z)[0]
+    F1 = oracle.full(W1)
+    # idempotence: project the (dense) projection again
+    W2 = oracle.project_sparse(X, grid, F1.reshape(-1))[0]
+    np.testing.assert_allclose(oracle.full(W2), F1, atol=1e-12)
+    # identity on X itself: P_X(X) = X
+    FX = oracle.full(X)
+    WX = oracle.project_sparse(X, grid, FX.reshape(-1))[0]
+    np.testing.assert_allclose(oracle.full(WX), FX, atol=1e-12)
+    # symmetry <P Z1, Z2> = <Z1, P Z2>
+    idx2 = random_indices(rng, ns, 70)
+    z2 = rng.standard_normal(70)
+    Z1 = _dense_sparse(ns, idx, z)
+    Z2 = _dense_sparse(ns, idx2, z2)
+    F2 = oracle.full(oracle.project_sparse(X, idx2, z2)[0])
+    assert np.sum(F1 * Z2) == pytest.approx(np.sum(Z1 * F2), rel=1e-11)
+    # beta=1 adds X; alpha scales
+    W3 = oracle.project_sparse(X, idx, z, alpha=-0.1, beta=1.0)[0]
+    np.testing.assert_allclose(oracle.full(W3), FX - 0.1 * F1, atol=1e-12)
+
+
+def test_projection_identity_on_random_tangent_vector():
+    """xi built from random gauge-satisfying tangent cores is fixed by P."""
+    rng = _rng(7)
+    ns, r = [3, 3, 4, 3], 3
+    X = _X(7, ns, r)
+    U = oracle.orthogonalize_lr(X)
+    V = oracle.orthogonalize_rl(X)
+    dG = []
+    for k in range(len(ns)):
+        H = rng.standard_normal(U[k].shape)
+        if k < len(ns) - 1:
+            UL = U[k].reshape(-1, U[k].shape[2])
+            HL = H.reshape(UL.shape[0], -1)
+            H = (HL - UL @ (UL.T @ HL)).reshape(H.shape)
+        dG.append(H)
+    xi = oracle.full(oracle.tangent_tt(U, V, dG))
+    W = oracle.project_sparse(X, _all_entries(ns), xi.reshape(-1))[0]
+    np.testing.assert_allclose(oracle.full(W), xi, atol=1e-12)
+
+
+def test_projection_linearity_project_sum():
+    """P(sum c_i A_i) = sum c_i P(A_i) (the identity project_sum relies on)."""
+    rng = _rng(8)
+    ns, r = [3, 4, 3], 3
+    X = _X(8, ns, r)
+    parts = [(random_indices(rng, ns, 30), rng.standard_normal(30)) for _ in range(3)]
+    c = [0.5, -2.0, 1.25]
+    idx = np.concatenate([p[0] for p in parts], axis=1)
+    z = np.concatenate([ci * p[1] for ci, p in zip(c, parts)])
+    lhs = oracle.full(oracle.project_sparse(X, idx, z)[0])
+    rhs = sum(ci * oracle.full(oracle.project_sparse(X, p[0], p[1])[0]) for ci, p in zip(c, parts))
+    np.testing.assert_allclose(lhs, rhs, atol=1e-12)
+
+
+def test_projection_inner_identity_without_dense():
+    """<P_X Z, xi> = sum_m z_m xi(i^m) for a tangent xi (P is symmetric and
+    fixes xi); only TT inner products and gathers, so it scales."""
+    rng = _rng(9)
+    ns, r = [6] * 6, 5
+    X = _X(9, ns, r)
+    idx = random_indices(rng, ns, 3000)
+    z = rng.standard_normal(3000)
+    W, U, V, _ = oracle.project_sparse(X, idx, z)
+    dG = []
+    for k in range(len(ns)):
+        H = rng.standard_normal(U[k].shape)
+        if k < len(ns) - 1:
+            UL = U[k].reshape(-1, U[k].shape[2])
+            HL = H.reshape(UL.shape[0], -1)
+            H = (HL - UL @ (UL.T @ HL)).reshape(H.shape)
+        dG.append(H)
+    xi = oracle.tangent_tt(U, V, dG)
+    lhs = oracle.inner(W, xi)
+    rhs = np.dot(z, oracle.gather(xi, idx))
+    assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+# ------------------------------------------------------------------ rounding
+
+def _tt_svd_dense(F, max_rank):
+    """TT-SVD of a dense tensor: truncated SVDs of successive unfoldings."""
+    ns = F.shape
+    cores = []
+    C = F.reshape(1, -1)
+    r0 = 1
+    for k in range(len(ns) - 1):
+        C = C.reshape(r0 * ns[k], -1)
+        Uf, s, Vt = np.linalg.svd(C, full_matrices=False)
+        rk = min(max_rank, s.shape[0])
+        cores.append(Uf[:, :rk].reshape(r0, ns[k], rk))
+        C = s[:rk, None] * Vt[:rk]
+        r0 = rk
+    cores.append(C.reshape(r0, ns[-1], 1))
+    return cores
+
+
+@pytest.mark.parametrize("ns,r,rmax", [([3, 4, 3, 4], 4, 2), ([4, 4, 4], 4, 3), ([2, 3, 4, 3, 2], 5, 2)])
+def test_round_matches_dense_tt_svd_and_error_identity(ns, r, rmax):
+    X = _X(10, ns, r)
+    Y, disc = oracle.round_tt(X, rmax)
+    F = oracle.full(X)
+    ref = oracle.full(_tt_svd_dense(F, rmax))
+    np.testing.assert_allclose(oracle.full(Y), ref, atol=1e-12)
+    err2 = np.sum((F - oracle.full(Y)) ** 2)
+    assert err2 == pytest.approx(np.sum(disc), rel=1e-9, abs=1e-20)
+    assert max(c.shape[2] for c in Y) <= rmax
+    # quasi-optimality: error^2 <= (d-1) * max_k (best rank-rmax error of unfolding k)^2
+    tails = []
+    for k in range(1, len(ns)):
+        s = np.linalg.svd(F.reshape(int(np.prod(ns[:k])), -1), compute_uv=False)
+        tails.append(np.sum(s[rmax:] ** 2))
+    assert err2 <= (len(ns) - 1) * max(tails) * (1 + 1e-9) + 1e-24
+    assert err2 >= max(tails) * (1 - 1e-9) - 1e-24
+
+
+def test_round_d2_is_eckart_young():
+    A = [c.astype(np.float64) for c in random_tt(11, [7, 9], [1, 6, 1])]
+    M = A[0][0] @ A[1][:, :, 0]
+    Y, disc = oracle.round_tt(A, 3)
+    Uf, s, Vt = np.linalg.svd(M)
+    best = (Uf[:, :3] * s[:3]) @ Vt[:3]
+    np.testing.assert_allclose(oracle.full(Y), best, atol=1e-12)
+    assert disc[0] == pytest.approx(np.sum(s[3:] ** 2), rel=1e-12)
+
+
+def test_round_exact_when_ranks_suffice():
+    """round(X + X, r) = 2X (the sum has rank 2r but represents a rank-r tensor)."""
+    ns, r = [3, 4, 4, 3], 3
+    X = _X(12, ns, r)
+    Y, disc = oracle.round_tt(oracle.add(X, X), r)
+    np.testing.assert_allclose(oracle.full(Y), 2 * oracle.full(X), atol=1e-12)
+    assert np.all(disc < 1e-20 * np.sum(oracle.full(X) ** 2) + 1e-24)
+    assert [c.shape[2] for c in Y] == canonical_ranks(ns, r)[1:]
+
+
+def test_small_step_pipeline_consistent():
+    """One completion step on the small workload: the retraction input is
+    X - 0.1 P_X(grad) and the rounded point keeps rank <= 4."""
+    p = small_step()
+    X = [c.astype(np.float64) for c in p.cores]
+    t = oracle.gather(p.planted, p.idx) + p.noise
+    out = oracle.completion_step(X, p.idx, t, alpha=-0.1, max_rank=4)
+    P = oracle.dense_projector(out["U"], out["V"])
+    Z = _dense_sparse(p.ns, p.idx, out["g"])
+    expect = oracle.full(X).reshape(-1) - 0.1 * (P @ Z.reshape(-1))
+    np.testing.assert_allclose(oracle.full(out["W"]).reshape(-1), expect, atol=1e-12)
+    assert max(c.shape[2] for c in out["Y"]) <= 4
+    err2 = np.sum((oracle.full(out["W"]) - oracle.full(out["Y"])) ** 2)
+    assert err2 == pytest.approx(np.sum(out["disc_sq"]), rel=1e-8, abs=1e-18)
