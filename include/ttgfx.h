@@ -1,0 +1,225 @@
+/*
+ * ttgfx.h -- C ABI of the MI355X (gfx950) TT-completion hot path.
+ *
+ * Operations follow the T3F paper (Novikov et al., arXiv 1801.01928):
+ *   - the TT format and its entry formula (Introduction),
+ *   - the library shape "one or two TT objects in, a TT or a number out" and
+ *     batches of TT objects (Implementation Details, Batch Processing),
+ *   - rounding t3f.round(x, max_tt_rank) (Implementation Details),
+ *   - the tangent-space projection P_X, project_sum, the Gram matrix and
+ *     Riemannian gradients (Riemannian Geometry Operations),
+ *   - the TT-matrix layer t3f.matmul(tt_matrix, x) (Implementation Details).
+ * Where the paper only names an operation, the standard algorithm of the TT
+ * literature it cites is used (QR sweeps and TT-SVD rounding; tangent
+ * parametrisation by left/right orthonormal cores with a gauge condition).
+ *
+ * Conventions for every entry point
+ *   - Pointers marked (dev) are device memory owned by the CALLER; pointers
+ *     marked (host) are host memory read during the call only.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
+ *     default stream), never synchronizes and never allocates device memory
+ *     (scratch comes from the caller's workspace `ws` of `ws_bytes`; query
+ *     its size with the matching *_workspace function).  Exceptions: the
+ *     plan API (tt_plan_*) owns device memory allocated in tt_plan_create.
+ *   - Return value: TT_OK (0) or a negative TT_ERR_* code; the message of the
+ *     last failure of the calling thread is in tt_last_error().  Arguments are
+ *     validated on the host before any HIP call; on a validation error no
+ *     device work is queued and no output is touched.
+ *   - M = 0 (no observed entries) is a successful no-op that still writes
+ *     well-defined outputs (zero gradients, zero loss).
+ *   - Indices outside [0, n_k) are undefined behaviour (not checked on the
+ *     device).
+ *   - Floating point is float32 on the device (the oracle is float64).
+ */
+#ifndef TTGFX_H
+#define TTGFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTGFX_VERSION 1
+#define TT_MAX_D 32       /* modes per tensor */
+#define TT_MAX_RANK 64    /* largest bond rank any entry point accepts */
+#define TT_MAX_N 4096     /* largest mode size */
+
+enum {
+  TT_OK = 0,
+  TT_ERR_ARG = -1,          /* null pointer, negative size, d out of range     */
+  TT_ERR_SHAPE = -2,        /* rank or size mismatch between descriptors       */
+  TT_ERR_UNSUPPORTED = -3,  /* rank/mode size beyond what the kernels support   */
+  TT_ERR_WORKSPACE = -4,    /* workspace missing or smaller than required       */
+  TT_ERR_HIP = -5,          /* HIP launch or runtime error                      */
+  TT_ERR_INDEX = -6         /* reserved: out-of-range index detected            */
+};
+
+enum { TT_LR = 0, TT_RL = 1 };  /* orthogonalization direction */
+
+/*
+ * A TT tensor (Introduction, TT format): d cores, core k of shape
+ * r[k] x n[k] x r[k+1] with r[0] = r[d] = 1, stored row-major
+ * ([r_k][n_k][r_{k+1}], the paper's index order G^k_{alpha_{k-1} i_k alpha_k})
+ * at data + off[k] (off == NULL: cores packed back to back in mode order).
+ * n, r, off are host arrays; data is (dev).  Entry (i_1..i_d) is the product
+ * of the slices G^1[i_1] ... G^d[i_d].
+ */
+typedef struct {
+  int32_t d;              /* 1 <= d <= TT_MAX_D                       */
+  const int32_t *n;       /* (host) [d]   mode sizes, 1 <= n_k         */
+  const int32_t *r;       /* (host) [d+1] bond ranks, r[0] = r[d] = 1  */
+  const int64_t *off;     /* (host) [d]   element offsets or NULL      */
+  float *data;            /* (dev) core storage                        */
+} tt_tensor;
+
+/* A batch of TT tensors with the same mode sizes; ranks may differ per
+ * tensor (Batch Processing; uneven ranks are an extension). */
+typedef struct {
+  int32_t b;              /* number of tensors                          */
+  const tt_tensor *tt;    /* (host) [b]                                 */
+} tt_batch;
+
+/* ------------------------------------------------------------------ A1 */
+/* Gather (Introduction, entry formula): y[m] = G^1[i_1^m] ... G^d[i_d^m].
+ * idx: (dev) int32 structure-of-arrays [d][M] (mode k of entry m at
+ * idx[k*M + m]); y: (dev) [M].  Ranks up to TT_MAX_RANK. */
+int tt_gather(const tt_tensor *X, const int32_t *idx, int64_t M, float *y,
+              void *stream);
+
+/* ------------------------------------------------------------------ A3 */
+/* Adjoint of the gather (automatic differentiation, abstract): for every
+ * core k, gX^k[:, i, :] = sum over m with i_k^m = i of
+ *   gy[m] * (G^1[i_1]..G^{k-1}[i_{k-1}])^T (G^{k+1}[i_{k+1}]..G^d[i_d])^T.
+ * gX must have X's shape; its cores are overwritten (not accumulated).
+ * Repeated multi-indices contribute once per occurrence.  Summation over
+ * entries is hierarchical: workgroups accumulate their entries in LDS, and
+ * the per-workgroup partial sums are reduced in a fixed order.  The order
+ * inside a workgroup follows scheduling, so repeated calls may differ in the
+ * last bits (relative differences ~1e-7). */
+int64_t tt_gather_backward_workspace(const tt_tensor *X, int64_t M);
+int tt_gather_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
+                       const float *gy, tt_tensor *gX,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ A1+A2+A3 */
+/* One fused completion-loss pass: y = gather(X), loss = mean((y - t)^2),
+ * gX = gather_backward(X, 2 (y - t) / M).  t: (dev) [M] targets; y: (dev)
+ * [M] or NULL; loss: (dev) one float or NULL; gX overwritten as above. */
+int64_t tt_gather_mse_workspace(const tt_tensor *X, int64_t M);
+int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
+                           const float *t, float *y, float *loss,
+                           tt_tensor *gX, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ------------------------------------------------------------------ A4 */
+/* Orthogonalization sweep (QR sweeps of the TT literature the paper cites;
+ * needed by rounding and the tangent projection).
+ * TT_LR: for k = 1..d-1, Householder QR of reshape(G^k, r_{k-1} n_k x r_k)
+ *   with diag(R) >= 0; out^k = Q (left-orthonormal), R pushed into G^{k+1}.
+ * TT_RL: mirror, LQ of reshape(G^k, r_{k-1} x n_k r_k) with diag(L) >= 0,
+ *   for k = d..2; out^k right-orthonormal, L pushed into G^{k-1}.
+ * out ranks are min(r_{k-1} n_k, r_k) (LR) / min(r_k, n_k r_{k+1}) (RL)
+ * chained along the sweep; compute them with tt_orthogonalize_ranks and
+ * give `out` exactly those ranks.  The tensor represented is unchanged. */
+int tt_orthogonalize_ranks(const tt_tensor *X, int dir, int32_t *out_r /*(host)[d+1]*/);
+int64_t tt_orthogonalize_workspace(const tt_tensor *X, int dir);
+int tt_orthogonalize(const tt_tensor *X, int dir, tt_tensor *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- A5+A6 */
+/* Tangent projection of a sparse tensor (Riemannian Geometry Operations:
+ * P_X Z, computed as project_sum of the M one-hot rank-1 tensors
+ * z[m] e_{i^m}).  U: X after TT_LR (U^1..U^{d-1} left-orthonormal, U^d the
+ * last core S_d); V: X after TT_RL (V^2..V^d right-orthonormal); both must
+ * have the same ranks (X at feasible ranks).  Output W, a TT of ranks
+ * (1, 2r_1, ..., 2r_{d-1}, 1), represents
+ *     add_x * X + alpha * P_X(Z)          (add_x in {0, 1})
+ * with cores W^1 = [alpha dG^1, U^1], W^k = [[V^k, 0], [alpha dG^k, U^k]],
+ * W^d = [[V^d], [add_x S_d + alpha dG^d]], where dG are the gauge-fixed
+ * tangent cores (U_k^L^T dG_k^L = 0 for k < d).  d >= 2. */
+int64_t tt_project_sparse_workspace(const tt_tensor *U, int64_t M);
+int tt_project_sparse(const tt_tensor *U, const tt_tensor *V,
+                      const int32_t *idx, int64_t M, const float *z,
+                      float alpha, int add_x, tt_tensor *W,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ A7 */
+/* TT rounding (t3f.round(x, max_tt_rank), Implementation Details): TT_RL
+ * sweep, then left-to-right truncated SVDs of reshape(G^k, r_{k-1} n_k x r_k)
+ * keeping min(max_rank, r_{k-1} n_k, r_k) leading triplets; each kept left
+ * singular vector is sign-fixed (largest-magnitude component positive).
+ * disc_sq: (dev) [d-1] sums of discarded squared singular values per bond,
+ * or NULL.  Output ranks from tt_round_ranks. */
+int tt_round_ranks(const tt_tensor *Y, int32_t max_rank, int32_t *out_r /*(host)[d+1]*/);
+int64_t tt_round_workspace(const tt_tensor *Y, int32_t max_rank);
+int tt_round(const tt_tensor *Y, int32_t max_rank, tt_tensor *out,
+             float *disc_sq, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ A8 */
+/* Gram matrix of two batches (Riemannian Geometry Operations; Table 1
+ * 'gram'): G[a*bB + b] = <A_a, B_b> (Frobenius), B == NULL means B = A (the
+ * result is then symmetric and computed once per unordered pair).
+ * G: (dev) [bA][bB] row-major.  All tensors share mode sizes. */
+int64_t tt_gram_workspace(const tt_batch *A, const tt_batch *B);
+int tt_gram(const tt_batch *A, const tt_batch *B, float *G,
+            void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ A9 */
+/* Batched persistent gather + MSE + adjoint over many TT tensors of uneven
+ * ranks and entry counts (Batch Processing).  The plan owns its device
+ * buffers.  Instance j reads idx_j = idx + idx_off[j]*d ... see
+ * tt_plan_create for the layout; tt_plan_run launches ONE kernel (plus a
+ * fixed-order reduction) and is capturable into a hipGraph; tt_plan_capture
+ * captures it once and later tt_plan_run calls replay the graph. */
+typedef struct tt_plan tt_plan;
+/* X: the batch; idx: (dev) int32, instance j's entries are the SoA block
+ * [d][M_j] starting at element d*entry_off[j]; t: (dev) targets at
+ * entry_off[j]; entry_off: (host) [b+1] prefix sums of M_j; grads: the
+ * output batch (same shapes as X); loss: (dev) [b] per-instance MSE or
+ * NULL.  The pointers are bound into the plan. */
+int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t,
+                   const int64_t *entry_off, const tt_batch *grads, float *loss,
+                   tt_plan **plan);
+int tt_plan_run(tt_plan *plan, void *stream);
+int tt_plan_capture(tt_plan *plan, void *stream);
+/* Reference form: the same work as b plain per-instance calls of
+ * tt_gather_mse_backward (used to compare batched against plain launches). */
+int tt_plan_run_plain(tt_plan *plan, void *stream);
+void tt_plan_destroy(tt_plan *plan);
+
+/* ----------------------------------------------------------------- A10 */
+/* TT-matrix layer (t3f.matmul(tt_matrix, x), Implementation Details).
+ * W (prod m_k x prod n_k) is a TT-matrix with cores of shape
+ * r_k x m_k x n_k x r_{k+1} (row-major), W[(i_1..i_d),(j_1..j_d)] =
+ * G^1[i_1,j_1]...G^d[i_d,j_d] with C-ordered row/column multi-indices.
+ * Rows of X are input vectors: Y = X W^T, X (dev) [B][prod n], Y (dev)
+ * [B][prod m].  dtype: 0 = float32 everywhere, 1 = bfloat16 inputs/cores
+ * (X, cores, dY given as bf16 bit patterns) with float32 accumulation and
+ * float32 outputs. */
+typedef struct {
+  int32_t d;
+  const int32_t *m;       /* (host) [d] row (output) modes  */
+  const int32_t *n;       /* (host) [d] column (input) modes */
+  const int32_t *r;       /* (host) [d+1] ranks             */
+  const int64_t *off;     /* (host) [d] element offsets or NULL */
+  void *data;             /* (dev) cores (float32 or bf16)  */
+} tt_matrix;
+int64_t tt_matmul_workspace(const tt_matrix *W, int64_t B, int dtype);
+int tt_matmul(const tt_matrix *W, const void *X, int64_t B, float *Y, int dtype,
+              void *ws, size_t ws_bytes, void *stream);
+/* dX = dY W (float32 [B][prod n]); dW cores (float32, W's shapes) =
+ * gradient of <dY, X W^T>; either output may be NULL. */
+int tt_matmul_backward(const tt_matrix *W, const void *X, int64_t B,
+                       const void *dY, float *dX, float *dWdata, int dtype,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- misc */
+const char *tt_last_error(void);   /* thread-local message of the last failure */
+int tt_version(void);              /* TTGFX_VERSION                            */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTGFX_H */

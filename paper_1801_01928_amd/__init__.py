@@ -1,0 +1,13 @@
+"""MI355X-native TT-completion hot path (gather, adjoint, Riemannian step).
+
+The compute lives in libttgfx.so (hand-written HIP kernels for gfx950 behind
+the C ABI of include/ttgfx.h); this package marshals arguments only.
+"""
+from ._lib import load, TTError, last_error, TT_LR, TT_RL  # noqa: F401
+from .tt import (  # noqa: F401
+    TT,
+    gather,
+    gather_backward,
+    gather_mse_backward,
+    tt_gather,
+)

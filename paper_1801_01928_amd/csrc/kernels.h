@@ -1,0 +1,19 @@
+// Dispatch layer between the C ABI and the kernels: picks the specialised
+// kernel for a shape when one exists, else the generic one.
+#pragma once
+#include "common.h"
+
+namespace ttgfx {
+
+int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, hipStream_t s);
+
+// Adjoint with left cores L, right cores R, output O (all validated).
+size_t adjoint_dispatch_ws(const tt_tensor *X, int64_t M);
+int adjoint_dispatch(const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
+                     int64_t M, const float *w, void *ws, size_t ws_bytes, hipStream_t s);
+
+size_t fused_mse_ws(const tt_tensor *X, int64_t M);
+int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t, float *y,
+                       float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s);
+
+}  // namespace ttgfx

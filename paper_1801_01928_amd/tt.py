@@ -1,0 +1,164 @@
+"""TT tensors on the device and thin wrappers over the C ABI.
+
+PyTorch supplies device memory and the current stream; every computation is
+a call into libttgfx.  A ``TT`` stores its cores in one flat float32 buffer
+(core k, shape (r_k, n_k, r_{k+1}), row-major, at a packed offset), which is
+exactly the descriptor layout of include/ttgfx.h with ``off = NULL``.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _workspace(nbytes, device):
+    nbytes = int(nbytes)
+    if nbytes <= 0:
+        return None, 0
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+class TT:
+    """A TT tensor (Introduction: the TT format) with packed float32 cores."""
+
+    def __init__(self, ns, ranks, data=None, device="cuda"):
+        self.ns = [int(x) for x in ns]
+        self.ranks = [int(x) for x in ranks]
+        if len(self.ranks) != len(self.ns) + 1:
+            raise ValueError("ranks must have d+1 entries")
+        self.sizes = [self.ranks[k] * self.ns[k] * self.ranks[k + 1] for k in range(self.d)]
+        self.offs = [0]
+        for s in self.sizes:
+            self.offs.append(self.offs[-1] + s)
+        if data is None:
+            data = torch.empty(self.offs[-1], dtype=torch.float32, device=device)
+        if data.dtype != torch.float32 or data.dim() != 1 or data.numel() != self.offs[-1] \
+                or not data.is_contiguous():
+            raise ValueError("data must be a contiguous float32 vector of %d elements" % self.offs[-1])
+        self.data = data
+        self._desc = None
+
+    @property
+    def d(self):
+        return len(self.ns)
+
+    @property
+    def device(self):
+        return self.data.device
+
+    @classmethod
+    def from_cores(cls, cores, device="cuda"):
+        cores = [np.asarray(c, dtype=np.float32) if not torch.is_tensor(c) else c for c in cores]
+        ns = [int(c.shape[1]) for c in cores]
+        ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
+        flat = torch.cat([torch.as_tensor(c, dtype=torch.float32).reshape(-1) for c in cores])
+        return cls(ns, ranks, flat.to(device).contiguous(), device=device)
+
+    def core(self, k):
+        return self.data[self.offs[k]:self.offs[k + 1]].view(self.ranks[k], self.ns[k], self.ranks[k + 1])
+
+    def cores(self):
+        return [self.core(k) for k in range(self.d)]
+
+    def numpy_cores(self):
+        return [c.detach().cpu().numpy() for c in self.cores()]
+
+    def empty_like(self):
+        return TT(self.ns, self.ranks, device=self.device)
+
+    def desc(self):
+        """The ``tt_tensor`` descriptor (host arrays kept alive by this object)."""
+        if self._desc is None or self._desc.data != self.data.data_ptr():
+            d = self.d
+            self._n = (C.c_int32 * d)(*self.ns)
+            self._r = (C.c_int32 * (d + 1))(*self.ranks)
+            self._desc = L.tt_tensor(d, self._n, self._r, None, self.data.data_ptr())
+        return self._desc
+
+
+def _idx(idx, d, device):
+    if not torch.is_tensor(idx):
+        idx = torch.as_tensor(np.asarray(idx, dtype=np.int32))
+    idx = idx.to(device=device, dtype=torch.int32).contiguous()
+    if idx.dim() != 2 or idx.shape[0] != d:
+        raise ValueError("idx must have shape (d, M)")
+    return idx
+
+
+def _vec(v, M, device):
+    v = torch.as_tensor(v).to(device=device, dtype=torch.float32).contiguous()
+    if v.numel() != M:
+        raise ValueError("expected %d values" % M)
+    return v
+
+
+def gather(X, idx):
+    """y[m] = G^1[i_1^m] ... G^d[i_d^m] (the entry formula) for idx (d, M)."""
+    lib = L.load()
+    idx = _idx(idx, X.d, X.device)
+    M = idx.shape[1]
+    y = torch.empty(M, dtype=torch.float32, device=X.device)
+    L.check(lib.tt_gather(C.byref(X.desc()), _ptr(idx), M, _ptr(y), _stream(X.device)))
+    return y
+
+
+def gather_backward(X, idx, gy):
+    """Core gradients of sum_m gy[m] y[m] (the gather's adjoint)."""
+    lib = L.load()
+    idx = _idx(idx, X.d, X.device)
+    M = idx.shape[1]
+    gy = _vec(gy, M, X.device)
+    gX = X.empty_like()
+    ws, nb = _workspace(L.check(lib.tt_gather_backward_workspace(C.byref(X.desc()), M)), X.device)
+    L.check(lib.tt_gather_backward(C.byref(X.desc()), _ptr(idx), M, _ptr(gy), C.byref(gX.desc()),
+                                   _ptr(ws), nb, _stream(X.device)))
+    return gX
+
+
+def gather_mse_backward(X, idx, t, want_y=True):
+    """Fused completion-loss pass: returns (y, loss, core gradients) for
+    loss = mean((y - t)^2)."""
+    lib = L.load()
+    idx = _idx(idx, X.d, X.device)
+    M = idx.shape[1]
+    t = _vec(t, M, X.device)
+    y = torch.empty(M, dtype=torch.float32, device=X.device) if want_y else None
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    gX = X.empty_like()
+    ws, nb = _workspace(L.check(lib.tt_gather_mse_workspace(C.byref(X.desc()), M)), X.device)
+    L.check(lib.tt_gather_mse_backward(C.byref(X.desc()), _ptr(idx), M, _ptr(t), _ptr(y), _ptr(loss),
+                                       C.byref(gX.desc()), _ptr(ws), nb, _stream(X.device)))
+    return y, loss, gX
+
+
+class _GatherFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, flat, idx, ns, ranks):
+        X = TT(ns, ranks, flat.detach())
+        ctx.save_for_backward(flat.detach(), idx)
+        ctx.meta = (ns, ranks)
+        return gather(X, idx)
+
+    @staticmethod
+    def backward(ctx, gy):
+        flat, idx = ctx.saved_tensors
+        ns, ranks = ctx.meta
+        g = gather_backward(TT(ns, ranks, flat), idx, gy.contiguous())
+        return g.data, None, None, None
+
+
+def tt_gather(X, idx):
+    """Differentiable gather: gradients flow to ``X.data`` through the
+    hand-written adjoint kernel."""
+    idx = _idx(idx, X.d, X.device)
+    return _GatherFn.apply(X.data, idx, tuple(X.ns), tuple(X.ranks))

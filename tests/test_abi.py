@@ -1,0 +1,78 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttgfx.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(tt_[a-z_]+)\s*\(", src))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1801_01928_amd as tt
+    return tt.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1801_01928_amd._lib import SIGNATURES
+    names = _declared()
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+        assert n in SIGNATURES, n
+    assert lib.tt_version() == 1
+
+
+def _desc(ns, ranks, data=0x1000):
+    from paper_1801_01928_amd._lib import tt_tensor
+    d = len(ns)
+    n = (C.c_int32 * d)(*ns)
+    r = (C.c_int32 * (d + 1))(*ranks)
+    t = tt_tensor(d, n, r, None, data)
+    t._keep = (n, r)
+    return t
+
+
+def test_validation_errors_before_device(lib):
+    from paper_1801_01928_amd import _lib as L
+    X = _desc([3, 4], [1, 2, 1])
+    # negative M
+    assert lib.tt_gather(C.byref(X), C.c_void_p(0x10), -1, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    assert "negative" in L.last_error()
+    # null idx with M > 0
+    assert lib.tt_gather(C.byref(X), None, 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    # bad boundary rank
+    B = _desc([3, 4], [2, 2, 1])
+    assert lib.tt_gather(C.byref(B), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_SHAPE
+    # rank above the maximum
+    H = _desc([3, 4], [1, 65, 1])
+    assert lib.tt_gather(C.byref(H), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_UNSUPPORTED
+    # d out of range
+    Z = _desc([3], [1, 1])
+    Z.d = 0
+    assert lib.tt_gather(C.byref(Z), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    # null data
+    N = _desc([3, 4], [1, 2, 1], data=0)
+    assert lib.tt_gather(C.byref(N), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    # M = 0 is a no-op success (no device work)
+    assert lib.tt_gather(C.byref(X), None, 0, None, None) == L.TT_OK
+    # shape mismatch of the gradient descriptor
+    G = _desc([3, 4], [1, 3, 1])
+    assert lib.tt_gather_backward(C.byref(X), C.c_void_p(0x10), 5, C.c_void_p(0x10), C.byref(G),
+                                  None, 0, None) == L.TT_ERR_SHAPE
+    # workspace too small
+    ws = lib.tt_gather_backward_workspace(C.byref(X), 5)
+    assert ws > 0
+    assert lib.tt_gather_backward(C.byref(X), C.c_void_p(0x10), 5, C.c_void_p(0x10), C.byref(X),
+                                  C.c_void_p(0x10), ws - 1, None) == L.TT_ERR_WORKSPACE
+    assert "workspace" in L.last_error()

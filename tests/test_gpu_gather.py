@@ -1,0 +1,186 @@
+"""GPU parity of the gather, its adjoint and the fused MSE pass against the
+FP64 oracle (tolerances: 1e-5 relative, normwise)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _case(seed, ns, ranks, M, std=None):
+    rng = np.random.default_rng(seed)
+    std = std if std is not None else 1.0 / np.sqrt(max(ranks))
+    cores = W.random_cores(rng, ns, ranks, std)
+    idx = W.random_indices(rng, ns, M)
+    g = rng.standard_normal(M).astype(np.float32)
+    return cores, idx, g
+
+
+CASES = [
+    # (seed, ns, ranks, M)  -- several tiles plus a ragged tail, uneven ranks
+    (1, [8, 8, 8, 8], [1, 4, 4, 4, 1], 4096),
+    (2, [10] * 10, [1] + [16] * 9 + [1], 70001),
+    (3, [10] * 10, [1, 10, 32, 32, 32, 32, 32, 32, 32, 10, 1], 20011),
+    (4, [16] * 8, [1] + [8] * 7 + [1], 33333),
+    (5, [5, 7, 3, 9, 4], [1, 3, 11, 6, 2, 1], 9999),
+    (6, [3, 4], [1, 3, 1], 257),
+    (7, [13], [1, 1], 100),                       # d = 1
+    (8, [6, 6, 6], [1, 40, 40, 1], 3001),         # rank above 32
+    (9, [4, 4, 4, 4], [1, 4, 16, 4, 1], 1),       # a single entry
+]
+
+
+def _ids(c):
+    return "seed%d-d%d-M%d" % (c[0], len(c[1]), c[3])
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_gather_and_backward_parity(gpu_lib, case):
+    import torch
+    tt = gpu_lib
+    seed, ns, ranks, M = case
+    print("case", _ids(case), flush=True)
+    cores, idx, g = _case(seed, ns, ranks, M)
+    X = tt.TT.from_cores(cores)
+    y = tt.gather(X, idx).cpu().numpy()
+    yr = oracle.gather(cores, idx)
+    assert _rel(y, yr) <= TOL
+    gX = tt.gather_backward(X, idx, torch.from_numpy(g))
+    gr = oracle.gather_backward(cores, idx, g)
+    got = gX.numpy_cores()
+    for k in range(len(ns)):
+        assert _rel(got[k], gr[k]) <= TOL, (k, _rel(got[k], gr[k]))
+
+
+def test_empty_entries(gpu_lib):
+    import torch
+    tt = gpu_lib
+    cores, _, _ = _case(11, [4, 5, 6], [1, 3, 2, 1], 1)
+    X = tt.TT.from_cores(cores)
+    idx = np.zeros((3, 0), np.int32)
+    assert tt.gather(X, idx).numel() == 0
+    gX = tt.gather_backward(X, idx, torch.zeros(0))
+    assert float(gX.data.abs().max()) == 0.0
+    y, loss, gX = tt.gather_mse_backward(X, idx, torch.zeros(0))
+    assert float(loss.item()) == 0.0 and float(gX.data.abs().max()) == 0.0
+
+
+def test_duplicates_and_repeatability(gpu_lib):
+    import torch
+    tt = gpu_lib
+    cores, idx, g = _case(12, [3, 3, 3], [1, 2, 2, 1], 500)
+    idx = np.concatenate([idx, idx[:, :200]], axis=1)
+    g = np.concatenate([g, g[:200]])
+    X = tt.TT.from_cores(cores)
+    a = tt.gather_backward(X, idx, torch.from_numpy(g))
+    b = tt.gather_backward(X, idx, torch.from_numpy(g))
+    # repeated calls agree to rounding (LDS accumulation order may vary)
+    assert _rel(a.data.cpu().numpy(), b.data.cpu().numpy()) <= 1e-6
+    gr = oracle.gather_backward(cores, idx, g)
+    for k, c in enumerate(a.numpy_cores()):
+        assert _rel(c, gr[k]) <= TOL
+
+
+@pytest.mark.parametrize("M", [4096, 100003])
+def test_fused_mse_parity(gpu_lib, M):
+    tt = gpu_lib
+    p = W.gather_d10(M=M)
+    X = tt.TT.from_cores(p.cores)
+    t = (oracle.gather(p.planted, p.idx) + p.noise).astype(np.float32)
+    y, loss, gX = tt.gather_mse_backward(X, p.idx, t)
+    yr = oracle.gather(p.cores, p.idx)
+    lr, gr = oracle.mse_loss_and_grad(yr, t)
+    assert _rel(y.cpu().numpy(), yr) <= TOL
+    assert abs(float(loss.item()) - lr) <= TOL * lr
+    grr = oracle.gather_backward(p.cores, p.idx, gr)
+    for k, c in enumerate(gX.numpy_cores()):
+        assert _rel(c, grr[k]) <= TOL, k
+
+
+def test_autograd_function(gpu_lib):
+    import torch
+    tt = gpu_lib
+    cores, idx, g = _case(13, [6, 5, 7, 4], [1, 5, 6, 3, 1], 5000)
+    X = tt.TT.from_cores(cores)
+    X.data.requires_grad_(True)
+    y = tt.tt_gather(X, idx)
+    y.backward(torch.from_numpy(g).cuda())
+    gr = oracle.gather_backward(cores, idx, g)
+    flat = np.concatenate([x.reshape(-1) for x in gr])
+    assert _rel(X.data.grad.cpu().numpy(), flat) <= TOL
+
+
+@pytest.fixture(scope="module")
+def full_d10():
+    """The d=10, n=10, r=16 workload at 2^20 entries with its oracle results."""
+    p = W.gather_d10()
+    t = (oracle.gather(p.planted, p.idx) + p.noise).astype(np.float32)
+    yr = oracle.gather(p.cores, p.idx)
+    lr, gr = oracle.mse_loss_and_grad(yr, t)
+    grads = oracle.gather_backward(p.cores, p.idx, gr)
+    return p, t, yr, lr, grads
+
+
+def test_full_size_d10_r16(gpu_lib, full_d10):
+    """Full size (2^20 entries) in the launch configuration the benchmark
+    times: every output compared with the oracle."""
+    tt = gpu_lib
+    p, t, yr, lr, grads = full_d10
+    print("full d10 r16 M=2^20", flush=True)
+    X = tt.TT.from_cores(p.cores)
+    y, loss, gX = tt.gather_mse_backward(X, p.idx, t)
+    assert _rel(y.cpu().numpy(), yr) <= TOL
+    assert abs(float(loss.item()) - lr) <= TOL * lr
+    for k, c in enumerate(gX.numpy_cores()):
+        assert _rel(c, grads[k]) <= TOL, (k, _rel(c, grads[k]))
+
+
+def test_full_size_finite_differences(gpu_lib, full_d10):
+    """64 random core entries: exact central differences of the FP64 loss
+    agree with the GPU gradient."""
+    tt = gpu_lib
+    p, t, yr, lr, grads = full_d10
+    X = tt.TT.from_cores(p.cores)
+    _, _, gX = tt.gather_mse_backward(X, p.idx, t)
+    got = np.concatenate([c.reshape(-1) for c in gX.numpy_cores()])
+    flat = np.concatenate([c.reshape(-1).astype(np.float64) for c in p.cores])
+    sizes = [c.size for c in p.cores]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(16)
+    pick = rng.choice(flat.size, size=64, replace=False)
+    sub = np.arange(0, p.M, 16)   # every 16th entry keeps the FP64 loss cheap
+    idx = p.idx[:, sub]
+    ts = t[sub].astype(np.float64)
+    base = [c.astype(np.float64) for c in p.cores]
+    yb = oracle.gather(base, idx)
+    _, gs = oracle.mse_loss_and_grad(yb, ts)
+    gsub = np.concatenate([c.reshape(-1) for c in oracle.gather_backward(base, idx, gs)])
+    fd, an = [], []
+    for j in pick:
+        k = int(np.searchsorted(offs, j, side="right") - 1)
+        pos = np.unravel_index(j - offs[k], p.cores[k].shape)
+        mask = idx[k] == pos[1]          # only entries through this slice change
+        h = 0.1 * max(1.0, abs(flat[j]))
+        vals = []
+        for s in (1, -1):
+            cs = list(base)
+            cs[k] = base[k].copy()
+            cs[k][pos] += s * h
+            yp = yb.copy()
+            yp[mask] = oracle.gather(cs, idx[:, mask])
+            vals.append(oracle.mse_loss_and_grad(yp, ts)[0])
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        an.append(gsub[j])
+    assert _rel(an, fd) <= 1e-8          # the oracle gradient is exact
+    assert _rel(got[pick], np.concatenate([c.reshape(-1) for c in grads])[pick]) <= 1e-4
