@@ -85,8 +85,9 @@ typedef struct {
 /* Gather (Introduction, entry formula): y[m] = G^1[i_1^m] ... G^d[i_d^m].
  * idx: (dev) int32 structure-of-arrays [d][M] (mode k of entry m at
  * idx[k*M + m]); y: (dev) [M].  Ranks up to TT_MAX_RANK. */
+int64_t tt_gather_workspace(const tt_tensor *X, int64_t M);
 int tt_gather(const tt_tensor *X, const int32_t *idx, int64_t M, float *y,
-              void *stream);
+              void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ A3 */
 /* Adjoint of the gather (automatic differentiation, abstract): for every
@@ -94,10 +95,10 @@ int tt_gather(const tt_tensor *X, const int32_t *idx, int64_t M, float *y,
  *   gy[m] * (G^1[i_1]..G^{k-1}[i_{k-1}])^T (G^{k+1}[i_{k+1}]..G^d[i_d])^T.
  * gX must have X's shape; its cores are overwritten (not accumulated).
  * Repeated multi-indices contribute once per occurrence.  Summation over
- * entries is hierarchical: workgroups accumulate their entries in LDS, and
- * the per-workgroup partial sums are reduced in a fixed order.  The order
- * inside a workgroup follows scheduling, so repeated calls may differ in the
- * last bits (relative differences ~1e-7). */
+ * entries is hierarchical (per-tile sums, per-workgroup sums, then a
+ * fixed-order reduction over workgroups).  For ranks <= 32 the in-tile sums
+ * have a fixed order; workgroups combine their tiles with float atomics, so
+ * repeated calls may differ in the last bits (relative ~1e-7). */
 int64_t tt_gather_backward_workspace(const tt_tensor *X, int64_t M);
 int tt_gather_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
                        const float *gy, tt_tensor *gX,

@@ -60,7 +60,8 @@ PI64 = C.POINTER(C.c_int64)
 
 # name -> (restype, argtypes); the full exported surface of include/ttgfx.h
 SIGNATURES = {
-    "tt_gather": (C.c_int, [P_TT, VP, I64, VP, VP]),
+    "tt_gather_workspace": (I64, [P_TT, I64]),
+    "tt_gather": (C.c_int, [P_TT, VP, I64, VP, VP, SZ, VP]),
     "tt_gather_backward_workspace": (I64, [P_TT, I64]),
     "tt_gather_backward": (C.c_int, [P_TT, VP, I64, VP, P_TT, VP, SZ, VP]),
     "tt_gather_mse_workspace": (I64, [P_TT, I64]),

@@ -133,12 +133,21 @@ const char *tt_last_error(void) { return g_last_error.c_str(); }
 int tt_version(void) { return TTGFX_VERSION; }
 
 // ------------------------------------------------------------------ gather
-int tt_gather(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, void *stream) {
+int64_t tt_gather_workspace(const tt_tensor *X, int64_t M) {
+  int rc = validate_tt(X, "X", TT_MAX_RANK);
+  if (rc) return rc;
+  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
+  return (int64_t)gather_dispatch_ws(X, M);
+}
+
+int tt_gather(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, void *ws,
+              size_t ws_bytes, void *stream) {
   int rc = validate_tt(X, "X", TT_MAX_RANK);
   if (rc) return rc;
   if ((rc = check_entries(idx, M, y, "y"))) return rc;
   if (M == 0) return TT_OK;
-  return gather_dispatch(X, idx, M, y, (hipStream_t)stream);
+  if ((rc = check_ws(ws, ws_bytes, gather_dispatch_ws(X, M), "gather"))) return rc;
+  return gather_dispatch(X, idx, M, y, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int64_t tt_gather_backward_workspace(const tt_tensor *X, int64_t M) {

@@ -1,28 +1,62 @@
 // Kernel selection for the gather, its adjoint and the fused MSE pass.
+#include <stdlib.h>
+
 #include "kernels.h"
+#include "gather_mfma.h"
 
 namespace ttgfx {
 
-int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, hipStream_t s) {
+// The slice-grouped MFMA kernels serve ranks <= 32 and small mode sizes;
+// TTGFX_GENERIC=1 forces the generic one-lane-per-entry kernels.
+static bool use_mfma(const tt_tensor *L, const tt_tensor *R) {
+  static int forced = -1;
+  if (forced < 0) {
+    const char *e = getenv("TTGFX_GENERIC");
+    forced = (e && e[0] == '1') ? 1 : 0;
+  }
+  return !forced && mfma_supported(L, R);
+}
+
+size_t gather_dispatch_ws(const tt_tensor *X, int64_t M) {
+  return use_mfma(X, X) ? mfma_ws(X, mfma_rank_class(X, X), M, false) : 0;
+}
+
+int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, void *ws,
+                    size_t ws_bytes, hipStream_t s) {
+  if (use_mfma(X, X))
+    return mfma_run(0, X, X, nullptr, idx, M, nullptr, nullptr, y, nullptr, ws, ws_bytes, s);
   return generic_gather(make_dev(X), max_rank_of(X), idx, M, y, s);
 }
 
-size_t adjoint_dispatch_ws(const tt_tensor *X, int64_t M) { return generic_adjoint_ws(X, M); }
+size_t adjoint_dispatch_ws(const tt_tensor *X, int64_t M) {
+  if (use_mfma(X, X)) return mfma_ws(X, mfma_rank_class(X, X), M, true);
+  return generic_adjoint_ws(X, M);
+}
+
+size_t adjoint_dispatch_ws2(const tt_tensor *L, const tt_tensor *R, int64_t M) {
+  if (use_mfma(L, R)) return mfma_ws(R, mfma_rank_class(L, R), M, true);
+  return generic_adjoint_ws(R, M);
+}
 
 int adjoint_dispatch(const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
                      int64_t M, const float *w, void *ws, size_t ws_bytes, hipStream_t s) {
+  if (use_mfma(L, R))
+    return mfma_run(1, L, R, O, idx, M, nullptr, w, nullptr, nullptr, ws, ws_bytes, s);
   int mr = max_rank_of(L);
   if (max_rank_of(R) > mr) mr = max_rank_of(R);
   return generic_adjoint(make_dev(L), make_dev(R), make_dev(O), mr, idx, M, w, ws, ws_bytes, s);
 }
 
 size_t fused_mse_ws(const tt_tensor *X, int64_t M) {
+  if (use_mfma(X, X)) return mfma_ws(X, mfma_rank_class(X, X), M, true);
   const size_t m = (size_t)(M > 0 ? M : 1);
-  return arena_bytes<float>(m) * 2 + mse_ws(M) + adjoint_dispatch_ws(X, M);
+  return arena_bytes<float>(m) * 2 + mse_ws(M) + generic_adjoint_ws(X, M);
 }
 
 int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t, float *y,
                        float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s) {
+  if (use_mfma(X, X))
+    return mfma_run(2, X, X, gX, idx, M, t, nullptr, y, loss, ws, ws_bytes, s);
   const size_t m = (size_t)(M > 0 ? M : 1);
   Arena ar(ws, ws_bytes);
   float *ytmp = ar.take<float>(m);
@@ -30,14 +64,15 @@ int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const 
   void *mws = ar.base + align_up(ar.used, 256);
   ar.used = align_up(ar.used, 256) + mse_ws(M);
   void *aws = ar.base + align_up(ar.used, 256);
-  const size_t aws_bytes = adjoint_dispatch_ws(X, M);
+  const size_t aws_bytes = generic_adjoint_ws(X, M);
   ar.used = align_up(ar.used, 256) + aws_bytes;
   if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "gather_mse_backward: workspace too small");
   float *yy = y ? y : ytmp;
-  int rc = gather_dispatch(X, idx, M, yy, s);
+  int rc = generic_gather(make_dev(X), max_rank_of(X), idx, M, yy, s);
   if (rc) return rc;
   if ((rc = mse_residual(yy, t, M, g, loss, mws, mse_ws(M), s))) return rc;
-  return adjoint_dispatch(X, X, gX, idx, M, g, aws, aws_bytes, s);
+  int mr = max_rank_of(X);
+  return generic_adjoint(make_dev(X), make_dev(X), make_dev(gX), mr, idx, M, g, aws, aws_bytes, s);
 }
 
 }  // namespace ttgfx

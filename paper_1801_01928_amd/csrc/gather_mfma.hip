@@ -1,0 +1,777 @@
+// Slice-grouped MFMA kernels for the gather, its adjoint and the fused MSE
+// pass (bond ranks <= 32, mode sizes <= 32).
+//
+// The entry formula of the TT format (Introduction) multiplies, for every
+// observed entry, one core slice per mode.  A tile of T entries is sorted
+// by the slice index of each mode (a stable counting sort in LDS); entries
+// that use the same slice are packed into 16-entry blocks, so that one mode
+// step of a block is a dense product  (R x R slice) x (R x 16 entries)
+// evaluated with v_mfma_f32_16x16x4_f32.  Ranks are zero-padded to R.
+//
+// Right sweep (modes d..1):  rho_k = G^k[i_k] rho_{k+1},  rho_{d+1} = e_0,
+// so rho_1 = y (the gather).  Left sweep (modes 1..d):
+// lambda_{k+1}^T = G^k[i_k]^T lambda_k^T with lambda_1 = e_0; at every mode
+// the adjoint adds  sum_e w_e lambda_k,e (x) rho_{k+1},e  into slice i_k,
+// which for one block is again an MFMA product with K = entries.  Right
+// partials are stashed (in MFMA operand layout) in a per-workgroup global
+// buffer between the sweeps; left partials are recomputed by the left sweep.
+//
+// Layouts for a block of 16 entries (lane l, q = l / 16, c = l % 16):
+//   EL (entry on lane):     lane l holds components 16t + 4q + v of entry c
+//   CL (component on lane): lane l holds component 16t + c of entries 4q + v
+// for comp-tile t < R/16 and v < 4.  An MFMA with a slice as A operand maps
+// EL to EL (the contraction index 4q + v of chunk v is consistent between
+// operands); the adjoint's outer product takes both partials in CL.
+#include "common.h"
+#include "gather_mfma.h"
+
+namespace ttgfx {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr uint16_t kNone = 0xFFFF;
+
+// Workgroup barrier that waits for this wave's LDS operations only.  Inside
+// the sweeps no wave reads global memory written by another wave (each lane
+// reads back only its own stash and accumulator entries), so outstanding
+// global stores need not drain at every mode boundary.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+struct FusedArgs {
+  int d;
+  int n[MF_MAX_D];
+  int sbase[MF_MAX_D];         // slice index base of mode k in the padded slice arrays
+  const int32_t *idx;          // [d][M]
+  long long M;
+  const float *gp_right;       // padded slices, row-major (R x R), right-sweep cores
+  const float *gp_left;        // padded slices, transposed, left-sweep cores
+  const float *t;              // targets (fused MSE) or null
+  const float *gy;             // given weights (adjoint) or null
+  float *y;                    // gather output or null
+  float *stash;                // per workgroup: [d-1][nb_max][64 lanes][R/4]
+  float *acc;                  // per workgroup: [total slices][R*R]
+  float *loss_acc;             // per workgroup: one float
+  long long stash_stride;      // floats per workgroup
+  long long acc_stride;        // floats per workgroup
+  int nb_max;                  // blocks per mode capacity
+  int ntiles;
+  int total_slices;
+  float inv_m2;                // 2 / M
+};
+
+enum { MODE_GATHER = 0, MODE_ADJOINT = 1, MODE_MSE = 2 };
+
+// LDS layout (bytes), in this order:
+//   rows   float [T + 2][R + 4]  (row T: zeros, row T+1: write sink)
+//   slab   float [MAX_N][R][R + 4]    (adjoint modes: per-slice sums)
+//   edges  float [waves][R][R + 4]    (runs continuing the previous wave's slice)
+//   sflag  int   [MAX_N + 16]         (slice has a stored run; edge slice ids)
+//   wsum   float [T + 2]              (per-entry weight g_e; [T] = 0)
+//   perm   uint16 [PERM_CAP]
+//   bslc   uint8  [PERM_CAP / 16 + d]
+//   meta   int    pbase[d], bbase[d], nblk[d]
+template <int R, int T>
+struct Lds {
+  static constexpr int NMAX = MfTraits<R>::MAX_N;
+  static constexpr int PCAP = MfTraits<R>::PERM_CAP;
+  static constexpr size_t rows = 0;
+  static constexpr size_t slab = rows + (sizeof(float) * (T + 2) * (R + 4) + 15) / 16 * 16;
+  static constexpr size_t edges = slab + sizeof(float) * NMAX * R * (R + 4);
+  static constexpr size_t sflag = edges + sizeof(float) * (MfTraits<R>::THREADS / 64) * R * (R + 4);
+  static constexpr size_t wsum = sflag + sizeof(int) * (NMAX + 16);
+  static constexpr size_t perm = wsum + (sizeof(float) * (T + 2) + 15) / 16 * 16;
+  static constexpr size_t bslc = perm + sizeof(uint16_t) * PCAP;
+  static constexpr size_t meta = bslc + (PCAP / 16 + MF_MAX_D + 16) / 16 * 16;
+  static constexpr size_t total = meta + sizeof(int) * 3 * MF_MAX_D + 64;
+  static_assert(total <= 160 * 1024, "LDS budget");
+};
+
+template <int R, int T, int MODE>
+__global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p) {
+  constexpr int NTHR = MfTraits<R>::THREADS;
+  constexpr int NT = R / 16;      // comp tiles
+  constexpr int W = NTHR / 64;    // waves
+  constexpr int RS = R + 4;       // LDS row stride (padding spreads banks)
+  constexpr int SS = R + 4;       // slab/edge row stride (conflict-free D stores)
+  constexpr int G = (R == 16) ? 4 : 2;  // blocks per group
+  constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
+  constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
+  using L = Lds<R, T>;
+  extern __shared__ __align__(16) char smem[];
+  float *rows = (float *)(smem + L::rows);
+  float *slab = (float *)(smem + L::slab);
+  float *edges = (float *)(smem + L::edges);
+  int *sflag = (int *)(smem + L::sflag);
+  int *eslice = sflag + L::NMAX;
+  float *wsum = (float *)(smem + L::wsum);
+  uint16_t *perm = (uint16_t *)(smem + L::perm);
+  uint8_t *bslc = (uint8_t *)(smem + L::bslc);
+  int *pbase = (int *)(smem + L::meta);
+  int *bbase = pbase + MF_MAX_D;
+  int *nblk = bbase + MF_MAX_D;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int c16 = lane & 15;
+  const int q4 = lane >> 4;
+  const int d = p.d;
+  const long long M = p.M;
+  float *stash = p.stash + (long long)blockIdx.x * p.stash_stride;
+  float *accg = p.acc + (long long)blockIdx.x * p.acc_stride;
+  float loss_part = 0.f;
+  bool first_tile = true;
+
+  // per-mode layout of the permutation arrays (padded groups of 16)
+  if (tid == 0) {
+    int pb = 0, bb = 0;
+    for (int k = 0; k < d; ++k) {
+      pbase[k] = pb;
+      bbase[k] = bb;
+      const int cap = T + 16 * p.n[k];  // multiple of 16: 8-byte aligned block reads
+      pb += cap;
+      bb += cap / 16 + 1;
+    }
+  }
+  for (int c = tid; c < RS; c += NTHR) rows[ZROW * RS + c] = 0.f;
+  if (tid == 0) wsum[ZROW] = 0.f;
+  __syncthreads();
+
+  for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+    const long long e0 = (long long)tile * T;
+    const int cnt = (int)((M - e0) < T ? (M - e0) : T);
+
+    // ---------------------------------------------------------------- sort
+    // Wave w sorts modes w, w + W, ...: a stable counting sort of the tile's
+    // entries by slice index (ballot ranks, shuffle scans), groups padded to
+    // multiples of 16 entries.
+    for (int k = wave; k < d; k += W) {
+      constexpr int CH = T / 64;  // entries per lane
+      const int nk = p.n[k];
+      // per chunk: slice index + 1 in the low 8 bits (0 = no entry), rank above
+      int st[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int e = 64 * c + lane;
+        const int v = (e < cnt) ? p.idx[(long long)k * M + e0 + e] : -1;
+        st[c] = (v >= 0 && v < nk) ? v + 1 : 0;  // out-of-range indices are dropped
+      }
+      const unsigned long long below = (1ull << lane) - 1ull;
+      int run = 0;  // lane v: entries of slice v in the chunks seen so far
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int sc = st[c] - 1;
+        unsigned long long mine = 0ull;
+        int add = 0;
+        for (int v = 0; v < nk; ++v) {
+          const unsigned long long m = __ballot(sc == v);
+          if (sc == v) mine = m;
+          if (lane == v) add = __popcll(m);
+        }
+        const int rk = __shfl(run, sc >= 0 ? sc : 0) + __popcll(mine & below);
+        st[c] |= rk << 8;
+        run += add;
+      }
+      const int padded = (lane < nk) ? ((run + 15) & ~15) : 0;
+      int incl = padded;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      const int base = incl - padded;
+      uint16_t *pk = perm + pbase[k];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int sc = (st[c] & 255) - 1;
+        const int b = __shfl(base, sc >= 0 ? sc : 0);
+        if (sc >= 0) pk[b + (st[c] >> 8)] = (uint16_t)(64 * c + lane);
+      }
+      if (lane < nk) {
+        for (int j = run; j < padded; ++j) pk[base + j] = kNone;
+        uint8_t *bk = bslc + bbase[k] + base / 16;
+        for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
+      }
+      if (lane == 63) nblk[k] = incl / 16;
+    }
+    lds_barrier();
+
+    // --------------------------------------------------------- right sweep
+    // Each wave walks its blocks of mode k in groups of G: the LDS reads of a
+    // group are issued together and its MFMA chains are independent, so the
+    // matrix pipe is fed back to back.  Padding columns read the zero row.
+    for (int k = d - 1; k >= 0; --k) {
+      const int nb = nblk[k];
+      const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
+      const uint16_t *pk = perm + pbase[k];
+      const uint8_t *bk = bslc + bbase[k];
+      const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
+      for (int j0 = jb; j0 < je; j0 += G) {
+        int ent[G], ev[G][4];
+        bool act[G];
+        v4f a[G][NT * NT];
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+          const int j = j0 + b;
+          act[b] = j < je;
+          ent[b] = ZROW;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
+          if (act[b]) {
+            const int e = pk[16 * j + c16];
+            ent[b] = (e == kNone) ? ZROW : e;
+            const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+            const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
+            const float *gs = gk + (long long)bk[j] * R * R;
+#pragma unroll
+            for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+          } else {
+#pragma unroll
+            for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+        v4f bv[G][NT];
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            if (k == d - 1)
+              bv[b][t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
+            else
+              bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
+          }
+        }
+        if (MODE != MODE_GATHER && k <= d - 2) {
+          // stash rho_{k+1} of these blocks in CL layout
+#pragma unroll
+          for (int b = 0; b < G; ++b) {
+            v4f cl[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[b][v] * RS + 16 * t + c16];
+            if (act[b]) {
+              float *st = stash + ((long long)k * p.nb_max + j0 + b) * (64 * R / 4);
+#pragma unroll
+              for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = cl[t];
+            }
+          }
+        }
+        v4f out[G][NT];
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) out[b][t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int to = 0; to < NT; ++to)
+#pragma unroll
+              for (int b = 0; b < G; ++b)
+                out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+          if (!act[b]) continue;
+          if (k > 0) {
+            const int w = (ent[b] == ZROW) ? SROW : ent[b];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
+          } else if (q4 == 0 && ent[b] != ZROW) {
+            wsum[ent[b]] = out[b][0][0];  // component 0 of rho_1 = y
+          }
+        }
+      }
+      lds_barrier();
+    }
+
+    // ------------------------------------------------------------ residual
+    for (int e = tid; e < cnt; e += NTHR) {
+      const float yv = wsum[e];
+      if (p.y) p.y[e0 + e] = yv;
+      float w = 0.f;
+      if (MODE == MODE_MSE) {
+        const float rho = yv - p.t[e0 + e];
+        w = p.inv_m2 * rho;
+        loss_part += rho * rho;
+      } else if (MODE == MODE_ADJOINT) {
+        w = p.gy[e0 + e];
+      }
+      wsum[e] = w;
+    }
+    if (MODE == MODE_GATHER) {
+      lds_barrier();
+      continue;
+    }
+    // lambda_1 = e_0 for every entry (and the zero row stays zero)
+    for (int e = tid; e < T; e += NTHR) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) rows[e * RS + c] = (c == 0) ? 1.f : 0.f;
+    }
+    lds_barrier();
+
+    // ---------------------------------------------------------- left sweep
+    // Outer products are summed in registers over each run of consecutive
+    // blocks with the same slice.  The wave that holds the first block of a
+    // slice stores its run into slab[s]; a wave whose first run continues a
+    // slice of the previous wave stores that run into its edge buffer.  The
+    // flush adds slab and edges in a fixed order: no atomics, deterministic.
+    for (int k = 0; k < d; ++k) {
+      const int nk = p.n[k];
+      for (int e = tid; e < nk; e += NTHR) sflag[e] = 0;
+      if (lane == 0) eslice[wave] = -1;
+      lds_barrier();
+      const int nb = nblk[k];
+      const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
+      const uint16_t *pk = perm + pbase[k];
+      const uint8_t *bk = bslc + bbase[k];
+      const float *gk = p.gp_left + (long long)p.sbase[k] * R * R;
+      const bool chain = k < d - 1;
+      const bool cont_first = (jb < je) && jb > 0 && bk[jb - 1] == bk[jb];
+      bool first_run = true;
+      int rsid = -1;
+      v4f racc[NT * NT];
+      for (int j0 = jb; j0 < je; j0 += G) {
+        int ent[G], ev[G][4], sid[G];
+        bool act[G];
+        v4f a[G][NT * NT];
+        v4f rcl[G][NT];
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+          const int j = j0 + b;
+          act[b] = j < je;
+          ent[b] = ZROW;
+          sid[b] = -1;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
+            rcl[b][t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+          }
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+          if (act[b]) {
+            const int e = pk[16 * j + c16];
+            ent[b] = (e == kNone) ? ZROW : e;
+            const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+            const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
+            sid[b] = bk[j];
+            if (k <= d - 2) {
+              const float *st = stash + ((long long)k * p.nb_max + j) * (64 * R / 4);
+#pragma unroll
+              for (int t = 0; t < NT; ++t) rcl[b][t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+            }
+            if (chain) {
+              const float *gs = gk + (long long)sid[b] * R * R;
+#pragma unroll
+              for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+            }
+          }
+        }
+        // lambda_k: CL (weighted, A operand of the outer product) and EL (chain)
+        v4f lcl[G][NT], bv[G][NT];
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float wv = wsum[ev[b][v]];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) lcl[b][t][v] = wv * rows[ev[b][v] * RS + 16 * t + c16];
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
+        }
+        // outer products (G * NT * NT independent chains)
+        v4f dg[G][NT * NT];
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) dg[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+              for (int b = 0; b < G; ++b)
+                dg[b][ta * NT + tb] = mfma4(lcl[b][ta][c], rcl[b][tb][c], dg[b][ta * NT + tb]);
+        // chain lambda_{k+1}^T = G^T lambda_k^T
+        v4f out[G][NT];
+        if (chain) {
+#pragma unroll
+          for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) out[b][t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int to = 0; to < NT; ++to)
+#pragma unroll
+                for (int b = 0; b < G; ++b)
+                  out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
+#pragma unroll
+          for (int b = 0; b < G; ++b) {
+            if (!act[b]) continue;
+            const int w = (ent[b] == ZROW) ? SROW : ent[b];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
+          }
+        }
+        // merge the group's outer products into runs
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+          if (!act[b]) continue;
+          if (sid[b] != rsid) {
+            if (rsid >= 0) {
+              float *dst = (first_run && cont_first) ? edges + wave * R * SS : slab + rsid * R * SS;
+              if (first_run && cont_first) {
+                if (lane == 0) eslice[wave] = rsid;
+              } else if (lane == 0) {
+                sflag[rsid] = 1;
+              }
+#pragma unroll
+              for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+                  for (int v = 0; v < 4; ++v)
+                    dst[(16 * ta + 4 * q4 + v) * SS + 16 * tb + c16] = racc[ta * NT + tb][v];
+              first_run = false;
+            }
+            rsid = sid[b];
+#pragma unroll
+            for (int x = 0; x < NT * NT; ++x) racc[x] = dg[b][x];
+          } else {
+#pragma unroll
+            for (int x = 0; x < NT * NT; ++x) racc[x] += dg[b][x];
+          }
+        }
+      }
+      if (rsid >= 0) {
+        float *dst = (first_run && cont_first) ? edges + wave * R * SS : slab + rsid * R * SS;
+        if (first_run && cont_first) {
+          if (lane == 0) eslice[wave] = rsid;
+        } else if (lane == 0) {
+          sflag[rsid] = 1;
+        }
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              dst[(16 * ta + 4 * q4 + v) * SS + 16 * tb + c16] = racc[ta * NT + tb][v];
+      }
+      lds_barrier();
+      // flush this mode into the workgroup's accumulator without waiting: a
+      // plain store on the first tile, no-return atomics after
+      float *ak = accg + (long long)p.sbase[k] * R * R;
+      for (int e = tid; e < nk * R * R; e += NTHR) {
+        const int sl = e / (R * R), a = (e / R) % R, b = e % R;
+        float v = 0.f;
+        if (sflag[sl]) {
+          v = slab[sl * R * SS + a * SS + b];
+          for (int w = 0; w < W; ++w)
+            if (eslice[w] == sl) v += edges[w * R * SS + a * SS + b];
+        }
+        if (first_tile) ak[e] = v;
+        else unsafeAtomicAdd(ak + e, v);
+      }
+      lds_barrier();
+    }
+    first_tile = false;
+  }
+
+  if (MODE == MODE_MSE) {
+    // deterministic block reduction of the squared residuals
+    float *red = wsum;
+    __syncthreads();
+    red[tid] = loss_part;
+    __syncthreads();
+    for (int st = NTHR / 2; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) p.loss_acc[blockIdx.x] = red[0];
+  }
+}
+
+// Padded slice copies in MFMA A-operand order: for slice G (R x R, zero
+// outside the true ranks) and comp tiles (to, ti), lane l's float4 holds
+// M[16 to + l%16][16 ti + 4 (l/16) + c], c < 4, with M = G for the right
+// sweep and M = G^T for the left sweep.
+__global__ void pad_slices_kernel(TTDev Xr, TTDev Xl, int R, float *__restrict__ right,
+                                  float *__restrict__ left, int total_slices) {
+  const int slice = blockIdx.x;
+  if (slice >= total_slices) return;
+  int k = 0, base = 0;
+  while (k < Xr.d && slice >= base + Xr.n[k]) {
+    base += Xr.n[k];
+    ++k;
+  }
+  const int s = slice - base;
+  const int NT = R / 16;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int c = e & 3, lane = (e >> 2) & 63, x = e >> 8;
+    const int to = x / NT, ti = x % NT;
+    const int row = 16 * to + (lane & 15), col = 16 * ti + 4 * (lane >> 4) + c;
+    if (right) {
+      float v = 0.f;  // G[row][col]
+      if (row < Xr.r[k] && col < Xr.r[k + 1])
+        v = Xr.data[Xr.off[k] + ((long long)row * Xr.n[k] + s) * Xr.r[k + 1] + col];
+      right[(long long)slice * R * R + e] = v;
+    }
+    if (left) {
+      float v = 0.f;  // G^T[row][col] = G[col][row]
+      if (col < Xl.r[k] && row < Xl.r[k + 1])
+        v = Xl.data[Xl.off[k] + ((long long)col * Xl.n[k] + s) * Xl.r[k + 1] + row];
+      left[(long long)slice * R * R + e] = v;
+    }
+  }
+}
+
+// Stage 1 of the gradient reduction: tmp[g][e] = sum of acc[w][e] over the
+// workgroups w of group g (32 per group), in increasing w.
+__global__ void reduce_acc_stage1(const float *__restrict__ acc, long long acc_stride, int nwg,
+                                  long long E, float *__restrict__ tmp) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int w0 = blockIdx.y * 32;
+  const int w1 = (w0 + 32 < nwg) ? w0 + 32 : nwg;
+  float v = 0.f;
+  for (int w = w0; w < w1; ++w) v += acc[(long long)w * acc_stride + e];
+  tmp[(long long)blockIdx.y * E + e] = v;
+}
+
+// Stage 2: out core k (a, s, b) = sum over groups (increasing) of the padded
+// element (slice(k, s), a, b).
+__global__ void reduce_acc_stage2(TTDev O, int R, const float *__restrict__ tmp, long long E,
+                                  int ngroups) {
+  const int k = blockIdx.y;
+  if (k >= O.d) return;
+  int sbase = 0;
+  for (int j = 0; j < k; ++j) sbase += O.n[j];
+  const int rk = O.r[k], nk = O.n[k], rk1 = O.r[k + 1];
+  const long long total = (long long)rk * nk * rk1;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(e % rk1);
+    const int s = (int)((e / rk1) % nk);
+    const int a = (int)(e / ((long long)rk1 * nk));
+    const long long src = ((long long)(sbase + s) * R + a) * R + b;
+    float v = 0.f;
+    for (int g = 0; g < ngroups; ++g) v += tmp[(long long)g * E + src];
+    O.data[O.off[k] + e] = v;
+  }
+}
+
+// One wave: loss = (fixed-order sum of the per-workgroup squared residuals) / M.
+__global__ void reduce_loss_kernel(const float *__restrict__ part, int nwg, long long M,
+                                   float *__restrict__ loss) {
+  const int lane = threadIdx.x;
+  float v = 0.f;
+  for (int w = lane; w < nwg; w += 64) v += part[w];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) *loss = (M > 0) ? v / (float)M : 0.f;
+}
+
+int device_cus() {
+  static int cached = -1;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  cached = cus;
+  return cus;
+}
+
+template <int R>
+constexpr int tile_of() { return MfTraits<R>::T; }
+
+struct Geometry {
+  int R, T, nb_max, total_slices, ntiles, nwg;
+  long long stash_stride, acc_stride;
+};
+
+Geometry geometry(const tt_tensor *X, int R, int64_t M) {
+  Geometry g;
+  g.R = R;
+  g.T = (R == 16) ? tile_of<16>() : tile_of<32>();
+  int nmax = 1;
+  g.total_slices = 0;
+  for (int k = 0; k < X->d; ++k) {
+    nmax = X->n[k] > nmax ? X->n[k] : nmax;
+    g.total_slices += X->n[k];
+  }
+  g.nb_max = g.T / 16 + nmax;
+  g.ntiles = (int)((M + g.T - 1) / g.T);
+  const int cus = device_cus();
+  g.nwg = g.ntiles < cus ? g.ntiles : cus;
+  if (g.nwg < 1) g.nwg = 1;
+  g.stash_stride = (long long)(X->d > 1 ? X->d - 1 : 1) * g.nb_max * 64 * (R / 4);
+  g.acc_stride = (long long)g.total_slices * R * R;
+  return g;
+}
+
+template <int R, int MODE>
+int launch_fused(const FusedArgs &a, int nwg, hipStream_t s) {
+  constexpr int T = tile_of<R>();
+  using L = Lds<R, T>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<R, T, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::total);
+    if (e != hipSuccess) return hip_check(e, "fused kernel LDS attribute");
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((fused_kernel<R, T, MODE>), dim3(nwg), dim3(MfTraits<R>::THREADS), L::total, s, a);
+  return launch_check("fused MFMA kernel");
+}
+
+}  // namespace
+
+template <int R>
+static bool fits_class(const tt_tensor *X) {
+  if (X->d < 2 || X->d > MF_MAX_D) return false;
+  int pcap = 0;
+  for (int k = 0; k < X->d; ++k) {
+    if (X->n[k] > MfTraits<R>::MAX_N) return false;
+    pcap += MfTraits<R>::T + 16 * X->n[k];
+  }
+  return pcap <= MfTraits<R>::PERM_CAP;
+}
+
+bool mfma_supported(const tt_tensor *L, const tt_tensor *R) {
+  const int rc = mfma_rank_class(L, R);
+  const tt_tensor *ts[2] = {L, R};
+  for (const tt_tensor *X : ts) {
+    if (!X) continue;
+    if (max_rank_of(X) > 32) return false;
+    if (rc == 16 ? !fits_class<16>(X) : !fits_class<32>(X)) return false;
+  }
+  return true;
+}
+
+int mfma_rank_class(const tt_tensor *L, const tt_tensor *R) {
+  int mr = L ? max_rank_of(L) : 1;
+  if (R && max_rank_of(R) > mr) mr = max_rank_of(R);
+  return mr <= 16 ? 16 : 32;
+}
+
+size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint) {
+  const Geometry g = geometry(X, R, M);
+  size_t b = 2 * arena_bytes<float>((size_t)g.total_slices * R * R);
+  if (adjoint) {
+    b += arena_bytes<float>((size_t)g.nwg * g.stash_stride);
+    b += arena_bytes<float>((size_t)g.nwg * g.acc_stride);
+    b += arena_bytes<float>((size_t)g.nwg);
+    b += arena_bytes<float>((size_t)((g.nwg + 31) / 32) * g.total_slices * R * R);
+  }
+  return b;
+}
+
+int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, const int32_t *idx,
+             int64_t M, const float *t, const float *gy, float *y, float *loss, void *ws,
+             size_t ws_bytes, hipStream_t s) {
+  const int R = mfma_rank_class(Lt, Rt);
+  const bool adjoint = mode != MODE_GATHER;
+  const Geometry g = geometry(Rt, R, M);
+  Arena ar(ws, ws_bytes);
+  float *gpr = ar.take<float>((size_t)g.total_slices * R * R);
+  float *gpl = ar.take<float>((size_t)g.total_slices * R * R);
+  float *stash = nullptr, *acc = nullptr, *lacc = nullptr, *rtmp = nullptr;
+  if (adjoint) {
+    stash = ar.take<float>((size_t)g.nwg * g.stash_stride);
+    acc = ar.take<float>((size_t)g.nwg * g.acc_stride);
+    lacc = ar.take<float>((size_t)g.nwg);
+    rtmp = ar.take<float>((size_t)((g.nwg + 31) / 32) * g.total_slices * R * R);
+  }
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "gather (MFMA): workspace too small");
+  const TTDev dr = make_dev(Rt);
+  const TTDev dl = make_dev(Lt ? Lt : Rt);
+  hipLaunchKernelGGL(pad_slices_kernel, dim3(g.total_slices), dim3(256), 0, s, dr, dl, R, gpr,
+                     adjoint ? gpl : (float *)nullptr, g.total_slices);
+  int rc = launch_check("pad slices");
+  if (rc) return rc;
+
+  FusedArgs a = {};
+  a.d = Rt->d;
+  int sb = 0;
+  for (int k = 0; k < Rt->d; ++k) {
+    a.n[k] = Rt->n[k];
+    a.sbase[k] = sb;
+    sb += Rt->n[k];
+  }
+  a.idx = idx;
+  a.M = M;
+  a.gp_right = gpr;
+  a.gp_left = gpl;
+  a.t = t;
+  a.gy = gy;
+  a.y = y;
+  a.stash = stash;
+  a.acc = acc;
+  a.loss_acc = lacc;
+  a.stash_stride = g.stash_stride;
+  a.acc_stride = g.acc_stride;
+  a.nb_max = g.nb_max;
+  a.ntiles = g.ntiles;
+  a.total_slices = g.total_slices;
+  a.inv_m2 = M > 0 ? 2.0f / (float)M : 0.f;
+
+  if (M > 0) {
+    if (R == 16) {
+      if (mode == MODE_GATHER) rc = launch_fused<16, MODE_GATHER>(a, g.nwg, s);
+      else if (mode == MODE_ADJOINT) rc = launch_fused<16, MODE_ADJOINT>(a, g.nwg, s);
+      else rc = launch_fused<16, MODE_MSE>(a, g.nwg, s);
+    } else {
+      if (mode == MODE_GATHER) rc = launch_fused<32, MODE_GATHER>(a, g.nwg, s);
+      else if (mode == MODE_ADJOINT) rc = launch_fused<32, MODE_ADJOINT>(a, g.nwg, s);
+      else rc = launch_fused<32, MODE_MSE>(a, g.nwg, s);
+    }
+    if (rc) return rc;
+  }
+  if (!adjoint) return TT_OK;
+  if (M == 0) {
+    // no entries: zero gradients and loss
+    for (int k = 0; k < O->d; ++k) {
+      rc = fill_zero(O->data + core_off(O, k), core_elems(O, k), s);
+      if (rc) return rc;
+    }
+    if (loss) return fill_zero(loss, 1, s);
+    return TT_OK;
+  }
+  const TTDev od = make_dev(O);
+  const long long E = (long long)g.total_slices * R * R;
+  const int ngroups = (g.nwg + 31) / 32;
+  hipLaunchKernelGGL(reduce_acc_stage1, dim3((unsigned)((E + 255) / 256), ngroups), dim3(256), 0, s,
+                     acc, g.acc_stride, g.nwg, E, rtmp);
+  if ((rc = launch_check("reduce partial gradients"))) return rc;
+  hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, od, R, rtmp, E, ngroups);
+  if ((rc = launch_check("reduce partial gradients (2)"))) return rc;
+  if (mode == MODE_MSE && loss) {
+    hipLaunchKernelGGL(reduce_loss_kernel, dim3(1), dim3(64), 0, s, lacc, g.nwg, (long long)M, loss);
+    return launch_check("reduce loss");
+  }
+  return TT_OK;
+}
+
+}  // namespace ttgfx

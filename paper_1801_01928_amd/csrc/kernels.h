@@ -5,10 +5,13 @@
 
 namespace ttgfx {
 
-int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, hipStream_t s);
+size_t gather_dispatch_ws(const tt_tensor *X, int64_t M);
+int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, void *ws,
+                    size_t ws_bytes, hipStream_t s);
 
 // Adjoint with left cores L, right cores R, output O (all validated).
 size_t adjoint_dispatch_ws(const tt_tensor *X, int64_t M);
+size_t adjoint_dispatch_ws2(const tt_tensor *L, const tt_tensor *R, int64_t M);
 int adjoint_dispatch(const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
                      int64_t M, const float *w, void *ws, size_t ws_bytes, hipStream_t s);
 

@@ -108,7 +108,8 @@ def gather(X, idx):
     idx = _idx(idx, X.d, X.device)
     M = idx.shape[1]
     y = torch.empty(M, dtype=torch.float32, device=X.device)
-    L.check(lib.tt_gather(C.byref(X.desc()), _ptr(idx), M, _ptr(y), _stream(X.device)))
+    ws, nb = _workspace(L.check(lib.tt_gather_workspace(C.byref(X.desc()), M)), X.device)
+    L.check(lib.tt_gather(C.byref(X.desc()), _ptr(idx), M, _ptr(y), _ptr(ws), nb, _stream(X.device)))
     return y
 
 

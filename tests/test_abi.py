@@ -47,25 +47,25 @@ def test_validation_errors_before_device(lib):
     from paper_1801_01928_amd import _lib as L
     X = _desc([3, 4], [1, 2, 1])
     # negative M
-    assert lib.tt_gather(C.byref(X), C.c_void_p(0x10), -1, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    assert lib.tt_gather(C.byref(X), C.c_void_p(0x10), -1, C.c_void_p(0x10), None, 0, None) == L.TT_ERR_ARG
     assert "negative" in L.last_error()
     # null idx with M > 0
-    assert lib.tt_gather(C.byref(X), None, 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    assert lib.tt_gather(C.byref(X), None, 5, C.c_void_p(0x10), None, 0, None) == L.TT_ERR_ARG
     # bad boundary rank
     B = _desc([3, 4], [2, 2, 1])
-    assert lib.tt_gather(C.byref(B), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_SHAPE
+    assert lib.tt_gather(C.byref(B), C.c_void_p(0x10), 5, C.c_void_p(0x10), None, 0, None) == L.TT_ERR_SHAPE
     # rank above the maximum
     H = _desc([3, 4], [1, 65, 1])
-    assert lib.tt_gather(C.byref(H), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_UNSUPPORTED
+    assert lib.tt_gather(C.byref(H), C.c_void_p(0x10), 5, C.c_void_p(0x10), None, 0, None) == L.TT_ERR_UNSUPPORTED
     # d out of range
     Z = _desc([3], [1, 1])
     Z.d = 0
-    assert lib.tt_gather(C.byref(Z), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    assert lib.tt_gather(C.byref(Z), C.c_void_p(0x10), 5, C.c_void_p(0x10), None, 0, None) == L.TT_ERR_ARG
     # null data
     N = _desc([3, 4], [1, 2, 1], data=0)
-    assert lib.tt_gather(C.byref(N), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    assert lib.tt_gather(C.byref(N), C.c_void_p(0x10), 5, C.c_void_p(0x10), None, 0, None) == L.TT_ERR_ARG
     # M = 0 is a no-op success (no device work)
-    assert lib.tt_gather(C.byref(X), None, 0, None, None) == L.TT_OK
+    assert lib.tt_gather(C.byref(X), None, 0, None, None, 0, None) == L.TT_OK
     # shape mismatch of the gradient descriptor
     G = _desc([3, 4], [1, 3, 1])
     assert lib.tt_gather_backward(C.byref(X), C.c_void_p(0x10), 5, C.c_void_p(0x10), C.byref(G),
