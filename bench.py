@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the TT-completion hot path on one MI355X.
+
+One step = one fused pass over the observed entries of a d=10, n=10, r=16 TT
+(2^20 uniform observed entries, planted rank-8 targets): the gather
+(entry formula), the mean-squared-residual loss and the adjoint into all
+core gradients, as one call of tt_gather_mse_backward.  Inputs are resident
+in HBM before the timed region.
+
+Prints one JSON line with the whole-job rate (observed entries/s), the
+roofline of the dominant kernel (its duration measured with HIP events on
+its launch stream) and the FP64 oracle timed on the host as a reported
+baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "observed entries/s, TT gather fwd+bwd (d=10,n=10,r=16) + % roofline, batched vs plain"
+# Algorithmic work of the fused pass per observed entry (d=10, r=16, first
+# and last cores 1 x r and r x 1): right sweep 8 (1x16)(16x16) products plus
+# one 16-dot = 4128 flop (it yields y), left sweep 8 products = 4096 flop,
+# outer products g * lambda (x) rho for all 10 modes = 2 * (16 + 8*256 + 16)
+# = 4160 flop.  The forward is not recomputed by the adjoint.
+FLOP_PER_ENTRY = 4128 + 4096 + 4160
+PEAK_MFMA_F32_TFLOPS = 157.3
+KERNEL_SOURCES = ["gather_mfma.hip", "gather_mfma.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_gather_d10_r16.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
+                    help="observed entries the oracle processes for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain 512 MiB device-to-device copy, repeated: reading its
+    FETCH_SIZE / WRITE_SIZE per dispatch gives the counter scale."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+
+
+def traffic_bytes():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when absent or taken on different kernel sources."""
+    from paper_1801_01928_amd.profiling import source_hash
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_hash(KERNEL_SOURCES):
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(p, t, sample):
+    """The FP64 oracle (gather, loss, adjoint) on the first `sample` observed
+    entries, single-threaded BLAS."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import oracle
+    S = min(sample, p.M)
+    idx = p.idx[:, :S]
+    ts = t[:S].astype(np.float64)
+    cores = [c.astype(np.float64) for c in p.cores]
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        if ctx:
+            ctx.__enter__()
+        t0 = time.perf_counter()
+        y = oracle.gather(cores, idx)
+        _, g = oracle.mse_loss_and_grad(y, ts)
+        oracle.gather_backward(cores, idx, g)
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return {"value": S / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d observed entries (gather + MSE + adjoint, float64, %.1f s)"
+                      % (S, p.M, dt)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print("bench.py measures one GPU only: this build has no multi-GPU path "
+                  "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    import paper_1801_01928_amd as tt
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    torch.cuda.set_device(0)
+    p = W.gather_d10()
+    X = tt.TT.from_cores(p.cores)
+    idx = torch.from_numpy(p.idx).cuda()
+    planted = tt.TT.from_cores(p.planted)
+    t = tt.gather(planted, idx) + torch.from_numpy(p.noise).cuda()
+    torch.cuda.synchronize()
+
+    ws = torch.empty(tt.gather_mse_workspace(X, p.M), dtype=torch.uint8, device="cuda")
+    gX = X.empty_like()
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+
+    def step():
+        tt.gather_mse_backward(X, idx, t, want_y=False, ws=ws, out=gX, loss=loss)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with tt.KernelTimer() as kt:
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    ms_per_step = total_ms / args.steps
+    value = p.M * args.steps / (total_ms * 1e-3)
+
+    kernel_ms = kt.ms / max(kt.launches, 1)
+    achieved = FLOP_PER_ENTRY * p.M / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_MFMA_F32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_MFMA_F32_TFLOPS, 4),
+                "traffic": traffic_bytes(),
+                "kernel": "fused_kernel<16,1024,MSE>", "kernel_ms": round(kernel_ms, 4),
+                "flop_per_entry": FLOP_PER_ENTRY}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "entries/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "fused TT gather + MSE + adjoint, d=10 n=10 r=16, "
+                                  "2^20 uniform observed entries, planted rank-8 targets",
+                      "d": 10, "n": 10, "r": 16, "M": p.M, "global_batch": p.M},
+           "roofline": roofline,
+           "loss": float(loss.item())}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, t.cpu().numpy(), args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -220,6 +220,17 @@ int tt_matmul_backward(const tt_matrix *W, const void *X, int64_t B,
 const char *tt_last_error(void);   /* thread-local message of the last failure */
 int tt_version(void);              /* TTGFX_VERSION                            */
 
+/* Kernel timer (measurement support, not part of any algorithm).  Between
+ * tt_timer_start() and tt_timer_stop(), every entry point records a pair of
+ * HIP events on its stream immediately around its dominant kernel (the
+ * fused sweep kernel of the gather family, the sweep kernel of the dense
+ * steps).  tt_timer_stop synchronizes those events and returns the summed
+ * elapsed milliseconds and the number of timed launches.  At most 4096
+ * launches are timed per start/stop pair; later ones are not recorded.
+ * The events are created once and kept by the library. */
+int tt_timer_start(void);
+int tt_timer_stop(float *total_ms, int32_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,5 +9,7 @@ from .tt import (  # noqa: F401
     gather,
     gather_backward,
     gather_mse_backward,
+    gather_mse_workspace,
     tt_gather,
+    KernelTimer,
 )

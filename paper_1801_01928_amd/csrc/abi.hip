@@ -107,6 +107,39 @@ TTDev make_dev(const tt_tensor *X) {
   return t;
 }
 
+// ------------------------------------------------------------ kernel timer
+namespace {
+constexpr int kTimerCap = 4096;
+struct Timer {
+  bool on = false;
+  int n = 0;
+  hipEvent_t ev[2 * kTimerCap];
+  bool made[2 * kTimerCap] = {};
+};
+Timer g_timer;
+
+hipEvent_t timer_event(int i) {
+  if (!g_timer.made[i]) {
+    if (hipEventCreate(&g_timer.ev[i]) != hipSuccess) return nullptr;
+    g_timer.made[i] = true;
+  }
+  return g_timer.ev[i];
+}
+}  // namespace
+
+void timer_before(hipStream_t s) {
+  if (!g_timer.on || g_timer.n >= kTimerCap) return;
+  hipEvent_t e = timer_event(2 * g_timer.n);
+  if (e) (void)hipEventRecord(e, s);
+}
+
+void timer_after(hipStream_t s) {
+  if (!g_timer.on || g_timer.n >= kTimerCap) return;
+  hipEvent_t e = timer_event(2 * g_timer.n + 1);
+  if (e) (void)hipEventRecord(e, s);
+  ++g_timer.n;
+}
+
 static int check_entries(const int32_t *idx, int64_t M, const void *vals, const char *vname) {
   if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
   if (M > 0 && !idx) return set_error(TT_ERR_ARG, "null index array with M = %lld", (long long)M);
@@ -131,6 +164,29 @@ extern "C" {
 
 const char *tt_last_error(void) { return g_last_error.c_str(); }
 int tt_version(void) { return TTGFX_VERSION; }
+
+int tt_timer_start(void) {
+  g_timer.on = true;
+  g_timer.n = 0;
+  return TT_OK;
+}
+
+int tt_timer_stop(float *total_ms, int32_t *launches) {
+  g_timer.on = false;
+  float tot = 0.f;
+  for (int i = 0; i < g_timer.n; ++i) {
+    int rc = hip_check(hipEventSynchronize(g_timer.ev[2 * i + 1]), "timer sync");
+    if (rc) return rc;
+    float ms = 0.f;
+    rc = hip_check(hipEventElapsedTime(&ms, g_timer.ev[2 * i], g_timer.ev[2 * i + 1]), "timer read");
+    if (rc) return rc;
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = g_timer.n;
+  g_timer.n = 0;
+  return TT_OK;
+}
 
 // ------------------------------------------------------------------ gather
 int64_t tt_gather_workspace(const tt_tensor *X, int64_t M) {

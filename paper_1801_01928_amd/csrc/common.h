@@ -68,6 +68,10 @@ int generic_adjoint(const TTDev &L, const TTDev &R, const TTDev &O, int max_rank
 size_t mse_ws(int64_t M);
 int mse_residual(const float *y, const float *t, int64_t M, float *g, float *loss,
                  void *ws, size_t ws_bytes, hipStream_t s);
+// Kernel timer hooks (abi.hip): no-ops unless tt_timer_start() is active.
+void timer_before(hipStream_t s);
+void timer_after(hipStream_t s);
+
 // Zero-fill by a kernel (safe inside stream capture).
 int fill_zero(float *p, long long count, hipStream_t s);
 

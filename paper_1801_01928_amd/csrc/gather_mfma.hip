@@ -642,7 +642,9 @@ int launch_fused(const FusedArgs &a, int nwg, hipStream_t s) {
     if (e != hipSuccess) return hip_check(e, "fused kernel LDS attribute");
     attr_set = true;
   }
+  timer_before(s);
   hipLaunchKernelGGL((fused_kernel<R, T, MODE>), dim3(nwg), dim3(MfTraits<R>::THREADS), L::total, s, a);
+  timer_after(s);
   return launch_check("fused MFMA kernel");
 }
 

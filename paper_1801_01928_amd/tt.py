@@ -126,20 +126,51 @@ def gather_backward(X, idx, gy):
     return gX
 
 
-def gather_mse_backward(X, idx, t, want_y=True):
+def gather_mse_workspace(X, M):
+    """Workspace bytes of ``gather_mse_backward`` for M entries."""
+    return int(L.check(L.load().tt_gather_mse_workspace(C.byref(X.desc()), int(M))))
+
+
+def gather_mse_backward(X, idx, t, want_y=True, ws=None, out=None, loss=None):
     """Fused completion-loss pass: returns (y, loss, core gradients) for
-    loss = mean((y - t)^2)."""
+    loss = mean((y - t)^2).  ``ws`` (uint8 device tensor), ``out`` (a TT of
+    X's shape) and ``loss`` (1-element float32 tensor) may be given to reuse
+    buffers across calls."""
     lib = L.load()
     idx = _idx(idx, X.d, X.device)
     M = idx.shape[1]
     t = _vec(t, M, X.device)
     y = torch.empty(M, dtype=torch.float32, device=X.device) if want_y else None
-    loss = torch.empty(1, dtype=torch.float32, device=X.device)
-    gX = X.empty_like()
-    ws, nb = _workspace(L.check(lib.tt_gather_mse_workspace(C.byref(X.desc()), M)), X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    gX = out if out is not None else X.empty_like()
+    need = gather_mse_workspace(X, M)
+    if ws is None or ws.numel() < need:
+        ws, nb = _workspace(need, X.device)
+    else:
+        nb = ws.numel()
     L.check(lib.tt_gather_mse_backward(C.byref(X.desc()), _ptr(idx), M, _ptr(t), _ptr(y), _ptr(loss),
                                        C.byref(gX.desc()), _ptr(ws), nb, _stream(X.device)))
     return y, loss, gX
+
+
+class KernelTimer:
+    """Times the library's dominant kernels with HIP events recorded on the
+    launch stream (tt_timer_start / tt_timer_stop)."""
+
+    def __enter__(self):
+        L.check(L.load().tt_timer_start())
+        self.ms = 0.0
+        self.launches = 0
+        return self
+
+    def __exit__(self, *exc):
+        ms = C.c_float(0)
+        n = C.c_int32(0)
+        L.check(L.load().tt_timer_stop(C.byref(ms), C.byref(n)))
+        self.ms = float(ms.value)
+        self.launches = int(n.value)
+        return False
 
 
 class _GatherFn(torch.autograd.Function):
