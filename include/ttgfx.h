@@ -106,11 +106,13 @@ int tt_gather_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
 
 /* ------------------------------------------------------------ A1+A2+A3 */
 /* One fused completion-loss pass: y = gather(X), loss = mean((y - t)^2),
- * gX = gather_backward(X, 2 (y - t) / M).  t: (dev) [M] targets; y: (dev)
- * [M] or NULL; loss: (dev) one float or NULL; gX overwritten as above. */
+ * g = dloss/dy = 2 (y - t) / M, gX = gather_backward(X, g).  t: (dev) [M]
+ * targets; y, g: (dev) [M] or NULL; loss: (dev) one float or NULL; gX
+ * overwritten as above.  g is the value vector of the sparse Euclidean
+ * gradient that tt_project_sparse projects. */
 int64_t tt_gather_mse_workspace(const tt_tensor *X, int64_t M);
 int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
-                           const float *t, float *y, float *loss,
+                           const float *t, float *y, float *g, float *loss,
                            tt_tensor *gX, void *ws, size_t ws_bytes,
                            void *stream);
 

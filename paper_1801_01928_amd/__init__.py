@@ -12,4 +12,8 @@ from .tt import (  # noqa: F401
     gather_mse_workspace,
     tt_gather,
     KernelTimer,
+    orthogonalize,
+    project_sparse,
+    round_tt,
+    riemannian_step,
 )

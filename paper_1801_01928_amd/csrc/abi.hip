@@ -233,7 +233,7 @@ int64_t tt_gather_mse_workspace(const tt_tensor *X, int64_t M) {
 }
 
 int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t,
-                           float *y, float *loss, tt_tensor *gX, void *ws, size_t ws_bytes,
+                           float *y, float *g, float *loss, tt_tensor *gX, void *ws, size_t ws_bytes,
                            void *stream) {
   int rc = validate_tt(X, "X", TT_MAX_RANK);
   if (rc) return rc;
@@ -241,7 +241,7 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M, co
   if (!same_shape(X, gX)) return set_error(TT_ERR_SHAPE, "gX must have the shape of X");
   if ((rc = check_entries(idx, M, t, "t"))) return rc;
   if ((rc = check_ws(ws, ws_bytes, fused_mse_ws(X, M), "gather_mse_backward"))) return rc;
-  return fused_mse_dispatch(X, idx, M, t, y, loss, gX, ws, ws_bytes, (hipStream_t)stream);
+  return fused_mse_dispatch(X, idx, M, t, y, g, loss, gX, ws, ws_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,130 @@
+// C ABI of the Riemannian step: orthogonalization, sparse tangent projection
+// and rounding.
+#include "common.h"
+#include "dense.h"
+#include "kernels.h"
+
+using namespace ttgfx;
+
+namespace {
+
+int check_dir(int dir) {
+  if (dir != TT_LR && dir != TT_RL) return set_error(TT_ERR_ARG, "dir must be TT_LR or TT_RL");
+  return TT_OK;
+}
+
+int check_ranks(const tt_tensor *O, const int32_t *want, const char *what) {
+  for (int k = 0; k <= O->d; ++k)
+    if (O->r[k] != want[k])
+      return set_error(TT_ERR_SHAPE, "%s: output rank r[%d] = %d, expected %d", what, k, O->r[k], want[k]);
+  return TT_OK;
+}
+
+int check_ws(void *ws, size_t bytes, size_t need, const char *what) {
+  if (need && (!ws || bytes < need))
+    return set_error(TT_ERR_WORKSPACE, "%s: workspace of %zu bytes given, %zu required", what,
+                     ws ? bytes : (size_t)0, need);
+  return TT_OK;
+}
+
+// Zhat shares U's mode sizes and ranks; it lives in the workspace.
+size_t zhat_bytes(const tt_tensor *U) { return arena_bytes<float>((size_t)tt_elems(U)); }
+
+}  // namespace
+
+extern "C" {
+
+int tt_orthogonalize_ranks(const tt_tensor *X, int dir, int32_t *out_r) {
+  int rc = validate_tt(X, "X", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = check_dir(dir))) return rc;
+  if (!out_r) return set_error(TT_ERR_ARG, "null out_r");
+  return dense_orth_ranks(X, dir, out_r);
+}
+
+int64_t tt_orthogonalize_workspace(const tt_tensor *X, int dir) {
+  int rc = validate_tt(X, "X", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = check_dir(dir))) return rc;
+  return (int64_t)dense_ws(X);
+}
+
+int tt_orthogonalize(const tt_tensor *X, int dir, tt_tensor *out, void *ws, size_t ws_bytes,
+                     void *stream) {
+  int rc = validate_tt(X, "X", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = check_dir(dir))) return rc;
+  if ((rc = validate_tt(out, "out", DENSE_MAX_RANK))) return rc;
+  if (!same_modes(X, out)) return set_error(TT_ERR_SHAPE, "out must have X's mode sizes");
+  int32_t want[TT_MAX_D + 1];
+  dense_orth_ranks(X, dir, want);
+  if ((rc = check_ranks(out, want, "orthogonalize"))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, dense_ws(X), "orthogonalize"))) return rc;
+  return dense_orth(X, dir, out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int64_t tt_project_sparse_workspace(const tt_tensor *U, int64_t M) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
+  return (int64_t)(zhat_bytes(U) + adjoint_dispatch_ws2(U, U, M) + tangent_ws(U));
+}
+
+int tt_project_sparse(const tt_tensor *U, const tt_tensor *V, const int32_t *idx, int64_t M,
+                      const float *z, float alpha, int add_x, tt_tensor *W, void *ws,
+                      size_t ws_bytes, void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = validate_tt(V, "V", TT_MAX_RANK))) return rc;
+  if ((rc = validate_tt(W, "W", 2 * TT_MAX_RANK))) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "project_sparse needs d >= 2");
+  if (!same_shape(U, V))
+    return set_error(TT_ERR_SHAPE, "U and V must have the same modes and ranks (X at feasible ranks)");
+  if (!same_modes(U, W)) return set_error(TT_ERR_SHAPE, "W must have U's mode sizes");
+  for (int k = 1; k < U->d; ++k)
+    if (W->r[k] != 2 * U->r[k])
+      return set_error(TT_ERR_SHAPE, "W rank r[%d] = %d, expected %d", k, W->r[k], 2 * U->r[k]);
+  if (add_x != 0 && add_x != 1) return set_error(TT_ERR_ARG, "add_x must be 0 or 1");
+  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
+  if (M > 0 && (!idx || !z)) return set_error(TT_ERR_ARG, "null idx or z with M > 0");
+  const size_t need = zhat_bytes(U) + adjoint_dispatch_ws2(U, V, M) + tangent_ws(U);
+  if ((rc = check_ws(ws, ws_bytes, need, "project_sparse"))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char *base = (char *)ws;
+  tt_tensor Z = {U->d, U->n, U->r, nullptr, (float *)base};
+  const size_t zb = zhat_bytes(U);
+  const size_t ab = adjoint_dispatch_ws2(U, V, M);
+  if ((rc = adjoint_dispatch(U, V, &Z, idx, M, z, base + zb, ab, s))) return rc;
+  return tangent_assemble(U, V, &Z, W, alpha, add_x, base + zb + ab, ws_bytes - zb - ab, s);
+}
+
+int tt_round_ranks(const tt_tensor *Y, int32_t max_rank, int32_t *out_r) {
+  int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if (max_rank < 1) return set_error(TT_ERR_ARG, "max_rank must be >= 1");
+  if (!out_r) return set_error(TT_ERR_ARG, "null out_r");
+  return dense_round_ranks(Y, max_rank, out_r);
+}
+
+int64_t tt_round_workspace(const tt_tensor *Y, int32_t max_rank) {
+  int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if (max_rank < 1) return set_error(TT_ERR_ARG, "max_rank must be >= 1");
+  return (int64_t)dense_ws(Y);
+}
+
+int tt_round(const tt_tensor *Y, int32_t max_rank, tt_tensor *out, float *disc_sq, void *ws,
+             size_t ws_bytes, void *stream) {
+  int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if (max_rank < 1) return set_error(TT_ERR_ARG, "max_rank must be >= 1");
+  if ((rc = validate_tt(out, "out", DENSE_MAX_RANK))) return rc;
+  if (!same_modes(Y, out)) return set_error(TT_ERR_SHAPE, "out must have Y's mode sizes");
+  int32_t want[TT_MAX_D + 1];
+  dense_round_ranks(Y, max_rank, want);
+  if ((rc = check_ranks(out, want, "round"))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, dense_ws(Y), "round"))) return rc;
+  return dense_round(Y, max_rank, out, disc_sq, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -26,13 +26,4 @@ int64_t tt_gram_workspace(const tt_batch *, const tt_batch *) { return set_error
 int tt_gram(const tt_batch *, const tt_batch *, float *, void *, size_t, void *) {
   return set_error(TT_ERR_UNSUPPORTED, "tt_gram: not available");
 }
-int tt_orthogonalize_ranks(const tt_tensor *, int, int32_t *) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int64_t tt_orthogonalize_workspace(const tt_tensor *, int) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int tt_orthogonalize(const tt_tensor *, int, tt_tensor *, void *, size_t, void *) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int64_t tt_project_sparse_workspace(const tt_tensor *, int64_t) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int tt_project_sparse(const tt_tensor *, const tt_tensor *, const int32_t *, int64_t, const float *, float, int,
-                      tt_tensor *, void *, size_t, void *) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int tt_round_ranks(const tt_tensor *, int32_t, int32_t *) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int64_t tt_round_workspace(const tt_tensor *, int32_t) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
-int tt_round(const tt_tensor *, int32_t, tt_tensor *, float *, void *, size_t, void *) { return set_error(TT_ERR_UNSUPPORTED, "not available"); }
 }

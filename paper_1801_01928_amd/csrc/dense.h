@@ -1,0 +1,19 @@
+// Dense sweeps of the Riemannian step (dense.hip).
+#pragma once
+#include "common.h"
+
+namespace ttgfx {
+
+#define DENSE_MAX_RANK 64
+
+int dense_orth_ranks(const tt_tensor *X, int dir, int32_t *out);
+int dense_round_ranks(const tt_tensor *Y, int max_rank, int32_t *out);
+size_t dense_ws(const tt_tensor *X);
+int dense_orth(const tt_tensor *X, int dir, tt_tensor *O, void *ws, size_t bytes, hipStream_t s);
+int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, void *ws, size_t bytes,
+                hipStream_t s);
+size_t tangent_ws(const tt_tensor *U);
+int tangent_assemble(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Z, tt_tensor *W,
+                     float alpha, int add_x, void *ws, size_t bytes, hipStream_t s);
+
+}  // namespace ttgfx

@@ -1,0 +1,582 @@
+// Dense steps of the Riemannian update: QR orthogonalization sweeps, the
+// tangent-space core assembly and TT-SVD rounding.
+//
+// The paper names rounding (t3f.round with max_tt_rank) and the tangent
+// projection P_X; the algorithms are the standard ones of the TT literature
+// it cites.  Each sweep is sequential over the cores, so one workgroup runs a
+// whole sweep; the factorizations inside it are block-parallel:
+//   * Householder QR (Golub & Van Loan, Alg. 5.1.1 / 5.2.1) with the sign
+//     chosen so that diag(R) >= 0, thin Q by backward accumulation;
+//   * SVD of the small R factor by one-sided (Hestenes) Jacobi rotations in
+//     round-robin order, one wave per column pair;
+//   * small GEMMs, one output element per thread.
+// Matrices live in a global workspace (they stay in L2); the Jacobi state
+// lives in LDS.  All arithmetic is float32.
+#include "common.h"
+#include "dense.h"
+
+namespace ttgfx {
+
+namespace {
+
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr int kJac = DENSE_MAX_RANK;  // Jacobi matrices are at most 64 x 64
+
+struct Shared {
+  float red[kWaves];
+  float bval[4];
+  int ival[4];
+  float jb[kJac * kJac];   // Jacobi working matrix B (column-major, ld = kJac)
+  float jv[kJac * kJac];   // accumulated rotations V (column-major, ld = kJac)
+  float sig[kJac];
+  int perm[kJac];
+  int rotated;
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum over the block; every thread gets the result.
+__device__ float block_sum(float v, Shared &sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh.red[wave] = v;
+  __syncthreads();
+  float s = 0.f;
+  for (int w = 0; w < kWaves; ++w) s += sh.red[w];
+  return s;
+}
+
+// C (M x N) = A (M x K) * B (K x N); element (i, j) of X at X[i*xr + j*xc].
+__device__ void blk_gemm(int M, int N, int K, const float *A, long ar, long ac, const float *B,
+                         long br, long bc, float *C, long cr, long cc) {
+  for (long e = threadIdx.x; e < (long)M * N; e += kThreads) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    float s = 0.f;
+    for (int k = 0; k < K; ++k) s = fmaf(A[i * ar + k * ac], B[k * br + j * bc], s);
+    C[i * cr + j * cc] = s;
+  }
+}
+
+// In-place Householder QR of the column-major m x c matrix W (ld = m).
+// On return the upper triangle holds R (diag >= 0) and column j below the
+// diagonal holds v_j (v_j[j] = 1 implied); tau[j] = beta_j.
+__device__ void blk_qr(float *W, int m, int c, float *tau, Shared &sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = m < c ? m : c;
+  for (int j = 0; j < p; ++j) {
+    float *col = W + (long)j * m;
+    float part = 0.f;
+    for (int i = j + 1 + threadIdx.x; i < m; i += kThreads) part = fmaf(col[i], col[i], part);
+    const float sigma = block_sum(part, sh);
+    if (threadIdx.x == 0) {
+      const float x0 = col[j];
+      float beta, v0, rjj;
+      if (sigma == 0.f) {
+        v0 = 1.f;
+        beta = (x0 >= 0.f) ? 0.f : 2.f;
+        rjj = fabsf(x0);
+      } else {
+        const float mu = sqrtf(x0 * x0 + sigma);
+        v0 = (x0 <= 0.f) ? x0 - mu : -sigma / (x0 + mu);
+        beta = 2.f * v0 * v0 / (sigma + v0 * v0);
+        rjj = mu;
+      }
+      sh.bval[0] = v0;
+      sh.bval[1] = beta;
+      sh.bval[2] = rjj;
+      tau[j] = beta;
+    }
+    __syncthreads();
+    const float v0 = sh.bval[0], beta = sh.bval[1];
+    if (sigma != 0.f) {
+      const float inv = 1.f / v0;
+      for (int i = j + 1 + threadIdx.x; i < m; i += kThreads) col[i] *= inv;
+    }
+    __syncthreads();
+    // apply H_j to the trailing columns, one wave per column
+    for (int l = j + 1 + wave; l < c; l += kWaves) {
+      float *cl = W + (long)l * m;
+      float s = 0.f;
+      for (int i = j + 1 + lane; i < m; i += 64) s = fmaf(col[i], cl[i], s);
+      s = wave_sum(s) + cl[j];
+      const float w = beta * s;
+      if (lane == 0) cl[j] -= w;
+      for (int i = j + 1 + lane; i < m; i += 64) cl[i] = fmaf(-w, col[i], cl[i]);
+    }
+    if (threadIdx.x == 0) col[j] = sh.bval[2];
+    __syncthreads();
+  }
+}
+
+// Thin Q (m x p, column-major, ld = m) from the reflectors stored in W.
+__device__ void blk_form_q(const float *W, int m, int c, const float *tau, float *Q, Shared &sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = m < c ? m : c;
+  for (long e = threadIdx.x; e < (long)m * p; e += kThreads) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    Q[e] = (i == j) ? 1.f : 0.f;
+  }
+  __syncthreads();
+  for (int j = p - 1; j >= 0; --j) {
+    const float *v = W + (long)j * m;
+    const float beta = tau[j];
+    for (int l = j + wave; l < p; l += kWaves) {
+      float *ql = Q + (long)l * m;
+      float s = 0.f;
+      for (int i = j + 1 + lane; i < m; i += 64) s = fmaf(v[i], ql[i], s);
+      s = wave_sum(s) + ql[j];
+      const float w = beta * s;
+      if (lane == 0) ql[j] -= w;
+      for (int i = j + 1 + lane; i < m; i += 64) ql[i] = fmaf(-w, v[i], ql[i]);
+    }
+    __syncthreads();
+  }
+}
+
+// One-sided Jacobi on the columns of sh.jb (rows x cols, ld = kJac); sh.jv
+// accumulates the rotations (cols x cols).  On return the columns of jb are
+// mutually orthogonal (jb = B V) and V is orthogonal.
+__device__ void blk_jacobi(int rows, int cols, Shared &sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
+    const int i = e % kJac, j = e / kJac;
+    sh.jv[e] = (i == j) ? 1.f : 0.f;
+  }
+  __syncthreads();
+  const int P = (cols + 1) & ~1;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) sh.rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < P - 1; ++round) {
+      for (int pr = wave; pr < P / 2; pr += kWaves) {
+        const int qa = pr, qb = P - 1 - pr;
+        const int a = (qa == 0) ? 0 : 1 + (qa - 1 + round) % (P - 1);
+        const int b = (qb == 0) ? 0 : 1 + (qb - 1 + round) % (P - 1);
+        if (a >= cols || b >= cols) continue;
+        float *ca = sh.jb + a * kJac, *cb = sh.jb + b * kJac;
+        const float xa = lane < rows ? ca[lane] : 0.f;
+        const float xb = lane < rows ? cb[lane] : 0.f;
+        const float alpha = wave_sum(xa * xa);
+        const float beta = wave_sum(xb * xb);
+        const float gamma = wave_sum(xa * xb);
+        if (fabsf(gamma) > 1e-6f * sqrtf(alpha * beta) && gamma != 0.f) {
+          const float zeta = (beta - alpha) / (2.f * gamma);
+          const float t = copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
+          const float cs = 1.f / sqrtf(1.f + t * t);
+          const float sn = cs * t;
+          if (lane < rows) {
+            ca[lane] = cs * xa - sn * xb;
+            cb[lane] = sn * xa + cs * xb;
+          }
+          float *va = sh.jv + a * kJac, *vb = sh.jv + b * kJac;
+          if (lane < cols) {
+            const float ya = va[lane], yb = vb[lane];
+            va[lane] = cs * ya - sn * yb;
+            vb[lane] = sn * ya + cs * yb;
+          }
+          if (lane == 0) sh.rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = sh.rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+}
+
+// Cores of the working TT in the workspace: each core has its own slot of
+// `slot` floats; shape (r[k], n[k], r[k+1]) row-major.
+struct WorkTT {
+  float *data;
+  long slot;
+  __device__ float *core(int k) const { return data + (long)k * slot; }
+};
+
+__device__ void copy_in(const TTDev &X, WorkTT &w) {
+  for (int k = 0; k < X.d; ++k) {
+    const long n = (long)X.r[k] * X.n[k] * X.r[k + 1];
+    const float *src = X.data + X.off[k];
+    float *dst = w.core(k);
+    for (long e = threadIdx.x; e < n; e += kThreads) dst[e] = src[e];
+  }
+  __syncthreads();
+}
+
+// Left-to-right QR sweep over the working TT; ranks r[] updated in place.
+// Core k becomes left-orthonormal; the last core carries the tensor.
+__device__ void sweep_lr(WorkTT &w, int d, const int *n, int *r, float *Wm, float *Q, float *tau,
+                         Shared &sh) {
+  for (int k = 0; k + 1 < d; ++k) {
+    const int m = r[k] * n[k], c = r[k + 1];
+    const int p = m < c ? m : c;
+    float *G = w.core(k);
+    // column-major copy of the left unfolding (row-major m x c)
+    for (long e = threadIdx.x; e < (long)m * c; e += kThreads) {
+      const int i = (int)(e % m), j = (int)(e / m);
+      Wm[e] = G[(long)i * c + j];
+    }
+    __syncthreads();
+    blk_qr(Wm, m, c, tau, sh);
+    blk_form_q(Wm, m, c, tau, Q, sh);
+    // core k <- Q (row-major m x p)
+    for (long e = threadIdx.x; e < (long)m * p; e += kThreads) {
+      const int i = (int)(e / p), j = (int)(e % p);
+      G[e] = Q[(long)j * m + i];
+    }
+    __syncthreads();  // Q's buffer is reused below
+    // next core <- R (p x c, upper triangle of Wm) * next (c x n r'); the
+    // product goes to Q's buffer first, then back into the core slot.
+    const int nn = n[k + 1] * r[k + 2];
+    float *Gn = w.core(k + 1);
+    for (long e = threadIdx.x; e < (long)p * nn; e += kThreads) {
+      const int i = (int)(e / nn), j = (int)(e % nn);
+      float s = 0.f;
+      for (int l = i; l < c; ++l) s = fmaf(Wm[(long)l * m + i], Gn[(long)l * nn + j], s);
+      Q[e] = s;
+    }
+    __syncthreads();
+    for (long e = threadIdx.x; e < (long)p * nn; e += kThreads) Gn[e] = Q[e];
+    if (threadIdx.x == 0) r[k + 1] = p;
+    __syncthreads();
+  }
+}
+
+// Right-to-left LQ sweep; core k becomes right-orthonormal, the first core
+// carries the tensor.
+__device__ void sweep_rl(WorkTT &w, int d, const int *n, int *r, float *Wm, float *Q, float *tau,
+                         Shared &sh) {
+  for (int k = d - 1; k >= 1; --k) {
+    const int rows = r[k], mm = n[k] * r[k + 1];  // unfolding rows x mm; QR of its transpose
+    const int p = mm < rows ? mm : rows;
+    float *G = w.core(k);
+    // transpose of the right unfolding, column-major (mm x rows): the
+    // row-major core already has that layout
+    for (long e = threadIdx.x; e < (long)mm * rows; e += kThreads) Wm[e] = G[e];
+    __syncthreads();
+    blk_qr(Wm, mm, rows, tau, sh);
+    blk_form_q(Wm, mm, rows, tau, Q, sh);
+    // core k <- Q^T (p x mm row-major) = Q column-major
+    for (long e = threadIdx.x; e < (long)p * mm; e += kThreads) G[e] = Q[e];
+    __syncthreads();  // Q's buffer is reused below
+    // previous core (r[k-1] n[k-1] x rows) <- prev * L, L = R^T (rows x p)
+    const int mp = r[k - 1] * n[k - 1];
+    float *Gp = w.core(k - 1);
+    for (long e = threadIdx.x; e < (long)mp * p; e += kThreads) {
+      const int i = (int)(e / p), j = (int)(e % p);
+      float s = 0.f;
+      // L[l][j] = R[j][l], nonzero for l >= j
+      for (int l = j; l < rows; ++l) s = fmaf(Gp[(long)i * rows + l], Wm[(long)l * mm + j], s);
+      Q[e] = s;
+    }
+    __syncthreads();
+    for (long e = threadIdx.x; e < (long)mp * p; e += kThreads) Gp[e] = Q[e];
+    if (threadIdx.x == 0) r[k] = p;
+    __syncthreads();
+  }
+}
+
+__device__ void copy_out(const WorkTT &w, int d, const int *n, const int *r, const TTDev &O) {
+  for (int k = 0; k < d; ++k) {
+    const long cnt = (long)r[k] * n[k] * r[k + 1];
+    const float *src = w.core(k);
+    float *dst = O.data + O.off[k];
+    for (long e = threadIdx.x; e < cnt; e += kThreads) dst[e] = src[e];
+  }
+}
+
+struct DenseBufs {
+  float *work;    // working TT cores
+  long slot;      // floats per core slot
+  float *wm;      // m x c matrix
+  float *q;       // m x p matrix
+  float *tau;     // reflector coefficients
+};
+
+__global__ void __launch_bounds__(kThreads) orth_kernel(TTDev X, TTDev O, int dir, DenseBufs b) {
+  __shared__ Shared sh;
+  __shared__ int n[TT_MAX_D], r[TT_MAX_D + 1];
+  for (int k = threadIdx.x; k < X.d; k += kThreads) n[k] = X.n[k];
+  for (int k = threadIdx.x; k <= X.d; k += kThreads) r[k] = X.r[k];
+  WorkTT w{b.work, b.slot};
+  copy_in(X, w);
+  if (dir == TT_LR) sweep_lr(w, X.d, n, r, b.wm, b.q, b.tau, sh);
+  else sweep_rl(w, X.d, n, r, b.wm, b.q, b.tau, sh);
+  copy_out(w, X.d, n, r, O);
+}
+
+// TT rounding: right-to-left LQ sweep, then left-to-right truncated SVDs.
+__global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int max_rank,
+                                                         float *disc, DenseBufs b) {
+  __shared__ Shared sh;
+  __shared__ int n[TT_MAX_D], r[TT_MAX_D + 1];
+  const int d = Y.d;
+  for (int k = threadIdx.x; k < d; k += kThreads) n[k] = Y.n[k];
+  for (int k = threadIdx.x; k <= d; k += kThreads) r[k] = Y.r[k];
+  WorkTT w{b.work, b.slot};
+  copy_in(Y, w);
+  sweep_rl(w, d, n, r, b.wm, b.q, b.tau, sh);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k + 1 < d; ++k) {
+    const int m = r[k] * n[k], c = r[k + 1];
+    const int p = m < c ? m : c;
+    float *G = w.core(k);
+    for (long e = threadIdx.x; e < (long)m * c; e += kThreads) {
+      const int i = (int)(e % m), j = (int)(e / m);
+      b.wm[e] = G[(long)i * c + j];
+    }
+    __syncthreads();
+    blk_qr(b.wm, m, c, b.tau, sh);
+    blk_form_q(b.wm, m, c, b.tau, b.q, sh);
+    // Jacobi on B = R^T (c x p): jb[row l][col j] = R[j][l]
+    for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
+      const int l = e % kJac, j = e / kJac;
+      sh.jb[e] = (l < c && j < p && l >= j) ? b.wm[(long)l * m + j] : 0.f;
+    }
+    __syncthreads();
+    blk_jacobi(c, p, sh);
+    // singular values (column norms of B V) and their descending order
+    for (int j = wave; j < p; j += kWaves) {
+      const float x = lane < c ? sh.jb[j * kJac + lane] : 0.f;
+      const float s2 = wave_sum(x * x);
+      if (lane == 0) sh.sig[j] = sqrtf(s2);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < p; j += kThreads) {
+      int rank = 0;
+      for (int l = 0; l < p; ++l)
+        rank += (sh.sig[l] > sh.sig[j]) || (sh.sig[l] == sh.sig[j] && l < j);
+      sh.perm[rank] = j;
+    }
+    __syncthreads();
+    const int keep = max_rank < p ? max_rank : p;
+    if (threadIdx.x == 0 && disc) {
+      float s = 0.f;
+      for (int l = keep; l < p; ++l) s += sh.sig[sh.perm[l]] * sh.sig[sh.perm[l]];
+      disc[k] = s;
+    }
+    // U = Q (m x p) * V[:, perm[j]] for j < keep -> core k (row-major m x keep)
+    for (long e = threadIdx.x; e < (long)m * keep; e += kThreads) {
+      const int i = (int)(e / keep), j = (int)(e % keep);
+      const float *vj = sh.jv + sh.perm[j] * kJac;
+      float s = 0.f;
+      for (int l = 0; l < p; ++l) s = fmaf(b.q[(long)l * m + i], vj[l], s);
+      G[e] = s;
+    }
+    __syncthreads();
+    // sign fix: the largest-magnitude component of each kept column is positive
+    for (int j = wave; j < keep; j += kWaves) {
+      float best = -1.f, val = 0.f;
+      int bi = 1 << 30;
+      for (int i = lane; i < m; i += 64) {
+        const float x = G[(long)i * keep + j];
+        if (fabsf(x) > best) {
+          best = fabsf(x);
+          val = x;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off), ov = __shfl_xor(val, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          val = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) sh.sig[j] = (val < 0.f) ? -1.f : 1.f;  // reuse as the sign of column j
+    }
+    __syncthreads();
+    for (long e = threadIdx.x; e < (long)m * keep; e += kThreads) G[e] *= sh.sig[(int)(e % keep)];
+    // next core <- (Sigma V^T)[kept] (keep x c) * next (c x n r'');
+    // (Sigma V^T) row j = sign_j * column perm[j] of B V, transposed
+    const int nn = n[k + 1] * r[k + 2];
+    float *Gn = w.core(k + 1);
+    for (long e = threadIdx.x; e < (long)keep * nn; e += kThreads) {
+      const int i = (int)(e / nn), j = (int)(e % nn);
+      const float *bj = sh.jb + sh.perm[i] * kJac;
+      float s = 0.f;
+      for (int l = 0; l < c; ++l) s = fmaf(bj[l], Gn[(long)l * nn + j], s);
+      b.q[e] = sh.sig[i] * s;
+    }
+    __syncthreads();
+    for (long e = threadIdx.x; e < (long)keep * nn; e += kThreads) Gn[e] = b.q[e];
+    if (threadIdx.x == 0) r[k + 1] = keep;
+    __syncthreads();
+  }
+  copy_out(w, d, n, r, O);
+}
+
+// Tangent cores and the rank-2r tangent TT (one workgroup per mode):
+// dG_k = Zhat_k - U_k (U_k^L^T Zhat_k^L) for k < d-1, dG_{d-1} = Zhat_{d-1};
+// W_1 = [a dG_1, U_1], W_k = [[V_k, 0], [a dG_k, U_k]],
+// W_d = [[V_d], [x S_d + a dG_d]].
+__global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTDev Z, TTDev W,
+                                                           float alpha, float addx, float *scratch,
+                                                           long scratch_stride) {
+  const int k = blockIdx.x, d = U.d;
+  const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
+  const int m = r0 * nk;
+  const float *Uk = U.data + U.off[k];
+  const float *Zk = Z.data + Z.off[k];
+  float *dG = scratch + (long)k * scratch_stride;   // m x r1 (row-major)
+  float *C = dG + (long)m * r1;                     // r1 x r1
+  if (k < d - 1) {
+    // C = U^T Z  (r1 x r1), K = m
+    blk_gemm(r1, r1, m, Uk, 1, r1, Zk, r1, 1, C, r1, 1);
+    __syncthreads();
+    // dG = Z - U C
+    for (long e = threadIdx.x; e < (long)m * r1; e += kThreads) {
+      const int i = (int)(e / r1), j = (int)(e % r1);
+      float s = 0.f;
+      for (int l = 0; l < r1; ++l) s = fmaf(Uk[(long)i * r1 + l], C[l * r1 + j], s);
+      dG[e] = Zk[e] - s;
+    }
+  } else {
+    for (long e = threadIdx.x; e < (long)m * r1; e += kThreads) dG[e] = Zk[e];
+  }
+  __syncthreads();
+  float *Wk = W.data + W.off[k];
+  const int w0 = W.r[k], w1 = W.r[k + 1];
+  const float *Vk = V.data + V.off[k];
+  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
+    const int b = (int)(e % w1), s = (int)((e / w1) % nk), a = (int)(e / ((long)w1 * nk));
+    float v = 0.f;
+    if (k == 0) {  // [alpha dG, U]
+      v = (b < r1) ? alpha * dG[(long)s * r1 + b] : Uk[(long)s * r1 + (b - r1)];
+    } else if (k == d - 1) {  // [[V], [addx S + alpha dG]]
+      if (a < r0) v = Vk[((long)a * nk + s) * r1 + b];
+      else v = addx * Uk[((long)(a - r0) * nk + s) * r1 + b] + alpha * dG[((long)(a - r0) * nk + s) * r1 + b];
+    } else {  // [[V, 0], [alpha dG, U]]
+      if (a < r0) v = (b < r1) ? Vk[((long)a * nk + s) * r1 + b] : 0.f;
+      else if (b < r1) v = alpha * dG[((long)(a - r0) * nk + s) * r1 + b];
+      else v = Uk[((long)(a - r0) * nk + s) * r1 + (b - r1)];
+    }
+    Wk[e] = v;
+  }
+}
+
+long slot_of(const int *n, const int *r, int d) {
+  long s = 1;
+  for (int k = 0; k < d; ++k) {
+    const long c = (long)r[k] * n[k] * r[k + 1];
+    s = c > s ? c : s;
+  }
+  return s;
+}
+
+long mat_of(const int *n, const int *r, int d) {
+  long s = 1;
+  for (int k = 0; k < d; ++k) {
+    const long a = (long)r[k] * n[k] * r[k + 1];
+    s = a > s ? a : s;
+  }
+  return s;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- host side
+int dense_orth_ranks(const tt_tensor *X, int dir, int32_t *out) {
+  const int d = X->d;
+  for (int k = 0; k <= d; ++k) out[k] = X->r[k];
+  if (dir == TT_LR) {
+    for (int k = 0; k + 1 < d; ++k) {
+      const long m = (long)out[k] * X->n[k];
+      out[k + 1] = (int32_t)(m < out[k + 1] ? m : out[k + 1]);
+    }
+  } else {
+    for (int k = d - 1; k >= 1; --k) {
+      const long mm = (long)X->n[k] * out[k + 1];
+      out[k] = (int32_t)(mm < out[k] ? mm : out[k]);
+    }
+  }
+  return TT_OK;
+}
+
+int dense_round_ranks(const tt_tensor *Y, int max_rank, int32_t *out) {
+  dense_orth_ranks(Y, TT_RL, out);
+  for (int k = 0; k + 1 < Y->d; ++k) {
+    long t = (long)out[k] * Y->n[k];
+    if (out[k + 1] < t) t = out[k + 1];
+    if (max_rank < t) t = max_rank;
+    out[k + 1] = (int32_t)t;
+  }
+  return TT_OK;
+}
+
+size_t dense_ws(const tt_tensor *X) {
+  const long slot = slot_of(X->n, X->r, X->d);
+  const long mat = mat_of(X->n, X->r, X->d);
+  return arena_bytes<float>((size_t)slot * X->d) + 2 * arena_bytes<float>((size_t)mat) +
+         arena_bytes<float>(DENSE_MAX_RANK + 64);
+}
+
+static int dense_bufs(const tt_tensor *X, void *ws, size_t bytes, DenseBufs &b) {
+  const long slot = slot_of(X->n, X->r, X->d);
+  const long mat = mat_of(X->n, X->r, X->d);
+  Arena ar(ws, bytes);
+  b.work = ar.take<float>((size_t)slot * X->d);
+  b.slot = slot;
+  b.wm = ar.take<float>((size_t)mat);
+  b.q = ar.take<float>((size_t)mat);
+  b.tau = ar.take<float>(DENSE_MAX_RANK + 64);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "dense sweep: workspace too small");
+  return TT_OK;
+}
+
+int dense_orth(const tt_tensor *X, int dir, tt_tensor *O, void *ws, size_t bytes, hipStream_t s) {
+  DenseBufs b;
+  int rc = dense_bufs(X, ws, bytes, b);
+  if (rc) return rc;
+  timer_before(s);
+  hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(kThreads), 0, s, make_dev(X), make_dev(O), dir, b);
+  timer_after(s);
+  return launch_check("orthogonalize");
+}
+
+int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, void *ws, size_t bytes,
+                hipStream_t s) {
+  DenseBufs b;
+  int rc = dense_bufs(Y, ws, bytes, b);
+  if (rc) return rc;
+  timer_before(s);
+  hipLaunchKernelGGL(round_kernel, dim3(1), dim3(kThreads), 0, s, make_dev(Y), make_dev(O), max_rank,
+                     disc, b);
+  timer_after(s);
+  return launch_check("round");
+}
+
+size_t tangent_ws(const tt_tensor *U) {
+  long stride = 0;
+  for (int k = 0; k < U->d; ++k) {
+    const long m = (long)U->r[k] * U->n[k];
+    const long need = m * U->r[k + 1] + (long)U->r[k + 1] * U->r[k + 1];
+    stride = need > stride ? need : stride;
+  }
+  return arena_bytes<float>((size_t)stride * U->d);
+}
+
+int tangent_assemble(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Z, tt_tensor *W,
+                     float alpha, int add_x, void *ws, size_t bytes, hipStream_t s) {
+  long stride = 0;
+  for (int k = 0; k < U->d; ++k) {
+    const long m = (long)U->r[k] * U->n[k];
+    const long need = m * U->r[k + 1] + (long)U->r[k + 1] * U->r[k + 1];
+    stride = need > stride ? need : stride;
+  }
+  Arena ar(ws, bytes);
+  float *scratch = ar.take<float>((size_t)stride * U->d);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "tangent assembly: workspace too small");
+  hipLaunchKernelGGL(tangent_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(V),
+                     make_dev(Z), make_dev(W), alpha, add_x ? 1.f : 0.f, scratch, stride);
+  return launch_check("tangent assembly");
+}
+
+}  // namespace ttgfx

@@ -24,7 +24,7 @@ size_t gather_dispatch_ws(const tt_tensor *X, int64_t M) {
 int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, void *ws,
                     size_t ws_bytes, hipStream_t s) {
   if (use_mfma(X, X))
-    return mfma_run(0, X, X, nullptr, idx, M, nullptr, nullptr, y, nullptr, ws, ws_bytes, s);
+    return mfma_run(0, X, X, nullptr, idx, M, nullptr, nullptr, y, nullptr, nullptr, ws, ws_bytes, s);
   return generic_gather(make_dev(X), max_rank_of(X), idx, M, y, s);
 }
 
@@ -41,7 +41,7 @@ size_t adjoint_dispatch_ws2(const tt_tensor *L, const tt_tensor *R, int64_t M) {
 int adjoint_dispatch(const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
                      int64_t M, const float *w, void *ws, size_t ws_bytes, hipStream_t s) {
   if (use_mfma(L, R))
-    return mfma_run(1, L, R, O, idx, M, nullptr, w, nullptr, nullptr, ws, ws_bytes, s);
+    return mfma_run(1, L, R, O, idx, M, nullptr, w, nullptr, nullptr, nullptr, ws, ws_bytes, s);
   int mr = max_rank_of(L);
   if (max_rank_of(R) > mr) mr = max_rank_of(R);
   return generic_adjoint(make_dev(L), make_dev(R), make_dev(O), mr, idx, M, w, ws, ws_bytes, s);
@@ -54,13 +54,14 @@ size_t fused_mse_ws(const tt_tensor *X, int64_t M) {
 }
 
 int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t, float *y,
-                       float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s) {
+                       float *g, float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s) {
   if (use_mfma(X, X))
-    return mfma_run(2, X, X, gX, idx, M, t, nullptr, y, loss, ws, ws_bytes, s);
+    return mfma_run(2, X, X, gX, idx, M, t, nullptr, y, g, loss, ws, ws_bytes, s);
   const size_t m = (size_t)(M > 0 ? M : 1);
   Arena ar(ws, ws_bytes);
   float *ytmp = ar.take<float>(m);
-  float *g = ar.take<float>(m);
+  float *gtmp = ar.take<float>(m);
+  if (!g) g = gtmp;
   void *mws = ar.base + align_up(ar.used, 256);
   ar.used = align_up(ar.used, 256) + mse_ws(M);
   void *aws = ar.base + align_up(ar.used, 256);

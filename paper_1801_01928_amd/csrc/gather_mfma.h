@@ -31,7 +31,7 @@ int mfma_rank_class(const tt_tensor *L, const tt_tensor *R);
 size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint);
 // mode: 0 gather (y), 1 adjoint with weights gy, 2 fused MSE (t -> y, loss, O)
 int mfma_run(int mode, const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
-             int64_t M, const float *t, const float *gy, float *y, float *loss, void *ws,
+             int64_t M, const float *t, const float *gy, float *y, float *gout, float *loss, void *ws,
              size_t ws_bytes, hipStream_t s);
 
 }  // namespace ttgfx

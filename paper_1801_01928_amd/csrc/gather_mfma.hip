@@ -56,6 +56,7 @@ struct FusedArgs {
   const float *t;              // targets (fused MSE) or null
   const float *gy;             // given weights (adjoint) or null
   float *y;                    // gather output or null
+  float *gout;                 // dloss/dy output (fused MSE) or null
   float *stash;                // per workgroup: [d-1][nb_max][64 lanes][R/4]
   float *acc;                  // per workgroup: [total slices][R*R]
   float *loss_acc;             // per workgroup: one float
@@ -305,6 +306,7 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p
         const float rho = yv - p.t[e0 + e];
         w = p.inv_m2 * rho;
         loss_part += rho * rho;
+        if (p.gout) p.gout[e0 + e] = w;
       } else if (MODE == MODE_ADJOINT) {
         w = p.gy[e0 + e];
       }
@@ -691,7 +693,7 @@ size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint) {
 }
 
 int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, const int32_t *idx,
-             int64_t M, const float *t, const float *gy, float *y, float *loss, void *ws,
+             int64_t M, const float *t, const float *gy, float *y, float *gout, float *loss, void *ws,
              size_t ws_bytes, hipStream_t s) {
   const int R = mfma_rank_class(Lt, Rt);
   const bool adjoint = mode != MODE_GATHER;
@@ -729,6 +731,7 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
   a.t = t;
   a.gy = gy;
   a.y = y;
+  a.gout = gout;
   a.stash = stash;
   a.acc = acc;
   a.loss_acc = lacc;

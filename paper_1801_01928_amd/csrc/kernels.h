@@ -17,6 +17,6 @@ int adjoint_dispatch(const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const
 
 size_t fused_mse_ws(const tt_tensor *X, int64_t M);
 int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t, float *y,
-                       float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s);
+                       float *g, float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace ttgfx

@@ -131,16 +131,18 @@ def gather_mse_workspace(X, M):
     return int(L.check(L.load().tt_gather_mse_workspace(C.byref(X.desc()), int(M))))
 
 
-def gather_mse_backward(X, idx, t, want_y=True, ws=None, out=None, loss=None):
+def gather_mse_backward(X, idx, t, want_y=True, ws=None, out=None, loss=None, want_g=False):
     """Fused completion-loss pass: returns (y, loss, core gradients) for
-    loss = mean((y - t)^2).  ``ws`` (uint8 device tensor), ``out`` (a TT of
-    X's shape) and ``loss`` (1-element float32 tensor) may be given to reuse
-    buffers across calls."""
+    loss = mean((y - t)^2), or (y, g, loss, core gradients) with
+    g = dloss/dy when want_g.  ``ws`` (uint8 device tensor), ``out`` (a TT
+    of X's shape) and ``loss`` (1-element float32 tensor) may be given to
+    reuse buffers across calls."""
     lib = L.load()
     idx = _idx(idx, X.d, X.device)
     M = idx.shape[1]
     t = _vec(t, M, X.device)
     y = torch.empty(M, dtype=torch.float32, device=X.device) if want_y else None
+    g = torch.empty(M, dtype=torch.float32, device=X.device) if want_g else None
     if loss is None:
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
     gX = out if out is not None else X.empty_like()
@@ -149,8 +151,10 @@ def gather_mse_backward(X, idx, t, want_y=True, ws=None, out=None, loss=None):
         ws, nb = _workspace(need, X.device)
     else:
         nb = ws.numel()
-    L.check(lib.tt_gather_mse_backward(C.byref(X.desc()), _ptr(idx), M, _ptr(t), _ptr(y), _ptr(loss),
-                                       C.byref(gX.desc()), _ptr(ws), nb, _stream(X.device)))
+    L.check(lib.tt_gather_mse_backward(C.byref(X.desc()), _ptr(idx), M, _ptr(t), _ptr(y), _ptr(g),
+                                       _ptr(loss), C.byref(gX.desc()), _ptr(ws), nb, _stream(X.device)))
+    if want_g:
+        return y, g, loss, gX
     return y, loss, gX
 
 
@@ -194,3 +198,67 @@ def tt_gather(X, idx):
     hand-written adjoint kernel."""
     idx = _idx(idx, X.d, X.device)
     return _GatherFn.apply(X.data, idx, tuple(X.ns), tuple(X.ranks))
+
+
+def _ranks_call(fn, X, *args):
+    out = (C.c_int32 * (X.d + 1))()
+    L.check(fn(C.byref(X.desc()), *args, out))
+    return list(out)
+
+
+def orthogonalize(X, direction):
+    """QR sweep (direction L.TT_LR or L.TT_RL); returns a new TT with the
+    reduced ranks.  LR: cores 1..d-1 left-orthonormal; RL: cores 2..d
+    right-orthonormal."""
+    lib = L.load()
+    ranks = _ranks_call(lib.tt_orthogonalize_ranks, X, int(direction))
+    out = TT(X.ns, ranks, device=X.device)
+    ws, nb = _workspace(L.check(lib.tt_orthogonalize_workspace(C.byref(X.desc()), int(direction))), X.device)
+    L.check(lib.tt_orthogonalize(C.byref(X.desc()), int(direction), C.byref(out.desc()), _ptr(ws), nb,
+                                 _stream(X.device)))
+    return out
+
+
+def project_sparse(U, V, idx, z, alpha=1.0, add_x=0):
+    """Tangent projection of the sparse tensor sum_m z[m] e_{i^m} at X, with
+    U = orthogonalize(X, LR) and V = orthogonalize(X, RL); returns the rank-2r
+    TT  add_x * X + alpha * P_X(Z)."""
+    lib = L.load()
+    idx = _idx(idx, U.d, U.device)
+    M = idx.shape[1]
+    z = _vec(z, M, U.device)
+    W = TT(U.ns, [1] + [2 * r for r in U.ranks[1:-1]] + [1], device=U.device)
+    ws, nb = _workspace(L.check(lib.tt_project_sparse_workspace(C.byref(U.desc()), M)), U.device)
+    L.check(lib.tt_project_sparse(C.byref(U.desc()), C.byref(V.desc()), _ptr(idx), M, _ptr(z),
+                                  C.c_float(alpha), int(add_x), C.byref(W.desc()), _ptr(ws), nb,
+                                  _stream(U.device)))
+    return W
+
+
+def round_tt(Y, max_rank):
+    """TT rounding to ranks <= max_rank (t3f.round); returns (TT, disc_sq)
+    with disc_sq[k] the discarded squared singular values at bond k+1."""
+    lib = L.load()
+    ranks = _ranks_call(lib.tt_round_ranks, Y, int(max_rank))
+    out = TT(Y.ns, ranks, device=Y.device)
+    disc = torch.zeros(max(Y.d - 1, 1), dtype=torch.float32, device=Y.device)
+    ws, nb = _workspace(L.check(lib.tt_round_workspace(C.byref(Y.desc()), int(max_rank))), Y.device)
+    L.check(lib.tt_round(C.byref(Y.desc()), int(max_rank), C.byref(out.desc()), _ptr(disc), _ptr(ws), nb,
+                         _stream(Y.device)))
+    return out, disc[:max(Y.d - 1, 0)]
+
+
+def riemannian_step(X, idx, t, alpha=-0.1, max_rank=None):
+    """One Riemannian completion step: loss and Euclidean core gradients of
+    mean((y - t)^2), then Y = round(X + alpha * P_X(grad), max_rank).
+    Returns dict(loss, grads, W, Y, disc_sq)."""
+    if max_rank is None:
+        max_rank = max(X.ranks)
+    idx = _idx(idx, X.d, X.device)
+    M = idx.shape[1]
+    y, g, loss, grads = gather_mse_backward(X, idx, t, want_g=True)
+    U = orthogonalize(X, L.TT_LR)
+    V = orthogonalize(X, L.TT_RL)
+    W = project_sparse(U, V, idx, g, alpha=alpha, add_x=1)
+    Y, disc = round_tt(W, max_rank)
+    return dict(y=y, loss=loss, grads=grads, U=U, V=V, W=W, Y=Y, disc_sq=disc)
