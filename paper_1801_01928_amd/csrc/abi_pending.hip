@@ -22,8 +22,4 @@ int tt_matmul_backward(const tt_matrix *, const void *, int64_t, const void *, f
                        void *, size_t, void *) {
   return set_error(TT_ERR_UNSUPPORTED, "tt_matmul_backward: not available");
 }
-int64_t tt_gram_workspace(const tt_batch *, const tt_batch *) { return set_error(TT_ERR_UNSUPPORTED, "tt_gram: not available"); }
-int tt_gram(const tt_batch *, const tt_batch *, float *, void *, size_t, void *) {
-  return set_error(TT_ERR_UNSUPPORTED, "tt_gram: not available");
-}
 }
