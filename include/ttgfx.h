@@ -171,25 +171,36 @@ int tt_gram(const tt_batch *A, const tt_batch *B, float *G,
 
 /* ------------------------------------------------------------------ A9 */
 /* Batched persistent gather + MSE + adjoint over many TT tensors of uneven
- * ranks and entry counts (Batch Processing).  The plan owns its device
- * buffers.  Instance j reads idx_j = idx + idx_off[j]*d ... see
- * tt_plan_create for the layout; tt_plan_run launches ONE kernel (plus a
- * fixed-order reduction) and is capturable into a hipGraph; tt_plan_capture
- * captures it once and later tt_plan_run calls replay the graph. */
+ * ranks (<= 32) and entry counts (Batch Processing).  X: the batch (same
+ * mode sizes; 2 <= d <= 16); idx: (dev) int32, tensor j's entries are the
+ * structure-of-arrays block [d][M_j] starting at element d*entry_off[j];
+ * t: (dev) targets, tensor j's at t + entry_off[j]; entry_off: (host) [b+1]
+ * prefix sums of M_j (entry_off[0] = 0); grads: output batch with X's shapes
+ * (cores overwritten); loss: (dev) [b] per-tensor mean squared residual.
+ * The pointers and shapes are bound into the plan; core VALUES may change
+ * between runs.  The plan owns its device buffers (allocated here, freed by
+ * tt_plan_destroy).  Gradients of one tensor are summed with float atomics
+ * (run-to-run differences ~1e-7 relative).
+ * tt_plan_run: padded-slice copies, zero fills (kernels), ONE persistent
+ *   kernel over all tensors (work items = chunks of tiles, longest first,
+ *   from an atomic queue), and the unpadding into grads.
+ * tt_plan_capture: records that sequence into a hipGraph on `stream` (not
+ *   the NULL stream); later tt_plan_run calls on the same stream replay it.
+ *   Do not run tt_timer_start() across a capture.
+ * tt_plan_run_plain: the same results by b plain tt_gather_mse_backward
+ *   launch sequences (the reference that the batched form is compared with).
+ * tt_plan_autotune: times the tile-chunk size of the work list (1..16) and
+ *   keeps the fastest; *chosen receives it.  With the environment variable
+ *   TTGFX_TUNE_CACHE naming a file, choices are read from / appended to it
+ *   (keyed by the batch's shape signature).  Drops a captured graph. */
 typedef struct tt_plan tt_plan;
-/* X: the batch; idx: (dev) int32, instance j's entries are the SoA block
- * [d][M_j] starting at element d*entry_off[j]; t: (dev) targets at
- * entry_off[j]; entry_off: (host) [b+1] prefix sums of M_j; grads: the
- * output batch (same shapes as X); loss: (dev) [b] per-instance MSE or
- * NULL.  The pointers are bound into the plan. */
 int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t,
                    const int64_t *entry_off, const tt_batch *grads, float *loss,
                    tt_plan **plan);
 int tt_plan_run(tt_plan *plan, void *stream);
 int tt_plan_capture(tt_plan *plan, void *stream);
-/* Reference form: the same work as b plain per-instance calls of
- * tt_gather_mse_backward (used to compare batched against plain launches). */
 int tt_plan_run_plain(tt_plan *plan, void *stream);
+int tt_plan_autotune(tt_plan *plan, void *stream, int32_t *chosen);
 void tt_plan_destroy(tt_plan *plan);
 
 /* ----------------------------------------------------------------- A10 */

@@ -16,4 +16,6 @@ from .tt import (  # noqa: F401
     project_sparse,
     round_tt,
     riemannian_step,
+    gram,
+    BatchedPlan,
 )

@@ -80,6 +80,7 @@ SIGNATURES = {
     "tt_plan_run": (C.c_int, [VP, VP]),
     "tt_plan_capture": (C.c_int, [VP, VP]),
     "tt_plan_run_plain": (C.c_int, [VP, VP]),
+    "tt_plan_autotune": (C.c_int, [VP, VP, PI32]),
     "tt_plan_destroy": (None, [VP]),
     "tt_matmul_workspace": (I64, [P_TTM, I64, C.c_int]),
     "tt_matmul": (C.c_int, [P_TTM, VP, I64, VP, C.c_int, VP, SZ, VP]),

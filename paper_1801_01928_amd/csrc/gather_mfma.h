@@ -20,15 +20,64 @@ template <>
 struct MfTraits<32> {
   static constexpr int T = 512;
   static constexpr int THREADS = 256;
-  static constexpr int MAX_N = 10;
-  static constexpr int PERM_CAP = 7168;
+  static constexpr int MAX_N = 32;
+  static constexpr int PERM_CAP = 16384;
 };
+
+// One tensor of the slice-grouped kernels (kernel argument or batch table).
+struct MfInst {
+  int d;
+  int n[MF_MAX_D];
+  int sbase[MF_MAX_D];     // first padded slice of mode k
+  long long M;
+  const int32_t *idx;      // [d][M]
+  const float *gp_right;   // padded slices (right sweep), MFMA operand order
+  const float *gp_left;    // padded transposed slices (left sweep)
+  const float *t;          // targets (fused MSE)
+  const float *gy;         // given weights (adjoint)
+  float *y;                // gather output or null
+  float *gout;             // dloss/dy output or null
+  float *grad;             // DIRECT accumulation target [slices][R][R] (zeroed)
+  float *loss;             // batched: per-tensor loss (atomic target) or null
+  float inv_m2;            // 2 / M
+  float inv_m;             // 1 / M
+  int rclass;              // 16 or 32
+};
+
+#define MF_BATCH_THREADS 512
+
+// Work item of the batched kernel: `ntile` consecutive tiles of one tensor.
+struct MfWorkItem {
+  int inst;
+  int tile0;
+  int ntile;
+  int rclass;
+};
+
+struct MfBatchArgs {
+  const MfInst *table;
+  const MfWorkItem *items;
+  int nitems;
+  int *counter;            // reset to 0 before every launch
+  float *stash;            // per workgroup, stash_stride floats
+  long long stash_stride;
+  int nb16, nb32;          // blocks-per-mode capacities of the two classes
+};
+
+size_t mfma_batch_lds();
+int mfma_batch_prepare();
+int mfma_batch_launch(const MfBatchArgs &a, int nwg, hipStream_t s);
+int mfma_device_cus();
 
 // True when every descriptor fits the MFMA kernels (2 <= d <= 16, ranks <= 32,
 // mode sizes within the rank class's limit).
 bool mfma_supported(const tt_tensor *L, const tt_tensor *R);
 int mfma_rank_class(const tt_tensor *L, const tt_tensor *R);
+bool mfma_class_fits(const tt_tensor *X, int R);
 size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint);
+// padded slice copies (right: G, left: G^T of Lt or Rt) and the unpad copy
+int mfma_pad(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float *gpl, hipStream_t s);
+int mfma_unpad(const tt_tensor *O, int R, const float *padded, hipStream_t s);
 // mode: 0 gather (y), 1 adjoint with weights gy, 2 fused MSE (t -> y, loss, O)
 int mfma_run(int mode, const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
              int64_t M, const float *t, const float *gy, float *y, float *gout, float *loss, void *ws,

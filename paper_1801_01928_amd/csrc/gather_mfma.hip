@@ -1,5 +1,5 @@
 // Slice-grouped MFMA kernels for the gather, its adjoint and the fused MSE
-// pass (bond ranks <= 32, mode sizes <= 32).
+// pass (bond ranks <= 32).
 //
 // The entry formula of the TT format (Introduction) multiplies, for every
 // observed entry, one core slice per mode.  A tile of T entries is sorted
@@ -22,14 +22,26 @@
 // for comp-tile t < R/16 and v < 4.  An MFMA with a slice as A operand maps
 // EL to EL (the contraction index 4q + v of chunk v is consistent between
 // operands); the adjoint's outer product takes both partials in CL.
+//
+// Outer products are summed in registers over each run of consecutive
+// blocks with the same slice.  Two ways to combine runs:
+//   SLAB   (rank class 16): the wave holding a slice's first block stores its
+//          run into an LDS slab, continuation runs go to per-wave edge
+//          buffers, and a fixed-order flush adds them (no LDS atomics);
+//   DIRECT (rank class 32, batched kernel): runs are added to a zeroed
+//          global gradient with no-return float atomics (no LDS slab, so
+//          larger mode sizes fit).
+// The per-tile work is one device function shared by the single-tensor
+// kernel (tiles in grid-stride order) and the batched persistent kernel
+// (work items from an atomic queue).
 #include "common.h"
 #include "gather_mfma.h"
 
 namespace ttgfx {
 
-namespace {
-
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
 
 __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -39,65 +51,60 @@ constexpr uint16_t kNone = 0xFFFF;
 
 // Workgroup barrier that waits for this wave's LDS operations only.  Inside
 // the sweeps no wave reads global memory written by another wave (each lane
-// reads back only its own stash and accumulator entries), so outstanding
-// global stores need not drain at every mode boundary.
+// reads back only its own stash entries), so outstanding global stores need
+// not drain at every mode boundary.
 __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-struct FusedArgs {
-  int d;
-  int n[MF_MAX_D];
-  int sbase[MF_MAX_D];         // slice index base of mode k in the padded slice arrays
-  const int32_t *idx;          // [d][M]
-  long long M;
-  const float *gp_right;       // padded slices, row-major (R x R), right-sweep cores
-  const float *gp_left;        // padded slices, transposed, left-sweep cores
-  const float *t;              // targets (fused MSE) or null
-  const float *gy;             // given weights (adjoint) or null
-  float *y;                    // gather output or null
-  float *gout;                 // dloss/dy output (fused MSE) or null
-  float *stash;                // per workgroup: [d-1][nb_max][64 lanes][R/4]
-  float *acc;                  // per workgroup: [total slices][R*R]
-  float *loss_acc;             // per workgroup: one float
-  long long stash_stride;      // floats per workgroup
-  long long acc_stride;        // floats per workgroup
-  int nb_max;                  // blocks per mode capacity
-  int ntiles;
-  int total_slices;
-  float inv_m2;                // 2 / M
-};
-
 enum { MODE_GATHER = 0, MODE_ADJOINT = 1, MODE_MSE = 2 };
+enum { ACC_SLAB = 0, ACC_DIRECT = 1 };
+
+template <int T>
+__device__ __forceinline__ int pbase_of(const MfInst &p, int k) {
+  int s = 0;
+  for (int j = 0; j < k; ++j) s += T + 16 * p.n[j];  // multiple of 16: aligned block reads
+  return s;
+}
+
+template <int T>
+__device__ __forceinline__ int bbase_of(const MfInst &p, int k) {
+  int s = 0;
+  for (int j = 0; j < k; ++j) s += (T + 16 * p.n[j]) / 16 + 1;
+  return s;
+}
 
 // LDS layout (bytes), in this order:
 //   rows   float [T + 2][R + 4]  (row T: zeros, row T+1: write sink)
-//   slab   float [MAX_N][R][R + 4]    (adjoint modes: per-slice sums)
-//   edges  float [waves][R][R + 4]    (runs continuing the previous wave's slice)
-//   sflag  int   [MAX_N + 16]         (slice has a stored run; edge slice ids)
+//   slab   float [MAX_N][R][R + 4]    (SLAB: per-slice sums)
+//   edges  float [waves][R][R + 4]    (SLAB: runs continuing the previous wave's slice)
+//   sflag  int   [MAX_N + 16]         (SLAB: slice has a stored run; edge slice ids)
 //   wsum   float [T + 2]              (per-entry weight g_e; [T] = 0)
 //   perm   uint16 [PERM_CAP]
 //   bslc   uint8  [PERM_CAP / 16 + d]
-//   meta   int    pbase[d], bbase[d], nblk[d]
-template <int R, int T>
+//   nblk   int   [MF_MAX_D]
+template <int R, int T, int NTHR, int ACC>
 struct Lds {
-  static constexpr int NMAX = MfTraits<R>::MAX_N;
+  static constexpr int NMAX = (ACC == ACC_SLAB) ? MfTraits<R>::MAX_N : 0;
   static constexpr int PCAP = MfTraits<R>::PERM_CAP;
   static constexpr size_t rows = 0;
   static constexpr size_t slab = rows + (sizeof(float) * (T + 2) * (R + 4) + 15) / 16 * 16;
   static constexpr size_t edges = slab + sizeof(float) * NMAX * R * (R + 4);
-  static constexpr size_t sflag = edges + sizeof(float) * (MfTraits<R>::THREADS / 64) * R * (R + 4);
-  static constexpr size_t wsum = sflag + sizeof(int) * (NMAX + 16);
+  static constexpr size_t sflag = edges + (ACC == ACC_SLAB ? sizeof(float) * (NTHR / 64) * R * (R + 4) : 0);
+  static constexpr size_t wsum = sflag + (ACC == ACC_SLAB ? sizeof(int) * (NMAX + 16) : 0);
   static constexpr size_t perm = wsum + (sizeof(float) * (T + 2) + 15) / 16 * 16;
   static constexpr size_t bslc = perm + sizeof(uint16_t) * PCAP;
-  static constexpr size_t meta = bslc + (PCAP / 16 + MF_MAX_D + 16) / 16 * 16;
-  static constexpr size_t total = meta + sizeof(int) * 3 * MF_MAX_D + 64;
+  static constexpr size_t nblk = bslc + (PCAP / 16 + MF_MAX_D + 16) / 16 * 16;
+  static constexpr size_t total = nblk + sizeof(int) * MF_MAX_D + 64;
   static_assert(total <= 160 * 1024, "LDS budget");
 };
 
-template <int R, int T, int MODE>
-__global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p) {
-  constexpr int NTHR = MfTraits<R>::THREADS;
+// One tile of T entries starting at entry e0 (cnt of them valid): sort,
+// right sweep, residual, left sweep.  `accg` is the workgroup accumulator
+// (SLAB), `loss_part` collects this thread's squared residuals (MSE).
+template <int R, int T, int NTHR, int MODE, int ACC>
+__device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, float *stash, int nb_max,
+                         float *accg, bool first_tile, float &loss_part) {
   constexpr int NT = R / 16;      // comp tiles
   constexpr int W = NTHR / 64;    // waves
   constexpr int RS = R + 4;       // LDS row stride (padding spreads banks)
@@ -105,8 +112,7 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p
   constexpr int G = (R == 16) ? 4 : 2;  // blocks per group
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
-  using L = Lds<R, T>;
-  extern __shared__ __align__(16) char smem[];
+  using L = Lds<R, T, NTHR, ACC>;
   float *rows = (float *)(smem + L::rows);
   float *slab = (float *)(smem + L::slab);
   float *edges = (float *)(smem + L::edges);
@@ -115,10 +121,7 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p
   float *wsum = (float *)(smem + L::wsum);
   uint16_t *perm = (uint16_t *)(smem + L::perm);
   uint8_t *bslc = (uint8_t *)(smem + L::bslc);
-  int *pbase = (int *)(smem + L::meta);
-  int *bbase = pbase + MF_MAX_D;
-  int *nblk = bbase + MF_MAX_D;
-
+  int *nblk = (int *)(smem + L::nblk);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -126,149 +129,310 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p
   const int q4 = lane >> 4;
   const int d = p.d;
   const long long M = p.M;
-  float *stash = p.stash + (long long)blockIdx.x * p.stash_stride;
-  float *accg = p.acc + (long long)blockIdx.x * p.acc_stride;
-  float loss_part = 0.f;
-  bool first_tile = true;
+  (void)slab;
+  (void)edges;
+  (void)sflag;
+  (void)eslice;
+  (void)accg;
+  (void)first_tile;
 
-  // per-mode layout of the permutation arrays (padded groups of 16)
-  if (tid == 0) {
-    int pb = 0, bb = 0;
-    for (int k = 0; k < d; ++k) {
-      pbase[k] = pb;
-      bbase[k] = bb;
-      const int cap = T + 16 * p.n[k];  // multiple of 16: 8-byte aligned block reads
-      pb += cap;
-      bb += cap / 16 + 1;
-    }
-  }
   for (int c = tid; c < RS; c += NTHR) rows[ZROW * RS + c] = 0.f;
   if (tid == 0) wsum[ZROW] = 0.f;
-  __syncthreads();
 
-  for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
-    const long long e0 = (long long)tile * T;
-    const int cnt = (int)((M - e0) < T ? (M - e0) : T);
-
-    // ---------------------------------------------------------------- sort
-    // Wave w sorts modes w, w + W, ...: a stable counting sort of the tile's
-    // entries by slice index (ballot ranks, shuffle scans), groups padded to
-    // multiples of 16 entries.
-    for (int k = wave; k < d; k += W) {
-      constexpr int CH = T / 64;  // entries per lane
-      const int nk = p.n[k];
-      // per chunk: slice index + 1 in the low 8 bits (0 = no entry), rank above
-      int st[CH];
+  // ---------------------------------------------------------------- sort
+  // Wave w sorts modes w, w + W, ...: a stable counting sort of the tile's
+  // entries by slice index (ballot ranks, shuffle scans), groups padded to
+  // multiples of 16 entries.
+  for (int k = wave; k < d; k += W) {
+    constexpr int CH = T / 64;  // entries per lane
+    const int nk = p.n[k];
+    // per chunk: slice index + 1 in the low 8 bits (0 = no entry), rank above
+    int st[CH];
 #pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int e = 64 * c + lane;
-        const int v = (e < cnt) ? p.idx[(long long)k * M + e0 + e] : -1;
-        st[c] = (v >= 0 && v < nk) ? v + 1 : 0;  // out-of-range indices are dropped
+    for (int c = 0; c < CH; ++c) {
+      const int e = 64 * c + lane;
+      const int v = (e < cnt) ? p.idx[(long long)k * M + e0 + e] : -1;
+      st[c] = (v >= 0 && v < nk) ? v + 1 : 0;  // out-of-range indices are dropped
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int run = 0;  // lane v: entries of slice v in the chunks seen so far
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int sc = st[c] - 1;
+      unsigned long long mine = 0ull;
+      int add = 0;
+      for (int v = 0; v < nk; ++v) {
+        const unsigned long long m = __ballot(sc == v);
+        if (sc == v) mine = m;
+        if (lane == v) add = __popcll(m);
       }
-      const unsigned long long below = (1ull << lane) - 1ull;
-      int run = 0;  // lane v: entries of slice v in the chunks seen so far
+      const int rk = __shfl(run, sc >= 0 ? sc : 0) + __popcll(mine & below);
+      st[c] |= rk << 8;
+      run += add;
+    }
+    const int padded = (lane < nk) ? ((run + 15) & ~15) : 0;
+    int incl = padded;
 #pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int sc = st[c] - 1;
-        unsigned long long mine = 0ull;
-        int add = 0;
-        for (int v = 0; v < nk; ++v) {
-          const unsigned long long m = __ballot(sc == v);
-          if (sc == v) mine = m;
-          if (lane == v) add = __popcll(m);
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    const int base = incl - padded;
+    uint16_t *pk = perm + pbase_of<T>(p, k);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int sc = (st[c] & 255) - 1;
+      const int b = __shfl(base, sc >= 0 ? sc : 0);
+      if (sc >= 0) pk[b + (st[c] >> 8)] = (uint16_t)(64 * c + lane);
+    }
+    if (lane < nk) {
+      for (int j = run; j < padded; ++j) pk[base + j] = kNone;
+      uint8_t *bk = bslc + bbase_of<T>(p, k) + base / 16;
+      for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
+    }
+    if (lane == 63) nblk[k] = incl / 16;
+  }
+  lds_barrier();
+
+  // --------------------------------------------------------- right sweep
+  // Each wave walks its blocks of mode k in groups of G: the LDS reads of a
+  // group are issued together and its MFMA chains are independent, so the
+  // matrix pipe is fed back to back.  Padding columns read the zero row.
+  for (int k = d - 1; k >= 0; --k) {
+    const int nb = nblk[k];
+    const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
+    const uint16_t *pk = perm + pbase_of<T>(p, k);
+    const uint8_t *bk = bslc + bbase_of<T>(p, k);
+    const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
+    for (int j0 = jb; j0 < je; j0 += G) {
+      int ent[G], ev[G][4];
+      bool act[G];
+      v4f a[G][NT * NT];
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        const int j = j0 + b;
+        act[b] = j < je;
+        ent[b] = ZROW;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
+        if (act[b]) {
+          const int e = pk[16 * j + c16];
+          ent[b] = (e == kNone) ? ZROW : e;
+          const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+          const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
+          const float *gs = gk + (long long)bk[j] * R * R;
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+        } else {
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-        const int rk = __shfl(run, sc >= 0 ? sc : 0) + __popcll(mine & below);
-        st[c] |= rk << 8;
-        run += add;
       }
-      const int padded = (lane < nk) ? ((run + 15) & ~15) : 0;
-      int incl = padded;
+      v4f bv[G][NT];
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off);
-        if (lane >= off) incl += t;
-      }
-      const int base = incl - padded;
-      uint16_t *pk = perm + pbase[k];
+      for (int b = 0; b < G; ++b) {
 #pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int sc = (st[c] & 255) - 1;
-        const int b = __shfl(base, sc >= 0 ? sc : 0);
-        if (sc >= 0) pk[b + (st[c] >> 8)] = (uint16_t)(64 * c + lane);
+        for (int t = 0; t < NT; ++t) {
+          if (k == d - 1)
+            bv[b][t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
+          else
+            bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
+        }
       }
-      if (lane < nk) {
-        for (int j = run; j < padded; ++j) pk[base + j] = kNone;
-        uint8_t *bk = bslc + bbase[k] + base / 16;
-        for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
+      if (MODE != MODE_GATHER && k <= d - 2) {
+        // stash rho_{k+1} of these blocks in CL layout
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+          v4f cl[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[b][v] * RS + 16 * t + c16];
+          if (act[b]) {
+            float *st = stash + ((long long)k * nb_max + j0 + b) * (64 * R / 4);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = cl[t];
+          }
+        }
       }
-      if (lane == 63) nblk[k] = incl / 16;
+      v4f out[G][NT];
+#pragma unroll
+      for (int b = 0; b < G; ++b)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[b][t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int to = 0; to < NT; ++to)
+#pragma unroll
+            for (int b = 0; b < G; ++b)
+              out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        if (!act[b]) continue;
+        if (k > 0) {
+          const int w = (ent[b] == ZROW) ? SROW : ent[b];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
+        } else if (q4 == 0 && ent[b] != ZROW) {
+          wsum[ent[b]] = out[b][0][0];  // component 0 of rho_1 = y
+        }
+      }
     }
     lds_barrier();
+  }
 
-    // --------------------------------------------------------- right sweep
-    // Each wave walks its blocks of mode k in groups of G: the LDS reads of a
-    // group are issued together and its MFMA chains are independent, so the
-    // matrix pipe is fed back to back.  Padding columns read the zero row.
-    for (int k = d - 1; k >= 0; --k) {
-      const int nb = nblk[k];
-      const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
-      const uint16_t *pk = perm + pbase[k];
-      const uint8_t *bk = bslc + bbase[k];
-      const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
-      for (int j0 = jb; j0 < je; j0 += G) {
-        int ent[G], ev[G][4];
-        bool act[G];
-        v4f a[G][NT * NT];
+  // ------------------------------------------------------------ residual
+  for (int e = tid; e < cnt; e += NTHR) {
+    const float yv = wsum[e];
+    if (p.y) p.y[e0 + e] = yv;
+    float w = 0.f;
+    if (MODE == MODE_MSE) {
+      const float rho = yv - p.t[e0 + e];
+      w = p.inv_m2 * rho;
+      loss_part += rho * rho;
+      if (p.gout) p.gout[e0 + e] = w;
+    } else if (MODE == MODE_ADJOINT) {
+      w = p.gy[e0 + e];
+    }
+    wsum[e] = w;
+  }
+  if (MODE == MODE_GATHER) {
+    lds_barrier();
+    return;
+  }
+  // lambda_1 = e_0 for every entry (and the zero row stays zero)
+  for (int e = tid; e < T; e += NTHR) {
 #pragma unroll
-        for (int b = 0; b < G; ++b) {
-          const int j = j0 + b;
-          act[b] = j < je;
-          ent[b] = ZROW;
+    for (int c = 0; c < R; ++c) rows[e * RS + c] = (c == 0) ? 1.f : 0.f;
+  }
+  lds_barrier();
+
+  // ---------------------------------------------------------- left sweep
+  // Outer products are summed in registers over each run of consecutive
+  // blocks with the same slice.  The wave that holds the first block of a
+  // slice stores its run into slab[s]; a wave whose first run continues a
+  // slice of the previous wave stores that run into its edge buffer.  The
+  // flush adds slab and edges in a fixed order: no atomics, deterministic.
+  for (int k = 0; k < d; ++k) {
+    const int nk = p.n[k];
+    if constexpr (ACC == ACC_SLAB) {
+      for (int e = tid; e < nk; e += NTHR) sflag[e] = 0;
+      if (lane == 0) eslice[wave] = -1;
+      lds_barrier();
+    }
+    const int nb = nblk[k];
+    const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
+    const uint16_t *pk = perm + pbase_of<T>(p, k);
+    const uint8_t *bk = bslc + bbase_of<T>(p, k);
+    const float *gk = p.gp_left + (long long)p.sbase[k] * R * R;
+    const bool chain = k < d - 1;
+    const bool cont_first = (jb < je) && jb > 0 && bk[jb - 1] == bk[jb];
+    bool first_run = true;
+    int rsid = -1;
+    v4f racc[NT * NT];
+    // a finished run: SLAB stores it (owner slab or edge buffer), DIRECT adds
+    // it to the gradient target with no-return float atomics
+    auto emit_run = [&](int s, bool edge) {
+      if constexpr (ACC == ACC_SLAB) {
+        float *dst = edge ? edges + wave * R * SS : slab + s * R * SS;
+        if (lane == 0) {
+          if (edge) eslice[wave] = s;
+          else sflag[s] = 1;
+        }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
-          if (act[b]) {
-            const int e = pk[16 * j + c16];
-            ent[b] = (e == kNone) ? ZROW : e;
-            const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-            const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+        for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
-            const float *gs = gk + (long long)bk[j] * R * R;
+          for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              dst[(16 * ta + 4 * q4 + v) * SS + 16 * tb + c16] = racc[ta * NT + tb][v];
+      } else {
+        float *dst = p.grad + (long long)(p.sbase[k] + s) * R * R;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              unsafeAtomicAdd(dst + (16 * ta + 4 * q4 + v) * R + 16 * tb + c16, racc[ta * NT + tb][v]);
+      }
+    };
+    for (int j0 = jb; j0 < je; j0 += G) {
+      int ent[G], ev[G][4], sid[G];
+      bool act[G];
+      v4f a[G][NT * NT];
+      v4f rcl[G][NT];
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        const int j = j0 + b;
+        act[b] = j < je;
+        ent[b] = ZROW;
+        sid[b] = -1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
+          rcl[b][t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+        }
+#pragma unroll
+        for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (act[b]) {
+          const int e = pk[16 * j + c16];
+          ent[b] = (e == kNone) ? ZROW : e;
+          const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+          const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
+          sid[b] = bk[j];
+          if (k <= d - 2) {
+            const float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) rcl[b][t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+          }
+          if (chain) {
+            const float *gs = gk + (long long)sid[b] * R * R;
 #pragma unroll
             for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-          } else {
-#pragma unroll
-            for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
           }
         }
-        v4f bv[G][NT];
+      }
+      // lambda_k: CL (weighted, A operand of the outer product) and EL (chain)
+      v4f lcl[G][NT], bv[G][NT];
 #pragma unroll
-        for (int b = 0; b < G; ++b) {
+      for (int b = 0; b < G; ++b) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            if (k == d - 1)
-              bv[b][t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
-            else
-              bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
-          }
+        for (int v = 0; v < 4; ++v) {
+          const float wv = wsum[ev[b][v]];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) lcl[b][t][v] = wv * rows[ev[b][v] * RS + 16 * t + c16];
         }
-        if (MODE != MODE_GATHER && k <= d - 2) {
-          // stash rho_{k+1} of these blocks in CL layout
 #pragma unroll
-          for (int b = 0; b < G; ++b) {
-            v4f cl[NT];
+        for (int t = 0; t < NT; ++t) bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
+      }
+      // outer products (G * NT * NT independent chains)
+      v4f dg[G][NT * NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+      for (int b = 0; b < G; ++b)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[b][v] * RS + 16 * t + c16];
-            if (act[b]) {
-              float *st = stash + ((long long)k * p.nb_max + j0 + b) * (64 * R / 4);
+        for (int x = 0; x < NT * NT; ++x) dg[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-              for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = cl[t];
-            }
-          }
-        }
-        v4f out[G][NT];
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+            for (int b = 0; b < G; ++b)
+              dg[b][ta * NT + tb] = mfma4(lcl[b][ta][c], rcl[b][tb][c], dg[b][ta * NT + tb]);
+      // chain lambda_{k+1}^T = G^T lambda_k^T
+      v4f out[G][NT];
+      if (chain) {
 #pragma unroll
         for (int b = 0; b < G; ++b)
 #pragma unroll
@@ -285,203 +449,32 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p
 #pragma unroll
         for (int b = 0; b < G; ++b) {
           if (!act[b]) continue;
-          if (k > 0) {
-            const int w = (ent[b] == ZROW) ? SROW : ent[b];
+          const int w = (ent[b] == ZROW) ? SROW : ent[b];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
-          } else if (q4 == 0 && ent[b] != ZROW) {
-            wsum[ent[b]] = out[b][0][0];  // component 0 of rho_1 = y
-          }
+          for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
         }
       }
-      lds_barrier();
-    }
-
-    // ------------------------------------------------------------ residual
-    for (int e = tid; e < cnt; e += NTHR) {
-      const float yv = wsum[e];
-      if (p.y) p.y[e0 + e] = yv;
-      float w = 0.f;
-      if (MODE == MODE_MSE) {
-        const float rho = yv - p.t[e0 + e];
-        w = p.inv_m2 * rho;
-        loss_part += rho * rho;
-        if (p.gout) p.gout[e0 + e] = w;
-      } else if (MODE == MODE_ADJOINT) {
-        w = p.gy[e0 + e];
-      }
-      wsum[e] = w;
-    }
-    if (MODE == MODE_GATHER) {
-      lds_barrier();
-      continue;
-    }
-    // lambda_1 = e_0 for every entry (and the zero row stays zero)
-    for (int e = tid; e < T; e += NTHR) {
+      // merge the group's outer products into runs
 #pragma unroll
-      for (int c = 0; c < R; ++c) rows[e * RS + c] = (c == 0) ? 1.f : 0.f;
+      for (int b = 0; b < G; ++b) {
+        if (!act[b]) continue;
+        if (sid[b] != rsid) {
+          if (rsid >= 0) {
+            emit_run(rsid, first_run && cont_first);
+            first_run = false;
+          }
+          rsid = sid[b];
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) racc[x] = dg[b][x];
+        } else {
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) racc[x] += dg[b][x];
+        }
+      }
     }
+    if (rsid >= 0) emit_run(rsid, first_run && cont_first);
     lds_barrier();
-
-    // ---------------------------------------------------------- left sweep
-    // Outer products are summed in registers over each run of consecutive
-    // blocks with the same slice.  The wave that holds the first block of a
-    // slice stores its run into slab[s]; a wave whose first run continues a
-    // slice of the previous wave stores that run into its edge buffer.  The
-    // flush adds slab and edges in a fixed order: no atomics, deterministic.
-    for (int k = 0; k < d; ++k) {
-      const int nk = p.n[k];
-      for (int e = tid; e < nk; e += NTHR) sflag[e] = 0;
-      if (lane == 0) eslice[wave] = -1;
-      lds_barrier();
-      const int nb = nblk[k];
-      const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
-      const uint16_t *pk = perm + pbase[k];
-      const uint8_t *bk = bslc + bbase[k];
-      const float *gk = p.gp_left + (long long)p.sbase[k] * R * R;
-      const bool chain = k < d - 1;
-      const bool cont_first = (jb < je) && jb > 0 && bk[jb - 1] == bk[jb];
-      bool first_run = true;
-      int rsid = -1;
-      v4f racc[NT * NT];
-      for (int j0 = jb; j0 < je; j0 += G) {
-        int ent[G], ev[G][4], sid[G];
-        bool act[G];
-        v4f a[G][NT * NT];
-        v4f rcl[G][NT];
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-          const int j = j0 + b;
-          act[b] = j < je;
-          ent[b] = ZROW;
-          sid[b] = -1;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
-            rcl[b][t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
-          }
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
-          if (act[b]) {
-            const int e = pk[16 * j + c16];
-            ent[b] = (e == kNone) ? ZROW : e;
-            const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-            const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
-#pragma unroll
-            for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
-            sid[b] = bk[j];
-            if (k <= d - 2) {
-              const float *st = stash + ((long long)k * p.nb_max + j) * (64 * R / 4);
-#pragma unroll
-              for (int t = 0; t < NT; ++t) rcl[b][t] = *(const v4f *)(st + (t * 64 + lane) * 4);
-            }
-            if (chain) {
-              const float *gs = gk + (long long)sid[b] * R * R;
-#pragma unroll
-              for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-            }
-          }
-        }
-        // lambda_k: CL (weighted, A operand of the outer product) and EL (chain)
-        v4f lcl[G][NT], bv[G][NT];
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float wv = wsum[ev[b][v]];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) lcl[b][t][v] = wv * rows[ev[b][v] * RS + 16 * t + c16];
-          }
-#pragma unroll
-          for (int t = 0; t < NT; ++t) bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
-        }
-        // outer products (G * NT * NT independent chains)
-        v4f dg[G][NT * NT];
-#pragma unroll
-        for (int b = 0; b < G; ++b)
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) dg[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-            for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-              for (int b = 0; b < G; ++b)
-                dg[b][ta * NT + tb] = mfma4(lcl[b][ta][c], rcl[b][tb][c], dg[b][ta * NT + tb]);
-        // chain lambda_{k+1}^T = G^T lambda_k^T
-        v4f out[G][NT];
-        if (chain) {
-#pragma unroll
-          for (int b = 0; b < G; ++b)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) out[b][t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-              for (int to = 0; to < NT; ++to)
-#pragma unroll
-                for (int b = 0; b < G; ++b)
-                  out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
-#pragma unroll
-          for (int b = 0; b < G; ++b) {
-            if (!act[b]) continue;
-            const int w = (ent[b] == ZROW) ? SROW : ent[b];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
-          }
-        }
-        // merge the group's outer products into runs
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-          if (!act[b]) continue;
-          if (sid[b] != rsid) {
-            if (rsid >= 0) {
-              float *dst = (first_run && cont_first) ? edges + wave * R * SS : slab + rsid * R * SS;
-              if (first_run && cont_first) {
-                if (lane == 0) eslice[wave] = rsid;
-              } else if (lane == 0) {
-                sflag[rsid] = 1;
-              }
-#pragma unroll
-              for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-                for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-                  for (int v = 0; v < 4; ++v)
-                    dst[(16 * ta + 4 * q4 + v) * SS + 16 * tb + c16] = racc[ta * NT + tb][v];
-              first_run = false;
-            }
-            rsid = sid[b];
-#pragma unroll
-            for (int x = 0; x < NT * NT; ++x) racc[x] = dg[b][x];
-          } else {
-#pragma unroll
-            for (int x = 0; x < NT * NT; ++x) racc[x] += dg[b][x];
-          }
-        }
-      }
-      if (rsid >= 0) {
-        float *dst = (first_run && cont_first) ? edges + wave * R * SS : slab + rsid * R * SS;
-        if (first_run && cont_first) {
-          if (lane == 0) eslice[wave] = rsid;
-        } else if (lane == 0) {
-          sflag[rsid] = 1;
-        }
-#pragma unroll
-        for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-          for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              dst[(16 * ta + 4 * q4 + v) * SS + 16 * tb + c16] = racc[ta * NT + tb][v];
-      }
-      lds_barrier();
+    if constexpr (ACC == ACC_SLAB) {
       // flush this mode into the workgroup's accumulator without waiting: a
       // plain store on the first tile, no-return atomics after
       float *ak = accg + (long long)p.sbase[k] * R * R;
@@ -498,20 +491,92 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(FusedArgs p
       }
       lds_barrier();
     }
-    first_tile = false;
   }
+}
 
+// Single tensor: tiles in grid-stride order over the entries.
+struct Grid {
+  int ntiles;
+  int nb_max;
+  float *stash;            // per workgroup: [d-1][nb_max][64 lanes][R/4]
+  long long stash_stride;  // floats per workgroup
+  float *acc;              // SLAB: per workgroup [total slices][R*R]
+  long long acc_stride;
+  float *loss_acc;         // per workgroup squared-residual sums
+};
+
+template <int R, int T, int MODE, int ACC>
+__global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(MfInst p, Grid g) {
+  constexpr int NTHR = MfTraits<R>::THREADS;
+  extern __shared__ __align__(16) char smem[];
+  float *stash = g.stash + (long long)blockIdx.x * g.stash_stride;
+  float *accg = g.acc ? g.acc + (long long)blockIdx.x * g.acc_stride : nullptr;
+  float loss_part = 0.f;
+  bool first = true;
+  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+    const long long e0 = (long long)tile * T;
+    const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
+    run_tile<R, T, NTHR, MODE, ACC>(p, e0, cnt, smem, stash, g.nb_max, accg, first, loss_part);
+    first = false;
+  }
   if (MODE == MODE_MSE) {
     // deterministic block reduction of the squared residuals
-    float *red = wsum;
+    float *red = (float *)smem;
     __syncthreads();
-    red[tid] = loss_part;
+    red[threadIdx.x] = loss_part;
     __syncthreads();
     for (int st = NTHR / 2; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
-    if (tid == 0) p.loss_acc[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) g.loss_acc[blockIdx.x] = red[0];
+  }
+}
+
+// Batched persistent kernel: workgroups take (tensor, first tile, tile
+// count) items from an atomic counter (items are in decreasing-cost order)
+// until the list is exhausted; both rank classes share the launch.  Per
+// tensor: gradients accumulate into its zeroed padded buffer (DIRECT), the
+// loss into loss[b] (mean over that tensor's entries).
+__global__ void __launch_bounds__(MF_BATCH_THREADS) batched_kernel(MfBatchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int item_sh;
+  __shared__ float red[MF_BATCH_THREADS / 64];
+  float *stash = a.stash + (long long)blockIdx.x * a.stash_stride;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(item_sh);
+    __syncthreads();
+    if (it >= a.nitems) break;
+    const MfWorkItem w = a.items[it];
+    const MfInst &p = a.table[w.inst];
+    for (int t = 0; t < w.ntile; ++t) {
+      float lp = 0.f;
+      if (w.rclass == 16) {
+        constexpr int T = MfTraits<16>::T;
+        const long long e0 = (long long)(w.tile0 + t) * T;
+        const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
+        run_tile<16, T, MF_BATCH_THREADS, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb16, nullptr,
+                                                                false, lp);
+      } else {
+        constexpr int T = MfTraits<32>::T;
+        const long long e0 = (long long)(w.tile0 + t) * T;
+        const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
+        run_tile<32, T, MF_BATCH_THREADS, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb32, nullptr,
+                                                                false, lp);
+      }
+      // this tile's share of the tensor's mean squared residual
+      for (int off = 32; off > 0; off >>= 1) lp += __shfl_xor(lp, off);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lp;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int wv = 0; wv < MF_BATCH_THREADS / 64; ++wv) s += red[wv];
+        unsafeAtomicAdd(p.loss, s * p.inv_m);
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -605,8 +670,7 @@ int device_cus() {
   return cus;
 }
 
-template <int R>
-constexpr int tile_of() { return MfTraits<R>::T; }
+constexpr int acc_of(int R) { return R == 16 ? ACC_SLAB : ACC_DIRECT; }
 
 struct Geometry {
   int R, T, nb_max, total_slices, ntiles, nwg;
@@ -616,7 +680,7 @@ struct Geometry {
 Geometry geometry(const tt_tensor *X, int R, int64_t M) {
   Geometry g;
   g.R = R;
-  g.T = (R == 16) ? tile_of<16>() : tile_of<32>();
+  g.T = (R == 16) ? MfTraits<16>::T : MfTraits<32>::T;
   int nmax = 1;
   g.total_slices = 0;
   for (int k = 0; k < X->d; ++k) {
@@ -629,23 +693,25 @@ Geometry geometry(const tt_tensor *X, int R, int64_t M) {
   g.nwg = g.ntiles < cus ? g.ntiles : cus;
   if (g.nwg < 1) g.nwg = 1;
   g.stash_stride = (long long)(X->d > 1 ? X->d - 1 : 1) * g.nb_max * 64 * (R / 4);
-  g.acc_stride = (long long)g.total_slices * R * R;
+  g.acc_stride = (R == 16) ? (long long)g.total_slices * R * R : 0;
   return g;
 }
 
 template <int R, int MODE>
-int launch_fused(const FusedArgs &a, int nwg, hipStream_t s) {
-  constexpr int T = tile_of<R>();
-  using L = Lds<R, T>;
+int launch_fused(const MfInst &p, const Grid &g, int nwg, hipStream_t s) {
+  constexpr int T = MfTraits<R>::T;
+  constexpr int ACC = acc_of(R);
+  using L = Lds<R, T, MfTraits<R>::THREADS, ACC>;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<R, T, MODE>,
+    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<R, T, MODE, ACC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::total);
     if (e != hipSuccess) return hip_check(e, "fused kernel LDS attribute");
     attr_set = true;
   }
   timer_before(s);
-  hipLaunchKernelGGL((fused_kernel<R, T, MODE>), dim3(nwg), dim3(MfTraits<R>::THREADS), L::total, s, a);
+  hipLaunchKernelGGL((fused_kernel<R, T, MODE, ACC>), dim3(nwg), dim3(MfTraits<R>::THREADS), L::total, s,
+                     p, g);
   timer_after(s);
   return launch_check("fused MFMA kernel");
 }
@@ -663,6 +729,12 @@ static bool fits_class(const tt_tensor *X) {
   return pcap <= MfTraits<R>::PERM_CAP;
 }
 
+int mfma_rank_class(const tt_tensor *L, const tt_tensor *R) {
+  int mr = L ? max_rank_of(L) : 1;
+  if (R && max_rank_of(R) > mr) mr = max_rank_of(R);
+  return mr <= 16 ? 16 : 32;
+}
+
 bool mfma_supported(const tt_tensor *L, const tt_tensor *R) {
   const int rc = mfma_rank_class(L, R);
   const tt_tensor *ts[2] = {L, R};
@@ -674,22 +746,37 @@ bool mfma_supported(const tt_tensor *L, const tt_tensor *R) {
   return true;
 }
 
-int mfma_rank_class(const tt_tensor *L, const tt_tensor *R) {
-  int mr = L ? max_rank_of(L) : 1;
-  if (R && max_rank_of(R) > mr) mr = max_rank_of(R);
-  return mr <= 16 ? 16 : 32;
-}
+bool mfma_class_fits(const tt_tensor *X, int R) { return R == 16 ? fits_class<16>(X) : fits_class<32>(X); }
 
 size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint) {
   const Geometry g = geometry(X, R, M);
   size_t b = 2 * arena_bytes<float>((size_t)g.total_slices * R * R);
   if (adjoint) {
     b += arena_bytes<float>((size_t)g.nwg * g.stash_stride);
-    b += arena_bytes<float>((size_t)g.nwg * g.acc_stride);
+    if (R == 16) {
+      b += arena_bytes<float>((size_t)g.nwg * g.acc_stride);
+      b += arena_bytes<float>((size_t)((g.nwg + 31) / 32) * g.total_slices * R * R);
+    } else {
+      b += arena_bytes<float>((size_t)g.total_slices * R * R);
+    }
     b += arena_bytes<float>((size_t)g.nwg);
-    b += arena_bytes<float>((size_t)((g.nwg + 31) / 32) * g.total_slices * R * R);
   }
   return b;
+}
+
+int mfma_pad(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float *gpl, hipStream_t s) {
+  int total = 0;
+  for (int k = 0; k < Rt->d; ++k) total += Rt->n[k];
+  hipLaunchKernelGGL(pad_slices_kernel, dim3(total), dim3(256), 0, s, make_dev(Rt), make_dev(Lt ? Lt : Rt), R,
+                     gpr, gpl, total);
+  return launch_check("pad slices");
+}
+
+int mfma_unpad(const tt_tensor *O, int R, const float *padded, hipStream_t s) {
+  long long E = 0;
+  for (int k = 0; k < O->d; ++k) E += (long long)O->n[k] * R * R;
+  hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, make_dev(O), R, padded, E, 1);
+  return launch_check("unpad gradients");
 }
 
 int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, const int32_t *idx,
@@ -701,56 +788,62 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
   Arena ar(ws, ws_bytes);
   float *gpr = ar.take<float>((size_t)g.total_slices * R * R);
   float *gpl = ar.take<float>((size_t)g.total_slices * R * R);
-  float *stash = nullptr, *acc = nullptr, *lacc = nullptr, *rtmp = nullptr;
+  float *stash = nullptr, *acc = nullptr, *lacc = nullptr, *rtmp = nullptr, *grad = nullptr;
   if (adjoint) {
     stash = ar.take<float>((size_t)g.nwg * g.stash_stride);
-    acc = ar.take<float>((size_t)g.nwg * g.acc_stride);
+    if (R == 16) {
+      acc = ar.take<float>((size_t)g.nwg * g.acc_stride);
+      rtmp = ar.take<float>((size_t)((g.nwg + 31) / 32) * g.total_slices * R * R);
+    } else {
+      grad = ar.take<float>((size_t)g.total_slices * R * R);
+    }
     lacc = ar.take<float>((size_t)g.nwg);
-    rtmp = ar.take<float>((size_t)((g.nwg + 31) / 32) * g.total_slices * R * R);
   }
   if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "gather (MFMA): workspace too small");
-  const TTDev dr = make_dev(Rt);
-  const TTDev dl = make_dev(Lt ? Lt : Rt);
-  hipLaunchKernelGGL(pad_slices_kernel, dim3(g.total_slices), dim3(256), 0, s, dr, dl, R, gpr,
-                     adjoint ? gpl : (float *)nullptr, g.total_slices);
-  int rc = launch_check("pad slices");
+  int rc = mfma_pad(Rt, Lt, R, gpr, adjoint ? gpl : nullptr, s);
   if (rc) return rc;
 
-  FusedArgs a = {};
-  a.d = Rt->d;
+  MfInst p = {};
+  p.d = Rt->d;
   int sb = 0;
   for (int k = 0; k < Rt->d; ++k) {
-    a.n[k] = Rt->n[k];
-    a.sbase[k] = sb;
+    p.n[k] = Rt->n[k];
+    p.sbase[k] = sb;
     sb += Rt->n[k];
   }
-  a.idx = idx;
-  a.M = M;
-  a.gp_right = gpr;
-  a.gp_left = gpl;
-  a.t = t;
-  a.gy = gy;
-  a.y = y;
-  a.gout = gout;
-  a.stash = stash;
-  a.acc = acc;
-  a.loss_acc = lacc;
-  a.stash_stride = g.stash_stride;
-  a.acc_stride = g.acc_stride;
-  a.nb_max = g.nb_max;
-  a.ntiles = g.ntiles;
-  a.total_slices = g.total_slices;
-  a.inv_m2 = M > 0 ? 2.0f / (float)M : 0.f;
+  p.idx = idx;
+  p.M = M;
+  p.gp_right = gpr;
+  p.gp_left = gpl;
+  p.t = t;
+  p.gy = gy;
+  p.y = y;
+  p.gout = gout;
+  p.grad = grad;
+  p.inv_m2 = M > 0 ? 2.0f / (float)M : 0.f;
+  p.inv_m = M > 0 ? 1.0f / (float)M : 0.f;
+  p.rclass = R;
+  Grid gr = {};
+  gr.ntiles = g.ntiles;
+  gr.nb_max = g.nb_max;
+  gr.stash = stash;
+  gr.stash_stride = g.stash_stride;
+  gr.acc = acc;
+  gr.acc_stride = g.acc_stride;
+  gr.loss_acc = lacc;
 
+  if (adjoint && grad) {
+    if ((rc = fill_zero(grad, (long long)g.total_slices * R * R, s))) return rc;
+  }
   if (M > 0) {
     if (R == 16) {
-      if (mode == MODE_GATHER) rc = launch_fused<16, MODE_GATHER>(a, g.nwg, s);
-      else if (mode == MODE_ADJOINT) rc = launch_fused<16, MODE_ADJOINT>(a, g.nwg, s);
-      else rc = launch_fused<16, MODE_MSE>(a, g.nwg, s);
+      if (mode == MODE_GATHER) rc = launch_fused<16, MODE_GATHER>(p, gr, g.nwg, s);
+      else if (mode == MODE_ADJOINT) rc = launch_fused<16, MODE_ADJOINT>(p, gr, g.nwg, s);
+      else rc = launch_fused<16, MODE_MSE>(p, gr, g.nwg, s);
     } else {
-      if (mode == MODE_GATHER) rc = launch_fused<32, MODE_GATHER>(a, g.nwg, s);
-      else if (mode == MODE_ADJOINT) rc = launch_fused<32, MODE_ADJOINT>(a, g.nwg, s);
-      else rc = launch_fused<32, MODE_MSE>(a, g.nwg, s);
+      if (mode == MODE_GATHER) rc = launch_fused<32, MODE_GATHER>(p, gr, g.nwg, s);
+      else if (mode == MODE_ADJOINT) rc = launch_fused<32, MODE_ADJOINT>(p, gr, g.nwg, s);
+      else rc = launch_fused<32, MODE_MSE>(p, gr, g.nwg, s);
     }
     if (rc) return rc;
   }
@@ -764,19 +857,50 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
     if (loss) return fill_zero(loss, 1, s);
     return TT_OK;
   }
-  const TTDev od = make_dev(O);
-  const long long E = (long long)g.total_slices * R * R;
-  const int ngroups = (g.nwg + 31) / 32;
-  hipLaunchKernelGGL(reduce_acc_stage1, dim3((unsigned)((E + 255) / 256), ngroups), dim3(256), 0, s,
-                     acc, g.acc_stride, g.nwg, E, rtmp);
-  if ((rc = launch_check("reduce partial gradients"))) return rc;
-  hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, od, R, rtmp, E, ngroups);
-  if ((rc = launch_check("reduce partial gradients (2)"))) return rc;
+  if (R == 16) {
+    const TTDev od = make_dev(O);
+    const long long E = (long long)g.total_slices * R * R;
+    const int ngroups = (g.nwg + 31) / 32;
+    hipLaunchKernelGGL(reduce_acc_stage1, dim3((unsigned)((E + 255) / 256), ngroups), dim3(256), 0, s,
+                       acc, g.acc_stride, g.nwg, E, rtmp);
+    if ((rc = launch_check("reduce partial gradients"))) return rc;
+    hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, od, R, rtmp, E, ngroups);
+    if ((rc = launch_check("reduce partial gradients (2)"))) return rc;
+  } else {
+    if ((rc = mfma_unpad(O, R, grad, s))) return rc;
+  }
   if (mode == MODE_MSE && loss) {
     hipLaunchKernelGGL(reduce_loss_kernel, dim3(1), dim3(64), 0, s, lacc, g.nwg, (long long)M, loss);
     return launch_check("reduce loss");
   }
   return TT_OK;
 }
+
+size_t mfma_batch_lds() {
+  constexpr size_t a = Lds<16, MfTraits<16>::T, MF_BATCH_THREADS, ACC_DIRECT>::total;
+  constexpr size_t b = Lds<32, MfTraits<32>::T, MF_BATCH_THREADS, ACC_DIRECT>::total;
+  return a > b ? a : b;
+}
+
+int mfma_batch_prepare() {
+  static bool done = false;
+  if (done) return TT_OK;
+  hipError_t e = hipFuncSetAttribute((const void *)batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)mfma_batch_lds());
+  if (e != hipSuccess) return hip_check(e, "batched kernel LDS attribute");
+  done = true;
+  return TT_OK;
+}
+
+int mfma_batch_launch(const MfBatchArgs &a, int nwg, hipStream_t s) {
+  int rc = mfma_batch_prepare();
+  if (rc) return rc;
+  timer_before(s);
+  hipLaunchKernelGGL(batched_kernel, dim3(nwg), dim3(MF_BATCH_THREADS), mfma_batch_lds(), s, a);
+  timer_after(s);
+  return launch_check("batched kernel");
+}
+
+int mfma_device_cus() { return device_cus(); }
 
 }  // namespace ttgfx

@@ -262,3 +262,77 @@ def riemannian_step(X, idx, t, alpha=-0.1, max_rank=None):
     W = project_sparse(U, V, idx, g, alpha=alpha, add_x=1)
     Y, disc = round_tt(W, max_rank)
     return dict(y=y, loss=loss, grads=grads, U=U, V=V, W=W, Y=Y, disc_sq=disc)
+
+
+def _batch(tts):
+    """A tt_batch descriptor over TT objects (kept alive by the returned tuple)."""
+    arr = (L.tt_tensor * len(tts))(*[t.desc() for t in tts])
+    return L.tt_batch(len(tts), arr), arr
+
+
+def gram(As, Bs=None):
+    """Gram matrix G[a][b] = <As[a], Bs[b]> (Bs = None: As with itself,
+    computed once per unordered pair).  Ranks up to 32; ranks may differ
+    between tensors."""
+    lib = L.load()
+    dev = As[0].device
+    A, keepA = _batch(As)
+    B, keepB = _batch(Bs) if Bs is not None else (None, None)
+    pB = C.byref(B) if B is not None else None
+    nb = len(Bs) if Bs is not None else len(As)
+    G = torch.empty((len(As), nb), dtype=torch.float32, device=dev)
+    ws, n = _workspace(L.check(lib.tt_gram_workspace(C.byref(A), pB)), dev)
+    L.check(lib.tt_gram(C.byref(A), pB, _ptr(G), _ptr(ws), n, _stream(dev)))
+    return G
+
+
+class BatchedPlan:
+    """Batched persistent gather + MSE + adjoint over TT tensors of uneven
+    ranks and entry counts (tt_plan_*).  ``idx`` holds, for tensor j, the
+    (d, M_j) index block flattened at element d * entry_off[j]; ``t`` the
+    targets at entry_off[j].  Gradients land in ``self.grads`` (a list of TT)
+    and per-tensor losses in ``self.loss``."""
+
+    def __init__(self, Xs, idx, t, entry_off):
+        lib = L.load()
+        self.Xs = list(Xs)
+        dev = self.Xs[0].device
+        self.idx = torch.as_tensor(idx).to(device=dev, dtype=torch.int32).contiguous().reshape(-1)
+        self.t = torch.as_tensor(t).to(device=dev, dtype=torch.float32).contiguous()
+        self.entry_off = (C.c_int64 * len(entry_off))(*[int(x) for x in entry_off])
+        self.grads = [X.empty_like() for X in self.Xs]
+        self.loss = torch.empty(len(self.Xs), dtype=torch.float32, device=dev)
+        self._bx, self._kx = _batch(self.Xs)
+        self._bg, self._kg = _batch(self.grads)
+        self._plan = C.c_void_p()
+        L.check(lib.tt_plan_create(C.byref(self._bx), _ptr(self.idx), _ptr(self.t), self.entry_off,
+                                   C.byref(self._bg), _ptr(self.loss), C.byref(self._plan)))
+        self.device = dev
+
+    def run(self, stream=None):
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        L.check(L.load().tt_plan_run(self._plan, s))
+
+    def run_plain(self, stream=None):
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        L.check(L.load().tt_plan_run_plain(self._plan, s))
+
+    def capture(self, stream):
+        L.check(L.load().tt_plan_capture(self._plan, C.c_void_p(stream.cuda_stream)))
+
+    def autotune(self, stream=None):
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        chosen = C.c_int32(0)
+        L.check(L.load().tt_plan_autotune(self._plan, s, C.byref(chosen)))
+        return int(chosen.value)
+
+    def close(self):
+        if self._plan:
+            L.load().tt_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
