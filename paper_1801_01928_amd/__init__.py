@@ -1,4 +1,5 @@
-"""MI355X-native TT-completion hot path (gather, adjoint, Riemannian step).
+"""MI355X-native TT-completion hot path (gather, adjoint, Riemannian step,
+Gram matrices, batched plans) and the TT-matrix layer.
 
 The compute lives in libttgfx.so (hand-written HIP kernels for gfx950 behind
 the C ABI of include/ttgfx.h); this package marshals arguments only.
@@ -18,4 +19,8 @@ from .tt import (  # noqa: F401
     riemannian_step,
     gram,
     BatchedPlan,
+    TTMatrix,
+    ttm_matmul,
+    ttm_matmul_backward,
+    tt_linear,
 )

@@ -1,0 +1,474 @@
+// TT-matrix layer (t3f.matmul(tt_matrix, x), Implementation Details):
+// Y = X W^T with W[(i_1..i_d), (j_1..j_d)] = G^1[i_1, j_1] ... G^d[i_d, j_d]
+// (cores r_k x m_k x n_k x r_{k+1}), and its adjoint dX = dY W, dG^k.
+//
+// All sweeps are built from one contraction step over an intermediate laid
+// out as IN[p][j][q][a] (p = batch row and modes already produced, j = the
+// mode being contracted, q = modes still to come, a = bond index):
+//     OUT[p][i][q][b] = sum_{j, a} IN[p][j][q][a] * core(a, j -> i, b)
+// evaluated as a GEMM with rows (p, q), K = (j, a), N = (i, b) on
+// v_mfma_f32_16x16x4_f32, or v_mfma_f32_16x16x16_bf16 with float32
+// accumulation.  The core element is addressed through four strides, so the
+// same kernel runs the forward sweep (contract j_k, produce i_k), dX
+// (contract i_k, produce j_k) and the right-to-left sweep of dY that the core
+// gradient needs.  The gradient of core k is
+//     dG^k[a, i, j, b] = sum_{p, q} T_k[p][j][q][a] * V_{k+1}[p][i][q][b]
+// (forward intermediate against backward intermediate), a GEMM whose K = (p, q)
+// is split across workgroups; the per-workgroup partial tiles are summed in a
+// fixed order, so the gradient is deterministic.
+#include "common.h"
+#include "ttm.h"
+
+namespace ttgfx {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma_f32(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma_bf16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+// Round to nearest, ties to even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int BF16>
+__device__ __forceinline__ float load_el(const void *p, long long i) {
+  if (BF16) return bf16_to_f32(((const uint16_t *)p)[i]);
+  return ((const float *)p)[i];
+}
+
+constexpr int kThreads = 256;  // 4 waves
+constexpr int kRows = 64;      // rows per workgroup iteration, 16 per wave
+constexpr int kMaxTiles = TTM_MAX_FUSED / 16;
+
+struct Step {
+  long long P, Q;   // outer and trailing counts
+  int nin, rin;     // contracted mode size, bond of IN
+  int mout, rout;   // produced mode size, bond of OUT
+  const void *in;
+  void *out;
+  const void *core;
+  long long sa, sj, si, sb;  // core element (a, j, i, b) at a*sa + j*sj + i*si + b*sb
+};
+
+// One workgroup stages the whole core in B-operand order, then walks row
+// blocks of 64 (p, q) rows; every wave owns 16 rows and all N tiles.
+template <int BF16>
+__global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32) {
+  extern __shared__ __align__(16) float bsh[];
+  const int K = s.nin * s.rin, N = s.mout * s.rout;
+  const int KC = (K + 15) / 16, NT = (N + 15) / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c16 = lane & 15, q4 = lane >> 4;
+  // chunk x (16 K values), tile t: lane (q4, c16) holds B[16x + 4q4 + v][16t + c16]
+  for (int e = tid; e < KC * NT * 256; e += kThreads) {
+    const int v = e & 3, ln = (e >> 2) & 63, xt = e >> 8;
+    const int x = xt / NT, t = xt % NT;
+    const int kk = 16 * x + 4 * (ln >> 4) + v, nn = 16 * t + (ln & 15);
+    float val = 0.f;
+    if (kk < K && nn < N) {
+      const int j = kk / s.rin, a = kk % s.rin, i = nn / s.rout, b = nn % s.rout;
+      val = load_el<BF16>(s.core, a * s.sa + j * s.sj + i * s.si + b * s.sb);
+    }
+    bsh[e] = val;
+  }
+  __syncthreads();
+  const long long rows = s.P * s.Q;
+  const long long jstride = s.Q * s.rin;
+  for (long long r0 = (long long)blockIdx.x * kRows; r0 < rows; r0 += (long long)gridDim.x * kRows) {
+    const long long row = r0 + wave * 16 + c16;  // A-operand row of this lane
+    const bool rvalid = row < rows;
+    const long long p = rvalid ? row / s.Q : 0, q = rvalid ? row % s.Q : 0;
+    const long long abase = (p * s.nin * s.Q + q) * s.rin;
+    v4f acc[kMaxTiles];
+#pragma unroll
+    for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int x = 0; x < KC; ++x) {
+      float av[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int kk = 16 * x + 4 * q4 + v;
+        float val = 0.f;
+        if (rvalid && kk < K) val = load_el<BF16>(s.in, abase + (kk / s.rin) * jstride + kk % s.rin);
+        av[v] = val;
+      }
+      if (BF16) {
+        v4s a4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a4[v] = (short)f32_to_bf16(av[v]);  // exact: values are bf16
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) {
+          if (t < NT) {
+            const v4f bv = ((const v4f *)bsh)[(x * NT + t) * 64 + lane];
+            v4s b4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b4[v] = (short)f32_to_bf16(bv[v]);
+            acc[t] = mfma_bf16(a4, b4, acc[t]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) {
+          if (t < NT) {
+            const v4f bv = ((const v4f *)bsh)[(x * NT + t) * 64 + lane];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t] = mfma_f32(av[v], bv[v], acc[t]);
+          }
+        }
+      }
+    }
+    // D tile t: lane (q4, c16) value v is row r0 + 16 wave + 4 q4 + v, column 16 t + c16
+#pragma unroll
+    for (int t = 0; t < kMaxTiles; ++t) {
+      const int nn = 16 * t + c16;
+      if (t >= NT || nn >= N) continue;
+      const int i = nn / s.rout, b = nn % s.rout;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long orow = r0 + wave * 16 + 4 * q4 + v;
+        if (orow >= rows) continue;
+        const long long op = orow / s.Q, oq = orow % s.Q;
+        const long long off = ((op * s.mout + i) * s.Q + oq) * s.rout + b;
+        if (BF16 && !out_f32) ((uint16_t *)s.out)[off] = f32_to_bf16(acc[t][v]);
+        else ((float *)s.out)[off] = acc[t][v];
+      }
+    }
+  }
+}
+
+struct GradArgs {
+  long long P, Q;
+  int n, m, rT, rV;
+  const void *T;     // [P][n][Q][rT]
+  const void *V;     // [P][m][Q][rV]
+  float *part;       // [gridDim.x][rT * m * n * rV], core order
+  long long kchunk;  // (p, q) pairs per workgroup, a multiple of 4
+};
+
+// Partial core gradient over this workgroup's (p, q) range.  Rows of the
+// product are (j, a) with a fastest, columns (i, b) with b fastest, so the
+// 16 lanes of an operand read 16 consecutive bond entries.
+template <int BF16>
+__global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
+  const int ROWS = g.rT * g.n, COLS = g.m * g.rV;
+  const int RT = (ROWS + 15) / 16, CT = (COLS + 15) / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c16 = lane & 15, q4 = lane >> 4;
+  const long long K = g.P * g.Q;
+  const long long k0 = (long long)blockIdx.x * g.kchunk;
+  const long long k1 = (k0 + g.kchunk < K) ? k0 + g.kchunk : K;
+  float *part = g.part + (long long)blockIdx.x * ROWS * COLS;
+  for (int rt = wave; rt < RT; rt += kThreads / 64) {
+    v4f acc[kMaxTiles];
+#pragma unroll
+    for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int arow = 16 * rt + c16;
+    const bool aok = arow < ROWS;
+    const int aj = aok ? arow / g.rT : 0, aa = aok ? arow % g.rT : 0;
+    for (long long kb = k0; kb < k1; kb += 4) {
+      const long long kk = kb + q4;  // K slot q4 of this lane
+      const bool kok = kk < k1;
+      const long long p = kok ? kk / g.Q : 0, q = kok ? kk % g.Q : 0;
+      float a = 0.f;
+      if (kok && aok) a = load_el<BF16>(g.T, ((p * g.n + aj) * g.Q + q) * g.rT + aa);
+#pragma unroll
+      for (int t = 0; t < kMaxTiles; ++t) {
+        if (t >= CT) continue;
+        const int col = 16 * t + c16;
+        float b = 0.f;
+        if (kok && col < COLS) b = load_el<BF16>(g.V, ((p * g.m + col / g.rV) * g.Q + q) * g.rV + col % g.rV);
+        acc[t] = mfma_f32(a, b, acc[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxTiles; ++t) {
+      const int col = 16 * t + c16;
+      if (t >= CT || col >= COLS) continue;
+      const int i = col / g.rV, b = col % g.rV;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rt + 4 * q4 + v;
+        if (row >= ROWS) continue;
+        const int j = row / g.rT, a = row % g.rT;
+        part[(((long long)a * g.m + i) * g.n + j) * g.rV + b] = acc[t][v];
+      }
+    }
+  }
+}
+
+// out[e] = sum_w part[w][e] in a fixed order (4 interleaved partial sums).
+__global__ void __launch_bounds__(256) ttm_grad_reduce_kernel(const float *__restrict__ part, int nwg,
+                                                             long long cnt, float *__restrict__ out) {
+  __shared__ float red[4][64];
+  const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const long long e = (long long)blockIdx.x * 64 + el;
+  float s = 0.f;
+  if (e < cnt)
+    for (int w = grp; w < nwg; w += 4) s += part[(long long)w * cnt + e];
+  red[grp][el] = s;
+  __syncthreads();
+  if (grp == 0 && e < cnt) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
+}
+
+constexpr int kMaxGradWG = 512;
+
+size_t step_lds(int K, int N) { return sizeof(float) * 256 * ((K + 15) / 16) * ((N + 15) / 16); }
+
+int set_step_attrs() {
+  const int lds = (int)step_lds(TTM_MAX_FUSED, TTM_MAX_FUSED);
+  hipError_t e = hipFuncSetAttribute((const void *)ttm_step_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)ttm_step_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return hip_check(e, "ttm step LDS attribute");
+}
+
+int launch_step(const Step &s, int bf16, int out_f32, hipStream_t st) {
+  static const int attr_rc = set_step_attrs();
+  if (attr_rc) return attr_rc;
+  const size_t shm = step_lds(s.nin * s.rin, s.mout * s.rout);
+  const long long rows = s.P * s.Q;
+  long long nb = (rows + kRows - 1) / kRows;
+  nb = nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
+  if (bf16)
+    hipLaunchKernelGGL(ttm_step_kernel<1>, dim3((unsigned)nb), dim3(kThreads), shm, st, s, out_f32);
+  else
+    hipLaunchKernelGGL(ttm_step_kernel<0>, dim3((unsigned)nb), dim3(kThreads), shm, st, s, out_f32);
+  return launch_check("ttm step");
+}
+
+long long prod(const int *a, int lo, int hi) {
+  long long p = 1;
+  for (int k = lo; k < hi; ++k) p *= a[k];
+  return p;
+}
+
+size_t esz(int bf16) { return bf16 ? 2 : 4; }
+long long core_cnt(const TTMDims &D, int k) { return (long long)D.r[k] * D.m[k] * D.n[k] * D.r[k + 1]; }
+
+// Forward intermediate after k steps (also the size of the dY-sweep
+// intermediate V_k): B * prod m_<k * prod n_>=k * r_k elements.
+long long fwd_elems(const TTMDims &D, long long B, int k) {
+  return B * prod(D.m, 0, k) * prod(D.n, k, D.d) * D.r[k];
+}
+// dX-sweep intermediate after k steps: B * prod n_<k * prod m_>=k * r_k.
+long long adj_elems(const TTMDims &D, long long B, int k) {
+  return B * prod(D.n, 0, k) * prod(D.m, k, D.d) * D.r[k];
+}
+
+long long max_pingpong(const TTMDims &D, long long B, int backward) {
+  long long mx = 1;
+  for (int k = 1; k < D.d; ++k) {
+    mx = fwd_elems(D, B, k) > mx ? fwd_elems(D, B, k) : mx;
+    if (backward) mx = adj_elems(D, B, k) > mx ? adj_elems(D, B, k) : mx;
+  }
+  return mx;
+}
+
+// Step k of the forward sweep: contract (j_k, left bond), produce (i_k, right bond).
+Step forward_step(const TTMDims &D, const void *cores, int bf16, long long B, int k, const void *in, void *out) {
+  Step s;
+  s.P = B * prod(D.m, 0, k);
+  s.Q = prod(D.n, k + 1, D.d);
+  s.nin = D.n[k];
+  s.rin = D.r[k];
+  s.mout = D.m[k];
+  s.rout = D.r[k + 1];
+  s.in = in;
+  s.out = out;
+  s.core = (const char *)cores + esz(bf16) * D.off[k];
+  s.sa = (long long)D.m[k] * D.n[k] * D.r[k + 1];
+  s.si = (long long)D.n[k] * D.r[k + 1];
+  s.sj = D.r[k + 1];
+  s.sb = 1;
+  return s;
+}
+
+}  // namespace
+
+int ttm_validate(const tt_matrix *W, long long B, int dtype, TTMDims *D) {
+  if (!W) return set_error(TT_ERR_ARG, "W: null descriptor");
+  if (W->d < 1 || W->d > TT_MAX_D) return set_error(TT_ERR_ARG, "W: d = %d outside [1, %d]", W->d, TT_MAX_D);
+  if (!W->m || !W->n || !W->r) return set_error(TT_ERR_ARG, "W: null m, n or r array");
+  if (!W->data) return set_error(TT_ERR_ARG, "W: null data pointer");
+  if (dtype != 0 && dtype != 1) return set_error(TT_ERR_ARG, "dtype %d is neither 0 (float32) nor 1 (bf16)", dtype);
+  if (B < 0) return set_error(TT_ERR_ARG, "negative batch %lld", B);
+  if (B > (1LL << 24)) return set_error(TT_ERR_UNSUPPORTED, "batch %lld above 2^24", B);
+  if (W->r[0] != 1 || W->r[W->d] != 1)
+    return set_error(TT_ERR_SHAPE, "W: boundary ranks must be 1 (got %d, %d)", W->r[0], W->r[W->d]);
+  D->d = W->d;
+  for (int k = 0; k <= W->d; ++k) {
+    if (W->r[k] < 1 || W->r[k] > TT_MAX_RANK)
+      return set_error(TT_ERR_SHAPE, "W: r[%d] = %d outside [1, %d]", k, W->r[k], TT_MAX_RANK);
+    D->r[k] = W->r[k];
+  }
+  D->Mt = D->Nt = 1;
+  D->extent = 0;
+  long long o = 0;
+  for (int k = 0; k < W->d; ++k) {
+    if (W->m[k] < 1 || W->n[k] < 1 || W->m[k] > TT_MAX_N || W->n[k] > TT_MAX_N)
+      return set_error(TT_ERR_SHAPE, "W: mode sizes m[%d] = %d, n[%d] = %d outside [1, %d]", k, W->m[k], k,
+                       W->n[k], TT_MAX_N);
+    D->m[k] = W->m[k];
+    D->n[k] = W->n[k];
+    const int lim = TTM_MAX_FUSED;
+    if (W->m[k] * W->r[k] > lim || W->m[k] * W->r[k + 1] > lim || W->n[k] * W->r[k] > lim ||
+        W->n[k] * W->r[k + 1] > lim)
+      return set_error(TT_ERR_UNSUPPORTED, "W: core %d (%d x %d x %d x %d): a mode size times a rank exceeds %d",
+                       k, W->r[k], W->m[k], W->n[k], W->r[k + 1], lim);
+    D->Mt *= W->m[k];
+    D->Nt *= W->n[k];
+    if (D->Mt > (1LL << 31) || D->Nt > (1LL << 31))
+      return set_error(TT_ERR_UNSUPPORTED, "W: more than 2^31 rows or columns");
+    if (W->off && W->off[k] < 0) return set_error(TT_ERR_ARG, "W: negative offset for core %d", k);
+    D->off[k] = W->off ? W->off[k] : o;
+    o += core_cnt(*D, k);
+    const long long end = D->off[k] + core_cnt(*D, k);
+    D->extent = end > D->extent ? end : D->extent;
+  }
+  return TT_OK;
+}
+
+size_t ttm_ws(const TTMDims &D, long long B, int dtype, int backward) {
+  const size_t e = esz(dtype);
+  size_t bytes = 2 * arena_bytes<char>(e * (size_t)max_pingpong(D, B, backward));
+  if (backward) {
+    for (int k = 1; k < D.d; ++k) bytes += arena_bytes<char>(e * (size_t)fwd_elems(D, B, k));
+    long long mc = 1;
+    for (int k = 0; k < D.d; ++k) mc = core_cnt(D, k) > mc ? core_cnt(D, k) : mc;
+    bytes += arena_bytes<float>((size_t)kMaxGradWG * mc);
+  }
+  return bytes;
+}
+
+int ttm_forward(const TTMDims &D, const void *cores, const void *X, long long B, float *Y, int dtype, void *ws,
+                size_t bytes, hipStream_t st) {
+  Arena ar(ws, bytes);
+  const size_t pp = esz(dtype) * (size_t)max_pingpong(D, B, 0);
+  void *buf[2] = {ar.take<char>(pp), ar.take<char>(pp)};
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "tt_matmul: workspace too small");
+  timer_before(st);
+  const void *in = X;
+  for (int k = 0; k < D.d; ++k) {
+    const bool last = (k == D.d - 1);
+    const Step s = forward_step(D, cores, dtype, B, k, in, last ? (void *)Y : buf[k & 1]);
+    const int rc = launch_step(s, dtype, last ? 1 : 0, st);
+    if (rc) return rc;
+    in = s.out;
+  }
+  timer_after(st);
+  return TT_OK;
+}
+
+int ttm_backward(const TTMDims &D, const void *cores, const void *X, long long B, const void *dY, float *dX,
+                 float *dW, int dtype, void *ws, size_t bytes, hipStream_t st) {
+  const size_t e = esz(dtype);
+  const int d = D.d;
+  Arena ar(ws, bytes);
+  const size_t pp = e * (size_t)max_pingpong(D, B, 1);
+  void *buf[2] = {ar.take<char>(pp), ar.take<char>(pp)};
+  void *V[TT_MAX_D + 1] = {};  // V[k]: dY with cores k..d-1 contracted, k = 1..d-1
+  for (int k = 1; k < d; ++k) V[k] = ar.take<char>(e * (size_t)fwd_elems(D, B, k));
+  long long mc = 1;
+  for (int k = 0; k < d; ++k) mc = core_cnt(D, k) > mc ? core_cnt(D, k) : mc;
+  float *part = ar.take<float>((size_t)kMaxGradWG * mc);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "tt_matmul_backward: workspace too small");
+  const char *cb = (const char *)cores;
+  int rc;
+  timer_before(st);
+  // dX = dY W: contract (i_k, left bond), produce (j_k, right bond), left to right
+  if (dX) {
+    const void *in = dY;
+    for (int k = 0; k < d; ++k) {
+      const bool last = (k == d - 1);
+      Step s;
+      s.P = B * prod(D.n, 0, k);
+      s.Q = prod(D.m, k + 1, d);
+      s.nin = D.m[k];
+      s.rin = D.r[k];
+      s.mout = D.n[k];
+      s.rout = D.r[k + 1];
+      s.in = in;
+      s.out = last ? (void *)dX : buf[k & 1];
+      s.core = cb + e * D.off[k];
+      s.sa = (long long)D.m[k] * D.n[k] * D.r[k + 1];
+      s.sj = (long long)D.n[k] * D.r[k + 1];  // contracted i_k
+      s.si = D.r[k + 1];                      // produced j_k
+      s.sb = 1;
+      if ((rc = launch_step(s, dtype, last ? 1 : 0, st))) return rc;
+      in = s.out;
+    }
+  }
+  if (dW) {
+    // V_k from V_{k+1} (V_d = dY), k = d-1 .. 1.  V_{k+1} is laid out as
+    // [B prod m_<k][m_k][prod n_>k][r_{k+1}]; contracting (i_k, right bond)
+    // and producing (j_k, left bond) gives V_k as [B prod m_<k][n_k][prod n_>k][r_k].
+    for (int k = d - 1; k >= 1; --k) {
+      Step s;
+      s.P = B * prod(D.m, 0, k);
+      s.Q = prod(D.n, k + 1, d);
+      s.nin = D.m[k];
+      s.rin = D.r[k + 1];
+      s.mout = D.n[k];
+      s.rout = D.r[k];
+      s.in = (k == d - 1) ? dY : V[k + 1];
+      s.out = V[k];
+      s.core = cb + e * D.off[k];
+      s.sa = 1;                                        // right bond (contracted)
+      s.sj = (long long)D.n[k] * D.r[k + 1];           // i_k (contracted)
+      s.si = D.r[k + 1];                               // j_k (produced)
+      s.sb = (long long)D.m[k] * D.n[k] * D.r[k + 1];  // left bond (produced)
+      if ((rc = launch_step(s, dtype, 0, st))) return rc;
+    }
+    // forward sweep T_0 = X, T_{k+1} = step_k(T_k), with dG^k from T_k and V_{k+1}:
+    // T_k is [B prod m_<k][n_k][prod n_>k][r_k], V_{k+1} is [B prod m_<k][m_k][prod n_>k][r_{k+1}]
+    const void *T = X;
+    for (int k = 0; k < d; ++k) {
+      GradArgs g;
+      g.P = B * prod(D.m, 0, k);
+      g.Q = prod(D.n, k + 1, d);
+      g.n = D.n[k];
+      g.m = D.m[k];
+      g.rT = D.r[k];
+      g.rV = D.r[k + 1];
+      g.T = T;
+      g.V = (k == d - 1) ? dY : V[k + 1];
+      g.part = part;
+      const long long K = g.P * g.Q;
+      long long nwg = (K + 1023) / 1024;
+      nwg = nwg < 1 ? 1 : (nwg > kMaxGradWG ? kMaxGradWG : nwg);
+      g.kchunk = ((K + nwg - 1) / nwg + 3) / 4 * 4;
+      if (g.kchunk < 4) g.kchunk = 4;
+      nwg = (K + g.kchunk - 1) / g.kchunk;
+      if (nwg < 1) nwg = 1;
+      if (dtype)
+        hipLaunchKernelGGL(ttm_grad_kernel<1>, dim3((unsigned)nwg), dim3(kThreads), 0, st, g);
+      else
+        hipLaunchKernelGGL(ttm_grad_kernel<0>, dim3((unsigned)nwg), dim3(kThreads), 0, st, g);
+      if ((rc = launch_check("ttm core gradient"))) return rc;
+      const long long cnt = core_cnt(D, k);
+      hipLaunchKernelGGL(ttm_grad_reduce_kernel, dim3((unsigned)((cnt + 63) / 64)), dim3(256), 0, st,
+                         (const float *)part, (int)nwg, cnt, dW + D.off[k]);
+      if ((rc = launch_check("ttm gradient reduce"))) return rc;
+      if (k + 1 < d) {
+        const Step s = forward_step(D, cores, dtype, B, k, T, buf[k & 1]);
+        if ((rc = launch_step(s, dtype, 0, st))) return rc;
+        T = s.out;
+      }
+    }
+  }
+  timer_after(st);
+  return TT_OK;
+}
+
+}  // namespace ttgfx

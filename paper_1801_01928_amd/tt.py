@@ -336,3 +336,122 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+class TTMatrix:
+    """A TT-matrix (Implementation Details: the ``t3f.matmul`` layer) with
+    cores G^k of shape (r_k, m_k, n_k, r_{k+1}) packed in one flat buffer of
+    dtype float32 or bfloat16; W[(i_1..i_d), (j_1..j_d)] =
+    G^1[i_1, j_1] ... G^d[i_d, j_d] with C-ordered multi-indices."""
+
+    def __init__(self, row_modes, col_modes, ranks, data):
+        self.ms = [int(x) for x in row_modes]
+        self.ns = [int(x) for x in col_modes]
+        self.ranks = [int(x) for x in ranks]
+        d = len(self.ms)
+        if len(self.ns) != d or len(self.ranks) != d + 1:
+            raise ValueError("row modes, column modes and ranks disagree in length")
+        self.sizes = [self.ranks[k] * self.ms[k] * self.ns[k] * self.ranks[k + 1] for k in range(d)]
+        self.offs = [0]
+        for s in self.sizes:
+            self.offs.append(self.offs[-1] + s)
+        if data.dtype not in (torch.float32, torch.bfloat16) or data.dim() != 1 \
+                or data.numel() != self.offs[-1] or not data.is_contiguous():
+            raise ValueError("data must be a contiguous float32 or bfloat16 vector of %d elements" % self.offs[-1])
+        self.data = data
+        self._desc = None
+
+    @property
+    def d(self):
+        return len(self.ms)
+
+    @property
+    def dtype_code(self):
+        return 1 if self.data.dtype == torch.bfloat16 else 0
+
+    @classmethod
+    def from_cores(cls, cores, dtype=torch.float32, device="cuda"):
+        cores = [torch.as_tensor(np.asarray(c, dtype=np.float32)) if not torch.is_tensor(c) else c for c in cores]
+        ranks = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
+        flat = torch.cat([c.to(torch.float32).reshape(-1) for c in cores]).to(dtype)
+        return cls([c.shape[1] for c in cores], [c.shape[2] for c in cores], ranks,
+                   flat.to(device).contiguous())
+
+    def core(self, k):
+        return self.data[self.offs[k]:self.offs[k + 1]].view(self.ranks[k], self.ms[k], self.ns[k],
+                                                             self.ranks[k + 1])
+
+    def numpy_cores(self):
+        return [self.core(k).float().cpu().numpy() for k in range(self.d)]
+
+    def desc(self):
+        if self._desc is None or self._desc.data != self.data.data_ptr():
+            d = self.d
+            self._m = (C.c_int32 * d)(*self.ms)
+            self._n = (C.c_int32 * d)(*self.ns)
+            self._r = (C.c_int32 * (d + 1))(*self.ranks)
+            self._desc = L.tt_matrix(d, self._m, self._n, self._r, None, self.data.data_ptr())
+        return self._desc
+
+
+def _ttm_input(W, X, cols):
+    want = torch.bfloat16 if W.dtype_code else torch.float32
+    if X.dtype != want or X.dim() != 2 or X.shape[1] != cols or not X.is_contiguous():
+        raise ValueError("expected a contiguous %s matrix with %d columns" % (want, cols))
+    return X
+
+
+def ttm_matmul(W, X):
+    """Y = X W^T (float32) for a batch of rows X (B x prod n), X in W's dtype."""
+    lib = L.load()
+    Nt, Mt = int(np.prod(W.ns)), int(np.prod(W.ms))
+    X = _ttm_input(W, X, Nt)
+    B = X.shape[0]
+    Y = torch.empty((B, Mt), dtype=torch.float32, device=X.device)
+    # the forward needs a subset of the backward's workspace
+    ws, n = _workspace(L.check(lib.tt_matmul_workspace(C.byref(W.desc()), B, W.dtype_code)), X.device)
+    L.check(lib.tt_matmul(C.byref(W.desc()), _ptr(X), B, _ptr(Y), W.dtype_code, _ptr(ws), n,
+                          _stream(X.device)))
+    return Y
+
+
+def ttm_matmul_backward(W, X, dY, want_dx=True, want_dw=True):
+    """Adjoint of ``ttm_matmul``: dX = dY W (float32) and the core gradients
+    of <dY, X W^T> as a flat float32 vector in W's packed layout."""
+    lib = L.load()
+    Nt, Mt = int(np.prod(W.ns)), int(np.prod(W.ms))
+    dY = _ttm_input(W, dY, Mt)
+    B = dY.shape[0]
+    if want_dw:
+        X = _ttm_input(W, X, Nt)
+    dX = torch.empty((B, Nt), dtype=torch.float32, device=dY.device) if want_dx else None
+    dW = torch.empty(W.offs[-1], dtype=torch.float32, device=dY.device) if want_dw else None
+    ws, n = _workspace(L.check(lib.tt_matmul_workspace(C.byref(W.desc()), B, W.dtype_code)), dY.device)
+    L.check(lib.tt_matmul_backward(C.byref(W.desc()), _ptr(X if want_dw else None), B, _ptr(dY), _ptr(dX),
+                                   _ptr(dW), W.dtype_code, _ptr(ws), n, _stream(dY.device)))
+    return dX, dW
+
+
+class _TTLinearFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, flat, ms, ns, ranks):
+        W = TTMatrix(ms, ns, ranks, flat.detach())
+        ctx.save_for_backward(x.detach(), flat.detach())
+        ctx.meta = (ms, ns, ranks)
+        return ttm_matmul(W, x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, flat = ctx.saved_tensors
+        ms, ns, ranks = ctx.meta
+        W = TTMatrix(ms, ns, ranks, flat)
+        gy = gy.to(flat.dtype).contiguous()
+        dX, dW = ttm_matmul_backward(W, x, gy, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return (dX.to(x.dtype) if dX is not None else None,
+                dW.to(flat.dtype) if dW is not None else None, None, None, None)
+
+
+def tt_linear(x, W):
+    """Differentiable y = x W^T through the hand-written TT-matrix kernels;
+    gradients flow to ``x`` and ``W.data``."""
+    return _TTLinearFn.apply(x, W.data, tuple(W.ms), tuple(W.ns), tuple(W.ranks))

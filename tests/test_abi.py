@@ -76,3 +76,42 @@ def test_validation_errors_before_device(lib):
     assert lib.tt_gather_backward(C.byref(X), C.c_void_p(0x10), 5, C.c_void_p(0x10), C.byref(X),
                                   C.c_void_p(0x10), ws - 1, None) == L.TT_ERR_WORKSPACE
     assert "workspace" in L.last_error()
+
+
+def _mdesc(ms, ns, ranks, data=0x1000):
+    from paper_1801_01928_amd._lib import tt_matrix
+    d = len(ms)
+    m = (C.c_int32 * d)(*ms)
+    n = (C.c_int32 * d)(*ns)
+    r = (C.c_int32 * (d + 1))(*ranks)
+    t = tt_matrix(d, m, n, r, None, data)
+    t._keep = (m, n, r)
+    return t
+
+
+def test_matmul_validation_before_device(lib):
+    from paper_1801_01928_amd import _lib as L
+    W = _mdesc([4, 4], [4, 4], [1, 8, 1])
+    assert lib.tt_matmul_workspace(C.byref(W), 16, 0) > 0
+    # bf16 intermediates need half the bytes of float32 ones (plus fixed parts)
+    assert lib.tt_matmul_workspace(C.byref(W), 4096, 1) < lib.tt_matmul_workspace(C.byref(W), 4096, 0)
+    assert lib.tt_matmul_workspace(C.byref(W), 16, 2) == L.TT_ERR_ARG
+    assert lib.tt_matmul_workspace(C.byref(W), -1, 0) == L.TT_ERR_ARG
+    # a mode size times a rank above the fused step limit of 128
+    big = _mdesc([8, 4], [4, 4], [1, 32, 1])
+    assert lib.tt_matmul_workspace(C.byref(big), 16, 0) == L.TT_ERR_UNSUPPORTED
+    assert "128" in L.last_error()
+    bad = _mdesc([4, 4], [4, 4], [2, 8, 1])
+    assert lib.tt_matmul(C.byref(bad), C.c_void_p(0x10), 4, C.c_void_p(0x10), 0, None, 0, None) == L.TT_ERR_SHAPE
+    nul = _mdesc([4, 4], [4, 4], [1, 8, 1], data=0)
+    assert lib.tt_matmul(C.byref(nul), C.c_void_p(0x10), 4, C.c_void_p(0x10), 0, None, 0, None) == L.TT_ERR_ARG
+    # null X with a non-empty batch, and an empty batch (no device work)
+    assert lib.tt_matmul(C.byref(W), None, 4, C.c_void_p(0x10), 0, None, 0, None) == L.TT_ERR_ARG
+    assert lib.tt_matmul(C.byref(W), None, 0, None, 0, None, 0, None) == L.TT_OK
+    # workspace too small
+    assert lib.tt_matmul(C.byref(W), C.c_void_p(0x10), 4, C.c_void_p(0x10), 0, C.c_void_p(0x10), 8,
+                         None) == L.TT_ERR_WORKSPACE
+    assert lib.tt_matmul_backward(C.byref(W), C.c_void_p(0x10), 4, None, C.c_void_p(0x10), None, 0,
+                                  C.c_void_p(0x10), 1 << 30, None) == L.TT_ERR_ARG
+    # nothing requested: success without device work
+    assert lib.tt_matmul_backward(C.byref(W), None, 4, None, None, None, 0, None, 0, None) == L.TT_OK
