@@ -12,7 +12,7 @@ struct MfTraits;
 template <>
 struct MfTraits<16> {
   static constexpr int T = 1024;
-  static constexpr int THREADS = 512;
+  static constexpr int THREADS = 768;
   static constexpr int MAX_N = 16;
   static constexpr int PERM_CAP = 16384;
 };

@@ -103,7 +103,7 @@ struct Lds {
 // right sweep, residual, left sweep.  `accg` is the workgroup accumulator
 // (SLAB), `loss_part` collects this thread's squared residuals (MSE).
 template <int R, int T, int NTHR, int MODE, int ACC>
-__device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, float *stash, int nb_max,
+__device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *smem, float *stash, int nb_max,
                          float *accg, bool first_tile, float &loss_part) {
   constexpr int NT = R / 16;      // comp tiles
   constexpr int W = NTHR / 64;    // waves
@@ -112,6 +112,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
   constexpr int G = (R == 16) ? 4 : 2;  // blocks per group
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
+  constexpr bool PF = (R == 16);  // prefetch the next group (register budget allows it at R = 16)
   using L = Lds<R, T, NTHR, ACC>;
   float *rows = (float *)(smem + L::rows);
   float *slab = (float *)(smem + L::slab);
@@ -124,7 +125,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
   int *nblk = (int *)(smem + L::nblk);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c16 = lane & 15;
   const int q4 = lane >> 4;
   const int d = p.d;
@@ -140,102 +141,166 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
   if (tid == 0) wsum[ZROW] = 0.f;
 
   // ---------------------------------------------------------------- sort
-  // Wave w sorts modes w, w + W, ...: a stable counting sort of the tile's
-  // entries by slice index (ballot ranks, shuffle scans), groups padded to
-  // multiples of 16 entries.
-  for (int k = wave; k < d; k += W) {
-    constexpr int CH = T / 64;  // entries per lane
-    const int nk = p.n[k];
-    // per chunk: slice index + 1 in the low 8 bits (0 = no entry), rank above
-    int st[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int e = 64 * c + lane;
-      const int v = (e < cnt) ? p.idx[(long long)k * M + e0 + e] : -1;
-      st[c] = (v >= 0 && v < nk) ? v + 1 : 0;  // out-of-range indices are dropped
-    }
+  // Stable counting sort of the tile's entries by slice index, every mode,
+  // in three phases separated by barriers (scratch in the rows area, which
+  // is free until the right sweep):
+  //  1. wave w ranks the entries of its chunks (64 entries each) within the
+  //     chunk by bit-plane ballots and records, per chunk, how many entries
+  //     use each slice;
+  //  2. one wave per mode turns the counts into offsets (groups padded to
+  //     multiples of 16 entries; padding entries point at the zero row,
+  //     so the sweeps read zeros for them without a test) and fills the
+  //     block -> slice table;
+  //  3. every entry is written to its place.
+  // The order inside a slice group is the entry order, as before.
+  {
+    constexpr int CHUNKS = T / 64;
+    constexpr int CPW = (CHUNKS + W - 1) / W;             // chunks per wave (wave + W i)
+    constexpr int NSL = MfTraits<R>::MAX_N;               // slice values per count row
+    constexpr int NBITS = NSL <= 16 ? 4 : 5;
+    static_assert(sizeof(int) * MF_MAX_D * CHUNKS * NSL + 2 * MF_MAX_D * T <= sizeof(float) * T * RS,
+                  "sort scratch must fit the rows area");
+    int *cnt = (int *)rows;                                         // [d][CHUNKS][NSL]
+    uint16_t *key = (uint16_t *)(cnt + MF_MAX_D * CHUNKS * NSL);    // [d][T]: rank << 8 | slice
     const unsigned long long below = (1ull << lane) - 1ull;
-    int run = 0;  // lane v: entries of slice v in the chunks seen so far
+    // all index loads of the tile are issued before the first one is used
+    int iv[MF_MAX_D][CPW];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int sc = st[c] - 1;
-      unsigned long long mine = 0ull;
-      int add = 0;
-      for (int v = 0; v < nk; ++v) {
-        const unsigned long long m = __ballot(sc == v);
-        if (sc == v) mine = m;
-        if (lane == v) add = __popcll(m);
+    for (int k = 0; k < MF_MAX_D; ++k)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int e = 64 * (wave + W * c) + lane;
+        iv[k][c] = (k < d && wave + W * c < CHUNKS && e < cnt_valid) ? p.idx[(long long)k * M + e0 + e] : -1;
       }
-      const int rk = __shfl(run, sc >= 0 ? sc : 0) + __popcll(mine & below);
-      st[c] |= rk << 8;
-      run += add;
-    }
-    const int padded = (lane < nk) ? ((run + 15) & ~15) : 0;
-    int incl = padded;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(incl, off);
-      if (lane >= off) incl += t;
-    }
-    const int base = incl - padded;
-    uint16_t *pk = perm + pbase_of<T>(p, k);
+    for (int k = 0; k < MF_MAX_D; ++k) {
+      if (k >= d) break;
+      const int nk = p.n[k];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int sc = (st[c] & 255) - 1;
-      const int b = __shfl(base, sc >= 0 ? sc : 0);
-      if (sc >= 0) pk[b + (st[c] >> 8)] = (uint16_t)(64 * c + lane);
+      for (int c = 0; c < CPW; ++c) {
+        const int ch = wave + W * c;
+        if (ch >= CHUNKS) break;
+        const int v = iv[k][c];
+        const bool ok = v >= 0 && v < nk;  // out-of-range indices are dropped
+        // m: lanes of this chunk whose entry uses the same slice
+        unsigned long long m = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < NBITS; ++bit) {
+          const unsigned long long bb = __ballot(ok && ((v >> bit) & 1));
+          m &= ((v >> bit) & 1) ? bb : ~bb;
+        }
+        const int rk = __popcll(m & below);
+        key[k * T + 64 * ch + lane] = ok ? (uint16_t)((rk << 8) | v) : kNone;
+        // the count row of a chunk belongs to one wave: zero it, then the
+        // last lane of each slice value writes that value's count
+        int *crow = cnt + (k * CHUNKS + ch) * NSL;
+        if (lane < NSL) crow[lane] = 0;
+        if (ok && (m >> lane) == 1ull) crow[v] = rk + 1;
+      }
     }
-    if (lane < nk) {
-      for (int j = run; j < padded; ++j) pk[base + j] = kNone;
-      uint8_t *bk = bslc + bbase_of<T>(p, k) + base / 16;
-      for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
+    lds_barrier();
+    for (int k = wave; k < d; k += W) {
+      const int nk = p.n[k];
+      int c[CHUNKS];
+      int run = 0;
+#pragma unroll
+      for (int ch = 0; ch < CHUNKS; ++ch) {
+        c[ch] = (lane < nk) ? cnt[(k * CHUNKS + ch) * NSL + lane] : 0;
+        run += c[ch];
+      }
+      const int padded = (lane < nk) ? ((run + 15) & ~15) : 0;
+      int incl = padded;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      const int base = incl - padded;
+      if (lane < nk) {
+        int o = base;
+#pragma unroll
+        for (int ch = 0; ch < CHUNKS; ++ch) {
+          cnt[(k * CHUNKS + ch) * NSL + lane] = o;
+          o += c[ch];
+        }
+        uint16_t *pk = perm + pbase_of<T>(p, k);
+        for (int j = run; j < padded; ++j) pk[base + j] = (uint16_t)ZROW;
+        uint8_t *bk = bslc + bbase_of<T>(p, k) + base / 16;
+        for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
+      }
+      if (lane == 63) nblk[k] = incl / 16;
     }
-    if (lane == 63) nblk[k] = incl / 16;
+    lds_barrier();
+    for (int k = 0; k < d; ++k) {
+      uint16_t *pk = perm + pbase_of<T>(p, k);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int ch = wave + W * c;
+        if (ch >= CHUNKS) break;
+        const int kv = key[k * T + 64 * ch + lane];
+        if (kv != kNone) pk[cnt[(k * CHUNKS + ch) * NSL + (kv & 255)] + (kv >> 8)] = (uint16_t)(64 * ch + lane);
+      }
+    }
   }
   lds_barrier();
 
   // --------------------------------------------------------- right sweep
-  // Each wave walks its blocks of mode k in groups of G: the LDS reads of a
-  // group are issued together and its MFMA chains are independent, so the
-  // matrix pipe is fed back to back.  Padding columns read the zero row.
+  // Each wave walks its blocks of mode k in groups of G; the MFMA chains of
+  // a group are independent, so the matrix pipe is fed back to back.  Loop
+  // bounds and slice ids are wave-uniform (scalar registers): the loop has
+  // no divergent branches and the LDS reads of a group issue together.
+  // Blocks past the wave's range re-read its last block and their results
+  // are discarded.  Padding columns read the zero row.
   for (int k = d - 1; k >= 0; --k) {
-    const int nb = nblk[k];
+    const int nb = __builtin_amdgcn_readfirstlane(nblk[k]);
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
     const uint16_t *pk = perm + pbase_of<T>(p, k);
     const uint8_t *bk = bslc + bbase_of<T>(p, k);
     const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
-    for (int j0 = jb; j0 < je; j0 += G) {
-      int ent[G], ev[G][4];
-      bool act[G];
-      v4f a[G][NT * NT];
+    const int mysl = (lane < je - jb) ? bk[jb + lane] : 0;  // slice of block jb + lane
+    const bool last = (k == d - 1);
+    // the slices of the next group are loaded while this group computes
+    v4f an[G][NT * NT];
+    auto load_slices = [&](int jn) {
 #pragma unroll
       for (int b = 0; b < G; ++b) {
-        const int j = j0 + b;
-        act[b] = j < je;
-        ent[b] = ZROW;
+        const int j = jn + b;
+        if (j < je) {
+          const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, j - jb) * R * R;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
-        if (act[b]) {
-          const int e = pk[16 * j + c16];
-          ent[b] = (e == kNone) ? ZROW : e;
-          const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-          const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
-#pragma unroll
-          for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
-          const float *gs = gk + (long long)bk[j] * R * R;
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+          for (int x = 0; x < NT * NT; ++x) an[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
         } else {
 #pragma unroll
-          for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+          for (int x = 0; x < NT * NT; ++x) an[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
         }
+      }
+    };
+    if (PF && jb < je) load_slices(jb);
+    for (int j0 = jb; j0 < je; j0 += G) {
+      if (!PF) load_slices(j0);
+      v4f a[G][NT * NT];
+#pragma unroll
+      for (int b = 0; b < G; ++b)
+#pragma unroll
+        for (int x = 0; x < NT * NT; ++x) a[b][x] = an[b][x];
+      if (PF && j0 + G < je) load_slices(j0 + G);
+      int ent[G], ev[G][4];
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        const int j = (j0 + b < je) ? j0 + b : je - 1;
+        ent[b] = pk[16 * j + c16];
+        const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+        ev[b][0] = (int)(q.x & 0xFFFF);
+        ev[b][1] = (int)(q.x >> 16);
+        ev[b][2] = (int)(q.y & 0xFFFF);
+        ev[b][3] = (int)(q.y >> 16);
       }
       v4f bv[G][NT];
 #pragma unroll
       for (int b = 0; b < G; ++b) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          if (k == d - 1)
+          if (last)
             bv[b][t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
           else
             bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
@@ -250,7 +315,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
           for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[b][v] * RS + 16 * t + c16];
-          if (act[b]) {
+          if (j0 + b < je) {
             float *st = stash + ((long long)k * nb_max + j0 + b) * (64 * R / 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = cl[t];
@@ -273,9 +338,11 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
               out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
 #pragma unroll
       for (int b = 0; b < G; ++b) {
-        if (!act[b]) continue;
+        if (j0 + b >= je) continue;
         if (k > 0) {
-          const int w = (ent[b] == ZROW) ? SROW : ent[b];
+          // a padding column is zero (zero row in, zero out) except in the
+          // first step, where the input is e_0: that one goes to the sink row
+          const int w = (last && ent[b] == ZROW) ? SROW : ent[b];
 #pragma unroll
           for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
         } else if (q4 == 0 && ent[b] != ZROW) {
@@ -287,7 +354,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
   }
 
   // ------------------------------------------------------------ residual
-  for (int e = tid; e < cnt; e += NTHR) {
+  for (int e = tid; e < cnt_valid; e += NTHR) {
     const float yv = wsum[e];
     if (p.y) p.y[e0 + e] = yv;
     float w = 0.f;
@@ -305,10 +372,14 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
     lds_barrier();
     return;
   }
-  // lambda_1 = e_0 for every entry (and the zero row stays zero)
+  // lambda_1 = w_e e_0 for every entry: the left chain is linear in
+  // lambda_1, so every lambda_k carries the entry's weight and the outer
+  // products need no extra scaling (the zero row stays zero; the thread
+  // that wrote wsum[e] above reads it here)
   for (int e = tid; e < T; e += NTHR) {
+    const float w0 = (e < cnt_valid) ? wsum[e] : 0.f;
 #pragma unroll
-    for (int c = 0; c < R; ++c) rows[e * RS + c] = (c == 0) ? 1.f : 0.f;
+    for (int c = 0; c < R; ++c) rows[e * RS + c] = (c == 0) ? w0 : 0.f;
   }
   lds_barrier();
 
@@ -325,13 +396,15 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
       if (lane == 0) eslice[wave] = -1;
       lds_barrier();
     }
-    const int nb = nblk[k];
+    const int nb = __builtin_amdgcn_readfirstlane(nblk[k]);
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
     const uint16_t *pk = perm + pbase_of<T>(p, k);
     const uint8_t *bk = bslc + bbase_of<T>(p, k);
     const float *gk = p.gp_left + (long long)p.sbase[k] * R * R;
     const bool chain = k < d - 1;
-    const bool cont_first = (jb < je) && jb > 0 && bk[jb - 1] == bk[jb];
+    const int mysl = (lane < je - jb) ? bk[jb + lane] : 0;  // slice of block jb + lane
+    const int prev_sl = __builtin_amdgcn_readfirstlane(jb > 0 ? (int)bk[jb - 1] : -1);
+    const bool cont_first = (jb < je) && prev_sl == __builtin_amdgcn_readfirstlane(mysl);
     bool first_run = true;
     int rsid = -1;
     v4f racc[NT * NT];
@@ -362,56 +435,70 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
               unsafeAtomicAdd(dst + (16 * ta + 4 * q4 + v) * R + 16 * tb + c16, racc[ta * NT + tb][v]);
       }
     };
+    // stashed right partials and slices of the next group are loaded while
+    // this group computes
+    v4f an[G][NT * NT];
+    v4f rn[G][NT];
+    auto load_group = [&](int jn) {
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        const int j = jn + b;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
+          rn[b][t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+        }
+#pragma unroll
+        for (int x = 0; x < NT * NT; ++x) an[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (j < je) {
+          if (k <= d - 2) {
+            const float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) rn[b][t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+          }
+          if (chain) {
+            const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, j - jb) * R * R;
+#pragma unroll
+            for (int x = 0; x < NT * NT; ++x) an[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+          }
+        }
+      }
+    };
+    if (PF && jb < je) load_group(jb);
     for (int j0 = jb; j0 < je; j0 += G) {
       int ent[G], ev[G][4], sid[G];
       bool act[G];
       v4f a[G][NT * NT];
       v4f rcl[G][NT];
+      if (!PF) load_group(j0);
 #pragma unroll
       for (int b = 0; b < G; ++b) {
-        const int j = j0 + b;
-        act[b] = j < je;
-        ent[b] = ZROW;
-        sid[b] = -1;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ev[b][v] = ZROW;
+        for (int x = 0; x < NT * NT; ++x) a[b][x] = an[b][x];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
-          rcl[b][t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
-        }
-#pragma unroll
-        for (int x = 0; x < NT * NT; ++x) a[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
-        if (act[b]) {
-          const int e = pk[16 * j + c16];
-          ent[b] = (e == kNone) ? ZROW : e;
-          const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-          const int e4[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
-#pragma unroll
-          for (int v = 0; v < 4; ++v) ev[b][v] = (e4[v] == kNone) ? ZROW : e4[v];
-          sid[b] = bk[j];
-          if (k <= d - 2) {
-            const float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) rcl[b][t] = *(const v4f *)(st + (t * 64 + lane) * 4);
-          }
-          if (chain) {
-            const float *gs = gk + (long long)sid[b] * R * R;
-#pragma unroll
-            for (int x = 0; x < NT * NT; ++x) a[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-          }
-        }
+        for (int t = 0; t < NT; ++t) rcl[b][t] = rn[b][t];
       }
-      // lambda_k: CL (weighted, A operand of the outer product) and EL (chain)
+      if (PF && j0 + G < je) load_group(j0 + G);
+#pragma unroll
+      for (int b = 0; b < G; ++b) {
+        act[b] = j0 + b < je;
+        const int j = act[b] ? j0 + b : je - 1;
+        sid[b] = act[b] ? __builtin_amdgcn_readlane(mysl, j - jb) : -1;
+        ent[b] = pk[16 * j + c16];
+        const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+        ev[b][0] = (int)(q.x & 0xFFFF);
+        ev[b][1] = (int)(q.x >> 16);
+        ev[b][2] = (int)(q.y & 0xFFFF);
+        ev[b][3] = (int)(q.y >> 16);
+      }
+      // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
       v4f lcl[G][NT], bv[G][NT];
 #pragma unroll
       for (int b = 0; b < G; ++b) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float wv = wsum[ev[b][v]];
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-          for (int t = 0; t < NT; ++t) lcl[b][t][v] = wv * rows[ev[b][v] * RS + 16 * t + c16];
-        }
+          for (int t = 0; t < NT; ++t) lcl[b][t][v] = rows[ev[b][v] * RS + 16 * t + c16];
 #pragma unroll
         for (int t = 0; t < NT; ++t) bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
       }
@@ -449,9 +536,9 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
 #pragma unroll
         for (int b = 0; b < G; ++b) {
           if (!act[b]) continue;
-          const int w = (ent[b] == ZROW) ? SROW : ent[b];
+          // a padding column reads the zero row and writes zeros back to it
 #pragma unroll
-          for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
+          for (int t = 0; t < NT; ++t) *(v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4) = out[b][t];
         }
       }
       // merge the group's outer products into runs
@@ -475,19 +562,28 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt, char *smem, flo
     if (rsid >= 0) emit_run(rsid, first_run && cont_first);
     lds_barrier();
     if constexpr (ACC == ACC_SLAB) {
-      // flush this mode into the workgroup's accumulator without waiting: a
-      // plain store on the first tile, no-return atomics after
+      // flush this mode into the workgroup's accumulator: a plain store on
+      // the first tile, a load-add-store after (4 floats per thread and
+      // step; edge owners read once).  The same thread owns the same
+      // accumulator elements on every tile, so no synchronisation is needed,
+      // and no atomics sit in the in-order memory counter that later loads
+      // of this wave wait on.
       float *ak = accg + (long long)p.sbase[k] * R * R;
-      for (int e = tid; e < nk * R * R; e += NTHR) {
+      int es[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) es[w] = eslice[w];
+      for (int e4 = tid; e4 < nk * R * R / 4; e4 += NTHR) {
+        const int e = 4 * e4;
         const int sl = e / (R * R), a = (e / R) % R, b = e % R;
-        float v = 0.f;
+        v4f v = {0.f, 0.f, 0.f, 0.f};
         if (sflag[sl]) {
-          v = slab[sl * R * SS + a * SS + b];
+          v = *(const v4f *)(slab + sl * R * SS + a * SS + b);
+#pragma unroll
           for (int w = 0; w < W; ++w)
-            if (eslice[w] == sl) v += edges[w * R * SS + a * SS + b];
+            if (es[w] == sl) v += *(const v4f *)(edges + w * R * SS + a * SS + b);
         }
-        if (first_tile) ak[e] = v;
-        else unsafeAtomicAdd(ak + e, v);
+        if (!first_tile) v += *(const v4f *)(ak + e);
+        *(v4f *)(ak + e) = v;
       }
       lds_barrier();
     }
@@ -522,14 +618,15 @@ __global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(MfInst p, G
   if (MODE == MODE_MSE) {
     // deterministic block reduction of the squared residuals
     float *red = (float *)smem;
+    for (int off = 32; off > 0; off >>= 1) loss_part += __shfl_xor(loss_part, off);
     __syncthreads();
-    red[threadIdx.x] = loss_part;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss_part;
     __syncthreads();
-    for (int st = NTHR / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
+    if (threadIdx.x == 0) {
+      float v = 0.f;
+      for (int w = 0; w < NTHR / 64; ++w) v += red[w];
+      g.loss_acc[blockIdx.x] = v;
     }
-    if (threadIdx.x == 0) g.loss_acc[blockIdx.x] = red[0];
   }
 }
 
