@@ -109,7 +109,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   constexpr int W = NTHR / 64;    // waves
   constexpr int RS = R + 4;       // LDS row stride (padding spreads banks)
   constexpr int SS = R + 4;       // slab/edge row stride (conflict-free D stores)
-  constexpr int G = (R == 16) ? 4 : 2;  // blocks per group
+  constexpr int G = (R == 16) ? 1 : 2;  // blocks per group (one block per step measured fastest at R = 16)
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
   constexpr bool PF = (R == 16);  // prefetch the next group (register budget allows it at R = 16)
