@@ -45,6 +45,8 @@ def parse():
                     help="observed entries the oracle processes for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary measurements (batched plan, Riemannian step, Gram, TT-matrix)")
     return ap.parse_args()
 
 
@@ -103,6 +105,122 @@ def cpu_baseline(p, t, sample):
     return {"value": S / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
             "sample": "first %d of the %d observed entries (gather + MSE + adjoint, float64, %.1f s)"
                       % (S, p.M, dt)}
+
+
+def _event_ms(fn, reps, stream=None):
+    """Average milliseconds of fn() over reps calls, HIP events on the stream."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_leg(tt, W, reps=3):
+    """256 TT tensors (d=8, n=16, ranks from {4,8,16,32}, lognormal entry
+    counts): one graph-captured persistent launch of gather + MSE + adjoint
+    against per-tensor launches of the same kernels."""
+    import numpy as np
+    import torch
+    inst = W.batched()
+    Xs = [tt.TT.from_cores(p.cores) for p in inst]
+    M = sum(p.M for p in inst)
+    ts = []
+    for p in inst:  # targets: planted TT gathered on the device, plus noise
+        planted = tt.TT.from_cores(p.planted)
+        ts.append(tt.gather(planted, p.idx) + torch.from_numpy(p.noise).cuda())
+    t = torch.cat(ts)
+    idx = np.concatenate([p.idx.reshape(-1) for p in inst])
+    off = np.concatenate([[0], np.cumsum([p.M for p in inst])])
+    plan = tt.BatchedPlan(Xs, idx, t, off)
+    s = torch.cuda.Stream()
+    chunk = plan.autotune(s)
+    plan.capture(s)
+    plan.run(s)
+    s.synchronize()
+    graph_ms = _event_ms(lambda: plan.run(s), reps, s)
+    plan.run_plain(s)
+    s.synchronize()
+    plain_ms = _event_ms(lambda: plan.run_plain(s), reps, s)
+    plan.close()
+    return {"workload": "256 TT tensors d=8 n=16, ranks U{4,8,16,32}, lognormal(ln 5e4, 0.8) entries "
+                        "clipped to [1e4, 2e5], planted targets",
+            "entries": int(M), "autotuned_chunk": chunk,
+            "graph_ms": round(graph_ms, 3), "plain_ms": round(plain_ms, 3),
+            "graph_entries_per_s": round(M / (graph_ms * 1e-3), 1),
+            "plain_entries_per_s": round(M / (plain_ms * 1e-3), 1),
+            "speedup": round(plain_ms / graph_ms, 3)}
+
+
+def gram_leg(tt, W, reps=3):
+    """256 x 256 Gram matrix of the batched workload's tensors, ranks padded
+    to 32 (12.65 MFLOP per pair, 32,896 unordered pairs)."""
+    import torch
+    Xs = [tt.TT.from_cores(p.cores) for p in W.batched()]
+    tt.gram(Xs)
+    torch.cuda.synchronize()
+    with tt.KernelTimer() as kt:
+        for _ in range(reps):
+            tt.gram(Xs)
+        torch.cuda.synchronize()
+    ms = kt.ms / max(kt.launches, 1)
+    flop = 416.1e9
+    return {"kernel_ms": round(ms, 3), "tflops": round(flop / (ms * 1e-3) / 1e12, 2),
+            "frac_of_fp32_mfma": round(flop / (ms * 1e-3) / 1e12 / PEAK_MFMA_F32_TFLOPS, 4)}
+
+
+def riemann_leg(tt, W, reps=3):
+    """One Riemannian step on d=10, n=10, r=32 (canonical ranks) with 2^20
+    observed N(0,1) gradient values: both QR sweeps, the sparse tangent
+    projection with assembly, and TT rounding back to rank 32."""
+    import torch
+    p = W.riemann_d10()
+    X = tt.TT.from_cores(p.cores)
+    idx = torch.from_numpy(p.idx).cuda()
+    z = torch.from_numpy(p.values).cuda()
+    U = tt.orthogonalize(X, tt.TT_LR)
+    V = tt.orthogonalize(X, tt.TT_RL)
+    Wt = tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1)
+    tt.round_tt(Wt, 32)
+    torch.cuda.synchronize()
+    orth_ms = _event_ms(lambda: (tt.orthogonalize(X, tt.TT_LR), tt.orthogonalize(X, tt.TT_RL)), reps)
+    proj_ms = _event_ms(lambda: tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1), reps)
+    round_ms = _event_ms(lambda: tt.round_tt(Wt, 32), reps)
+    return {"workload": "d=10 n=10 r=32 (canonical), 2^20 entries", "orthogonalize_both_ms": round(orth_ms, 3),
+            "project_sparse_ms": round(proj_ms, 3),
+            "project_entries_per_s": round(p.M / (proj_ms * 1e-3), 1),
+            "round_ms": round(round_ms, 3), "step_ms": round(orth_ms + proj_ms + round_ms, 3)}
+
+
+def ttm_leg(tt, W, reps=3):
+    """TT-matrix layer 1024 x 1024 (modes 4^5, r=32) on a batch of 4096 rows:
+    forward and adjoint, float32 and bf16 (float32 accumulation)."""
+    import numpy as np
+    import torch
+    p = W.ttm_layer()
+    ms_, ns_, rk, B = p.row_modes, p.col_modes, p.ranks, p.X.shape[0]
+    fwd_flop = sum(2.0 * B * np.prod(ms_[:k]) * np.prod(ns_[k + 1:]) * ns_[k] * rk[k] * ms_[k] * rk[k + 1]
+                   for k in range(len(ms_)))
+    out = {"workload": "Y = X W^T, W 1024x1024 TT-matrix d=5 modes 4x4 r=32, batch 4096",
+           "chain_fwd_gflop": round(fwd_flop / 1e9, 2)}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        Wm = tt.TTMatrix.from_cores([torch.as_tensor(c).to(dt) for c in p.cores], dtype=dt)
+        X = torch.as_tensor(p.X).to(dt).cuda()
+        dY = torch.as_tensor(p.dY).to(dt).cuda()
+        tt.ttm_matmul(Wm, X)
+        tt.ttm_matmul_backward(Wm, X, dY)
+        torch.cuda.synchronize()
+        f = _event_ms(lambda: tt.ttm_matmul(Wm, X), reps)
+        b = _event_ms(lambda: tt.ttm_matmul_backward(Wm, X, dY), reps)
+        out[name] = {"fwd_ms": round(f, 3), "bwd_ms": round(b, 3),
+                     "fwd_chain_tflops": round(fwd_flop / (f * 1e-3) / 1e12, 2)}
+    return out
 
 
 def main():
@@ -171,6 +289,12 @@ def main():
                       "d": 10, "n": 10, "r": 16, "M": p.M, "global_batch": p.M},
            "roofline": roofline,
            "loss": float(loss.item())}
+    if not args.no_extras:
+        # secondary measurements, each on its own workload after the timed region
+        out["batched_vs_plain"] = batched_leg(tt, W)
+        out["gram"] = gram_leg(tt, W)
+        out["riemann_step"] = riemann_leg(tt, W)
+        out["ttm_layer"] = ttm_leg(tt, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, t.cpu().numpy(), args.cpu_sample)
     print(json.dumps(out), flush=True)
