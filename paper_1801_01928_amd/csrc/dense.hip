@@ -34,9 +34,25 @@ struct Shared {
   int rotated;
 };
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the 64 lanes (all lanes active), returned wave-uniform: DPP
+// butterflies inside each row of 16 (quad swaps, half-row and row
+// mirrors), then the four row sums read as scalars.  VALU only, no LDS
+// round trips.
 __device__ __forceinline__ float wave_sum(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 // Sum over the block; every thread gets the result.
@@ -57,6 +73,7 @@ __device__ void blk_gemm(int M, int N, int K, const float *A, long ar, long ac, 
   for (long e = threadIdx.x; e < (long)M * N; e += kThreads) {
     const int i = (int)(e / N), j = (int)(e % N);
     float s = 0.f;
+    #pragma unroll 8
     for (int k = 0; k < K; ++k) s = fmaf(A[i * ar + k * ac], B[k * br + j * bc], s);
     C[i * cr + j * cc] = s;
   }
@@ -71,6 +88,7 @@ __device__ void blk_qr(float *W, int m, int c, float *tau, Shared &sh) {
   for (int j = 0; j < p; ++j) {
     float *col = W + (long)j * m;
     float part = 0.f;
+    #pragma unroll 8
     for (int i = j + 1 + threadIdx.x; i < m; i += kThreads) part = fmaf(col[i], col[i], part);
     const float sigma = block_sum(part, sh);
     if (threadIdx.x == 0) {
@@ -102,10 +120,12 @@ __device__ void blk_qr(float *W, int m, int c, float *tau, Shared &sh) {
     for (int l = j + 1 + wave; l < c; l += kWaves) {
       float *cl = W + (long)l * m;
       float s = 0.f;
+      #pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) s = fmaf(col[i], cl[i], s);
       s = wave_sum(s) + cl[j];
       const float w = beta * s;
       if (lane == 0) cl[j] -= w;
+      #pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) cl[i] = fmaf(-w, col[i], cl[i]);
     }
     if (threadIdx.x == 0) col[j] = sh.bval[2];
@@ -128,10 +148,12 @@ __device__ void blk_form_q(const float *W, int m, int c, const float *tau, float
     for (int l = j + wave; l < p; l += kWaves) {
       float *ql = Q + (long)l * m;
       float s = 0.f;
+      #pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) s = fmaf(v[i], ql[i], s);
       s = wave_sum(s) + ql[j];
       const float w = beta * s;
       if (lane == 0) ql[j] -= w;
+      #pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) ql[i] = fmaf(-w, v[i], ql[i]);
     }
     __syncthreads();
@@ -237,6 +259,7 @@ __device__ void sweep_lr(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
     for (long e = threadIdx.x; e < (long)p * nn; e += kThreads) {
       const int i = (int)(e / nn), j = (int)(e % nn);
       float s = 0.f;
+      #pragma unroll 8
       for (int l = i; l < c; ++l) s = fmaf(Wm[(long)l * m + i], Gn[(long)l * nn + j], s);
       Q[e] = s;
     }
@@ -271,6 +294,7 @@ __device__ void sweep_rl(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
       const int i = (int)(e / p), j = (int)(e % p);
       float s = 0.f;
       // L[l][j] = R[j][l], nonzero for l >= j
+      #pragma unroll 8
       for (int l = j; l < rows; ++l) s = fmaf(Gp[(long)i * rows + l], Wm[(long)l * mm + j], s);
       Q[e] = s;
     }
@@ -365,6 +389,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       const int i = (int)(e / keep), j = (int)(e % keep);
       const float *vj = sh.jv + sh.perm[j] * kJac;
       float s = 0.f;
+#pragma unroll 8
       for (int l = 0; l < p; ++l) s = fmaf(b.q[(long)l * m + i], vj[l], s);
       G[e] = s;
     }
@@ -402,6 +427,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       const int i = (int)(e / nn), j = (int)(e % nn);
       const float *bj = sh.jb + sh.perm[i] * kJac;
       float s = 0.f;
+#pragma unroll 8
       for (int l = 0; l < c; ++l) s = fmaf(bj[l], Gn[(long)l * nn + j], s);
       b.q[e] = sh.sig[i] * s;
     }
@@ -435,6 +461,7 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
     for (long e = threadIdx.x; e < (long)m * r1; e += kThreads) {
       const int i = (int)(e / r1), j = (int)(e % r1);
       float s = 0.f;
+#pragma unroll 8
       for (int l = 0; l < r1; ++l) s = fmaf(Uk[(long)i * r1 + l], C[l * r1 + j], s);
       dG[e] = Zk[e] - s;
     }
