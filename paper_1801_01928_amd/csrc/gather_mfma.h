@@ -19,7 +19,7 @@ struct MfTraits<16> {
 template <>
 struct MfTraits<32> {
   static constexpr int T = 512;
-  static constexpr int THREADS = 256;
+  static constexpr int THREADS = 512;
   static constexpr int MAX_N = 32;
   static constexpr int PERM_CAP = 16384;
 };

@@ -109,10 +109,10 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   constexpr int W = NTHR / 64;    // waves
   constexpr int RS = R + 4;       // LDS row stride (padding spreads banks)
   constexpr int SS = R + 4;       // slab/edge row stride (conflict-free D stores)
-  constexpr int G = (R == 16) ? 1 : 2;  // blocks per group (one block per step measured fastest at R = 16)
+  constexpr int G = 1;            // blocks per step (one measured fastest at R = 16 and 32)
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
-  constexpr bool PF = (R == 16);  // prefetch the next group (register budget allows it at R = 16)
+  constexpr bool PF = true;       // prefetch the next block's slices and stash
   using L = Lds<R, T, NTHR, ACC>;
   float *rows = (float *)(smem + L::rows);
   float *slab = (float *)(smem + L::slab);
