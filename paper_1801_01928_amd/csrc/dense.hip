@@ -32,6 +32,8 @@ struct Shared {
   float sig[kJac];
   int perm[kJac];
   int rotated;
+  float hv[2][64 * 10];     // register QR: broadcast Householder vector (double-buffered)
+  float hb[kJac];           // register QR: reflector coefficients
 };
 
 template <int CTRL>
@@ -160,6 +162,175 @@ __device__ void blk_form_q(const float *W, int m, int c, const float *tau, float
   }
 }
 
+// Householder QR plus thin Q of a column-major m x c matrix (m <= 640,
+// c <= 64) held in registers: wave w owns columns w, w + 8, ..., lane l
+// rows l, l + 64, ...  For each column the owner wave forms the reflector
+// and broadcasts it through LDS (double-buffered, one barrier per column);
+// every wave applies it to its own columns.  Q is accumulated backwards in
+// registers the same way.  On return Wm holds R in its upper triangle (the
+// reflectors below it) and Q (m x p, column-major, ld = m) is written.
+// Same arithmetic as blk_qr / blk_form_q (diag(R) >= 0); only the data
+// placement differs.
+constexpr int kRegRows = 10;               // rows per lane
+constexpr int kRegCols = kJac / kWaves;    // columns per wave
+static_assert(kRegCols * kWaves == kJac, "columns must split over the waves");
+
+__device__ bool reg_qr_fits(int m, int c) { return m <= 64 * kRegRows && c <= kJac; }
+
+__device__ void reg_qr(float *Wm, int m, int c, float *Q, Shared &sh) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p = m < c ? m : c;
+  float x[kRegCols][kRegRows];
+#pragma unroll
+  for (int cc = 0; cc < kRegCols; ++cc)
+#pragma unroll
+    for (int rr = 0; rr < kRegRows; ++rr) {
+      const int col = wave + kWaves * cc, row = lane + 64 * rr;
+      x[cc][rr] = (col < c && row < m) ? Wm[(long)col * m + row] : 0.f;
+    }
+  // ---- factorization
+  for (int j = 0; j < p; ++j) {
+    const int owner = j % kWaves, cj = j / kWaves;
+    float *hv = sh.hv[j & 1];
+    if (wave == owner) {
+      float part = 0.f, x0l = 0.f;
+#pragma unroll
+      for (int cc = 0; cc < kRegCols; ++cc) {
+        if (cc != cj) continue;
+#pragma unroll
+        for (int rr = 0; rr < kRegRows; ++rr) {
+          const int row = lane + 64 * rr;
+          if (row > j) part = fmaf(x[cc][rr], x[cc][rr], part);
+          if (row == j) x0l = x[cc][rr];
+        }
+      }
+      const float sigma = wave_sum(part);
+      const float x0 = wave_sum(x0l);  // only lane j % 64 holds a non-zero
+      float beta, v0, rjj;
+      if (sigma == 0.f) {
+        v0 = 1.f;
+        beta = (x0 >= 0.f) ? 0.f : 2.f;
+        rjj = fabsf(x0);
+      } else {
+        const float mu = sqrtf(x0 * x0 + sigma);
+        v0 = (x0 <= 0.f) ? x0 - mu : -sigma / (x0 + mu);
+        beta = 2.f * v0 * v0 / (sigma + v0 * v0);
+        rjj = mu;
+      }
+      const float inv = (sigma != 0.f) ? 1.f / v0 : 1.f;
+#pragma unroll
+      for (int cc = 0; cc < kRegCols; ++cc) {
+        if (cc != cj) continue;
+#pragma unroll
+        for (int rr = 0; rr < kRegRows; ++rr) {
+          const int row = lane + 64 * rr;
+          float v = 0.f;
+          if (row > j) {
+            x[cc][rr] *= inv;      // reflector below the diagonal
+            v = x[cc][rr];
+          } else if (row == j) {
+            x[cc][rr] = rjj;       // R(j, j)
+            v = 1.f;
+          }
+          if (row < m) hv[row] = v;
+        }
+      }
+      if (lane == 0) sh.hb[j] = beta;
+    }
+    __syncthreads();
+    const float beta = sh.hb[j];
+    float v[kRegRows];
+#pragma unroll
+    for (int rr = 0; rr < kRegRows; ++rr) {
+      const int row = lane + 64 * rr;
+      v[rr] = (row < m) ? hv[row] : 0.f;
+    }
+#pragma unroll
+    for (int cc = 0; cc < kRegCols; ++cc) {
+      const int col = wave + kWaves * cc;
+      if (col <= j || col >= c) continue;
+      float sp = 0.f;
+#pragma unroll
+      for (int rr = 0; rr < kRegRows; ++rr) sp = fmaf(v[rr], x[cc][rr], sp);
+      const float w = beta * wave_sum(sp);
+#pragma unroll
+      for (int rr = 0; rr < kRegRows; ++rr) x[cc][rr] = fmaf(-w, v[rr], x[cc][rr]);
+    }
+  }
+  // R (and the reflectors) back to Wm
+#pragma unroll
+  for (int cc = 0; cc < kRegCols; ++cc)
+#pragma unroll
+    for (int rr = 0; rr < kRegRows; ++rr) {
+      const int col = wave + kWaves * cc, row = lane + 64 * rr;
+      if (col < c && row < m) Wm[(long)col * m + row] = x[cc][rr];
+    }
+  // ---- thin Q by backward accumulation, columns owned as above
+  float q[kRegCols][kRegRows];
+#pragma unroll
+  for (int cc = 0; cc < kRegCols; ++cc)
+#pragma unroll
+    for (int rr = 0; rr < kRegRows; ++rr) {
+      const int col = wave + kWaves * cc, row = lane + 64 * rr;
+      q[cc][rr] = (row == col) ? 1.f : 0.f;
+    }
+  for (int j = p - 1; j >= 0; --j) {
+    const int owner = j % kWaves, cj = j / kWaves;
+    float *hv = sh.hv[j & 1];
+    if (wave == owner) {
+#pragma unroll
+      for (int cc = 0; cc < kRegCols; ++cc) {
+        if (cc != cj) continue;
+#pragma unroll
+        for (int rr = 0; rr < kRegRows; ++rr) {
+          const int row = lane + 64 * rr;
+          const float vv = (row > j) ? x[cc][rr] : (row == j ? 1.f : 0.f);
+          if (row < m) hv[row] = vv;
+        }
+      }
+    }
+    __syncthreads();
+    const float beta = sh.hb[j];
+    float v[kRegRows];
+#pragma unroll
+    for (int rr = 0; rr < kRegRows; ++rr) {
+      const int row = lane + 64 * rr;
+      v[rr] = (row < m) ? hv[row] : 0.f;
+    }
+#pragma unroll
+    for (int cc = 0; cc < kRegCols; ++cc) {
+      const int col = wave + kWaves * cc;
+      if (col < j || col >= p) continue;
+      float sp = 0.f;
+#pragma unroll
+      for (int rr = 0; rr < kRegRows; ++rr) sp = fmaf(v[rr], q[cc][rr], sp);
+      const float w = beta * wave_sum(sp);
+#pragma unroll
+      for (int rr = 0; rr < kRegRows; ++rr) q[cc][rr] = fmaf(-w, v[rr], q[cc][rr]);
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < kRegCols; ++cc)
+#pragma unroll
+    for (int rr = 0; rr < kRegRows; ++rr) {
+      const int col = wave + kWaves * cc, row = lane + 64 * rr;
+      if (col < p && row < m) Q[(long)col * m + row] = q[cc][rr];
+    }
+  __syncthreads();
+}
+
+// QR with thin Q: registers when the matrix fits, the global-memory
+// kernels otherwise.
+__device__ void qr_thin(float *Wm, int m, int c, float *tau, float *Q, Shared &sh) {
+  if (reg_qr_fits(m, c)) {
+    reg_qr(Wm, m, c, Q, sh);
+  } else {
+    blk_qr(Wm, m, c, tau, sh);
+    blk_form_q(Wm, m, c, tau, Q, sh);
+  }
+}
+
 // One-sided Jacobi on the columns of sh.jb (rows x cols, ld = kJac); sh.jv
 // accumulates the rotations (cols x cols).  On return the columns of jb are
 // mutually orthogonal (jb = B V) and V is orthogonal.
@@ -244,8 +415,7 @@ __device__ void sweep_lr(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
       Wm[e] = G[(long)i * c + j];
     }
     __syncthreads();
-    blk_qr(Wm, m, c, tau, sh);
-    blk_form_q(Wm, m, c, tau, Q, sh);
+    qr_thin(Wm, m, c, tau, Q, sh);
     // core k <- Q (row-major m x p)
     for (long e = threadIdx.x; e < (long)m * p; e += kThreads) {
       const int i = (int)(e / p), j = (int)(e % p);
@@ -282,8 +452,7 @@ __device__ void sweep_rl(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
     // row-major core already has that layout
     for (long e = threadIdx.x; e < (long)mm * rows; e += kThreads) Wm[e] = G[e];
     __syncthreads();
-    blk_qr(Wm, mm, rows, tau, sh);
-    blk_form_q(Wm, mm, rows, tau, Q, sh);
+    qr_thin(Wm, mm, rows, tau, Q, sh);
     // core k <- Q^T (p x mm row-major) = Q column-major
     for (long e = threadIdx.x; e < (long)p * mm; e += kThreads) G[e] = Q[e];
     __syncthreads();  // Q's buffer is reused below
@@ -355,8 +524,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       b.wm[e] = G[(long)i * c + j];
     }
     __syncthreads();
-    blk_qr(b.wm, m, c, b.tau, sh);
-    blk_form_q(b.wm, m, c, b.tau, b.q, sh);
+    qr_thin(b.wm, m, c, b.tau, b.q, sh);
     // Jacobi on B = R^T (c x p): jb[row l][col j] = R[j][l]
     for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
       const int l = e % kJac, j = e / kJac;
