@@ -345,35 +345,57 @@ __device__ void blk_jacobi(int rows, int cols, Shared &sh) {
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) sh.rotated = 0;
     __syncthreads();
+    // round-robin pairing: position qa = pr pairs with qb = P-1-pr; every
+    // position other than 0 advances by one column per round
+    constexpr int kPairs = kJac / 2 / kWaves;
+    int pa[kPairs], pb[kPairs];
+#pragma unroll
+    for (int t = 0; t < kPairs; ++t) {
+      const int pr = wave + kWaves * t;
+      pa[t] = pr;                     // round 0: columns pr and P-1-pr
+      pb[t] = P - 1 - pr;
+    }
     for (int round = 0; round < P - 1; ++round) {
-      for (int pr = wave; pr < P / 2; pr += kWaves) {
-        const int qa = pr, qb = P - 1 - pr;
-        const int a = (qa == 0) ? 0 : 1 + (qa - 1 + round) % (P - 1);
-        const int b = (qb == 0) ? 0 : 1 + (qb - 1 + round) % (P - 1);
-        if (a >= cols || b >= cols) continue;
-        float *ca = sh.jb + a * kJac, *cb = sh.jb + b * kJac;
-        const float xa = lane < rows ? ca[lane] : 0.f;
-        const float xb = lane < rows ? cb[lane] : 0.f;
-        const float alpha = wave_sum(xa * xa);
-        const float beta = wave_sum(xb * xb);
-        const float gamma = wave_sum(xa * xb);
-        if (fabsf(gamma) > 1e-6f * sqrtf(alpha * beta) && gamma != 0.f) {
-          const float zeta = (beta - alpha) / (2.f * gamma);
-          const float t = copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-          const float cs = 1.f / sqrtf(1.f + t * t);
-          const float sn = cs * t;
-          if (lane < rows) {
-            ca[lane] = cs * xa - sn * xb;
-            cb[lane] = sn * xa + cs * xb;
-          }
-          float *va = sh.jv + a * kJac, *vb = sh.jv + b * kJac;
-          if (lane < cols) {
-            const float ya = va[lane], yb = vb[lane];
-            va[lane] = cs * ya - sn * yb;
-            vb[lane] = sn * ya + cs * yb;
-          }
+      // this wave's pairs of the round: all their columns are loaded first
+      // and the reductions interleaved.  jb and jv are zero beyond rows and
+      // cols, so whole columns of 64 are rotated without lane guards.
+      bool on[kPairs];
+      float xa[kPairs], xb[kPairs], ya[kPairs], yb[kPairs];
+#pragma unroll
+      for (int t = 0; t < kPairs; ++t) {
+        on[t] = wave + kWaves * t < P / 2 && pa[t] < cols && pb[t] < cols;
+        const int ca = on[t] ? pa[t] : 0, cb = on[t] ? pb[t] : 0;
+        xa[t] = sh.jb[ca * kJac + lane];
+        xb[t] = sh.jb[cb * kJac + lane];
+        ya[t] = sh.jv[ca * kJac + lane];
+        yb[t] = sh.jv[cb * kJac + lane];
+      }
+      float alpha[kPairs], beta[kPairs], gamma[kPairs];
+#pragma unroll
+      for (int t = 0; t < kPairs; ++t) {
+        alpha[t] = wave_sum(xa[t] * xa[t]);
+        beta[t] = wave_sum(xb[t] * xb[t]);
+        gamma[t] = wave_sum(xa[t] * xb[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < kPairs; ++t) {
+        if (!on[t]) continue;
+        if (fabsf(gamma[t]) > 1e-6f * sqrtf(alpha[t] * beta[t]) && gamma[t] != 0.f) {
+          const float zeta = (beta[t] - alpha[t]) / (2.f * gamma[t]);
+          const float tn = copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
+          const float cs = 1.f / sqrtf(1.f + tn * tn);
+          const float sn = cs * tn;
+          sh.jb[pa[t] * kJac + lane] = cs * xa[t] - sn * xb[t];
+          sh.jb[pb[t] * kJac + lane] = sn * xa[t] + cs * xb[t];
+          sh.jv[pa[t] * kJac + lane] = cs * ya[t] - sn * yb[t];
+          sh.jv[pb[t] * kJac + lane] = sn * ya[t] + cs * yb[t];
           if (lane == 0) sh.rotated = 1;
         }
+      }
+#pragma unroll
+      for (int t = 0; t < kPairs; ++t) {
+        if (pa[t] != 0) pa[t] = (pa[t] == P - 1) ? 1 : pa[t] + 1;
+        pb[t] = (pb[t] == P - 1) ? 1 : pb[t] + 1;
       }
       __syncthreads();
     }
