@@ -33,6 +33,7 @@ struct Shared {
   int perm[kJac];
   int rotated;
   float hv[2][64 * 10];     // register QR: broadcast Householder vector (double-buffered)
+  float stg[64 * 65];       // staging chunk of the large GEMM operand
   float hb[kJac];           // register QR: reflector coefficients
 };
 
@@ -75,7 +76,7 @@ __device__ void blk_gemm(int M, int N, int K, const float *A, long ar, long ac, 
   for (long e = threadIdx.x; e < (long)M * N; e += kThreads) {
     const int i = (int)(e / N), j = (int)(e % N);
     float s = 0.f;
-    #pragma unroll 8
+#pragma unroll 8
     for (int k = 0; k < K; ++k) s = fmaf(A[i * ar + k * ac], B[k * br + j * bc], s);
     C[i * cr + j * cc] = s;
   }
@@ -90,7 +91,7 @@ __device__ void blk_qr(float *W, int m, int c, float *tau, Shared &sh) {
   for (int j = 0; j < p; ++j) {
     float *col = W + (long)j * m;
     float part = 0.f;
-    #pragma unroll 8
+#pragma unroll 8
     for (int i = j + 1 + threadIdx.x; i < m; i += kThreads) part = fmaf(col[i], col[i], part);
     const float sigma = block_sum(part, sh);
     if (threadIdx.x == 0) {
@@ -122,12 +123,12 @@ __device__ void blk_qr(float *W, int m, int c, float *tau, Shared &sh) {
     for (int l = j + 1 + wave; l < c; l += kWaves) {
       float *cl = W + (long)l * m;
       float s = 0.f;
-      #pragma unroll 8
+#pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) s = fmaf(col[i], cl[i], s);
       s = wave_sum(s) + cl[j];
       const float w = beta * s;
       if (lane == 0) cl[j] -= w;
-      #pragma unroll 8
+#pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) cl[i] = fmaf(-w, col[i], cl[i]);
     }
     if (threadIdx.x == 0) col[j] = sh.bval[2];
@@ -150,12 +151,12 @@ __device__ void blk_form_q(const float *W, int m, int c, const float *tau, float
     for (int l = j + wave; l < p; l += kWaves) {
       float *ql = Q + (long)l * m;
       float s = 0.f;
-      #pragma unroll 8
+#pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) s = fmaf(v[i], ql[i], s);
       s = wave_sum(s) + ql[j];
       const float w = beta * s;
       if (lane == 0) ql[j] -= w;
-      #pragma unroll 8
+#pragma unroll 8
       for (int i = j + 1 + lane; i < m; i += 64) ql[i] = fmaf(-w, v[i], ql[i]);
     }
     __syncthreads();
@@ -405,6 +406,56 @@ __device__ void blk_jacobi(int rows, int cols, Shared &sh) {
   }
 }
 
+// C (M x N) = A (M x K) * B (K x N) for K <= 64, the small factor A read
+// from LDS through aop(i, l), B in global memory (element (l, j) at
+// B[l*br + j*bc]).  B is staged through sh.stg in chunks of 64 columns, so
+// every global element is read once and coalesced.  C may alias B: the
+// columns of a chunk are written only after that chunk was staged
+// (element (i, j) of C at C[i*cr + j*cc]).
+template <class AOp>
+__device__ void gemm_lds_a(int M, int N, int K, AOp aop, const float *B, long br, long bc, float *C, long cr,
+                           long cc, Shared &sh) {
+  for (int j0 = 0; j0 < N; j0 += 64) {
+    const int nc = (N - j0) < 64 ? (N - j0) : 64;
+    for (int e = threadIdx.x; e < K * 64; e += kThreads) {
+      const int l = e >> 6, jj = e & 63;
+      sh.stg[l * 65 + jj] = (jj < nc) ? B[(long)l * br + (long)(j0 + jj) * bc] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < M * nc; e += kThreads) {
+      const int i = e / nc, jj = e % nc;
+      float acc = 0.f;
+      for (int l = 0; l < K; ++l) acc = fmaf(aop(i, l), sh.stg[l * 65 + jj], acc);
+      C[(long)i * cr + (long)(j0 + jj) * cc] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// C (M x N) = A (M x K) * B (K x N) for K <= 64, A in global memory
+// (element (i, l) at A[i*ar + l*ac]) staged in chunks of 64 rows, the small
+// factor B read from LDS through bop(l, j).  C may alias A when row i of C
+// (C[i*ldc + j]) never reaches past row i of A, i.e. ldc <= A's row stride.
+template <class BOp>
+__device__ void gemm_lds_b(int M, int N, int K, const float *A, long ar, long ac, BOp bop, float *C, long ldc,
+                           Shared &sh) {
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    const int mr = (M - i0) < 64 ? (M - i0) : 64;
+    for (int e = threadIdx.x; e < 64 * K; e += kThreads) {
+      const int ii = e / K, l = e % K;
+      sh.stg[ii * 65 + l] = (ii < mr) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < mr * N; e += kThreads) {
+      const int ii = e / N, j = e % N;
+      float acc = 0.f;
+      for (int l = 0; l < K; ++l) acc = fmaf(sh.stg[ii * 65 + l], bop(l, j), acc);
+      C[(long)(i0 + ii) * ldc + j] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 // Cores of the working TT in the workspace: each core has its own slot of
 // `slot` floats; shape (r[k], n[k], r[k+1]) row-major.
 struct WorkTT {
@@ -444,19 +495,15 @@ __device__ void sweep_lr(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
       G[e] = Q[(long)j * m + i];
     }
     __syncthreads();  // Q's buffer is reused below
-    // next core <- R (p x c, upper triangle of Wm) * next (c x n r'); the
-    // product goes to Q's buffer first, then back into the core slot.
+    // next core <- R (p x c, upper triangle of Wm) * next (c x n r'), in place
     const int nn = n[k + 1] * r[k + 2];
     float *Gn = w.core(k + 1);
-    for (long e = threadIdx.x; e < (long)p * nn; e += kThreads) {
-      const int i = (int)(e / nn), j = (int)(e % nn);
-      float s = 0.f;
-      #pragma unroll 8
-      for (int l = i; l < c; ++l) s = fmaf(Wm[(long)l * m + i], Gn[(long)l * nn + j], s);
-      Q[e] = s;
+    for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
+      const int i = e / kJac, l = e % kJac;
+      sh.jb[e] = (i < p && l < c && l >= i) ? Wm[(long)l * m + i] : 0.f;
     }
     __syncthreads();
-    for (long e = threadIdx.x; e < (long)p * nn; e += kThreads) Gn[e] = Q[e];
+    gemm_lds_a(p, nn, c, [&](int i, int l) { return sh.jb[i * kJac + l]; }, Gn, nn, 1, Gn, nn, 1, sh);
     if (threadIdx.x == 0) r[k + 1] = p;
     __syncthreads();
   }
@@ -478,19 +525,16 @@ __device__ void sweep_rl(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
     // core k <- Q^T (p x mm row-major) = Q column-major
     for (long e = threadIdx.x; e < (long)p * mm; e += kThreads) G[e] = Q[e];
     __syncthreads();  // Q's buffer is reused below
-    // previous core (r[k-1] n[k-1] x rows) <- prev * L, L = R^T (rows x p)
+    // previous core (r[k-1] n[k-1] x rows) <- prev * L, L = R^T (rows x p),
+    // in place (the output row stride p does not exceed rows)
     const int mp = r[k - 1] * n[k - 1];
     float *Gp = w.core(k - 1);
-    for (long e = threadIdx.x; e < (long)mp * p; e += kThreads) {
-      const int i = (int)(e / p), j = (int)(e % p);
-      float s = 0.f;
-      // L[l][j] = R[j][l], nonzero for l >= j
-      #pragma unroll 8
-      for (int l = j; l < rows; ++l) s = fmaf(Gp[(long)i * rows + l], Wm[(long)l * mm + j], s);
-      Q[e] = s;
+    for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
+      const int l = e / kJac, j = e % kJac;  // L[l][j] = R[j][l], nonzero for l >= j
+      sh.jb[e] = (l < rows && j < p && l >= j) ? Wm[(long)l * mm + j] : 0.f;
     }
     __syncthreads();
-    for (long e = threadIdx.x; e < (long)mp * p; e += kThreads) Gp[e] = Q[e];
+    gemm_lds_b(mp, p, rows, Gp, rows, 1, [&](int l, int j) { return sh.jb[l * kJac + j]; }, Gp, p, sh);
     if (threadIdx.x == 0) r[k] = p;
     __syncthreads();
   }
@@ -575,15 +619,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       disc[k] = s;
     }
     // U = Q (m x p) * V[:, perm[j]] for j < keep -> core k (row-major m x keep)
-    for (long e = threadIdx.x; e < (long)m * keep; e += kThreads) {
-      const int i = (int)(e / keep), j = (int)(e % keep);
-      const float *vj = sh.jv + sh.perm[j] * kJac;
-      float s = 0.f;
-#pragma unroll 8
-      for (int l = 0; l < p; ++l) s = fmaf(b.q[(long)l * m + i], vj[l], s);
-      G[e] = s;
-    }
-    __syncthreads();
+    gemm_lds_b(m, keep, p, b.q, 1, m, [&](int l, int j) { return sh.jv[sh.perm[j] * kJac + l]; }, G, keep, sh);
     // sign fix: the largest-magnitude component of each kept column is positive
     for (int j = wave; j < keep; j += kWaves) {
       float best = -1.f, val = 0.f;
@@ -613,16 +649,8 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
     // (Sigma V^T) row j = sign_j * column perm[j] of B V, transposed
     const int nn = n[k + 1] * r[k + 2];
     float *Gn = w.core(k + 1);
-    for (long e = threadIdx.x; e < (long)keep * nn; e += kThreads) {
-      const int i = (int)(e / nn), j = (int)(e % nn);
-      const float *bj = sh.jb + sh.perm[i] * kJac;
-      float s = 0.f;
-#pragma unroll 8
-      for (int l = 0; l < c; ++l) s = fmaf(bj[l], Gn[(long)l * nn + j], s);
-      b.q[e] = sh.sig[i] * s;
-    }
-    __syncthreads();
-    for (long e = threadIdx.x; e < (long)keep * nn; e += kThreads) Gn[e] = b.q[e];
+    gemm_lds_a(keep, nn, c, [&](int i, int l) { return sh.sig[i] * sh.jb[sh.perm[i] * kJac + l]; }, Gn, nn, 1,
+               Gn, nn, 1, sh);
     if (threadIdx.x == 0) r[k + 1] = keep;
     __syncthreads();
   }
