@@ -62,30 +62,44 @@ struct Step {
   long long sa, sj, si, sb;  // core element (a, j, i, b) at a*sa + j*sj + i*si + b*sb
 };
 
-// One workgroup stages the whole core in B-operand order, then walks row
-// blocks of 64 (p, q) rows; every wave owns 16 rows and all N tiles.
-template <int BF16>
+// One workgroup stages the whole core in B-operand order (in its own
+// precision) and the offsets of the K indices (j, a) inside an IN row, then
+// walks row blocks of 64 (p, q) rows; every wave owns 16 rows and all N
+// tiles.  Row and column offsets are computed once per block and per lane,
+// so the inner loop has no integer division.  VEC: the bond of IN is a
+// multiple of 4, so the 4 K values of a lane are contiguous and load as
+// one vector.
+template <int BF16, int VEC>
 __global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32) {
-  extern __shared__ __align__(16) float bsh[];
+  extern __shared__ __align__(16) char smem[];
   const int K = s.nin * s.rin, N = s.mout * s.rout;
   const int KC = (K + 15) / 16, NT = (N + 15) / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c16 = lane & 15, q4 = lane >> 4;
+  long long *koff = (long long *)smem;  // [KC * 16], -1 past K
+  char *bsm = smem + 16 * ((KC * 16 * 8 + 15) / 16);
+  const long long jstride = s.Q * s.rin;
+  for (int kk = tid; kk < KC * 16; kk += kThreads) koff[kk] = kk < K ? (kk / s.rin) * jstride + kk % s.rin : -1;
   // chunk x (16 K values), tile t: lane (q4, c16) holds B[16x + 4q4 + v][16t + c16]
   for (int e = tid; e < KC * NT * 256; e += kThreads) {
     const int v = e & 3, ln = (e >> 2) & 63, xt = e >> 8;
     const int x = xt / NT, t = xt % NT;
     const int kk = 16 * x + 4 * (ln >> 4) + v, nn = 16 * t + (ln & 15);
-    float val = 0.f;
-    if (kk < K && nn < N) {
-      const int j = kk / s.rin, a = kk % s.rin, i = nn / s.rout, b = nn % s.rout;
-      val = load_el<BF16>(s.core, a * s.sa + j * s.sj + i * s.si + b * s.sb);
-    }
-    bsh[e] = val;
+    const long long ci = (kk < K && nn < N)
+                             ? (kk / s.rin) * s.sj + (kk % s.rin) * s.sa + (nn / s.rout) * s.si + (nn % s.rout) * s.sb
+                             : -1;
+    if (BF16) ((uint16_t *)bsm)[e] = ci >= 0 ? ((const uint16_t *)s.core)[ci] : (uint16_t)0;
+    else ((float *)bsm)[e] = ci >= 0 ? ((const float *)s.core)[ci] : 0.f;
+  }
+  // per-lane output column offsets
+  long long coff[kMaxTiles];
+#pragma unroll
+  for (int t = 0; t < kMaxTiles; ++t) {
+    const int nn = 16 * t + c16;
+    coff[t] = (t < NT && nn < N) ? (long long)(nn / s.rout) * s.Q * s.rout + nn % s.rout : -1;
   }
   __syncthreads();
   const long long rows = s.P * s.Q;
-  const long long jstride = s.Q * s.rin;
   for (long long r0 = (long long)blockIdx.x * kRows; r0 < rows; r0 += (long long)gridDim.x * kRows) {
     const long long row = r0 + wave * 16 + c16;  // A-operand row of this lane
     const bool rvalid = row < rows;
@@ -95,33 +109,38 @@ __global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32)
 #pragma unroll
     for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
     for (int x = 0; x < KC; ++x) {
-      float av[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int kk = 16 * x + 4 * q4 + v;
-        float val = 0.f;
-        if (rvalid && kk < K) val = load_el<BF16>(s.in, abase + (kk / s.rin) * jstride + kk % s.rin);
-        av[v] = val;
-      }
+      const int kb = 16 * x + 4 * q4;
       if (BF16) {
         v4s a4;
+        if (VEC) {
+          const long long o = koff[kb];
+          a4 = (rvalid && o >= 0) ? *(const v4s *)((const uint16_t *)s.in + abase + o) : v4s{0, 0, 0, 0};
+        } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) a4[v] = (short)f32_to_bf16(av[v]);  // exact: values are bf16
-#pragma unroll
-        for (int t = 0; t < kMaxTiles; ++t) {
-          if (t < NT) {
-            const v4f bv = ((const v4f *)bsh)[(x * NT + t) * 64 + lane];
-            v4s b4;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) b4[v] = (short)f32_to_bf16(bv[v]);
-            acc[t] = mfma_bf16(a4, b4, acc[t]);
+          for (int v = 0; v < 4; ++v) {
+            const long long o = koff[kb + v];
+            a4[v] = (rvalid && o >= 0) ? (short)((const uint16_t *)s.in)[abase + o] : (short)0;
           }
         }
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t)
+          if (t < NT) acc[t] = mfma_bf16(a4, ((const v4s *)bsm)[(x * NT + t) * 64 + lane], acc[t]);
       } else {
+        v4f av;
+        if (VEC) {
+          const long long o = koff[kb];
+          av = (rvalid && o >= 0) ? *(const v4f *)((const float *)s.in + abase + o) : v4f{0.f, 0.f, 0.f, 0.f};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const long long o = koff[kb + v];
+            av[v] = (rvalid && o >= 0) ? ((const float *)s.in)[abase + o] : 0.f;
+          }
+        }
 #pragma unroll
         for (int t = 0; t < kMaxTiles; ++t) {
           if (t < NT) {
-            const v4f bv = ((const v4f *)bsh)[(x * NT + t) * 64 + lane];
+            const v4f bv = ((const v4f *)bsm)[(x * NT + t) * 64 + lane];
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[t] = mfma_f32(av[v], bv[v], acc[t]);
           }
@@ -130,16 +149,15 @@ __global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32)
     }
     // D tile t: lane (q4, c16) value v is row r0 + 16 wave + 4 q4 + v, column 16 t + c16
 #pragma unroll
-    for (int t = 0; t < kMaxTiles; ++t) {
-      const int nn = 16 * t + c16;
-      if (t >= NT || nn >= N) continue;
-      const int i = nn / s.rout, b = nn % s.rout;
+    for (int v = 0; v < 4; ++v) {
+      const long long orow = r0 + wave * 16 + 4 * q4 + v;
+      if (orow >= rows) continue;
+      const long long op = orow / s.Q, oq = orow % s.Q;
+      const long long rbase = op * s.mout * s.Q * s.rout + oq * s.rout;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const long long orow = r0 + wave * 16 + 4 * q4 + v;
-        if (orow >= rows) continue;
-        const long long op = orow / s.Q, oq = orow % s.Q;
-        const long long off = ((op * s.mout + i) * s.Q + oq) * s.rout + b;
+      for (int t = 0; t < kMaxTiles; ++t) {
+        if (coff[t] < 0) continue;
+        const long long off = rbase + coff[t];
         if (BF16 && !out_f32) ((uint16_t *)s.out)[off] = f32_to_bf16(acc[t][v]);
         else ((float *)s.out)[off] = acc[t][v];
       }
@@ -157,40 +175,104 @@ struct GradArgs {
 };
 
 // Partial core gradient over this workgroup's (p, q) range.  Rows of the
-// product are (j, a) with a fastest, columns (i, b) with b fastest, so the
-// 16 lanes of an operand read 16 consecutive bond entries.
+// product are (j, a) with a fastest, columns (i, b) with b fastest.  Slabs
+// of kSlab consecutive (p, q) pairs of T and V are staged in LDS (coalesced
+// loads through precomputed row/column offsets, no division in the loop),
+// then every wave multiplies its row tiles against all column tiles.
+constexpr int kSlab = 32;
+constexpr int kLd = TTM_MAX_FUSED + 4;
+
 template <int BF16>
 __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
+  __shared__ float ts[kSlab][kLd];
+  __shared__ float vs[kSlab][kLd];
+  __shared__ long long roff[TTM_MAX_FUSED], coffs[TTM_MAX_FUSED];
   const int ROWS = g.rT * g.n, COLS = g.m * g.rV;
   const int RT = (ROWS + 15) / 16, CT = (COLS + 15) / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c16 = lane & 15, q4 = lane >> 4;
+  for (int i = tid; i < ROWS; i += kThreads) roff[i] = (long long)(i / g.rT) * g.Q * g.rT + i % g.rT;
+  for (int i = tid; i < COLS; i += kThreads) coffs[i] = (long long)(i / g.rV) * g.Q * g.rV + i % g.rV;
+  // rows and columns past the product are zero (their outputs are discarded)
+  for (int e = tid; e < kSlab * kLd; e += kThreads) {
+    (&ts[0][0])[e] = 0.f;
+    (&vs[0][0])[e] = 0.f;
+  }
   const long long K = g.P * g.Q;
   const long long k0 = (long long)blockIdx.x * g.kchunk;
   const long long k1 = (k0 + g.kchunk < K) ? k0 + g.kchunk : K;
-  float *part = g.part + (long long)blockIdx.x * ROWS * COLS;
-  for (int rt = wave; rt < RT; rt += kThreads / 64) {
-    v4f acc[kMaxTiles];
+  constexpr int RPW = kMaxTiles / (kThreads / 64);  // row tiles per wave
+  v4f acc[RPW][kMaxTiles];
 #pragma unroll
-    for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int arow = 16 * rt + c16;
-    const bool aok = arow < ROWS;
-    const int aj = aok ? arow / g.rT : 0, aa = aok ? arow % g.rT : 0;
-    for (long long kb = k0; kb < k1; kb += 4) {
-      const long long kk = kb + q4;  // K slot q4 of this lane
-      const bool kok = kk < k1;
-      const long long p = kok ? kk / g.Q : 0, q = kok ? kk % g.Q : 0;
-      float a = 0.f;
-      if (kok && aok) a = load_el<BF16>(g.T, ((p * g.n + aj) * g.Q + q) * g.rT + aa);
+  for (int u = 0; u < RPW; ++u)
+#pragma unroll
+    for (int t = 0; t < kMaxTiles; ++t) acc[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
+  // slab loads go through registers: the next slab is fetched while the
+  // current one is multiplied.  Per-slab (p, q) base offsets are computed
+  // one slab ahead by kSlab threads into a double-buffered table.
+  __shared__ long long tb[2][kSlab], vb[2][kSlab];
+  constexpr int kPer = kSlab * TTM_MAX_FUSED / kThreads;  // loads per thread and operand
+  float tr[kPer], vr[kPer];
+  auto bases = [&](long long kb, int buf) {
+    if (tid < kSlab) {
+      const long long kk = kb + tid;
+      const long long p = kk / g.Q, q = kk % g.Q;
+      tb[buf][tid] = kk < k1 ? (p * g.n * g.Q + q) * g.rT : -1;
+      vb[buf][tid] = kk < k1 ? (p * g.m * g.Q + q) * g.rV : -1;
+    }
+  };
+  auto fetch = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kThreads;
+      tr[u] = 0.f;
+      vr[u] = 0.f;
+      if (e < kSlab * ROWS) {
+        const long long base = tb[buf][e / ROWS];
+        if (base >= 0) tr[u] = load_el<BF16>(g.T, base + roff[e % ROWS]);
+      }
+      if (e < kSlab * COLS) {
+        const long long base = vb[buf][e / COLS];
+        if (base >= 0) vr[u] = load_el<BF16>(g.V, base + coffs[e % COLS]);
+      }
+    }
+  };
+  bases(k0, 0);
+  __syncthreads();  // offsets and the first bases ready
+  if (k0 < k1) fetch(0);
+  int sl = 0;
+  for (long long kb = k0; kb < k1; kb += kSlab, ++sl) {
+    __syncthreads();  // the previous slab is consumed
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kThreads;
+      if (e < kSlab * ROWS) ts[e / ROWS][e % ROWS] = tr[u];
+      if (e < kSlab * COLS) vs[e / COLS][e % COLS] = vr[u];
+    }
+    bases(kb + kSlab, (sl + 1) & 1);
+    __syncthreads();
+    if (kb + kSlab < k1) fetch((sl + 1) & 1);
+#pragma unroll
+    for (int ks = 0; ks < kSlab / 4; ++ks) {
+      const int kl = 4 * ks + q4;  // K slot q4 of this lane
+      float av[RPW];
+#pragma unroll
+      for (int u = 0; u < RPW; ++u) av[u] = ts[kl][16 * (wave + 4 * u) + c16];
 #pragma unroll
       for (int t = 0; t < kMaxTiles; ++t) {
         if (t >= CT) continue;
-        const int col = 16 * t + c16;
-        float b = 0.f;
-        if (kok && col < COLS) b = load_el<BF16>(g.V, ((p * g.m + col / g.rV) * g.Q + q) * g.rV + col % g.rV);
-        acc[t] = mfma_f32(a, b, acc[t]);
+        const float bv = vs[kl][16 * t + c16];
+#pragma unroll
+        for (int u = 0; u < RPW; ++u)
+          if (wave + 4 * u < RT) acc[u][t] = mfma_f32(av[u], bv, acc[u][t]);
       }
     }
+  }
+  float *part = g.part + (long long)blockIdx.x * ROWS * COLS;
+#pragma unroll
+  for (int u = 0; u < RPW; ++u) {
+    const int rt = wave + 4 * u;
+    if (rt >= RT) continue;
 #pragma unroll
     for (int t = 0; t < kMaxTiles; ++t) {
       const int col = 16 * t + c16;
@@ -201,7 +283,7 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
         const int row = 16 * rt + 4 * q4 + v;
         if (row >= ROWS) continue;
         const int j = row / g.rT, a = row % g.rT;
-        part[(((long long)a * g.m + i) * g.n + j) * g.rV + b] = acc[t][v];
+        part[(((long long)a * g.m + i) * g.n + j) * g.rV + b] = acc[u][t][v];
       }
     }
   }
@@ -223,27 +305,39 @@ __global__ void __launch_bounds__(256) ttm_grad_reduce_kernel(const float *__res
 
 constexpr int kMaxGradWG = 512;
 
-size_t step_lds(int K, int N) { return sizeof(float) * 256 * ((K + 15) / 16) * ((N + 15) / 16); }
+size_t step_lds(int K, int N, int bf16) {
+  const size_t kc = (K + 15) / 16, nt = (N + 15) / 16;
+  return 16 * ((kc * 16 * 8 + 15) / 16) + (bf16 ? 2 : 4) * 256 * kc * nt;
+}
 
 int set_step_attrs() {
-  const int lds = (int)step_lds(TTM_MAX_FUSED, TTM_MAX_FUSED);
-  hipError_t e = hipFuncSetAttribute((const void *)ttm_step_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)ttm_step_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const int lds = (int)step_lds(TTM_MAX_FUSED, TTM_MAX_FUSED, 0);
+  const void *fns[4] = {(const void *)ttm_step_kernel<0, 0>, (const void *)ttm_step_kernel<0, 1>,
+                        (const void *)ttm_step_kernel<1, 0>, (const void *)ttm_step_kernel<1, 1>};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   return hip_check(e, "ttm step LDS attribute");
 }
 
 int launch_step(const Step &s, int bf16, int out_f32, hipStream_t st) {
   static const int attr_rc = set_step_attrs();
   if (attr_rc) return attr_rc;
-  const size_t shm = step_lds(s.nin * s.rin, s.mout * s.rout);
+  const size_t shm = step_lds(s.nin * s.rin, s.mout * s.rout, bf16);
   const long long rows = s.P * s.Q;
+  // enough workgroups to fill the chip a few times over; each one stages the
+  // core once and then walks many row blocks
   long long nb = (rows + kRows - 1) / kRows;
-  nb = nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
-  if (bf16)
-    hipLaunchKernelGGL(ttm_step_kernel<1>, dim3((unsigned)nb), dim3(kThreads), shm, st, s, out_f32);
-  else
-    hipLaunchKernelGGL(ttm_step_kernel<0>, dim3((unsigned)nb), dim3(kThreads), shm, st, s, out_f32);
+  nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+  // vector loads need the 4 K values of a lane contiguous: a bond of IN
+  // that is a multiple of 4 and an IN pointer aligned to 4 elements
+  const size_t esize = bf16 ? 2 : 4;
+  const bool vec = (s.rin % 4 == 0) && ((uintptr_t)s.in % (4 * esize) == 0);
+  const dim3 g((unsigned)nb), blk(kThreads);
+  if (bf16 && vec) hipLaunchKernelGGL((ttm_step_kernel<1, 1>), g, blk, shm, st, s, out_f32);
+  else if (bf16) hipLaunchKernelGGL((ttm_step_kernel<1, 0>), g, blk, shm, st, s, out_f32);
+  else if (vec) hipLaunchKernelGGL((ttm_step_kernel<0, 1>), g, blk, shm, st, s, out_f32);
+  else hipLaunchKernelGGL((ttm_step_kernel<0, 0>), g, blk, shm, st, s, out_f32);
   return launch_check("ttm step");
 }
 
