@@ -37,6 +37,7 @@ SHAPES = [
     ([3, 4, 5, 3], [1, 3, 5, 4, 1]),        # ranks above feasibility shrink
     ([6, 5, 7], [1, 6, 7, 1]),
     ([4, 4, 4, 4, 4], [1, 4, 16, 16, 4, 1]),
+    ([16, 16, 16, 16], [1, 16, 48, 16, 1]),  # 768-row unfolding: QR in global memory
 ]
 
 
@@ -67,6 +68,7 @@ ROUND = [
     ([5, 7], [1, 5, 1], 3),                  # d = 2: Eckart-Young
     ([4, 5, 3, 6], [1, 4, 12, 6, 1], 64),    # nothing to truncate
     ([10] * 10, [1, 20, 64, 64, 64, 64, 64, 64, 64, 20, 1], 32),
+    ([12, 12, 12, 12], [1, 12, 64, 12, 1], 20),  # 768-row unfoldings: QR in global memory
 ]
 
 
