@@ -19,6 +19,8 @@ namespace ttgfx {
 
 namespace {
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kJac = DENSE_MAX_RANK;  // Jacobi matrices are at most 64 x 64
@@ -27,8 +29,8 @@ struct Shared {
   float red[kWaves];
   float bval[4];
   int ival[4];
-  float jb[kJac * kJac];   // Jacobi working matrix B (column-major, ld = kJac)
-  float jv[kJac * kJac];   // accumulated rotations V (column-major, ld = kJac)
+  __attribute__((aligned(16))) float jb[kJac * kJac];  // Jacobi working matrix B (column-major, ld = kJac)
+  __attribute__((aligned(16))) float jv[kJac * kJac];  // accumulated rotations V (column-major, ld = kJac)
   float sig[kJac];
   int perm[kJac];
   int rotated;
@@ -332,10 +334,23 @@ __device__ void qr_thin(float *Wm, int m, int c, float *tau, float *Q, Shared &s
   }
 }
 
+// Sum over the 16 lanes of a DPP row; every lane of the row gets it.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  return v;
+}
+
 // One-sided Jacobi on the columns of sh.jb (rows x cols, ld = kJac); sh.jv
 // accumulates the rotations (cols x cols).  On return the columns of jb are
-// mutually orthogonal (jb = B V) and V is orthogonal.
-__device__ void blk_jacobi(int rows, int cols, Shared &sh) {
+// mutually orthogonal (jb = B V) and V is orthogonal.  Round-robin pairing:
+// every round rotates up to 32 disjoint column pairs, 4 per wave, one pair
+// per row of 16 lanes with 4 matrix rows per lane (jb and jv are zero beyond
+// rows and cols, so whole columns of 64 are rotated).
+__device__ int blk_jacobi(int rows, int cols, Shared &sh) {
+  (void)rows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
     const int i = e % kJac, j = e / kJac;
@@ -343,67 +358,61 @@ __device__ void blk_jacobi(int rows, int cols, Shared &sh) {
   }
   __syncthreads();
   const int P = (cols + 1) & ~1;
+  const int slot = lane >> 4, c4 = 4 * (lane & 15);
+  const int pr = wave + kWaves * slot;  // pair position of this row of lanes
+  const bool live = pr < P / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) sh.rotated = 0;
     __syncthreads();
-    // round-robin pairing: position qa = pr pairs with qb = P-1-pr; every
-    // position other than 0 advances by one column per round
-    constexpr int kPairs = kJac / 2 / kWaves;
-    int pa[kPairs], pb[kPairs];
-#pragma unroll
-    for (int t = 0; t < kPairs; ++t) {
-      const int pr = wave + kWaves * t;
-      pa[t] = pr;                     // round 0: columns pr and P-1-pr
-      pb[t] = P - 1 - pr;
-    }
+    // position qa = pr pairs with qb = P-1-pr; every position other than 0
+    // advances by one column per round
+    int pa = pr, pb = P - 1 - pr;
     for (int round = 0; round < P - 1; ++round) {
-      // this wave's pairs of the round: all their columns are loaded first
-      // and the reductions interleaved.  jb and jv are zero beyond rows and
-      // cols, so whole columns of 64 are rotated without lane guards.
-      bool on[kPairs];
-      float xa[kPairs], xb[kPairs], ya[kPairs], yb[kPairs];
+      const bool on = live && pa < cols && pb < cols;
+      const int ca = on ? pa : 0, cb = on ? pb : 0;
+      const v4f xa = *(const v4f *)(sh.jb + ca * kJac + c4);
+      const v4f xb = *(const v4f *)(sh.jb + cb * kJac + c4);
+      const v4f ya = *(const v4f *)(sh.jv + ca * kJac + c4);
+      const v4f yb = *(const v4f *)(sh.jv + cb * kJac + c4);
+      float al = 0.f, be = 0.f, ga = 0.f;
 #pragma unroll
-      for (int t = 0; t < kPairs; ++t) {
-        on[t] = wave + kWaves * t < P / 2 && pa[t] < cols && pb[t] < cols;
-        const int ca = on[t] ? pa[t] : 0, cb = on[t] ? pb[t] : 0;
-        xa[t] = sh.jb[ca * kJac + lane];
-        xb[t] = sh.jb[cb * kJac + lane];
-        ya[t] = sh.jv[ca * kJac + lane];
-        yb[t] = sh.jv[cb * kJac + lane];
+      for (int v = 0; v < 4; ++v) {
+        al = fmaf(xa[v], xa[v], al);
+        be = fmaf(xb[v], xb[v], be);
+        ga = fmaf(xa[v], xb[v], ga);
       }
-      float alpha[kPairs], beta[kPairs], gamma[kPairs];
+      al = row16_sum(al);
+      be = row16_sum(be);
+      ga = row16_sum(ga);
+      // every lane of the row takes the same decision
+      if (on && fabsf(ga) > 1e-6f * sqrtf(al * be) && ga != 0.f) {
+        const float zeta = (be - al) / (2.f * ga);
+        const float tn = copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
+        const float cs = 1.f / sqrtf(1.f + tn * tn);
+        const float sn = cs * tn;
+        v4f na, nb, ma, mb;
 #pragma unroll
-      for (int t = 0; t < kPairs; ++t) {
-        alpha[t] = wave_sum(xa[t] * xa[t]);
-        beta[t] = wave_sum(xb[t] * xb[t]);
-        gamma[t] = wave_sum(xa[t] * xb[t]);
-      }
-#pragma unroll
-      for (int t = 0; t < kPairs; ++t) {
-        if (!on[t]) continue;
-        if (fabsf(gamma[t]) > 1e-6f * sqrtf(alpha[t] * beta[t]) && gamma[t] != 0.f) {
-          const float zeta = (beta[t] - alpha[t]) / (2.f * gamma[t]);
-          const float tn = copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-          const float cs = 1.f / sqrtf(1.f + tn * tn);
-          const float sn = cs * tn;
-          sh.jb[pa[t] * kJac + lane] = cs * xa[t] - sn * xb[t];
-          sh.jb[pb[t] * kJac + lane] = sn * xa[t] + cs * xb[t];
-          sh.jv[pa[t] * kJac + lane] = cs * ya[t] - sn * yb[t];
-          sh.jv[pb[t] * kJac + lane] = sn * ya[t] + cs * yb[t];
-          if (lane == 0) sh.rotated = 1;
+        for (int v = 0; v < 4; ++v) {
+          na[v] = cs * xa[v] - sn * xb[v];
+          nb[v] = sn * xa[v] + cs * xb[v];
+          ma[v] = cs * ya[v] - sn * yb[v];
+          mb[v] = sn * ya[v] + cs * yb[v];
         }
+        *(v4f *)(sh.jb + pa * kJac + c4) = na;
+        *(v4f *)(sh.jb + pb * kJac + c4) = nb;
+        *(v4f *)(sh.jv + pa * kJac + c4) = ma;
+        *(v4f *)(sh.jv + pb * kJac + c4) = mb;
+        if ((lane & 15) == 0) sh.rotated = 1;
       }
-#pragma unroll
-      for (int t = 0; t < kPairs; ++t) {
-        if (pa[t] != 0) pa[t] = (pa[t] == P - 1) ? 1 : pa[t] + 1;
-        pb[t] = (pb[t] == P - 1) ? 1 : pb[t] + 1;
-      }
+      if (pa != 0) pa = (pa == P - 1) ? 1 : pa + 1;
+      pb = (pb == P - 1) ? 1 : pb + 1;
       __syncthreads();
     }
     const int any = sh.rotated;
     __syncthreads();
-    if (!any) break;
+    if (!any) return sweep + 1;
   }
+  return 40;
 }
 
 // C (M x N) = A (M x K) * B (K x N) for K <= 64, the small factor A read
