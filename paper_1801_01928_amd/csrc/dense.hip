@@ -450,8 +450,9 @@ __device__ void gemm_lds_b(int M, int N, int K, const float *A, long ar, long ac
                            Shared &sh) {
   for (int i0 = 0; i0 < M; i0 += 64) {
     const int mr = (M - i0) < 64 ? (M - i0) : 64;
+    // consecutive threads walk the unit-stride index of A (coalesced loads)
     for (int e = threadIdx.x; e < 64 * K; e += kThreads) {
-      const int ii = e / K, l = e % K;
+      const int ii = (ar == 1) ? (e & 63) : e / K, l = (ar == 1) ? (e >> 6) : e % K;
       sh.stg[ii * 65 + l] = (ii < mr) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
     }
     __syncthreads();
