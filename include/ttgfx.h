@@ -27,8 +27,8 @@
  *     device work is queued and no output is touched.
  *   - M = 0 (no observed entries) is a successful no-op that still writes
  *     well-defined outputs (zero gradients, zero loss).
- *   - Indices outside [0, n_k) are undefined behaviour (not checked on the
- *     device).
+ *   - Indices outside [0, n_k) are undefined behaviour in every entry point
+ *     except tt_check_indices, which finds them (checked mode).
  *   - Floating point is float32 on the device (the oracle is float64).
  */
 #ifndef TTGFX_H
@@ -53,7 +53,7 @@ enum {
   TT_ERR_UNSUPPORTED = -3,  /* rank/mode size beyond what the kernels support   */
   TT_ERR_WORKSPACE = -4,    /* workspace missing or smaller than required       */
   TT_ERR_HIP = -5,          /* HIP launch or runtime error                      */
-  TT_ERR_INDEX = -6         /* reserved: out-of-range index detected            */
+  TT_ERR_INDEX = -6         /* out-of-range index (tt_check_indices, checked mode) */
 };
 
 enum { TT_LR = 0, TT_RL = 1 };  /* orthogonalization direction */
@@ -115,6 +115,20 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
                            const float *t, float *y, float *g, float *loss,
                            tt_tensor *gX, void *ws, size_t ws_bytes,
                            void *stream);
+
+/* ------------------------------------------------------- checked mode */
+/* Index check.  The entry formula (Introduction) is defined for
+ * 0 <= i_k < n_k only, and the entry points above do not test their
+ * indices; a caller that cannot trust them runs this first.
+ * X: only d and n are read (data may be any non-null pointer).
+ * idx: (dev) int32 [d][M] as above.  out: (dev) int64 [2], written
+ * asynchronously: out[0] = number of entries m with some idx[k*M + m]
+ * outside [0, n_k); out[1] = the smallest such m, or M when there is none.
+ * M = 0 writes {0, 0}.  Reads idx once; no workspace; capturable.  The
+ * caller turns a nonzero out[0] into TT_ERR_INDEX (the Python binding does
+ * so before every call that takes indices when TTGFX_CHECKED=1). */
+int tt_check_indices(const tt_tensor *X, const int32_t *idx, int64_t M,
+                     int64_t *out, void *stream);
 
 /* ------------------------------------------------------------------ A4 */
 /* Orthogonalization sweep (QR sweeps of the TT literature the paper cites;

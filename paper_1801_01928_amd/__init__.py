@@ -7,6 +7,7 @@ the C ABI of include/ttgfx.h); this package marshals arguments only.
 from ._lib import load, TTError, last_error, TT_LR, TT_RL  # noqa: F401
 from .tt import (  # noqa: F401
     TT,
+    check_indices,
     gather,
     gather_backward,
     gather_mse_backward,

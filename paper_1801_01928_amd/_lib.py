@@ -66,6 +66,7 @@ SIGNATURES = {
     "tt_gather_backward": (C.c_int, [P_TT, VP, I64, VP, P_TT, VP, SZ, VP]),
     "tt_gather_mse_workspace": (I64, [P_TT, I64]),
     "tt_gather_mse_backward": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, P_TT, VP, SZ, VP]),
+    "tt_check_indices": (C.c_int, [P_TT, VP, I64, VP, VP]),
     "tt_orthogonalize_ranks": (C.c_int, [P_TT, C.c_int, PI32]),
     "tt_orthogonalize_workspace": (I64, [P_TT, C.c_int]),
     "tt_orthogonalize": (C.c_int, [P_TT, C.c_int, P_TT, VP, SZ, VP]),

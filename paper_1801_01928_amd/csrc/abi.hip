@@ -244,4 +244,13 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M, co
   return fused_mse_dispatch(X, idx, M, t, y, g, loss, gX, ws, ws_bytes, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------ index check
+int tt_check_indices(const tt_tensor *X, const int32_t *idx, int64_t M, int64_t *out, void *stream) {
+  int rc = validate_tt(X, "X", TT_MAX_RANK);
+  if (rc) return rc;
+  if (!out) return set_error(TT_ERR_ARG, "check_indices: null out");
+  if ((rc = check_entries(idx, M, nullptr, nullptr))) return rc;
+  return index_check(X, idx, M, out, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -6,6 +6,7 @@ a call into libttgfx.  A ``TT`` stores its cores in one flat float32 buffer
 exactly the descriptor layout of include/ttgfx.h with ``off = NULL``.
 """
 import ctypes as C
+import os
 
 import numpy as np
 import torch
@@ -102,10 +103,36 @@ def _vec(v, M, device):
     return v
 
 
+def check_indices(X, idx):
+    """Index check (tt_check_indices): returns (bad, first), the number of
+    entries of idx (d, M) with some index outside [0, n_k) of X's modes and
+    the smallest such entry (M when there is none)."""
+    lib = L.load()
+    idx = _idx(idx, X.d, X.device)
+    M = idx.shape[1]
+    out = torch.empty(2, dtype=torch.int64, device=X.device)
+    L.check(lib.tt_check_indices(C.byref(X.desc()), _ptr(idx), M, _ptr(out), _stream(X.device)))
+    bad, first = (int(v) for v in out.cpu())
+    return bad, first
+
+
+def _checked(X, idx):
+    """Checked mode, on when TTGFX_CHECKED=1: raise TT_ERR_INDEX before a
+    call whose indices leave [0, n_k) (the library's entry points treat such
+    indices as undefined behaviour).  Synchronizes with the device."""
+    if os.environ.get("TTGFX_CHECKED", "0") != "1":
+        return
+    bad, first = check_indices(X, idx)
+    if bad:
+        raise L.TTError(L.TT_ERR_INDEX, "%d of %d entries have an index outside [0, n_k); the first is "
+                        "entry %d with indices %s" % (bad, idx.shape[1], first, idx[:, first].tolist()))
+
+
 def gather(X, idx):
     """y[m] = G^1[i_1^m] ... G^d[i_d^m] (the entry formula) for idx (d, M)."""
     lib = L.load()
     idx = _idx(idx, X.d, X.device)
+    _checked(X, idx)
     M = idx.shape[1]
     y = torch.empty(M, dtype=torch.float32, device=X.device)
     ws, nb = _workspace(L.check(lib.tt_gather_workspace(C.byref(X.desc()), M)), X.device)
@@ -117,6 +144,7 @@ def gather_backward(X, idx, gy):
     """Core gradients of sum_m gy[m] y[m] (the gather's adjoint)."""
     lib = L.load()
     idx = _idx(idx, X.d, X.device)
+    _checked(X, idx)
     M = idx.shape[1]
     gy = _vec(gy, M, X.device)
     gX = X.empty_like()
@@ -139,6 +167,7 @@ def gather_mse_backward(X, idx, t, want_y=True, ws=None, out=None, loss=None, wa
     reuse buffers across calls."""
     lib = L.load()
     idx = _idx(idx, X.d, X.device)
+    _checked(X, idx)
     M = idx.shape[1]
     t = _vec(t, M, X.device)
     y = torch.empty(M, dtype=torch.float32, device=X.device) if want_y else None
@@ -225,6 +254,7 @@ def project_sparse(U, V, idx, z, alpha=1.0, add_x=0):
     TT  add_x * X + alpha * P_X(Z)."""
     lib = L.load()
     idx = _idx(idx, U.d, U.device)
+    _checked(U, idx)
     M = idx.shape[1]
     z = _vec(z, M, U.device)
     W = TT(U.ns, [1] + [2 * r for r in U.ranks[1:-1]] + [1], device=U.device)
@@ -300,6 +330,9 @@ class BatchedPlan:
         self.idx = torch.as_tensor(idx).to(device=dev, dtype=torch.int32).contiguous().reshape(-1)
         self.t = torch.as_tensor(t).to(device=dev, dtype=torch.float32).contiguous()
         self.entry_off = (C.c_int64 * len(entry_off))(*[int(x) for x in entry_off])
+        for j, X in enumerate(self.Xs):
+            e0, e1 = int(entry_off[j]), int(entry_off[j + 1])
+            _checked(X, self.idx[X.d * e0:X.d * e1].view(X.d, e1 - e0))
         self.grads = [X.empty_like() for X in self.Xs]
         self.loss = torch.empty(len(self.Xs), dtype=torch.float32, device=dev)
         self._bx, self._kx = _batch(self.Xs)

@@ -115,3 +115,15 @@ def test_matmul_validation_before_device(lib):
                                   C.c_void_p(0x10), 1 << 30, None) == L.TT_ERR_ARG
     # nothing requested: success without device work
     assert lib.tt_matmul_backward(C.byref(W), None, 4, None, None, None, 0, None, 0, None) == L.TT_OK
+
+
+def test_check_indices_validation_before_device(lib):
+    from paper_1801_01928_amd import _lib as L
+    X = _desc([3, 4], [1, 2, 1])
+    assert lib.tt_check_indices(C.byref(X), C.c_void_p(0x10), 5, None, None) == L.TT_ERR_ARG
+    assert "null out" in L.last_error()
+    assert lib.tt_check_indices(C.byref(X), C.c_void_p(0x10), -1, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    assert lib.tt_check_indices(C.byref(X), None, 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    Z = _desc([3], [1, 1])
+    Z.d = 0
+    assert lib.tt_check_indices(C.byref(Z), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
