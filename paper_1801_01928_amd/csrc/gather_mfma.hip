@@ -34,6 +34,8 @@
 // The per-tile work is one device function shared by the single-tensor
 // kernel (tiles in grid-stride order) and the batched persistent kernel
 // (work items from an atomic queue).
+#include <type_traits>
+
 #include "common.h"
 #include "gather_mfma.h"
 
@@ -109,10 +111,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   constexpr int W = NTHR / 64;    // waves
   constexpr int RS = R + 4;       // LDS row stride (padding spreads banks)
   constexpr int SS = R + 4;       // slab/edge row stride (conflict-free D stores)
-  constexpr int G = 1;            // blocks per step (one measured fastest at R = 16 and 32)
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
-  constexpr bool PF = true;       // prefetch the next block's slices and stash
   using L = Lds<R, T, NTHR, ACC>;
   float *rows = (float *)(smem + L::rows);
   float *slab = (float *)(smem + L::slab);
@@ -245,110 +245,92 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   lds_barrier();
 
   // --------------------------------------------------------- right sweep
-  // Each wave walks its blocks of mode k in groups of G; the MFMA chains of
-  // a group are independent, so the matrix pipe is fed back to back.  Loop
-  // bounds and slice ids are wave-uniform (scalar registers): the loop has
-  // no divergent branches and the LDS reads of a group issue together.
-  // Blocks past the wave's range re-read its last block and their results
-  // are discarded.  Padding columns read the zero row.
+  // Each wave walks its blocks of mode k.  Loop bounds and slice ids are
+  // wave-uniform (scalar registers): no divergent branches.  Slices load
+  // two blocks ahead into two register sets used in turn (the loop is
+  // unrolled by two and its first pair peeled).  Every global access inside
+  // the loop is unconditional (loads past the wave's last block re-read
+  // it), so the compiler's memory-counter waits are exact: a block waits
+  // for its own slices, not for the stash stores of the blocks before it.
+  // Padding columns read the zero row.
   for (int k = d - 1; k >= 0; --k) {
     const int nb = __builtin_amdgcn_readfirstlane(nblk[k]);
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
-    const uint16_t *pk = perm + pbase_of<T>(p, k);
-    const uint8_t *bk = bslc + bbase_of<T>(p, k);
-    const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
-    const int mysl = (lane < je - jb) ? bk[jb + lane] : 0;  // slice of block jb + lane
-    const bool last = (k == d - 1);
-    // the slices of the next group are loaded while this group computes
-    v4f an[G][NT * NT];
-    auto load_slices = [&](int jn) {
+    if (jb < je) {
+      const uint16_t *pk = perm + pbase_of<T>(p, k);
+      const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
+      const int mysl = (lane < je - jb) ? bslc[bbase_of<T>(p, k) + jb + lane] : 0;  // slice of block jb + lane
+      const bool last = (k == d - 1);
+      auto ld = [&](int j, v4f(&dst)[NT * NT]) {
+        const int jj = j < je ? j : je - 1;
+        const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, jj - jb) * R * R;
 #pragma unroll
-      for (int b = 0; b < G; ++b) {
-        const int j = jn + b;
-        if (j < je) {
-          const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, j - jb) * R * R;
+        for (int x = 0; x < NT * NT; ++x) dst[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+      };
+      auto sweep = [&](auto stash_tag) {
+        constexpr bool ST = decltype(stash_tag)::value;
+        auto block = [&](int j, const v4f(&a)[NT * NT]) {
+          const int ent = pk[16 * j + c16];
+          v4f bv[NT];
 #pragma unroll
-          for (int x = 0; x < NT * NT; ++x) an[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-        } else {
+          for (int t = 0; t < NT; ++t) {
+            if (last)
+              bv[t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
+            else
+              bv[t] = *(const v4f *)(rows + ent * RS + 16 * t + 4 * q4);
+          }
+          if constexpr (ST) {
+            // stash rho_{k+1} of this block in CL layout
+            const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+            const int ev[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+            v4f cl[NT];
 #pragma unroll
-          for (int x = 0; x < NT * NT; ++x) an[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-    };
-    if (PF && jb < je) load_slices(jb);
-    for (int j0 = jb; j0 < je; j0 += G) {
-      if (!PF) load_slices(j0);
-      v4f a[G][NT * NT];
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int b = 0; b < G; ++b)
-#pragma unroll
-        for (int x = 0; x < NT * NT; ++x) a[b][x] = an[b][x];
-      if (PF && j0 + G < je) load_slices(j0 + G);
-      int ent[G], ev[G][4];
-#pragma unroll
-      for (int b = 0; b < G; ++b) {
-        const int j = (j0 + b < je) ? j0 + b : je - 1;
-        ent[b] = pk[16 * j + c16];
-        const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-        ev[b][0] = (int)(q.x & 0xFFFF);
-        ev[b][1] = (int)(q.x >> 16);
-        ev[b][2] = (int)(q.y & 0xFFFF);
-        ev[b][3] = (int)(q.y >> 16);
-      }
-      v4f bv[G][NT];
-#pragma unroll
-      for (int b = 0; b < G; ++b) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          if (last)
-            bv[b][t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
-          else
-            bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
-        }
-      }
-      if (MODE != MODE_GATHER && k <= d - 2) {
-        // stash rho_{k+1} of these blocks in CL layout
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-          v4f cl[NT];
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[b][v] * RS + 16 * t + c16];
-          if (j0 + b < je) {
-            float *st = stash + ((long long)k * nb_max + j0 + b) * (64 * R / 4);
+              for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[v] * RS + 16 * t + c16];
+            float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
 #pragma unroll
             for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = cl[t];
           }
+          v4f out[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) out[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
+          if (k > 0) {
+            // a padding column is zero (zero row in, zero out) except in the
+            // first step, where the input is e_0: that one goes to the sink row
+            const int w = (last && ent == ZROW) ? SROW : ent;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[t];
+          } else if (q4 == 0 && ent != ZROW) {
+            wsum[ent] = out[0][0];  // component 0 of rho_1 = y
+          }
+        };
+        v4f a0[NT * NT], a1[NT * NT];
+        ld(jb, a0);
+        ld(jb + 1, a1);
+        auto pair = [&](int j) {
+          block(j, a0);
+          ld(j + 2, a0);
+          block(j + 1, a1);
+          ld(j + 3, a1);
+        };
+        int j = jb;
+        if (j + 1 < je) {
+          pair(j);
+          for (j += 2; j + 1 < je; j += 2) pair(j);
         }
-      }
-      v4f out[G][NT];
-#pragma unroll
-      for (int b = 0; b < G; ++b)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) out[b][t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int to = 0; to < NT; ++to)
-#pragma unroll
-            for (int b = 0; b < G; ++b)
-              out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
-#pragma unroll
-      for (int b = 0; b < G; ++b) {
-        if (j0 + b >= je) continue;
-        if (k > 0) {
-          // a padding column is zero (zero row in, zero out) except in the
-          // first step, where the input is e_0: that one goes to the sink row
-          const int w = (last && ent[b] == ZROW) ? SROW : ent[b];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) *(v4f *)(rows + w * RS + 16 * t + 4 * q4) = out[b][t];
-        } else if (q4 == 0 && ent[b] != ZROW) {
-          wsum[ent[b]] = out[b][0][0];  // component 0 of rho_1 = y
-        }
-      }
+        if (j < je) block(j, a0);
+      };
+      if (MODE != MODE_GATHER && k <= d - 2)
+        sweep(std::true_type{});
+      else
+        sweep(std::false_type{});
     }
     lds_barrier();
   }
@@ -389,6 +371,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   // slice stores its run into slab[s]; a wave whose first run continues a
   // slice of the previous wave stores that run into its edge buffer.  The
   // flush adds slab and edges in a fixed order: no atomics, deterministic.
+  // The accumulator values of the flush load at mode start.
+  constexpr int FLN = (ACC == ACC_SLAB) ? (L::NMAX * R * R / 4 + NTHR - 1) / NTHR : 1;
   for (int k = 0; k < d; ++k) {
     const int nk = p.n[k];
     if constexpr (ACC == ACC_SLAB) {
@@ -400,11 +384,19 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
     const uint16_t *pk = perm + pbase_of<T>(p, k);
     const uint8_t *bk = bslc + bbase_of<T>(p, k);
-    const float *gk = p.gp_left + (long long)p.sbase[k] * R * R;
     const bool chain = k < d - 1;
     const int mysl = (lane < je - jb) ? bk[jb + lane] : 0;  // slice of block jb + lane
     const int prev_sl = __builtin_amdgcn_readfirstlane(jb > 0 ? (int)bk[jb - 1] : -1);
     const bool cont_first = (jb < je) && prev_sl == __builtin_amdgcn_readfirstlane(mysl);
+    float *ak = (ACC == ACC_SLAB) ? accg + (long long)p.sbase[k] * R * R : nullptr;
+    v4f accp[FLN];
+    if constexpr (ACC == ACC_SLAB) {
+#pragma unroll
+      for (int i = 0; i < FLN; ++i) {
+        const int e4 = tid + i * NTHR;
+        accp[i] = (!first_tile && e4 < nk * R * R / 4) ? *(const v4f *)(ak + 4 * e4) : v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    }
     bool first_run = true;
     int rsid = -1;
     v4f racc[NT * NT];
@@ -435,154 +427,122 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
               unsafeAtomicAdd(dst + (16 * ta + 4 * q4 + v) * R + 16 * tb + c16, racc[ta * NT + tb][v]);
       }
     };
-    // stashed right partials and slices of the next group are loaded while
-    // this group computes
-    v4f an[G][NT * NT];
-    v4f rn[G][NT];
-    auto load_group = [&](int jn) {
+    // operands of block j: rho_{k+1} (stash; e_0 for the last mode) in CL
+    // layout and slice G^k^T in A-operand layout, two blocks ahead in two
+    // register sets used in turn, as in the right sweep
+    auto ld = [&](int j, v4f(&ga)[NT * NT], v4f(&rr)[NT]) {
+      const int jj = j < je ? j : je - 1;
+      if (k <= d - 2) {
+        const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
 #pragma unroll
-      for (int b = 0; b < G; ++b) {
-        const int j = jn + b;
+        for (int t = 0; t < NT; ++t) rr[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+      } else {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
-          rn[b][t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+          rr[t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
         }
+      }
+      if (chain) {
+        const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
 #pragma unroll
-        for (int x = 0; x < NT * NT; ++x) an[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
-        if (j < je) {
-          if (k <= d - 2) {
-            const float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) rn[b][t] = *(const v4f *)(st + (t * 64 + lane) * 4);
-          }
-          if (chain) {
-            const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, j - jb) * R * R;
-#pragma unroll
-            for (int x = 0; x < NT * NT; ++x) an[b][x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-          }
-        }
+        for (int x = 0; x < NT * NT; ++x) ga[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
       }
     };
-    if (PF && jb < je) load_group(jb);
-    for (int j0 = jb; j0 < je; j0 += G) {
-      int ent[G], ev[G][4], sid[G];
-      bool act[G];
-      v4f a[G][NT * NT];
-      v4f rcl[G][NT];
-      if (!PF) load_group(j0);
-#pragma unroll
-      for (int b = 0; b < G; ++b) {
-#pragma unroll
-        for (int x = 0; x < NT * NT; ++x) a[b][x] = an[b][x];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) rcl[b][t] = rn[b][t];
-      }
-      if (PF && j0 + G < je) load_group(j0 + G);
-#pragma unroll
-      for (int b = 0; b < G; ++b) {
-        act[b] = j0 + b < je;
-        const int j = act[b] ? j0 + b : je - 1;
-        sid[b] = act[b] ? __builtin_amdgcn_readlane(mysl, j - jb) : -1;
-        ent[b] = pk[16 * j + c16];
-        const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-        ev[b][0] = (int)(q.x & 0xFFFF);
-        ev[b][1] = (int)(q.x >> 16);
-        ev[b][2] = (int)(q.y & 0xFFFF);
-        ev[b][3] = (int)(q.y >> 16);
-      }
+    auto block = [&](int j, const v4f(&a)[NT * NT], const v4f(&rcl)[NT]) {
+      const int sid = __builtin_amdgcn_readlane(mysl, j - jb);
+      const int ent = pk[16 * j + c16];
+      const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+      const int ev[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
       // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
-      v4f lcl[G][NT], bv[G][NT];
+      v4f lcl[NT], bv[NT];
 #pragma unroll
-      for (int b = 0; b < G; ++b) {
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int t = 0; t < NT; ++t) lcl[t][v] = rows[ev[v] * RS + 16 * t + c16];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) lcl[b][t][v] = rows[ev[b][v] * RS + 16 * t + c16];
+      for (int t = 0; t < NT; ++t) bv[t] = *(const v4f *)(rows + ent * RS + 16 * t + 4 * q4);
+      // outer products (NT * NT independent chains)
+      v4f dg[NT * NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) bv[b][t] = *(const v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4);
-      }
-      // outer products (G * NT * NT independent chains)
-      v4f dg[G][NT * NT];
-#pragma unroll
-      for (int b = 0; b < G; ++b)
-#pragma unroll
-        for (int x = 0; x < NT * NT; ++x) dg[b][x] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int x = 0; x < NT * NT; ++x) dg[x] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-          for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-            for (int b = 0; b < G; ++b)
-              dg[b][ta * NT + tb] = mfma4(lcl[b][ta][c], rcl[b][tb][c], dg[b][ta * NT + tb]);
+          for (int tb = 0; tb < NT; ++tb) dg[ta * NT + tb] = mfma4(lcl[ta][c], rcl[tb][c], dg[ta * NT + tb]);
       // chain lambda_{k+1}^T = G^T lambda_k^T
-      v4f out[G][NT];
       if (chain) {
+        v4f out[NT];
 #pragma unroll
-        for (int b = 0; b < G; ++b)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) out[b][t] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; ++t) out[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int to = 0; to < NT; ++to)
+            for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
+        // a padding column reads the zero row and writes zeros back to it
 #pragma unroll
-              for (int b = 0; b < G; ++b)
-                out[b][to] = mfma4(a[b][to * NT + ti][c], bv[b][ti][c], out[b][to]);
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-          if (!act[b]) continue;
-          // a padding column reads the zero row and writes zeros back to it
-#pragma unroll
-          for (int t = 0; t < NT; ++t) *(v4f *)(rows + ent[b] * RS + 16 * t + 4 * q4) = out[b][t];
-        }
+        for (int t = 0; t < NT; ++t) *(v4f *)(rows + ent * RS + 16 * t + 4 * q4) = out[t];
       }
-      // merge the group's outer products into runs
-#pragma unroll
-      for (int b = 0; b < G; ++b) {
-        if (!act[b]) continue;
-        if (sid[b] != rsid) {
-          if (rsid >= 0) {
-            emit_run(rsid, first_run && cont_first);
-            first_run = false;
-          }
-          rsid = sid[b];
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) racc[x] = dg[b][x];
-        } else {
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) racc[x] += dg[b][x];
+      // merge the block's outer products into runs
+      if (sid != rsid) {
+        if (rsid >= 0) {
+          emit_run(rsid, first_run && cont_first);
+          first_run = false;
         }
+        rsid = sid;
+#pragma unroll
+        for (int x = 0; x < NT * NT; ++x) racc[x] = dg[x];
+      } else {
+#pragma unroll
+        for (int x = 0; x < NT * NT; ++x) racc[x] += dg[x];
       }
+    };
+    if (jb < je) {
+      v4f a0[NT * NT], a1[NT * NT], r0[NT], r1[NT];
+      ld(jb, a0, r0);
+      ld(jb + 1, a1, r1);
+      auto pair = [&](int j) {
+        block(j, a0, r0);
+        ld(j + 2, a0, r0);
+        block(j + 1, a1, r1);
+        ld(j + 3, a1, r1);
+      };
+      int j = jb;
+      if (j + 1 < je) {
+        pair(j);
+        for (j += 2; j + 1 < je; j += 2) pair(j);
+      }
+      if (j < je) block(j, a0, r0);
     }
     if (rsid >= 0) emit_run(rsid, first_run && cont_first);
     lds_barrier();
     if constexpr (ACC == ACC_SLAB) {
       // flush this mode into the workgroup's accumulator: a plain store on
-      // the first tile, a load-add-store after (4 floats per thread and
-      // step; edge owners read once).  The same thread owns the same
-      // accumulator elements on every tile, so no synchronisation is needed,
-      // and no atomics sit in the in-order memory counter that later loads
-      // of this wave wait on.
-      float *ak = accg + (long long)p.sbase[k] * R * R;
+      // the first tile, an add to the values loaded at mode start after
+      // (4 floats per thread and step; edge owners read once).  The same
+      // thread owns the same accumulator elements on every tile, so no
+      // synchronisation is needed, and no atomics sit in the in-order
+      // memory counter that later loads of this wave wait on.
       int es[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) es[w] = eslice[w];
-      for (int e4 = tid; e4 < nk * R * R / 4; e4 += NTHR) {
+#pragma unroll
+      for (int i = 0; i < FLN; ++i) {
+        const int e4 = tid + i * NTHR;
+        if (e4 >= nk * R * R / 4) break;
         const int e = 4 * e4;
         const int sl = e / (R * R), a = (e / R) % R, b = e % R;
-        v4f v = {0.f, 0.f, 0.f, 0.f};
+        v4f v = accp[i];
         if (sflag[sl]) {
-          v = *(const v4f *)(slab + sl * R * SS + a * SS + b);
+          v += *(const v4f *)(slab + sl * R * SS + a * SS + b);
 #pragma unroll
           for (int w = 0; w < W; ++w)
             if (es[w] == sl) v += *(const v4f *)(edges + w * R * SS + a * SS + b);
         }
-        if (!first_tile) v += *(const v4f *)(ak + e);
         *(v4f *)(ak + e) = v;
       }
       lds_barrier();
