@@ -260,15 +260,19 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
       const uint16_t *pk = perm + pbase_of<T>(p, k);
       const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
       const int mysl = (lane < je - jb) ? bslc[bbase_of<T>(p, k) + jb + lane] : 0;  // slice of block jb + lane
-      const bool last = (k == d - 1);
       auto ld = [&](int j, v4f(&dst)[NT * NT]) {
         const int jj = j < je ? j : je - 1;
         const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, jj - jb) * R * R;
 #pragma unroll
         for (int x = 0; x < NT * NT; ++x) dst[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
       };
-      auto sweep = [&](auto stash_tag) {
+      // mode kinds get their own loop bodies, free of runtime branches:
+      // first step (k = d-1: input e_0, nothing to stash), middle steps, and
+      // the last step (k = 0: writes y)
+      auto sweep = [&](auto stash_tag, auto last_tag, auto end_tag) {
         constexpr bool ST = decltype(stash_tag)::value;
+        constexpr bool last = decltype(last_tag)::value;
+        constexpr bool END = decltype(end_tag)::value;
         auto block = [&](int j, const v4f(&a)[NT * NT]) {
           const int ent = pk[16 * j + c16];
           v4f bv[NT];
@@ -301,7 +305,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
             for (int c = 0; c < 4; ++c)
 #pragma unroll
               for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
-          if (k > 0) {
+          if constexpr (!END) {
             // a padding column is zero (zero row in, zero out) except in the
             // first step, where the input is e_0: that one goes to the sink row
             const int w = (last && ent == ZROW) ? SROW : ent;
@@ -327,10 +331,15 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         }
         if (j < je) block(j, a0);
       };
-      if (MODE != MODE_GATHER && k <= d - 2)
-        sweep(std::true_type{});
+      using T1 = std::true_type;
+      using F0 = std::false_type;
+      constexpr bool STASH = MODE != MODE_GATHER;
+      if (k == d - 1)  // d >= 2, so this step is never the last
+        sweep(F0{}, T1{}, F0{});
+      else if (k > 0)
+        sweep(std::bool_constant<STASH>{}, F0{}, F0{});
       else
-        sweep(std::false_type{});
+        sweep(std::bool_constant<STASH>{}, F0{}, T1{});
     }
     lds_barrier();
   }
@@ -384,7 +393,6 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
     const uint16_t *pk = perm + pbase_of<T>(p, k);
     const uint8_t *bk = bslc + bbase_of<T>(p, k);
-    const bool chain = k < d - 1;
     const int mysl = (lane < je - jb) ? bk[jb + lane] : 0;  // slice of block jb + lane
     const int prev_sl = __builtin_amdgcn_readfirstlane(jb > 0 ? (int)bk[jb - 1] : -1);
     const bool cont_first = (jb < je) && prev_sl == __builtin_amdgcn_readfirstlane(mysl);
@@ -427,81 +435,86 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
               unsafeAtomicAdd(dst + (16 * ta + 4 * q4 + v) * R + 16 * tb + c16, racc[ta * NT + tb][v]);
       }
     };
-    // operands of block j: rho_{k+1} (stash; e_0 for the last mode) in CL
-    // layout and slice G^k^T in A-operand layout, two blocks ahead in two
-    // register sets used in turn, as in the right sweep
-    auto ld = [&](int j, v4f(&ga)[NT * NT], v4f(&rr)[NT]) {
-      const int jj = j < je ? j : je - 1;
-      if (k <= d - 2) {
-        const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
+    // Two kinds of mode get their own loop bodies, free of runtime branches:
+    // k < d-1 (chain step, stashed rho_{k+1}) and k = d-1 (no chain step,
+    // rho_{d+1} = e_0, no global loads).  Operands of block j are rho_{k+1}
+    // in CL layout and slice G^k^T in A-operand layout, loaded two blocks
+    // ahead into two register sets used in turn, as in the right sweep.
+    auto sweep = [&](auto chain_tag) {
+      constexpr bool CHAIN = decltype(chain_tag)::value;
+      auto ld = [&](int j, v4f(&ga)[NT * NT], v4f(&rr)[NT]) {
+        if constexpr (CHAIN) {
+          const int jj = j < je ? j : je - 1;
+          const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) rr[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
-      } else {
+          for (int t = 0; t < NT; ++t) rr[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+          const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
-          rr[t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+          for (int x = 0; x < NT * NT; ++x) ga[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+        } else {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
+            rr[t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+          }
         }
-      }
-      if (chain) {
-        const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
+      };
+      auto block = [&](int j, const v4f(&a)[NT * NT], const v4f(&rcl)[NT]) {
+        const int sid = __builtin_amdgcn_readlane(mysl, j - jb);
+        const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
+        const int ev[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
+        // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
+        v4f lcl[NT];
 #pragma unroll
-        for (int x = 0; x < NT * NT; ++x) ga[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-      }
-    };
-    auto block = [&](int j, const v4f(&a)[NT * NT], const v4f(&rcl)[NT]) {
-      const int sid = __builtin_amdgcn_readlane(mysl, j - jb);
-      const int ent = pk[16 * j + c16];
-      const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-      const int ev[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
-      // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
-      v4f lcl[NT], bv[NT];
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+          for (int t = 0; t < NT; ++t) lcl[t][v] = rows[ev[v] * RS + 16 * t + c16];
+        int ent = 0;
+        v4f bv[NT];
+        if constexpr (CHAIN) {
+          ent = pk[16 * j + c16];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) lcl[t][v] = rows[ev[v] * RS + 16 * t + c16];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) bv[t] = *(const v4f *)(rows + ent * RS + 16 * t + 4 * q4);
-      // outer products (NT * NT independent chains)
-      v4f dg[NT * NT];
-#pragma unroll
-      for (int x = 0; x < NT * NT; ++x) dg[x] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-          for (int tb = 0; tb < NT; ++tb) dg[ta * NT + tb] = mfma4(lcl[ta][c], rcl[tb][c], dg[ta * NT + tb]);
-      // chain lambda_{k+1}^T = G^T lambda_k^T
-      if (chain) {
-        v4f out[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) out[t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
-        // a padding column reads the zero row and writes zeros back to it
-#pragma unroll
-        for (int t = 0; t < NT; ++t) *(v4f *)(rows + ent * RS + 16 * t + 4 * q4) = out[t];
-      }
-      // merge the block's outer products into runs
-      if (sid != rsid) {
-        if (rsid >= 0) {
-          emit_run(rsid, first_run && cont_first);
-          first_run = false;
+          for (int t = 0; t < NT; ++t) bv[t] = *(const v4f *)(rows + ent * RS + 16 * t + 4 * q4);
         }
-        rsid = sid;
+        // outer products (NT * NT independent chains)
+        v4f dg[NT * NT];
 #pragma unroll
-        for (int x = 0; x < NT * NT; ++x) racc[x] = dg[x];
-      } else {
+        for (int x = 0; x < NT * NT; ++x) dg[x] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int x = 0; x < NT * NT; ++x) racc[x] += dg[x];
-      }
-    };
-    if (jb < je) {
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb) dg[ta * NT + tb] = mfma4(lcl[ta][c], rcl[tb][c], dg[ta * NT + tb]);
+        // chain lambda_{k+1}^T = G^T lambda_k^T
+        if constexpr (CHAIN) {
+          v4f out[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) out[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
+          // a padding column reads the zero row and writes zeros back to it
+#pragma unroll
+          for (int t = 0; t < NT; ++t) *(v4f *)(rows + ent * RS + 16 * t + 4 * q4) = out[t];
+        }
+        // merge the block's outer products into runs
+        if (sid != rsid) {
+          if (rsid >= 0) {
+            emit_run(rsid, first_run && cont_first);
+            first_run = false;
+          }
+          rsid = sid;
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) racc[x] = dg[x];
+        } else {
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) racc[x] += dg[x];
+        }
+      };
       v4f a0[NT * NT], a1[NT * NT], r0[NT], r1[NT];
       ld(jb, a0, r0);
       ld(jb + 1, a1, r1);
@@ -517,6 +530,12 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         for (j += 2; j + 1 < je; j += 2) pair(j);
       }
       if (j < je) block(j, a0, r0);
+    };
+    if (jb < je) {
+      if (k < d - 1)
+        sweep(std::true_type{});
+      else
+        sweep(std::false_type{});
     }
     if (rsid >= 0) emit_run(rsid, first_run && cont_first);
     lds_barrier();
