@@ -247,8 +247,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   // --------------------------------------------------------- right sweep
   // Each wave walks its blocks of mode k.  Loop bounds and slice ids are
   // wave-uniform (scalar registers): no divergent branches.  Slices load
-  // two blocks ahead into two register sets used in turn (the loop is
-  // unrolled by two and its first pair peeled).  Every global access inside
+  // U blocks ahead into U register sets used in turn (the loop is unrolled
+  // by U and its first group peeled).  Every global access inside
   // the loop is unconditional (loads past the wave's last block re-read
   // it), so the compiler's memory-counter waits are exact: a block waits
   // for its own slices, not for the stash stores of the blocks before it.
@@ -315,21 +315,25 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
             wsum[ent] = out[0][0];  // component 0 of rho_1 = y
           }
         };
-        v4f a0[NT * NT], a1[NT * NT];
-        ld(jb, a0);
-        ld(jb + 1, a1);
-        auto pair = [&](int j) {
-          block(j, a0);
-          ld(j + 2, a0);
-          block(j + 1, a1);
-          ld(j + 3, a1);
+        constexpr int U = 2;  // blocks in flight (two and three measured best)
+        v4f ab[U][NT * NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ld(jb + u, ab[u]);
+        auto grp = [&](int j) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            block(j + u, ab[u]);
+            ld(j + u + U, ab[u]);
+          }
         };
         int j = jb;
-        if (j + 1 < je) {
-          pair(j);
-          for (j += 2; j + 1 < je; j += 2) pair(j);
+        if (j + U - 1 < je) {
+          grp(j);
+          for (j += U; j + U - 1 < je; j += U) grp(j);
         }
-        if (j < je) block(j, a0);
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u)
+          if (j + u < je) block(j + u, ab[u]);
       };
       using T1 = std::true_type;
       using F0 = std::false_type;
@@ -438,8 +442,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
     // Two kinds of mode get their own loop bodies, free of runtime branches:
     // k < d-1 (chain step, stashed rho_{k+1}) and k = d-1 (no chain step,
     // rho_{d+1} = e_0, no global loads).  Operands of block j are rho_{k+1}
-    // in CL layout and slice G^k^T in A-operand layout, loaded two blocks
-    // ahead into two register sets used in turn, as in the right sweep.
+    // in CL layout and slice G^k^T in A-operand layout, loaded U blocks
+    // ahead into U register sets used in turn, as in the right sweep.
     auto sweep = [&](auto chain_tag) {
       constexpr bool CHAIN = decltype(chain_tag)::value;
       auto ld = [&](int j, v4f(&ga)[NT * NT], v4f(&rr)[NT]) {
@@ -515,21 +519,25 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           for (int x = 0; x < NT * NT; ++x) racc[x] += dg[x];
         }
       };
-      v4f a0[NT * NT], a1[NT * NT], r0[NT], r1[NT];
-      ld(jb, a0, r0);
-      ld(jb + 1, a1, r1);
-      auto pair = [&](int j) {
-        block(j, a0, r0);
-        ld(j + 2, a0, r0);
-        block(j + 1, a1, r1);
-        ld(j + 3, a1, r1);
+      constexpr int U = 3;
+      v4f ab[U][NT * NT], rb[U][NT];
+#pragma unroll
+      for (int u = 0; u < U; ++u) ld(jb + u, ab[u], rb[u]);
+      auto grp = [&](int j) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          block(j + u, ab[u], rb[u]);
+          ld(j + u + U, ab[u], rb[u]);
+        }
       };
       int j = jb;
-      if (j + 1 < je) {
-        pair(j);
-        for (j += 2; j + 1 < je; j += 2) pair(j);
+      if (j + U - 1 < je) {
+        grp(j);
+        for (j += U; j + U - 1 < je; j += U) grp(j);
       }
-      if (j < je) block(j, a0, r0);
+#pragma unroll
+      for (int u = 0; u < U - 1; ++u)
+        if (j + u < je) block(j + u, ab[u], rb[u]);
     };
     if (jb < je) {
       if (k < d - 1)
