@@ -209,12 +209,19 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         run += c[ch];
       }
       const int padded = (lane < nk) ? ((run + 15) & ~15) : 0;
+      // inclusive prefix sum over the NSL slice lanes: row shifts inside
+      // 16-lane DPP rows (shifted-in lanes read zero), then, for 32 slices,
+      // lane 15 of row 0 broadcast into row 1
       int incl = padded;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off);
-        if (lane >= off) incl += t;
+      incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xF, 0xF, true);  // row_shr:1
+      incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xF, 0xF, true);  // row_shr:2
+      incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xF, 0xF, true);  // row_shr:4
+      incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xF, 0xF, true);  // row_shr:8
+      if constexpr (NSL > 16) {
+        static_assert(NSL <= 32, "slice counts must fit two DPP rows");
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xA, 0xF, false);  // row_bcast:15
       }
+      const int total = __builtin_amdgcn_readlane(incl, NSL - 1);
       const int base = incl - padded;
       if (lane < nk) {
         int o = base;
@@ -228,7 +235,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         uint8_t *bk = bslc + bbase_of<T>(p, k) + base / 16;
         for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
       }
-      if (lane == 63) nblk[k] = incl / 16;
+      if (lane == 0) nblk[k] = total / 16;
     }
     lds_barrier();
     for (int k = 0; k < d; ++k) {
