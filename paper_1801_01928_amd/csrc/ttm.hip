@@ -48,6 +48,19 @@ __device__ __forceinline__ float load_el(const void *p, long long i) {
   return ((const float *)p)[i];
 }
 
+// Four consecutive elements at element offset i (a multiple of 4), widened
+// to float.
+template <int BF16>
+__device__ __forceinline__ v4f load4(const void *p, long long i) {
+  if constexpr (BF16) {
+    const uint2 u = *(const uint2 *)((const uint16_t *)p + i);
+    return v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+               __uint_as_float(u.y & 0xffff0000u)};
+  } else {
+    return *(const v4f *)((const float *)p + i);
+  }
+}
+
 constexpr int kThreads = 256;  // 4 waves
 constexpr int kRows = 64;      // rows per workgroup iteration, 16 per wave
 constexpr int kMaxTiles = TTM_MAX_FUSED / 16;
@@ -182,7 +195,9 @@ struct GradArgs {
 constexpr int kSlab = 32;
 constexpr int kLd = TTM_MAX_FUSED + 4;
 
-template <int BF16>
+// VT, VV: the rank of T (of V) is a multiple of 4, so that operand's
+// elements (a, or b, fastest) load four at a time.
+template <int BF16, int VT, int VV>
 __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   __shared__ float ts[kSlab][kLd];
   __shared__ float vs[kSlab][kLd];
@@ -211,8 +226,9 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   // current one is multiplied.  Per-slab (p, q) base offsets are computed
   // one slab ahead by kSlab threads into a double-buffered table.
   __shared__ long long tb[2][kSlab], vb[2][kSlab];
-  constexpr int kPer = kSlab * TTM_MAX_FUSED / kThreads;  // loads per thread and operand
-  float tr[kPer], vr[kPer];
+  constexpr int ET = VT ? 4 : 1, EV = VV ? 4 : 1;  // elements per load
+  constexpr int kPerT = kSlab * TTM_MAX_FUSED / kThreads / ET, kPerV = kSlab * TTM_MAX_FUSED / kThreads / EV;
+  float tr[kPerT][ET], vr[kPerV][EV];
   auto bases = [&](long long kb, int buf) {
     if (tid < kSlab) {
       const long long kk = kb + tid;
@@ -223,17 +239,39 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   };
   auto fetch = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int e = tid + u * kThreads;
-      tr[u] = 0.f;
-      vr[u] = 0.f;
+    for (int u = 0; u < kPerT; ++u) {
+      const int e = ET * (tid + u * kThreads);  // first of this load's elements
+#pragma unroll
+      for (int x = 0; x < ET; ++x) tr[u][x] = 0.f;
       if (e < kSlab * ROWS) {
         const long long base = tb[buf][e / ROWS];
-        if (base >= 0) tr[u] = load_el<BF16>(g.T, base + roff[e % ROWS]);
+        if (base >= 0) {
+          if constexpr (VT) {
+            const v4f w = load4<BF16>(g.T, base + roff[e % ROWS]);
+#pragma unroll
+            for (int x = 0; x < ET; ++x) tr[u][x] = w[x];
+          } else {
+            tr[u][0] = load_el<BF16>(g.T, base + roff[e % ROWS]);
+          }
+        }
       }
+    }
+#pragma unroll
+    for (int u = 0; u < kPerV; ++u) {
+      const int e = EV * (tid + u * kThreads);
+#pragma unroll
+      for (int x = 0; x < EV; ++x) vr[u][x] = 0.f;
       if (e < kSlab * COLS) {
         const long long base = vb[buf][e / COLS];
-        if (base >= 0) vr[u] = load_el<BF16>(g.V, base + coffs[e % COLS]);
+        if (base >= 0) {
+          if constexpr (VV) {
+            const v4f w = load4<BF16>(g.V, base + coffs[e % COLS]);
+#pragma unroll
+            for (int x = 0; x < EV; ++x) vr[u][x] = w[x];
+          } else {
+            vr[u][0] = load_el<BF16>(g.V, base + coffs[e % COLS]);
+          }
+        }
       }
     }
   };
@@ -244,10 +282,18 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   for (long long kb = k0; kb < k1; kb += kSlab, ++sl) {
     __syncthreads();  // the previous slab is consumed
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int e = tid + u * kThreads;
-      if (e < kSlab * ROWS) ts[e / ROWS][e % ROWS] = tr[u];
-      if (e < kSlab * COLS) vs[e / COLS][e % COLS] = vr[u];
+    for (int u = 0; u < kPerT; ++u) {
+      const int e = ET * (tid + u * kThreads);
+#pragma unroll
+      for (int x = 0; x < ET; ++x)
+        if (e < kSlab * ROWS) ts[e / ROWS][e % ROWS + x] = tr[u][x];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerV; ++u) {
+      const int e = EV * (tid + u * kThreads);
+#pragma unroll
+      for (int x = 0; x < EV; ++x)
+        if (e < kSlab * COLS) vs[e / COLS][e % COLS + x] = vr[u][x];
     }
     bases(kb + kSlab, (sl + 1) & 1);
     __syncthreads();
@@ -545,10 +591,15 @@ int ttm_backward(const TTMDims &D, const void *cores, const void *X, long long B
       if (g.kchunk < 4) g.kchunk = 4;
       nwg = (K + g.kchunk - 1) / g.kchunk;
       if (nwg < 1) nwg = 1;
-      if (dtype)
-        hipLaunchKernelGGL(ttm_grad_kernel<1>, dim3((unsigned)nwg), dim3(kThreads), 0, st, g);
-      else
-        hipLaunchKernelGGL(ttm_grad_kernel<0>, dim3((unsigned)nwg), dim3(kThreads), 0, st, g);
+      // four-element loads need the operand's rank and base 4-aligned
+      const int al = dtype ? 8 : 16;
+      const int vt = g.rT % 4 == 0 && (uintptr_t)g.T % al == 0;
+      const int vv = g.rV % 4 == 0 && (uintptr_t)g.V % al == 0;
+      typedef void (*GradFn)(GradArgs);
+      static const GradFn fns[2][2][2] = {
+          {{ttm_grad_kernel<0, 0, 0>, ttm_grad_kernel<0, 0, 1>}, {ttm_grad_kernel<0, 1, 0>, ttm_grad_kernel<0, 1, 1>}},
+          {{ttm_grad_kernel<1, 0, 0>, ttm_grad_kernel<1, 0, 1>}, {ttm_grad_kernel<1, 1, 0>, ttm_grad_kernel<1, 1, 1>}}};
+      hipLaunchKernelGGL(fns[dtype ? 1 : 0][vt][vv], dim3((unsigned)nwg), dim3(kThreads), 0, st, g);
       if ((rc = launch_check("ttm core gradient"))) return rc;
       const long long cnt = core_cnt(D, k);
       hipLaunchKernelGGL(ttm_grad_reduce_kernel, dim3((unsigned)((cnt + 63) / 64)), dim3(256), 0, st,
