@@ -48,16 +48,16 @@ __device__ __forceinline__ float load_el(const void *p, long long i) {
   return ((const float *)p)[i];
 }
 
-// Four consecutive elements at element offset i (a multiple of 4), widened
-// to float.
-template <int BF16>
-__device__ __forceinline__ v4f load4(const void *p, long long i) {
-  if constexpr (BF16) {
-    const uint2 u = *(const uint2 *)((const uint16_t *)p + i);
-    return v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
-               __uint_as_float(u.y & 0xffff0000u)};
-  } else {
-    return *(const v4f *)((const float *)p + i);
+
+// Eight consecutive bfloat16 elements at element offset i (a multiple of
+// 8), widened to float.
+__device__ __forceinline__ void load8_bf16(const void *p, long long i, float (&o)[8]) {
+  const uint4 u = *(const uint4 *)((const uint16_t *)p + i);
+  const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    o[2 * x] = __uint_as_float(w[x] << 16);
+    o[2 * x + 1] = __uint_as_float(w[x] & 0xffff0000u);
   }
 }
 
@@ -195,8 +195,8 @@ struct GradArgs {
 constexpr int kSlab = 32;
 constexpr int kLd = TTM_MAX_FUSED + 4;
 
-// VT, VV: the rank of T (of V) is a multiple of 4, so that operand's
-// elements (a, or b, fastest) load four at a time.
+// VT, VV: the rank of T (of V) is a multiple of 4 (8 for bfloat16), so that
+// operand's elements (a, or b, fastest) load 16 bytes at a time.
 template <int BF16, int VT, int VV>
 __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   __shared__ float ts[kSlab][kLd];
@@ -226,7 +226,8 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   // current one is multiplied.  Per-slab (p, q) base offsets are computed
   // one slab ahead by kSlab threads into a double-buffered table.
   __shared__ long long tb[2][kSlab], vb[2][kSlab];
-  constexpr int ET = VT ? 4 : 1, EV = VV ? 4 : 1;  // elements per load
+  constexpr int EW = BF16 ? 8 : 4;                   // elements in 16 bytes
+  constexpr int ET = VT ? EW : 1, EV = VV ? EW : 1;  // elements per load
   constexpr int kPerT = kSlab * TTM_MAX_FUSED / kThreads / ET, kPerV = kSlab * TTM_MAX_FUSED / kThreads / EV;
   float tr[kPerT][ET], vr[kPerV][EV];
   auto bases = [&](long long kb, int buf) {
@@ -246,8 +247,10 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
       if (e < kSlab * ROWS) {
         const long long base = tb[buf][e / ROWS];
         if (base >= 0) {
-          if constexpr (VT) {
-            const v4f w = load4<BF16>(g.T, base + roff[e % ROWS]);
+          if constexpr (VT && BF16) {
+            load8_bf16(g.T, base + roff[e % ROWS], tr[u]);
+          } else if constexpr (VT) {
+            const v4f w = *(const v4f *)((const float *)g.T + base + roff[e % ROWS]);
 #pragma unroll
             for (int x = 0; x < ET; ++x) tr[u][x] = w[x];
           } else {
@@ -264,8 +267,10 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
       if (e < kSlab * COLS) {
         const long long base = vb[buf][e / COLS];
         if (base >= 0) {
-          if constexpr (VV) {
-            const v4f w = load4<BF16>(g.V, base + coffs[e % COLS]);
+          if constexpr (VV && BF16) {
+            load8_bf16(g.V, base + coffs[e % COLS], vr[u]);
+          } else if constexpr (VV) {
+            const v4f w = *(const v4f *)((const float *)g.V + base + coffs[e % COLS]);
 #pragma unroll
             for (int x = 0; x < EV; ++x) vr[u][x] = w[x];
           } else {
@@ -591,10 +596,11 @@ int ttm_backward(const TTMDims &D, const void *cores, const void *X, long long B
       if (g.kchunk < 4) g.kchunk = 4;
       nwg = (K + g.kchunk - 1) / g.kchunk;
       if (nwg < 1) nwg = 1;
-      // four-element loads need the operand's rank and base 4-aligned
-      const int al = dtype ? 8 : 16;
-      const int vt = g.rT % 4 == 0 && (uintptr_t)g.T % al == 0;
-      const int vv = g.rV % 4 == 0 && (uintptr_t)g.V % al == 0;
+      // 16-byte loads need the operand's rank to fill them and its base
+      // 16-byte aligned
+      const int ew = dtype ? 8 : 4;
+      const int vt = g.rT % ew == 0 && (uintptr_t)g.T % 16 == 0;
+      const int vv = g.rV % ew == 0 && (uintptr_t)g.V % 16 == 0;
       typedef void (*GradFn)(GradArgs);
       static const GradFn fns[2][2][2] = {
           {{ttm_grad_kernel<0, 0, 0>, ttm_grad_kernel<0, 0, 1>}, {ttm_grad_kernel<0, 1, 0>, ttm_grad_kernel<0, 1, 1>}},
