@@ -431,11 +431,25 @@ __device__ void gemm_lds_a(int M, int N, int K, AOp aop, const float *B, long br
       sh.stg[l * 65 + jj] = (jj < nc) ? B[(long)l * br + (long)(j0 + jj) * bc] : 0.f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < M * nc; e += kThreads) {
-      const int i = e / nc, jj = e % nc;
-      float acc = 0.f;
-      for (int l = 0; l < K; ++l) acc = fmaf(aop(i, l), sh.stg[l * 65 + jj], acc);
-      C[(long)i * cr + (long)(j0 + jj) * cc] = acc;
+    // four outputs per thread at a time (independent FMA chains), K unrolled
+    const int tot = M * nc;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * kThreads) {
+      int i[4], jj[4];
+      float acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * kThreads < tot ? e0 + q * kThreads : e0;
+        i[q] = e / nc;
+        jj[q] = e % nc;
+        acc[q] = 0.f;
+      }
+#pragma unroll 4
+      for (int l = 0; l < K; ++l)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fmaf(aop(i[q], l), sh.stg[l * 65 + jj[q]], acc[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q * kThreads < tot) C[(long)i[q] * cr + (long)(j0 + jj[q]) * cc] = acc[q];
     }
     __syncthreads();
   }
@@ -445,7 +459,11 @@ __device__ void gemm_lds_a(int M, int N, int K, AOp aop, const float *B, long br
 // (element (i, l) at A[i*ar + l*ac]) staged in chunks of 64 rows, the small
 // factor B read from LDS through bop(l, j).  C may alias A when row i of C
 // (C[i*ldc + j]) never reaches past row i of A, i.e. ldc <= A's row stride.
-template <class BOp>
+// ROWS_ON_LANES: the lanes of a wave take the rows of one column (bop is
+// then read at one address per wave), for factors whose elements of one
+// row l sit in a single LDS bank across columns; otherwise lanes take
+// consecutive columns of a row (coalesced stores).
+template <bool ROWS_ON_LANES = false, class BOp>
 __device__ void gemm_lds_b(int M, int N, int K, const float *A, long ar, long ac, BOp bop, float *C, long ldc,
                            Shared &sh) {
   for (int i0 = 0; i0 < M; i0 += 64) {
@@ -456,11 +474,25 @@ __device__ void gemm_lds_b(int M, int N, int K, const float *A, long ar, long ac
       sh.stg[ii * 65 + l] = (ii < mr) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < mr * N; e += kThreads) {
-      const int ii = e / N, j = e % N;
-      float acc = 0.f;
-      for (int l = 0; l < K; ++l) acc = fmaf(sh.stg[ii * 65 + l], bop(l, j), acc);
-      C[(long)(i0 + ii) * ldc + j] = acc;
+    // four outputs per thread at a time (independent FMA chains), K unrolled
+    const int tot = (ROWS_ON_LANES ? 64 : mr) * N;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * kThreads) {
+      int ii[4], j[4];
+      float acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * kThreads < tot ? e0 + q * kThreads : e0;
+        ii[q] = ROWS_ON_LANES ? (e & 63) : e / N;
+        j[q] = ROWS_ON_LANES ? (e >> 6) : e % N;
+        acc[q] = 0.f;
+      }
+#pragma unroll 4
+      for (int l = 0; l < K; ++l)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fmaf(sh.stg[ii[q] * 65 + l], bop(l, j[q]), acc[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q * kThreads < tot && ii[q] < mr) C[(long)(i0 + ii[q]) * ldc + j[q]] = acc[q];
     }
     __syncthreads();
   }
@@ -629,7 +661,9 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       disc[k] = s;
     }
     // U = Q (m x p) * V[:, perm[j]] for j < keep -> core k (row-major m x keep)
-    gemm_lds_b(m, keep, p, b.q, 1, m, [&](int l, int j) { return sh.jv[sh.perm[j] * kJac + l]; }, G, keep, sh);
+    // (columns of V are kJac floats apart: one LDS bank for a fixed l)
+    gemm_lds_b<true>(m, keep, p, b.q, 1, m, [&](int l, int j) { return sh.jv[sh.perm[j] * kJac + l]; }, G, keep,
+                     sh);
     // sign fix: the largest-magnitude component of each kept column is positive
     for (int j = wave; j < keep; j += kWaves) {
       float best = -1.f, val = 0.f;
