@@ -385,10 +385,15 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
       be = row16_sum(be);
       ga = row16_sum(ga);
       // every lane of the row takes the same decision
-      if (on && fabsf(ga) > 1e-6f * sqrtf(al * be) && ga != 0.f) {
+      // |ga| > 1e-6 sqrt(al be), compared squared; the rotation uses the
+      // hardware reciprocal, square root and reciprocal square root (about
+      // 1 ulp each, so cs^2 + sn^2 = 1 to a few ulp), which shortens the
+      // dependent chain of every round
+      if (on && ga * ga > 1e-12f * (al * be) && ga != 0.f) {
         const float zeta = (be - al) / (2.f * ga);
-        const float tn = copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-        const float cs = 1.f / sqrtf(1.f + tn * tn);
+        const float tn = copysignf(1.f, zeta) *
+                         __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.f)));
+        const float cs = __builtin_amdgcn_rsqf(fmaf(tn, tn, 1.f));
         const float sn = cs * tn;
         v4f na, nb, ma, mb;
 #pragma unroll
