@@ -228,7 +228,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         if int(os.environ.get("RANK", "0")) == 0:
-            print("bench.py measures one GPU only: this build has no multi-GPU path "
+            print("bench.py measures one GPU only: the library has no multi-GPU path "
                   "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), flush=True)
         sys.exit(2)
 
