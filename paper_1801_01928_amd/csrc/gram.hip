@@ -87,22 +87,38 @@ __global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__
   const int ta = tp.x, tb = tp.y;
   const int a = ta * TILE + wa, b = tb * TILE + wb;
 
-  // stage one slice of the 4 + 4 tensors into buffer `buf`
-  auto stage = [&](int sl, int buf) {
-    for (int e = tid; e < 2 * TILE * SLICE / 4; e += THREADS) {
+  // one slice of the 4 + 4 tensors: loaded into registers (kPer vectors
+  // per thread) while the current slice is multiplied, stored to the other
+  // LDS buffer after the products
+  constexpr int kPer = 2 * TILE * SLICE / 4 / THREADS;
+  static_assert(kPer * THREADS == 2 * TILE * SLICE / 4, "whole vectors per thread");
+  v4f pre[kPer];
+  auto load = [&](int sl) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * THREADS;
       const int side = e / (TILE * SLICE / 4);
       const int rem = e % (TILE * SLICE / 4);
       const int which = rem / (SLICE / 4), off = rem % (SLICE / 4);
-      v4f x = {0.f, 0.f, 0.f, 0.f};
+      pre[u] = v4f{0.f, 0.f, 0.f, 0.f};
       if (side == 0) {
         const int ia = ta * TILE + which;
-        if (ia < na) x = ((const v4f *)(pa + ((long long)ia * md.total + sl) * SLICE))[off];
-        ((v4f *)sa[buf][which])[off] = x;
+        if (ia < na) pre[u] = ((const v4f *)(pa + ((long long)ia * md.total + sl) * SLICE))[off];
       } else {
         const int ib = tb * TILE + which;
-        if (ib < nb) x = ((const v4f *)(pb + ((long long)ib * md.total + sl) * SLICE))[off];
-        ((v4f *)sb[buf][which])[off] = x;
+        if (ib < nb) pre[u] = ((const v4f *)(pb + ((long long)ib * md.total + sl) * SLICE))[off];
       }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * THREADS;
+      const int side = e / (TILE * SLICE / 4);
+      const int rem = e % (TILE * SLICE / 4);
+      const int which = rem / (SLICE / 4), off = rem % (SLICE / 4);
+      if (side == 0) ((v4f *)sa[buf][which])[off] = pre[u];
+      else ((v4f *)sb[buf][which])[off] = pre[u];
     }
   };
 
@@ -116,11 +132,13 @@ __global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__
   if (lane == 0) psi[0][0] = 1.f;
 
   int sl = 0, buf = 0;
-  stage(0, 0);
+  load(0);
+  store(0);
   __syncthreads();
   for (int k = 0; k < md.d; ++k) {
     for (int i = 0; i < md.n[k]; ++i, ++sl) {
-      if (sl + 1 < md.total) stage(sl + 1, buf ^ 1);  // overlaps with this slice's products
+      const bool more = sl + 1 < md.total;
+      if (more) load(sl + 1);  // in flight during this slice's products
       v4f bo[4], ao[4];
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
@@ -152,6 +170,7 @@ __global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__
             for (int v = 0; v < 4; ++v) acc = mfma4(y[ti * 2 + to][v], ao[ti * 2 + tc][v], acc);
           nxt[to * 2 + tc] = acc;
         }
+      if (more) store(buf ^ 1);
       __syncthreads();  // the next slice's buffer is complete; this one may be overwritten
       buf ^= 1;
     }
