@@ -121,35 +121,47 @@ __global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32)
     v4f acc[kMaxTiles];
 #pragma unroll
     for (int t = 0; t < kMaxTiles; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int x = 0; x < KC; ++x) {
+    // A operand of K chunk x: the lane's 4 K values of its row (fp32), or
+    // the same 4 as bfloat16; the next chunk's load is in flight while this
+    // chunk's products run
+    auto load_a = [&](int x, v4f &af, v4s &ab) {
       const int kb = 16 * x + 4 * q4;
       if (BF16) {
-        v4s a4;
         if (VEC) {
           const long long o = koff[kb];
-          a4 = (rvalid && o >= 0) ? *(const v4s *)((const uint16_t *)s.in + abase + o) : v4s{0, 0, 0, 0};
+          ab = (rvalid && o >= 0) ? *(const v4s *)((const uint16_t *)s.in + abase + o) : v4s{0, 0, 0, 0};
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const long long o = koff[kb + v];
-            a4[v] = (rvalid && o >= 0) ? (short)((const uint16_t *)s.in)[abase + o] : (short)0;
+            ab[v] = (rvalid && o >= 0) ? (short)((const uint16_t *)s.in)[abase + o] : (short)0;
           }
         }
+      } else {
+        if (VEC) {
+          const long long o = koff[kb];
+          af = (rvalid && o >= 0) ? *(const v4f *)((const float *)s.in + abase + o) : v4f{0.f, 0.f, 0.f, 0.f};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const long long o = koff[kb + v];
+            af[v] = (rvalid && o >= 0) ? ((const float *)s.in)[abase + o] : 0.f;
+          }
+        }
+      }
+    };
+    v4f afn = {0.f, 0.f, 0.f, 0.f};
+    v4s abn = {0, 0, 0, 0};
+    load_a(0, afn, abn);
+    for (int x = 0; x < KC; ++x) {
+      const v4f av = afn;
+      const v4s a4 = abn;
+      if (x + 1 < KC) load_a(x + 1, afn, abn);
+      if (BF16) {
 #pragma unroll
         for (int t = 0; t < kMaxTiles; ++t)
           if (t < NT) acc[t] = mfma_bf16(a4, ((const v4s *)bsm)[(x * NT + t) * 64 + lane], acc[t]);
       } else {
-        v4f av;
-        if (VEC) {
-          const long long o = koff[kb];
-          av = (rvalid && o >= 0) ? *(const v4f *)((const float *)s.in + abase + o) : v4f{0.f, 0.f, 0.f, 0.f};
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const long long o = koff[kb + v];
-            av[v] = (rvalid && o >= 0) ? ((const float *)s.in)[abase + o] : 0.f;
-          }
-        }
 #pragma unroll
         for (int t = 0; t < kMaxTiles; ++t) {
           if (t < NT) {
