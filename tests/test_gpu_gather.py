@@ -184,3 +184,49 @@ def test_full_size_finite_differences(gpu_lib, full_d10):
         an.append(gsub[j])
     assert _rel(an, fd) <= 1e-8          # the oracle gradient is exact
     assert _rel(got[pick], np.concatenate([c.reshape(-1) for c in grads])[pick]) <= 1e-4
+
+
+def test_fused_pass_graph_replays(gpu_lib):
+    """The fused pass captured into a hipGraph (through torch.cuda.graph) and
+    replayed three times, with new targets written and an eager call made
+    between replays: every replay equals the eager result bit for bit (the
+    rank-16 path sums in a fixed order)."""
+    import torch
+    tt = gpu_lib
+    p = W.small_step(M=5000)
+    ns, ranks = p.ns, [1] + [16] * (len(p.ns) - 1) + [1]
+    rng = np.random.default_rng(77)
+    cores = [(rng.standard_normal((ranks[k], ns[k], ranks[k + 1])) / 4).astype(np.float32) for k in range(len(ns))]
+    X = tt.TT.from_cores(cores)
+    idx = torch.as_tensor(p.idx).cuda()
+    t = torch.zeros(p.M, device="cuda")
+    nbytes = tt.gather_mse_workspace(X, p.M)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ws_ref = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    gX, loss = X.empty_like(), torch.empty(1, device="cuda")
+    gX_ref, loss_ref = X.empty_like(), torch.empty(1, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tt.gather_mse_backward(X, idx, t, want_y=False, ws=ws, out=gX, loss=loss)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        tt.gather_mse_backward(X, idx, t, want_y=False, ws=ws, out=gX, loss=loss)
+    for rep in range(3):
+        t.copy_(torch.as_tensor(rng.standard_normal(p.M).astype(np.float32)).cuda())
+        tt.gather_mse_backward(X, idx, t, want_y=False, ws=ws_ref, out=gX_ref, loss=loss_ref)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gX.data, gX_ref.data), rep
+        assert torch.equal(loss, loss_ref), rep
+        # and against the oracle
+        y = oracle.gather(cores, p.idx)
+        tr = t.cpu().numpy().astype(np.float64)
+        g = 2.0 * (y - tr) / p.M
+        ref = oracle.gather_backward(cores, p.idx, g)
+        got = tt.TT(ns, ranks, gX.data).numpy_cores()
+        for a, b in zip(got, ref):
+            assert _rel(a, b) <= TOL
