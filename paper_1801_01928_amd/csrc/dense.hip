@@ -381,6 +381,10 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
         be = fmaf(xb[v], xb[v], be);
         ga = fmaf(xa[v], xb[v], ga);
       }
+      // the rotation's V columns were read with the B columns; this empty
+      // use keeps the compiler from sinking those reads into the branch
+      // below, which would add a second LDS round trip to every round
+      asm volatile("" ::"v"(ya), "v"(yb));
       al = row16_sum(al);
       be = row16_sum(be);
       ga = row16_sum(ga);
