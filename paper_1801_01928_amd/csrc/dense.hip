@@ -216,12 +216,15 @@ __device__ void reg_qr(float *Wm, int m, int c, float *Q, Shared &sh) {
         beta = (x0 >= 0.f) ? 0.f : 2.f;
         rjj = fabsf(x0);
       } else {
+        // sigma > 0, so x0 + mu > 0 when x0 > 0, v0 < 0 and sigma + v0^2 > 0:
+        // the hardware reciprocal (about 1 ulp) is safe for all three
+        // quotients on this wave's serial path
         const float mu = sqrtf(x0 * x0 + sigma);
-        v0 = (x0 <= 0.f) ? x0 - mu : -sigma / (x0 + mu);
-        beta = 2.f * v0 * v0 / (sigma + v0 * v0);
+        v0 = (x0 <= 0.f) ? x0 - mu : -sigma * __builtin_amdgcn_rcpf(x0 + mu);
+        beta = 2.f * v0 * v0 * __builtin_amdgcn_rcpf(sigma + v0 * v0);
         rjj = mu;
       }
-      const float inv = (sigma != 0.f) ? 1.f / v0 : 1.f;
+      const float inv = (sigma != 0.f) ? __builtin_amdgcn_rcpf(v0) : 1.f;
 #pragma unroll
       for (int cc = 0; cc < kRegCols; ++cc) {
         if (cc != cj) continue;
@@ -392,9 +395,10 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
       // |ga| > 1e-6 sqrt(al be), compared squared; the rotation uses the
       // hardware reciprocal, square root and reciprocal square root (about
       // 1 ulp each, so cs^2 + sn^2 = 1 to a few ulp), which shortens the
-      // dependent chain of every round
+      // dependent chain of every round.  A rotating pair has ga^2 > 0, so
+      // 1 / (2 ga) is finite and zeta is never 0 * inf.
       if (on && ga * ga > 1e-12f * (al * be) && ga != 0.f) {
-        const float zeta = (be - al) / (2.f * ga);
+        const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
         const float tn = copysignf(1.f, zeta) *
                          __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.f)));
         const float cs = __builtin_amdgcn_rsqf(fmaf(tn, tn, 1.f));
