@@ -116,6 +116,23 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
                            tt_tensor *gX, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ---------------------------------------------- completion line search */
+/* Terms of the exact line search of Riemannian tensor completion (the
+ * completion use case of the Introduction with the Riemannian gradient of
+ * the Riemannian Geometry Operations section; the step rule of Riemannian
+ * TT completion in the cited literature).  P: a TT (normally the projected
+ * gradient, rank 2r), y: (dev) [M] values of the current iterate at the
+ * observed entries, t: (dev) [M] targets, idx as for tt_gather.
+ * out: (dev) float [2], written asynchronously:
+ *   out[0] = sum_m P(i^m)^2,   out[1] = sum_m (y_m - t_m) P(i^m);
+ * the observed loss of the first-order model X - a P is smallest at
+ * a = out[1] / out[0].  Sums are in a fixed order (deterministic).
+ * M = 0 writes {0, 0}. */
+int64_t tt_line_search_workspace(const tt_tensor *P, int64_t M);
+int tt_line_search(const tt_tensor *P, const int32_t *idx, int64_t M,
+                   const float *y, const float *t, float *out,
+                   void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- checked mode */
 /* Index check.  The entry formula (Introduction) is defined for
  * 0 <= i_k < n_k only, and the entry points above do not test their

@@ -18,6 +18,9 @@ from .tt import (  # noqa: F401
     project_sparse,
     round_tt,
     riemannian_step,
+    line_search_terms,
+    completion_iteration,
+    riemannian_completion,
     gram,
     BatchedPlan,
     TTMatrix,

@@ -67,6 +67,8 @@ SIGNATURES = {
     "tt_gather_mse_workspace": (I64, [P_TT, I64]),
     "tt_gather_mse_backward": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, P_TT, VP, SZ, VP]),
     "tt_check_indices": (C.c_int, [P_TT, VP, I64, VP, VP]),
+    "tt_line_search_workspace": (I64, [P_TT, I64]),
+    "tt_line_search": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, SZ, VP]),
     "tt_orthogonalize_ranks": (C.c_int, [P_TT, C.c_int, PI32]),
     "tt_orthogonalize_workspace": (I64, [P_TT, C.c_int]),
     "tt_orthogonalize": (C.c_int, [P_TT, C.c_int, P_TT, VP, SZ, VP]),

@@ -244,6 +244,25 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M, co
   return fused_mse_dispatch(X, idx, M, t, y, g, loss, gX, ws, ws_bytes, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------ line search
+int64_t tt_line_search_workspace(const tt_tensor *P, int64_t M) {
+  int rc = validate_tt(P, "P", TT_MAX_RANK);
+  if (rc) return rc;
+  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
+  return (int64_t)line_search_ws(P, M);
+}
+
+int tt_line_search(const tt_tensor *P, const int32_t *idx, int64_t M, const float *y, const float *t,
+                   float *out, void *ws, size_t ws_bytes, void *stream) {
+  int rc = validate_tt(P, "P", TT_MAX_RANK);
+  if (rc) return rc;
+  if (!out) return set_error(TT_ERR_ARG, "line_search: null out");
+  if ((rc = check_entries(idx, M, y, "y"))) return rc;
+  if (M > 0 && !t) return set_error(TT_ERR_ARG, "null t array with M = %lld", (long long)M);
+  if ((rc = check_ws(ws, ws_bytes, line_search_ws(P, M), "line_search"))) return rc;
+  return line_search(P, idx, M, y, t, out, ws, ws_bytes, (hipStream_t)stream);
+}
+
 // ------------------------------------------------------------ index check
 int tt_check_indices(const tt_tensor *X, const int32_t *idx, int64_t M, int64_t *out, void *stream) {
   int rc = validate_tt(X, "X", TT_MAX_RANK);

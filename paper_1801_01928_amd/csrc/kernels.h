@@ -19,6 +19,11 @@ size_t fused_mse_ws(const tt_tensor *X, int64_t M);
 int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t, float *y,
                        float *g, float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s);
 
+// Line-search terms of Riemannian completion (linesearch.hip).
+size_t line_search_ws(const tt_tensor *P, int64_t M);
+int line_search(const tt_tensor *P, const int32_t *idx, int64_t M, const float *y, const float *t, float *out,
+                void *ws, size_t ws_bytes, hipStream_t s);
+
 // Counts entries with an index outside [0, n_k) into out[0] and stores the
 // smallest such entry (M if none) in out[1] (device int64 [2]).
 int index_check(const tt_tensor *X, const int32_t *idx, long long M, int64_t *out, hipStream_t s);

@@ -294,6 +294,66 @@ def riemannian_step(X, idx, t, alpha=-0.1, max_rank=None):
     return dict(y=y, loss=loss, grads=grads, U=U, V=V, W=W, Y=Y, disc_sq=disc)
 
 
+def line_search_terms(P, idx, y, t):
+    """Line-search terms (tt_line_search) as a device tensor of 2 floats:
+    sum_m P(i^m)^2 and sum_m (y_m - t_m) P(i^m)."""
+    lib = L.load()
+    idx = _idx(idx, P.d, P.device)
+    _checked(P, idx)
+    M = idx.shape[1]
+    y = _vec(y, M, P.device)
+    t = _vec(t, M, P.device)
+    out = torch.empty(2, dtype=torch.float32, device=P.device)
+    ws, nb = _workspace(L.check(lib.tt_line_search_workspace(C.byref(P.desc()), M)), P.device)
+    L.check(lib.tt_line_search(C.byref(P.desc()), _ptr(idx), M, _ptr(y), _ptr(t), _ptr(out), _ptr(ws), nb,
+                               _stream(P.device)))
+    return out
+
+
+def completion_iteration(X, idx, t, max_rank=None):
+    """One step of Riemannian gradient descent for tensor completion with the
+    exact line search on the linearised observed loss: g = dL/dy of the
+    fused pass, P = P_X(sum_m g_m e_{i^m}), step a = sum (y - t) P(i) /
+    sum P(i)^2 from tt_line_search, Y = round(X - a P, max_rank).  The step
+    size is the one host-side quotient (one synchronisation per step).
+    Returns dict(loss, step, Y)."""
+    if max_rank is None:
+        max_rank = max(X.ranks)
+    idx = _idx(idx, X.d, X.device)
+    y, g, loss, _ = gather_mse_backward(X, idx, t, want_g=True)
+    U = orthogonalize(X, L.TT_LR)
+    V = orthogonalize(X, L.TT_RL)
+    P = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
+    pp, rp = (float(v) for v in line_search_terms(P, idx, y, t).cpu())
+    a = rp / pp if pp > 0.0 else 0.0
+    W = project_sparse(U, V, idx, g, alpha=-a, add_x=1)
+    Y, _ = round_tt(W, max_rank)
+    return dict(loss=float(loss.item()), step=a, Y=Y)
+
+
+def riemannian_completion(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
+    """Riemannian gradient descent for tensor completion: ``iters`` steps of
+    ``completion_iteration`` from X0.  Returns (X, history), one
+    dict(loss, step, test_rmse) per step; test_rmse is the held-out RMSE of
+    the iterate before the step (from the fused pass on the test entries)."""
+    X = X0
+    idx = _idx(idx, X.d, X.device)
+    t = _vec(t, idx.shape[1], X.device)
+    if idx_test is not None:
+        idx_test = _idx(idx_test, X.d, X.device)
+        t_test = _vec(t_test, idx_test.shape[1], X.device)
+    hist = []
+    for _ in range(iters):
+        rmse = None
+        if idx_test is not None:
+            _, lt, _ = gather_mse_backward(X, idx_test, t_test, want_y=False)
+            rmse = float(lt.item()) ** 0.5
+        out = completion_iteration(X, idx, t, max_rank)
+        hist.append(dict(loss=out["loss"], step=out["step"], test_rmse=rmse))
+        X = out["Y"]
+    return X, hist
+
+
 def _batch(tts):
     """A tt_batch descriptor over TT objects (kept alive by the returned tuple)."""
     arr = (L.tt_tensor * len(tts))(*[t.desc() for t in tts])
