@@ -119,6 +119,23 @@ def riemann_d10(M=1 << 20, seed=3, r=32):
     return TTProblem(ns=ns, ranks=ranks, cores=cores, idx=idx, values=z)
 
 
+def completion_d10(M=1 << 20, M_test=1 << 16, seed=6, r=16):
+    """Riemannian completion workload: d=10, n=10, X at canonical ranks for
+    r=16, X ~ N(0, 1/16); planted uniform rank 8 ~ N(0, 1/8); M observed and
+    M_test held-out uniform indices; noise N(0, 0.01^2) on the observed
+    entries.  Targets are formed by the caller (gather of the planted TT)."""
+    ns = [10] * 10
+    rng = np.random.default_rng(seed)
+    ranks = canonical_ranks(ns, r)
+    cores = random_cores(rng, ns, ranks, 1 / np.sqrt(r))
+    planted = random_cores(rng, ns, uniform_ranks(10, 8), 1 / np.sqrt(8))
+    idx = random_indices(rng, ns, M)
+    noise = (0.01 * rng.standard_normal(M)).astype(F32)
+    idx_test = random_indices(rng, ns, M_test)
+    return TTProblem(ns=ns, ranks=ranks, cores=cores, idx=idx, planted=planted, noise=noise,
+                     meta={"idx_test": idx_test})
+
+
 def batched_instance(b, d=8, n=16, seed=4, rank_choices=(4, 8, 16, 32),
                      mu=np.log(50000.0), sigma=0.8, lo=10000, hi=200000):
     """Instance b of the batched workload (its own generator seeded [seed, b])."""
