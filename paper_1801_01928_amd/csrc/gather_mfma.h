@@ -44,7 +44,7 @@ struct MfInst {
   int rclass;              // 16 or 32
 };
 
-#define MF_BATCH_THREADS 768
+#define MF_BATCH_THREADS 512
 
 // Work item of the batched kernel: `ntile` consecutive tiles of one tensor.
 struct MfWorkItem {

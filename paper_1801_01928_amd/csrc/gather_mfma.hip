@@ -526,9 +526,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           for (int x = 0; x < NT * NT; ++x) racc[x] += dg[x];
         }
       };
-      // three blocks in flight; two for rank 32 in the 768-thread batched
-      // kernel, where three would not fit the register budget
-      constexpr int U = (R == 32 && NTHR > 512) ? 2 : 3;
+      constexpr int U = 3;
       v4f ab[U][NT * NT], rb[U][NT];
 #pragma unroll
       for (int u = 0; u < U; ++u) ld(jb + u, ab[u], rb[u]);
