@@ -179,6 +179,16 @@ int tt_project_sparse(const tt_tensor *U, const tt_tensor *V,
                       float alpha, int add_x, tt_tensor *W,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* Re-weighting of a tangent TT (Riemannian Geometry Operations: the
+ * tangent vector is linear in its gauge-fixed cores).  P: the tangent TT
+ * tt_project_sparse returned with alpha = 1, add_x = 0 for the point whose
+ * left-orthonormal sweep is U; W (P's shape, may alias P) receives
+ * add_x X + alpha P_X(Z), exactly as tt_project_sparse with these alpha
+ * and add_x would return it, without repeating the sparse projection.
+ * Needs no workspace. */
+int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha,
+                       int add_x, tt_tensor *W, void *stream);
+
 /* ------------------------------------------------------------------ A7 */
 /* TT rounding (t3f.round(x, max_tt_rank), Implementation Details): TT_RL
  * sweep, then left-to-right truncated SVDs of reshape(G^k, r_{k-1} n_k x r_k)

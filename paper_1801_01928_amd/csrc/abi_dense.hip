@@ -98,6 +98,22 @@ int tt_project_sparse(const tt_tensor *U, const tt_tensor *V, const int32_t *idx
   return tangent_assemble(U, V, &Z, W, alpha, add_x, base + zb + ab, ws_bytes - zb - ab, s);
 }
 
+int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha, int add_x, tt_tensor *W,
+                       void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = validate_tt(P, "P", 2 * TT_MAX_RANK))) return rc;
+  if ((rc = validate_tt(W, "W", 2 * TT_MAX_RANK))) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "tangent_combine needs d >= 2");
+  if (!same_shape(P, W)) return set_error(TT_ERR_SHAPE, "W must have P's shape");
+  if (!same_modes(U, P)) return set_error(TT_ERR_SHAPE, "P must have U's mode sizes");
+  for (int k = 1; k < U->d; ++k)
+    if (P->r[k] != 2 * U->r[k])
+      return set_error(TT_ERR_SHAPE, "P rank r[%d] = %d, expected %d", k, P->r[k], 2 * U->r[k]);
+  if (add_x != 0 && add_x != 1) return set_error(TT_ERR_ARG, "add_x must be 0 or 1");
+  return tangent_combine(U, P, W, alpha, add_x, (hipStream_t)stream);
+}
+
 int tt_round_ranks(const tt_tensor *Y, int32_t max_rank, int32_t *out_r) {
   int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
   if (rc) return rc;

@@ -764,6 +764,34 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
   }
 }
 
+// add_x X + alpha P_X(Z) from the tangent TT P = P_X(Z) that
+// tangent_kernel assembled with alpha = 1, add_x = 0 (same block layout):
+// the dG blocks are scaled by alpha and add_x S (S = the last core of the
+// left-orthonormal U) is added to the lower block of the last core.  One
+// workgroup per core; W may alias P (each element is read, then written, by
+// one thread).
+__global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDev P, TTDev W, float alpha,
+                                                                   float addx) {
+  const int k = blockIdx.x, d = U.d;
+  const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
+  const float *Uk = U.data + U.off[k];
+  const float *Pk = P.data + P.off[k];
+  float *Wk = W.data + W.off[k];
+  const int w0 = W.r[k], w1 = W.r[k + 1];
+  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
+    const int b = (int)(e % w1), s = (int)((e / w1) % nk), a = (int)(e / ((long)w1 * nk));
+    float v = Pk[e];
+    if (k == 0) {  // [dG, U]
+      if (b < r1) v *= alpha;
+    } else if (k == d - 1) {  // [[V], [dG]]
+      if (a >= r0) v = addx * Uk[((long)(a - r0) * nk + s) * r1 + b] + alpha * v;
+    } else {  // [[V, 0], [dG, U]]
+      if (a >= r0 && b < r1) v *= alpha;
+    }
+    Wk[e] = v;
+  }
+}
+
 long slot_of(const int *n, const int *r, int d) {
   long s = 1;
   for (int k = 0; k < d; ++k) {
@@ -879,6 +907,13 @@ int tangent_assemble(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Z,
   hipLaunchKernelGGL(tangent_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(V),
                      make_dev(Z), make_dev(W), alpha, add_x ? 1.f : 0.f, scratch, stride);
   return launch_check("tangent assembly");
+}
+
+int tangent_combine(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, float alpha, int add_x,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(tangent_combine_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(P),
+                     make_dev(W), alpha, add_x ? 1.f : 0.f);
+  return launch_check("tangent combine");
 }
 
 }  // namespace ttgfx

@@ -294,6 +294,15 @@ def riemannian_step(X, idx, t, alpha=-0.1, max_rank=None):
     return dict(y=y, loss=loss, grads=grads, U=U, V=V, W=W, Y=Y, disc_sq=disc)
 
 
+def tangent_combine(U, P, alpha, add_x, out=None):
+    """add_x X + alpha P_X(Z) from P = project_sparse(U, V, idx, z, 1, 0)
+    (tt_tangent_combine); ``out`` may be P itself."""
+    W = out if out is not None else TT(P.ns, P.ranks, device=P.device)
+    L.check(L.load().tt_tangent_combine(C.byref(U.desc()), C.byref(P.desc()), C.c_float(alpha), int(add_x),
+                                        C.byref(W.desc()), _stream(P.device)))
+    return W
+
+
 def line_search_terms(P, idx, y, t):
     """Line-search terms (tt_line_search) as a device tensor of 2 floats:
     sum_m P(i^m)^2 and sum_m (y_m - t_m) P(i^m)."""
@@ -314,8 +323,9 @@ def completion_iteration(X, idx, t, max_rank=None):
     """One step of Riemannian gradient descent for tensor completion with the
     exact line search on the linearised observed loss: g = dL/dy of the
     fused pass, P = P_X(sum_m g_m e_{i^m}), step a = sum (y - t) P(i) /
-    sum P(i)^2 from tt_line_search, Y = round(X - a P, max_rank).  The step
-    size is the one host-side quotient (one synchronisation per step).
+    sum P(i)^2 from tt_line_search, Y = round(X - a P, max_rank) with X - a P
+    re-weighted from P by tt_tangent_combine.  The step size is the one
+    host-side quotient (one synchronisation per step).
     Returns dict(loss, step, Y)."""
     if max_rank is None:
         max_rank = max(X.ranks)
@@ -326,7 +336,7 @@ def completion_iteration(X, idx, t, max_rank=None):
     P = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
     pp, rp = (float(v) for v in line_search_terms(P, idx, y, t).cpu())
     a = rp / pp if pp > 0.0 else 0.0
-    W = project_sparse(U, V, idx, g, alpha=-a, add_x=1)
+    W = tangent_combine(U, P, -a, 1, out=P)  # X - a P, without a second projection
     Y, _ = round_tt(W, max_rank)
     return dict(loss=float(loss.item()), step=a, Y=Y)
 

@@ -127,3 +127,15 @@ def test_check_indices_validation_before_device(lib):
     Z = _desc([3], [1, 1])
     Z.d = 0
     assert lib.tt_check_indices(C.byref(Z), C.c_void_p(0x10), 5, C.c_void_p(0x10), None) == L.TT_ERR_ARG
+
+
+def test_tangent_combine_validation_before_device(lib):
+    from paper_1801_01928_amd import _lib as L
+    U = _desc([3, 4, 5], [1, 2, 2, 1])
+    P = _desc([3, 4, 5], [1, 4, 4, 1])
+    bad = _desc([3, 4, 5], [1, 4, 3, 1])
+    assert lib.tt_tangent_combine(C.byref(U), C.byref(bad), 1.0, 1, C.byref(bad), None) == L.TT_ERR_SHAPE
+    assert lib.tt_tangent_combine(C.byref(U), C.byref(P), 1.0, 1, C.byref(bad), None) == L.TT_ERR_SHAPE
+    assert lib.tt_tangent_combine(C.byref(U), C.byref(P), 1.0, 2, C.byref(P), None) == L.TT_ERR_ARG
+    one = _desc([3], [1, 1])
+    assert lib.tt_tangent_combine(C.byref(one), C.byref(one), 1.0, 1, C.byref(one), None) == L.TT_ERR_ARG

@@ -103,3 +103,26 @@ def test_completion_recovers_planted_tensor(gpu_lib):
     e = oracle.gather([c.astype(np.float64) for c in X.numpy_cores()], idx_t) - t_t
     assert h[0]["test_rmse"] > 0.1
     assert float(np.sqrt(np.mean(e * e))) < 1e-4
+
+
+@pytest.mark.parametrize("add_x", [0, 1])
+def test_tangent_combine_equals_projection(gpu_lib, add_x):
+    """Re-weighting P = P_X(Z) (alpha 1, no X) gives what the projection
+    returns for (alpha, add_x) directly, in a new TT and in place."""
+    tt = gpu_lib
+    rng = np.random.default_rng(60 + add_x)
+    ns = [8] * 5
+    ranks = W.canonical_ranks(ns, 6)
+    X = tt.TT.from_cores(W.random_cores(rng, ns, ranks, 0.4))
+    idx = torch.as_tensor(W.random_indices(rng, ns, 3000)).cuda()
+    z = torch.as_tensor(rng.standard_normal(3000).astype(np.float32)).cuda()
+    U = tt.orthogonalize(X, tt.TT_LR)
+    V = tt.orthogonalize(X, tt.TT_RL)
+    alpha = -0.37
+    want = tt.project_sparse(U, V, idx, z, alpha=alpha, add_x=add_x).data
+    P = tt.project_sparse(U, V, idx, z, alpha=1.0, add_x=0)
+    got = tt.tangent_combine(U, P, alpha, add_x).data
+    scale = float(want.abs().max())
+    assert float((got - want).abs().max()) <= 1e-6 * scale
+    tt.tangent_combine(U, P, alpha, add_x, out=P)
+    assert torch.equal(P.data, got)
