@@ -6,24 +6,31 @@
 
 namespace ttgfx {
 
-// The slice-grouped MFMA kernels serve ranks <= 32 and small mode sizes;
-// TTGFX_GENERIC=1 forces the generic one-lane-per-entry kernels.
-static bool use_mfma(const tt_tensor *L, const tt_tensor *R) {
+// The slice-grouped MFMA kernels serve ranks <= 32 (the gather alone up to
+// 64) and small mode sizes; TTGFX_GENERIC=1 forces the generic
+// one-lane-per-entry kernels.
+static bool generic_forced() {
   static int forced = -1;
   if (forced < 0) {
     const char *e = getenv("TTGFX_GENERIC");
     forced = (e && e[0] == '1') ? 1 : 0;
   }
-  return !forced && mfma_supported(L, R);
+  return forced != 0;
 }
 
+static bool use_mfma(const tt_tensor *L, const tt_tensor *R) { return !generic_forced() && mfma_supported(L, R); }
+
+// The gather alone also has a rank-64 class (0: generic kernel).
+static int gather_class(const tt_tensor *X) { return generic_forced() ? 0 : mfma_gather_class(X); }
+
 size_t gather_dispatch_ws(const tt_tensor *X, int64_t M) {
-  return use_mfma(X, X) ? mfma_ws(X, mfma_rank_class(X, X), M, false) : 0;
+  const int rc = gather_class(X);
+  return rc ? mfma_ws(X, rc, M, false) : 0;
 }
 
 int gather_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, float *y, void *ws,
                     size_t ws_bytes, hipStream_t s) {
-  if (use_mfma(X, X))
+  if (gather_class(X))
     return mfma_run(0, X, X, nullptr, idx, M, nullptr, nullptr, y, nullptr, nullptr, ws, ws_bytes, s);
   return generic_gather(make_dev(X), max_rank_of(X), idx, M, y, s);
 }

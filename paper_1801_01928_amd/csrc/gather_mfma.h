@@ -23,6 +23,15 @@ struct MfTraits<32> {
   static constexpr int MAX_N = 32;
   static constexpr int PERM_CAP = 16384;
 };
+// Gather only (no adjoint): ranks 33..64, e.g. tangent vectors of rank-32
+// points; entry rows of 68 floats keep the tile at 256 entries.
+template <>
+struct MfTraits<64> {
+  static constexpr int T = 256;
+  static constexpr int THREADS = 512;
+  static constexpr int MAX_N = 16;
+  static constexpr int PERM_CAP = 8192;
+};
 
 // One tensor of the slice-grouped kernels (kernel argument or batch table).
 struct MfInst {
@@ -74,6 +83,7 @@ int mfma_device_cus();
 bool mfma_supported(const tt_tensor *L, const tt_tensor *R);
 int mfma_rank_class(const tt_tensor *L, const tt_tensor *R);
 bool mfma_class_fits(const tt_tensor *X, int R);
+int mfma_gather_class(const tt_tensor *X);  // 16, 32 or 64 for the gather alone; 0 if none fits
 size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint);
 // padded slice copies (right: G, left: G^T of Lt or Rt) and the unpad copy
 int mfma_pad(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float *gpl, hipStream_t s);

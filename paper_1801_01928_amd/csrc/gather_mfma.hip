@@ -771,7 +771,7 @@ struct Geometry {
 Geometry geometry(const tt_tensor *X, int R, int64_t M) {
   Geometry g;
   g.R = R;
-  g.T = (R == 16) ? MfTraits<16>::T : MfTraits<32>::T;
+  g.T = (R == 16) ? MfTraits<16>::T : (R == 32 ? MfTraits<32>::T : MfTraits<64>::T);
   int nmax = 1;
   g.total_slices = 0;
   for (int k = 0; k < X->d; ++k) {
@@ -839,6 +839,16 @@ bool mfma_supported(const tt_tensor *L, const tt_tensor *R) {
 
 bool mfma_class_fits(const tt_tensor *X, int R) { return R == 16 ? fits_class<16>(X) : fits_class<32>(X); }
 
+// Rank class of the gather alone (ranks up to 64), or 0 if none fits.
+int mfma_gather_class(const tt_tensor *X) {
+  const int mr = max_rank_of(X);
+  const int rc = mr <= 16 ? 16 : (mr <= 32 ? 32 : (mr <= 64 ? 64 : 0));
+  if (rc == 16) return fits_class<16>(X) ? 16 : 0;
+  if (rc == 32) return fits_class<32>(X) ? 32 : 0;
+  if (rc == 64) return fits_class<64>(X) ? 64 : 0;
+  return 0;
+}
+
 size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint) {
   const Geometry g = geometry(X, R, M);
   size_t b = 2 * arena_bytes<float>((size_t)g.total_slices * R * R);
@@ -873,8 +883,9 @@ int mfma_unpad(const tt_tensor *O, int R, const float *padded, hipStream_t s) {
 int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, const int32_t *idx,
              int64_t M, const float *t, const float *gy, float *y, float *gout, float *loss, void *ws,
              size_t ws_bytes, hipStream_t s) {
-  const int R = mfma_rank_class(Lt, Rt);
   const bool adjoint = mode != MODE_GATHER;
+  const int R = adjoint ? mfma_rank_class(Lt, Rt) : mfma_gather_class(Rt);
+  if (R == 0) return set_error(TT_ERR_UNSUPPORTED, "gather (MFMA): no rank class fits");
   const Geometry g = geometry(Rt, R, M);
   Arena ar(ws, ws_bytes);
   float *gpr = ar.take<float>((size_t)g.total_slices * R * R);
@@ -927,7 +938,9 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
     if ((rc = fill_zero(grad, (long long)g.total_slices * R * R, s))) return rc;
   }
   if (M > 0) {
-    if (R == 16) {
+    if (R == 64) {
+      rc = launch_fused<64, MODE_GATHER>(p, gr, g.nwg, s);
+    } else if (R == 16) {
       if (mode == MODE_GATHER) rc = launch_fused<16, MODE_GATHER>(p, gr, g.nwg, s);
       else if (mode == MODE_ADJOINT) rc = launch_fused<16, MODE_ADJOINT>(p, gr, g.nwg, s);
       else rc = launch_fused<16, MODE_MSE>(p, gr, g.nwg, s);

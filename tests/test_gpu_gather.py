@@ -230,3 +230,27 @@ def test_fused_pass_graph_replays(gpu_lib):
         got = tt.TT(ns, ranks, gX.data).numpy_cores()
         for a, b in zip(got, ref):
             assert _rel(a, b) <= TOL
+
+
+RANK64_CASES = [
+    (51, [10] * 10, W.canonical_ranks([10] * 10, 64), 70001),   # tangent rank of a rank-32 point
+    (52, [16, 16, 16, 16], [1, 16, 64, 16, 1], 30001),
+    (53, [6, 6, 6], [1, 6, 36, 1], 1000),
+    (54, [5, 9, 7, 3], [1, 5, 45, 21, 1], 257),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RANK64_CASES)))
+def test_gather_rank64_class(gpu_lib, case):
+    """Ranks 33..64 take the rank-64 MFMA gather (tiles of 256 entries):
+    parity with the oracle gather, several tiles and a ragged tail."""
+    import torch
+    tt = gpu_lib
+    seed, ns, ranks, M = RANK64_CASES[case]
+    print("rank-64 gather", ns, max(ranks), M, flush=True)
+    rng = np.random.default_rng(seed)
+    cores = W.random_cores(rng, ns, ranks, 1 / np.sqrt(max(ranks)))
+    idx = W.random_indices(rng, ns, M)
+    X = tt.TT.from_cores(cores)
+    y = tt.gather(X, torch.as_tensor(idx).cuda()).cpu().numpy()
+    assert _rel(y, oracle.gather(cores, idx)) <= TOL
