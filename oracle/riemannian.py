@@ -79,6 +79,43 @@ def project_sparse_cores(U, V, idx, z):
     return sparse_adjoint(U, V, idx, z)
 
 
+def project_tt_cores(U, V, Y):
+    """Core contractions Zhat_k of a TT tensor Y with the tangent-space
+    interfaces of X (projection of a TT onto the tangent space, Riemannian
+    Geometry Operations section: P_B A for TT tensors A and B).
+
+    Left interfaces Psi_0 = 1, Psi_k = sum_i U^k[i]^T Psi_{k-1} Y^k[i]
+    (r_k x s_k); right interfaces Phi_{d+1} = 1,
+    Phi_k = sum_i V^k[i] Phi_{k+1} Y^k[i]^T (r_{k-1} x s_{k-1}); then
+    Zhat_k[i] = Psi_{k-1} Y^k[i] Phi_{k+1}^T.  Each entry is the inner
+    product of Y with the tensor U_<k (x) e_i (x) V_>k, the same quantity the
+    sparse projection accumulates one observed entry at a time.
+    """
+    d = len(U)
+    Y = [np.asarray(c, dtype=np.float64) for c in Y]
+    psi = [np.ones((1, 1))]
+    for k in range(d - 1):
+        psi.append(np.einsum("aib,ac,cid->bd", U[k], psi[k], Y[k]))
+    phi = [None] * (d + 1)
+    phi[d] = np.ones((1, 1))
+    for k in range(d - 1, 0, -1):
+        phi[k] = np.einsum("aib,bc,dic->ad", V[k], phi[k + 1], Y[k])
+    return [np.einsum("ac,cid,bd->aib", psi[k], Y[k], phi[k + 1]) for k in range(d)]
+
+
+def project_tt(X, Y, alpha=1.0, beta=0.0):
+    """Projection of the TT tensor Y onto the tangent space of X, returned as
+    the rank-2r TT  beta*X + alpha*P_X(Y)  (Riemannian Geometry Operations:
+    P_B A).  Orthogonalize X both ways, contract Y with the interfaces
+    (``project_tt_cores``), fix the gauge, assemble.  Returns (W, U, V, dG).
+    """
+    U = orthogonalize_lr(X)
+    V = orthogonalize_rl(X)
+    _check_interfaces(U, V)
+    dG = tangent_cores(U, project_tt_cores(U, V, Y))
+    return tangent_tt(U, V, dG, alpha, beta), U, V, dG
+
+
 def tangent_cores(U, Zhat):
     """Gauge-fixed tangent cores dG from the core contractions Zhat.
 

@@ -355,3 +355,51 @@ def test_completion_with_noise_reaches_noise_level():
     assert loss < 1.5 * 1e-4
     e = oracle.gather(X, idx_t) - t_t
     assert float(np.sqrt(np.mean(e * e))) < 0.1 * h[0]["test_rmse"]
+
+
+# ------------------------------------------------ projection of a TT tensor
+@pytest.mark.parametrize("ns,r,sr", [([3, 4, 3, 2], 3, [1, 2, 5, 3, 1]), ([2, 3, 2], 2, [1, 4, 3, 1]),
+                                     ([3, 3, 3, 3], 2, [1, 3, 3, 3, 1])])
+def test_project_tt_equals_dense_projector(ns, r, sr):
+    from oracle import riemannian as R
+    X = random_tt(1, ns, canonical_ranks(ns, r))
+    Y = random_tt(2, ns, sr)
+    W, U, V, dG = R.project_tt(X, Y)
+    P = R.dense_projector(U, V)
+    want = P @ oracle.full(Y).reshape(-1)
+    got = oracle.full(W).reshape(-1)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_project_tt_of_one_hot_is_the_sparse_projection():
+    """A one-hot tensor e_i as a rank-1 TT projects exactly as the sparse
+    projection of the single entry i with weight 1."""
+    from oracle import riemannian as R
+    ns = [3, 4, 3, 2]
+    X = random_tt(3, ns, canonical_ranks(ns, 3))
+    i = np.array([[1], [3], [0], [1]], dtype=np.int32)
+    onehot = [np.zeros((1, n, 1)) for n in ns]
+    for k in range(len(ns)):
+        onehot[k][0, i[k, 0], 0] = 1.0
+    a = oracle.full(R.project_tt(X, onehot)[0])
+    b = oracle.full(R.project_sparse(X, i, np.array([1.0]))[0])
+    assert np.abs(a - b).max() <= 1e-14
+
+
+def test_project_tt_identity_idempotence_linearity():
+    from oracle import riemannian as R
+    ns = [3, 3, 4, 3]
+    X = random_tt(4, ns, canonical_ranks(ns, 3))
+    Y1 = random_tt(5, ns, [1, 3, 4, 2, 1])
+    Y2 = random_tt(6, ns, [1, 2, 2, 2, 1])
+    fx = oracle.full(X)
+    # P_X(X) = X
+    assert np.abs(oracle.full(R.project_tt(X, X)[0]) - fx).max() <= 1e-12 * np.abs(fx).max()
+    # P(P(Y)) = P(Y)
+    P1 = R.project_tt(X, Y1)[0]
+    assert np.abs(oracle.full(R.project_tt(X, P1)[0]) - oracle.full(P1)).max() <= 1e-12 * np.abs(oracle.full(P1)).max()
+    # P(2 Y1 - 3 Y2) = 2 P(Y1) - 3 P(Y2)
+    Ysum = oracle.add(oracle.scale(Y1, 2.0), oracle.scale(Y2, -3.0))
+    lhs = oracle.full(R.project_tt(X, Ysum)[0])
+    rhs = 2 * oracle.full(P1) - 3 * oracle.full(R.project_tt(X, Y2)[0])
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
