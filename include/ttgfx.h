@@ -179,6 +179,21 @@ int tt_project_sparse(const tt_tensor *U, const tt_tensor *V,
                       float alpha, int add_x, tt_tensor *W,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* Projection of a TT tensor onto the tangent space (Riemannian Geometry
+ * Operations: P_B A with TT tensors A and B).  U, V: as for
+ * tt_project_sparse (both sweeps of the point X, feasible ranks r); Y: any
+ * TT with X's mode sizes and ranks <= 64.  W (ranks 2r, as for
+ * tt_project_sparse) receives add_x X + alpha P_X(Y).  Interfaces
+ * Psi_k = sum_i U^k[i]^T Psi_{k-1} Y^k[i] and
+ * Phi_k = sum_i V^k[i] Phi_{k+1} Y^k[i]^T, core contractions
+ * Psi_{k-1} Y^k[i] Phi_{k+1}^T, then the same gauge fix and assembly as the
+ * sparse projection.  Used, e.g., to carry a tangent vector of one point
+ * to the tangent space of the next. */
+int64_t tt_project_tt_workspace(const tt_tensor *U, const tt_tensor *Y);
+int tt_project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y,
+                  float alpha, int add_x, tt_tensor *W,
+                  void *ws, size_t ws_bytes, void *stream);
+
 /* Re-weighting of a tangent TT (Riemannian Geometry Operations: the
  * tangent vector is linear in its gauge-fixed cores).  P: the tangent TT
  * tt_project_sparse returned with alpha = 1, add_x = 0 for the point whose

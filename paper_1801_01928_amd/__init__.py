@@ -19,6 +19,7 @@ from .tt import (  # noqa: F401
     round_tt,
     riemannian_step,
     line_search_terms,
+    project_tt,
     tangent_combine,
     completion_iteration,
     riemannian_completion,

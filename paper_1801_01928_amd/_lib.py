@@ -75,6 +75,8 @@ SIGNATURES = {
     "tt_project_sparse_workspace": (I64, [P_TT, I64]),
     "tt_project_sparse": (C.c_int, [P_TT, P_TT, VP, I64, VP, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_tangent_combine": (C.c_int, [P_TT, P_TT, C.c_float, C.c_int, P_TT, VP]),
+    "tt_project_tt_workspace": (I64, [P_TT, P_TT]),
+    "tt_project_tt": (C.c_int, [P_TT, P_TT, P_TT, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_round_ranks": (C.c_int, [P_TT, I32, PI32]),
     "tt_round_workspace": (I64, [P_TT, I32]),
     "tt_round": (C.c_int, [P_TT, I32, P_TT, VP, VP, SZ, VP]),

@@ -13,6 +13,9 @@ int dense_orth(const tt_tensor *X, int dir, tt_tensor *O, void *ws, size_t bytes
 int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, void *ws, size_t bytes,
                 hipStream_t s);
 size_t tangent_ws(const tt_tensor *U);
+size_t project_tt_ws(const tt_tensor *U, const tt_tensor *Y);
+int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float alpha, int add_x, tt_tensor *W,
+               void *ws, size_t bytes, hipStream_t s);
 int tangent_combine(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, float alpha, int add_x,
                     hipStream_t s);
 int tangent_assemble(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Z, tt_tensor *W,

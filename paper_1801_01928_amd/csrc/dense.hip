@@ -792,6 +792,62 @@ __global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDe
   }
 }
 
+// Projection of a TT tensor Y onto the tangent space at X (U left- and V
+// right-orthonormal cores of X).  Interfaces: Psi_0 = 1,
+// Psi_{k+1} = sum_i U_k[i]^T Psi_k Y_k[i] (left sweep, workgroup 0) and
+// Phi_d = 1, Phi_k = sum_i V_k[i] Phi_{k+1} Y_k[i]^T (right sweep,
+// workgroup 1), each a pair of row-major GEMMs per core through a scratch
+// T; then one workgroup per core forms Zhat_k[i] = Psi_k Y_k[i] Phi_{k+1}^T.
+struct ProjBufs {
+  float *psi, *phi, *tmp;
+  long pslot, tslot;
+};
+
+__global__ void __launch_bounds__(kThreads) proj_interfaces_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b) {
+  const int d = U.d;
+  if (blockIdx.x == 0) {
+    float *T = b.tmp;
+    if (threadIdx.x == 0) b.psi[0] = 1.f;
+    __syncthreads();
+    for (int k = 0; k + 1 < d; ++k) {
+      const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
+      const long ns1 = (long)n * s1;
+      // T (r0 x n s1) = Psi_k (r0 x s0) Y_k (s0 x n s1)
+      blk_gemm(r0, (int)ns1, s0, b.psi + k * b.pslot, s0, 1, Y.data + Y.off[k], ns1, 1, T, ns1, 1);
+      __syncthreads();
+      // Psi_{k+1} (r1 x s1) = U_k^T T, contracting the (r0 n) rows of both
+      blk_gemm(r1, s1, r0 * n, U.data + U.off[k], 1, r1, T, s1, 1, b.psi + (k + 1) * b.pslot, s1, 1);
+      __syncthreads();
+    }
+  } else {
+    float *T = b.tmp + b.tslot;
+    if (threadIdx.x == 0) b.phi[d * b.pslot] = 1.f;
+    __syncthreads();
+    for (int k = d - 1; k >= 1; --k) {
+      const int r0 = V.r[k], r1 = V.r[k + 1], n = V.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
+      const long ns1 = (long)n * s1;
+      // T ((r0 n) x s1) = V_k ((r0 n) x r1) Phi_{k+1} (r1 x s1)
+      blk_gemm(r0 * n, s1, r1, V.data + V.off[k], r1, 1, b.phi + (k + 1) * b.pslot, s1, 1, T, s1, 1);
+      __syncthreads();
+      // Phi_k (r0 x s0) = T (r0 x n s1) Y_k^T (n s1 x s0)
+      blk_gemm(r0, s0, (int)ns1, T, ns1, 1, Y.data + Y.off[k], 1, ns1, b.phi + k * b.pslot, s0, 1);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) proj_cores_kernel(TTDev U, TTDev Y, TTDev Z, ProjBufs b) {
+  const int k = blockIdx.x;
+  const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
+  const long ns1 = (long)n * s1;
+  float *T = b.tmp + (2 + k) * b.tslot;
+  // T (r0 x n s1) = Psi_k Y_k
+  blk_gemm(r0, (int)ns1, s0, b.psi + k * b.pslot, s0, 1, Y.data + Y.off[k], ns1, 1, T, ns1, 1);
+  __syncthreads();
+  // Zhat_k ((r0 n) x r1) = T ((r0 n) x s1) Phi_{k+1}^T (s1 x r1)
+  blk_gemm(r0 * n, r1, s1, T, s1, 1, b.phi + (k + 1) * b.pslot, 1, s1, Z.data + Z.off[k], r1, 1);
+}
+
 long slot_of(const int *n, const int *r, int d) {
   long s = 1;
   for (int k = 0; k < d; ++k) {
@@ -907,6 +963,62 @@ int tangent_assemble(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Z,
   hipLaunchKernelGGL(tangent_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(V),
                      make_dev(Z), make_dev(W), alpha, add_x ? 1.f : 0.f, scratch, stride);
   return launch_check("tangent assembly");
+}
+
+// Scratch of the TT projection: interface slots (r x s) and product slots
+// (r n x s) over all cores.
+static void proj_slots(const tt_tensor *U, const tt_tensor *Y, long *pslot, long *tslot) {
+  long ps = 1, ts = 1;
+  for (int k = 0; k <= U->d; ++k) {
+    const long a = (long)U->r[k] * Y->r[k];
+    ps = a > ps ? a : ps;
+  }
+  for (int k = 0; k < U->d; ++k) {
+    const long a = (long)U->r[k] * U->n[k] * Y->r[k + 1];
+    ts = a > ts ? a : ts;
+  }
+  *pslot = ps;
+  *tslot = ts;
+}
+
+size_t project_tt_ws(const tt_tensor *U, const tt_tensor *Y) {
+  long ps, ts;
+  proj_slots(U, Y, &ps, &ts);
+  long zel = 0;
+  for (int k = 0; k < U->d; ++k) zel += (long)U->r[k] * U->n[k] * U->r[k + 1];
+  size_t b = 2 * arena_bytes<float>((size_t)(U->d + 1) * ps);
+  b += arena_bytes<float>((size_t)(U->d + 2) * ts);
+  b += arena_bytes<float>((size_t)zel);
+  b += tangent_ws(U) + 256;
+  return b;
+}
+
+int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float alpha, int add_x, tt_tensor *W,
+               void *ws, size_t bytes, hipStream_t s) {
+  long ps, ts;
+  proj_slots(U, Y, &ps, &ts);
+  Arena ar(ws, bytes);
+  ProjBufs b;
+  b.psi = ar.take<float>((size_t)(U->d + 1) * ps);
+  b.phi = ar.take<float>((size_t)(U->d + 1) * ps);
+  b.tmp = ar.take<float>((size_t)(U->d + 2) * ts);
+  b.pslot = ps;
+  b.tslot = ts;
+  long zel = 0;
+  for (int k = 0; k < U->d; ++k) zel += (long)U->r[k] * U->n[k] * U->r[k + 1];
+  float *zbuf = ar.take<float>((size_t)zel);
+  const size_t tws = tangent_ws(U);
+  void *tw = ar.take<char>(tws);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "project_tt: workspace too small");
+  hipLaunchKernelGGL(proj_interfaces_kernel, dim3(2), dim3(kThreads), 0, s, make_dev(U), make_dev(V), make_dev(Y),
+                     b);
+  int rc = launch_check("TT projection interfaces");
+  if (rc) return rc;
+  tt_tensor Z = {U->d, U->n, U->r, nullptr, zbuf};
+  hipLaunchKernelGGL(proj_cores_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(Y), make_dev(&Z),
+                     b);
+  if ((rc = launch_check("TT projection cores"))) return rc;
+  return tangent_assemble(U, V, &Z, W, alpha, add_x, tw, tws, s);
 }
 
 int tangent_combine(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, float alpha, int add_x,

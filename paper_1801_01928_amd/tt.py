@@ -294,6 +294,18 @@ def riemannian_step(X, idx, t, alpha=-0.1, max_rank=None):
     return dict(y=y, loss=loss, grads=grads, U=U, V=V, W=W, Y=Y, disc_sq=disc)
 
 
+def project_tt(U, V, Y, alpha=1.0, add_x=0):
+    """Projection of the TT tensor Y onto the tangent space at X, with
+    U = orthogonalize(X, LR) and V = orthogonalize(X, RL); returns the
+    rank-2r TT  add_x * X + alpha * P_X(Y)  (tt_project_tt)."""
+    lib = L.load()
+    W = TT(U.ns, [1] + [2 * r for r in U.ranks[1:-1]] + [1], device=U.device)
+    ws, nb = _workspace(L.check(lib.tt_project_tt_workspace(C.byref(U.desc()), C.byref(Y.desc()))), U.device)
+    L.check(lib.tt_project_tt(C.byref(U.desc()), C.byref(V.desc()), C.byref(Y.desc()), C.c_float(alpha),
+                              int(add_x), C.byref(W.desc()), _ptr(ws), nb, _stream(U.device)))
+    return W
+
+
 def tangent_combine(U, P, alpha, add_x, out=None):
     """add_x X + alpha P_X(Z) from P = project_sparse(U, V, idx, z, 1, 0)
     (tt_tangent_combine); ``out`` may be P itself."""

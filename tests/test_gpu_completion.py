@@ -126,3 +126,47 @@ def test_tangent_combine_equals_projection(gpu_lib, add_x):
     assert float((got - want).abs().max()) <= 1e-6 * scale
     tt.tangent_combine(U, P, alpha, add_x, out=P)
     assert torch.equal(P.data, got)
+
+
+PROJ_CASES = [
+    (70, [3, 4, 3, 2], 3, [1, 2, 5, 3, 1]),
+    (71, [8] * 5, 6, [1, 7, 12, 12, 5, 1]),
+    (72, [10] * 10, 16, [1] + [32] * 9 + [1]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(PROJ_CASES)))
+def test_project_tt_matches_oracle(gpu_lib, case):
+    """P_X(Y) for a TT Y (tt_project_tt) against the FP64 oracle, compared as
+    tensors through exact inner products; add_x = 1 as well."""
+    tt = gpu_lib
+    seed, ns, r, sr = PROJ_CASES[case]
+    print("project_tt", ns, r, max(sr), flush=True)
+    rng = np.random.default_rng(seed)
+    Xc = W.random_cores(rng, ns, W.canonical_ranks(ns, r), 1 / np.sqrt(r))
+    Yc = W.random_cores(rng, ns, sr, 1 / np.sqrt(max(sr)))
+    X = tt.TT.from_cores(Xc)
+    U = tt.orthogonalize(X, tt.TT_LR)
+    V = tt.orthogonalize(X, tt.TT_RL)
+    Y = tt.TT.from_cores(Yc)
+    for alpha, add_x in ((1.0, 0), (-0.3, 1)):
+        got = tt.project_tt(U, V, Y, alpha=alpha, add_x=add_x).numpy_cores()
+        want = R.project_tt(Xc, Yc, alpha=alpha, beta=float(add_x))[0]
+        assert _tt_rel(got, want) <= 1e-4
+
+
+def test_project_tt_one_hot_equals_sparse_projection(gpu_lib):
+    tt = gpu_lib
+    ns = [8] * 5
+    rng = np.random.default_rng(73)
+    X = tt.TT.from_cores(W.random_cores(rng, ns, W.canonical_ranks(ns, 6), 0.4))
+    U = tt.orthogonalize(X, tt.TT_LR)
+    V = tt.orthogonalize(X, tt.TT_RL)
+    i = [3, 1, 7, 0, 5]
+    onehot = [np.zeros((1, n, 1), np.float32) for n in ns]
+    for k in range(len(ns)):
+        onehot[k][0, i[k], 0] = 1.0
+    a = tt.project_tt(U, V, tt.TT.from_cores(onehot)).numpy_cores()
+    idx = torch.as_tensor(np.array(i, np.int32).reshape(-1, 1)).cuda()
+    b = tt.project_sparse(U, V, idx, torch.ones(1, device="cuda")).numpy_cores()
+    assert _tt_rel(a, b) <= 1e-5
