@@ -84,6 +84,31 @@ __device__ void blk_gemm(int M, int N, int K, const float *A, long ar, long ac, 
   }
 }
 
+// blk_gemm with four outputs per thread (independent FMA chains), K
+// unrolled; for products whose K is too long for the LDS-staged helpers.
+__device__ void blk_gemm4(int M, int N, int K, const float *A, long ar, long ac, const float *B,
+                          long br, long bc, float *C, long cr, long cc) {
+  const long tot = (long)M * N;
+  for (long e0 = threadIdx.x; e0 < tot; e0 += 4L * kThreads) {
+    int i[4], j[4];
+    float acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long e = e0 + q * kThreads < tot ? e0 + q * kThreads : e0;
+      i[q] = (int)(e / N);
+      j[q] = (int)(e % N);
+      acc[q] = 0.f;
+    }
+#pragma unroll 4
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fmaf(A[i[q] * ar + k * ac], B[k * br + j[q] * bc], acc[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (e0 + q * kThreads < tot) C[i[q] * cr + j[q] * cc] = acc[q];
+  }
+}
+
 // In-place Householder QR of the column-major m x c matrix W (ld = m).
 // On return the upper triangle holds R (diag >= 0) and column j below the
 // diagonal holds v_j (v_j[j] = 1 implied); tau[j] = beta_j.
@@ -804,6 +829,7 @@ struct ProjBufs {
 };
 
 __global__ void __launch_bounds__(kThreads) proj_interfaces_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b) {
+  __shared__ Shared sh;
   const int d = U.d;
   if (blockIdx.x == 0) {
     float *T = b.tmp;
@@ -812,11 +838,13 @@ __global__ void __launch_bounds__(kThreads) proj_interfaces_kernel(TTDev U, TTDe
     for (int k = 0; k + 1 < d; ++k) {
       const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
       const long ns1 = (long)n * s1;
-      // T (r0 x n s1) = Psi_k (r0 x s0) Y_k (s0 x n s1)
-      blk_gemm(r0, (int)ns1, s0, b.psi + k * b.pslot, s0, 1, Y.data + Y.off[k], ns1, 1, T, ns1, 1);
+      // T (r0 x n s1) = Psi_k (r0 x s0) Y_k (s0 x n s1), Y_k staged in LDS
+      const float *Pk = b.psi + k * b.pslot;
+      gemm_lds_a((int)r0, (int)ns1, s0, [&](int i, int l) { return Pk[i * s0 + l]; }, Y.data + Y.off[k], ns1, 1,
+                 T, ns1, 1, sh);
       __syncthreads();
       // Psi_{k+1} (r1 x s1) = U_k^T T, contracting the (r0 n) rows of both
-      blk_gemm(r1, s1, r0 * n, U.data + U.off[k], 1, r1, T, s1, 1, b.psi + (k + 1) * b.pslot, s1, 1);
+      blk_gemm4(r1, s1, r0 * n, U.data + U.off[k], 1, r1, T, s1, 1, b.psi + (k + 1) * b.pslot, s1, 1);
       __syncthreads();
     }
   } else {
@@ -826,26 +854,32 @@ __global__ void __launch_bounds__(kThreads) proj_interfaces_kernel(TTDev U, TTDe
     for (int k = d - 1; k >= 1; --k) {
       const int r0 = V.r[k], r1 = V.r[k + 1], n = V.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
       const long ns1 = (long)n * s1;
-      // T ((r0 n) x s1) = V_k ((r0 n) x r1) Phi_{k+1} (r1 x s1)
-      blk_gemm(r0 * n, s1, r1, V.data + V.off[k], r1, 1, b.phi + (k + 1) * b.pslot, s1, 1, T, s1, 1);
+      // T ((r0 n) x s1) = V_k ((r0 n) x r1) Phi_{k+1} (r1 x s1), V_k staged in LDS
+      const float *Fk = b.phi + (k + 1) * b.pslot;
+      gemm_lds_b(r0 * n, s1, r1, V.data + V.off[k], r1, 1, [&](int l, int j) { return Fk[l * s1 + j]; }, T, s1,
+                 sh);
       __syncthreads();
       // Phi_k (r0 x s0) = T (r0 x n s1) Y_k^T (n s1 x s0)
-      blk_gemm(r0, s0, (int)ns1, T, ns1, 1, Y.data + Y.off[k], 1, ns1, b.phi + k * b.pslot, s0, 1);
+      blk_gemm4(r0, s0, (int)ns1, T, ns1, 1, Y.data + Y.off[k], 1, ns1, b.phi + k * b.pslot, s0, 1);
       __syncthreads();
     }
   }
 }
 
 __global__ void __launch_bounds__(kThreads) proj_cores_kernel(TTDev U, TTDev Y, TTDev Z, ProjBufs b) {
+  __shared__ Shared sh;
   const int k = blockIdx.x;
   const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
   const long ns1 = (long)n * s1;
   float *T = b.tmp + (2 + k) * b.tslot;
   // T (r0 x n s1) = Psi_k Y_k
-  blk_gemm(r0, (int)ns1, s0, b.psi + k * b.pslot, s0, 1, Y.data + Y.off[k], ns1, 1, T, ns1, 1);
+  const float *Pk = b.psi + k * b.pslot;
+  gemm_lds_a(r0, (int)ns1, s0, [&](int i, int l) { return Pk[i * s0 + l]; }, Y.data + Y.off[k], ns1, 1, T, ns1, 1,
+             sh);
   __syncthreads();
   // Zhat_k ((r0 n) x r1) = T ((r0 n) x s1) Phi_{k+1}^T (s1 x r1)
-  blk_gemm(r0 * n, r1, s1, T, s1, 1, b.phi + (k + 1) * b.pslot, 1, s1, Z.data + Z.off[k], r1, 1);
+  const float *Fk = b.phi + (k + 1) * b.pslot;
+  gemm_lds_b(r0 * n, r1, s1, T, s1, 1, [&](int l, int j) { return Fk[j * s1 + l]; }, Z.data + Z.off[k], r1, sh);
 }
 
 long slot_of(const int *n, const int *r, int d) {
