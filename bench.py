@@ -178,7 +178,9 @@ def gram_leg(tt, W, reps=3):
 def riemann_leg(tt, W, reps=3):
     """One Riemannian step on d=10, n=10, r=32 (canonical ranks) with 2^20
     observed N(0,1) gradient values: both QR sweeps, the sparse tangent
-    projection with assembly, and TT rounding back to rank 32."""
+    projection with assembly, and TT rounding back to rank 32; beside the
+    step, the projection of the rank-64 tangent TT onto the tangent space at
+    X (the transport of a search direction)."""
     import torch
     p = W.riemann_d10()
     X = tt.TT.from_cores(p.cores)
@@ -192,10 +194,14 @@ def riemann_leg(tt, W, reps=3):
     orth_ms = _event_ms(lambda: (tt.orthogonalize(X, tt.TT_LR), tt.orthogonalize(X, tt.TT_RL)), reps)
     proj_ms = _event_ms(lambda: tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1), reps)
     round_ms = _event_ms(lambda: tt.round_tt(Wt, 32), reps)
+    tt.project_tt(U, V, Wt)
+    torch.cuda.synchronize()
+    transport_ms = _event_ms(lambda: tt.project_tt(U, V, Wt), reps)
     return {"workload": "d=10 n=10 r=32 (canonical), 2^20 entries", "orthogonalize_both_ms": round(orth_ms, 3),
             "project_sparse_ms": round(proj_ms, 3),
             "project_entries_per_s": round(p.M / (proj_ms * 1e-3), 1),
-            "round_ms": round(round_ms, 3), "step_ms": round(orth_ms + proj_ms + round_ms, 3)}
+            "round_ms": round(round_ms, 3), "step_ms": round(orth_ms + proj_ms + round_ms, 3),
+            "project_tt_rank64_ms": round(transport_ms, 3)}
 
 
 def completion_leg(tt, W, iters=4):
