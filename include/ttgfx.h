@@ -89,6 +89,34 @@ int64_t tt_gather_workspace(const tt_tensor *X, int64_t M);
 int tt_gather(const tt_tensor *X, const int32_t *idx, int64_t M, float *y,
               void *ws, size_t ws_bytes, void *stream);
 
+/* --------------------------------------- gather by prefix/suffix tables */
+/* The same values as tt_gather (the entry formula of the Introduction),
+ * computed by regrouping the slice product: cut at bond `split`
+ * (1 <= split <= d-1, 0-based modes 0..split-1 on the left), each entry is
+ * the dot of its prefix product G^0[i_0]..G^{split-1}[i_{split-1}] and its
+ * suffix product G^{split}[i_split]..G^{d-1}[i_{d-1}].  tt_halves_build
+ * tabulates every prefix (prod_{k<split} n_k rows) and every suffix
+ * (prod_{k>=split} n_k rows) of r[split] floats each; tt_halves_gather then
+ * takes one r[split]-dot per entry.  This pays when M exceeds the table
+ * rows; the tables depend only on X, so one build serves any number of
+ * gathers until X changes.
+ *   tt_halves_split: the split minimising the table size (d >= 2).
+ *   tt_halves_bytes: bytes of the (dev) table buffer for that split, or a
+ *     negative error (TT_ERR_UNSUPPORTED when a table level would exceed
+ *     2^30 rows or reach 2^23 tiles of 64 x 64 outputs).
+ *   tt_halves_build: fills `tables` (caller-owned, >= tt_halves_bytes).
+ *   tt_halves_gather: y[m] as tt_gather, reading tables built for the same
+ *     X shape and split; idx and y as for tt_gather.  An entry with an index
+ *     outside [0, n_k) yields 0 (no out-of-bounds table read).
+ * Summation differs from tt_gather only in order (float32 rounding). */
+int32_t tt_halves_split(const tt_tensor *X);
+int64_t tt_halves_bytes(const tt_tensor *X, int32_t split);
+int tt_halves_build(const tt_tensor *X, int32_t split, void *tables, size_t bytes,
+                    void *stream);
+int tt_halves_gather(const tt_tensor *X, int32_t split, const void *tables,
+                     size_t bytes, const int32_t *idx, int64_t M, float *y,
+                     void *stream);
+
 /* ------------------------------------------------------------------ A3 */
 /* Adjoint of the gather (automatic differentiation, abstract): for every
  * core k, gX^k[:, i, :] = sum over m with i_k^m = i of

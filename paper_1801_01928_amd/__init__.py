@@ -10,6 +10,9 @@ from .tt import (  # noqa: F401
     check_indices,
     gather,
     gather_backward,
+    gather_halves,
+    halves_split,
+    halves_tables,
     gather_mse_backward,
     gather_mse_workspace,
     tt_gather,

@@ -67,6 +67,10 @@ SIGNATURES = {
     "tt_gather_mse_workspace": (I64, [P_TT, I64]),
     "tt_gather_mse_backward": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, P_TT, VP, SZ, VP]),
     "tt_check_indices": (C.c_int, [P_TT, VP, I64, VP, VP]),
+    "tt_halves_split": (C.c_int32, [P_TT]),
+    "tt_halves_bytes": (I64, [P_TT, C.c_int32]),
+    "tt_halves_build": (C.c_int, [P_TT, C.c_int32, VP, SZ, VP]),
+    "tt_halves_gather": (C.c_int, [P_TT, C.c_int32, VP, SZ, VP, I64, VP, VP]),
     "tt_line_search_workspace": (I64, [P_TT, I64]),
     "tt_line_search": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, SZ, VP]),
     "tt_orthogonalize_ranks": (C.c_int, [P_TT, C.c_int, PI32]),

@@ -140,6 +140,39 @@ def gather(X, idx):
     return y
 
 
+def halves_split(X):
+    """Bond at which the prefix/suffix tables of X are smallest."""
+    return int(L.check(L.load().tt_halves_split(C.byref(X.desc()))))
+
+
+def halves_tables(X, split=None):
+    """Prefix and suffix tables of X cut at bond ``split`` (the smallest
+    when None): returns (split, tables), tables a uint8 device tensor."""
+    lib = L.load()
+    split = halves_split(X) if split is None else int(split)
+    nb = int(L.check(lib.tt_halves_bytes(C.byref(X.desc()), split)))
+    tables = torch.empty(max(nb, 1), dtype=torch.uint8, device=X.device)
+    L.check(lib.tt_halves_build(C.byref(X.desc()), split, _ptr(tables), nb, _stream(X.device)))
+    return split, tables
+
+
+def gather_halves(X, idx, split=None, tables=None):
+    """The gather computed from prefix/suffix tables (built here unless
+    ``tables`` = (split, buffer) from ``halves_tables`` is given)."""
+    lib = L.load()
+    idx = _idx(idx, X.d, X.device)
+    _checked(X, idx)
+    M = idx.shape[1]
+    if tables is None:
+        split, buf = halves_tables(X, split)
+    else:
+        split, buf = tables
+    y = torch.empty(M, dtype=torch.float32, device=X.device)
+    L.check(lib.tt_halves_gather(C.byref(X.desc()), int(split), _ptr(buf), buf.numel(), _ptr(idx), M, _ptr(y),
+                                 _stream(X.device)))
+    return y
+
+
 def gather_backward(X, idx, gy):
     """Core gradients of sum_m gy[m] y[m] (the gather's adjoint)."""
     lib = L.load()

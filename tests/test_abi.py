@@ -139,3 +139,50 @@ def test_tangent_combine_validation_before_device(lib):
     assert lib.tt_tangent_combine(C.byref(U), C.byref(P), 1.0, 2, C.byref(P), None) == L.TT_ERR_ARG
     one = _desc([3], [1, 1])
     assert lib.tt_tangent_combine(C.byref(one), C.byref(one), 1.0, 1, C.byref(one), None) == L.TT_ERR_ARG
+
+
+def test_halves_host_logic(lib):
+    """Split choice, table bytes and argument checks of the prefix/suffix
+    gather: host-only code, no device call."""
+    from paper_1801_01928_amd import _lib as L
+
+    def al(b):
+        return (b + 255) // 256 * 256
+
+    X = _desc([10] * 10, [1] + [16] * 9 + [1])
+    assert lib.tt_halves_split(C.byref(X)) == 5
+    # left levels j = 1..5: 10^j rows of r_j floats; right levels j = 9..5:
+    # 10^(10-j) rows of r_j floats (r_j = 16 except nothing at the ends here)
+    want = sum(al(4 * 10 ** j * 16) for j in range(1, 6)) + sum(al(4 * 10 ** (10 - j) * 16) for j in range(5, 10))
+    assert lib.tt_halves_bytes(C.byref(X), 5) == want
+    # uneven modes: the smaller tables sit where the products balance
+    U = _desc([2, 2, 2, 2, 64, 64], [1, 2, 4, 4, 4, 4, 1])
+    s = lib.tt_halves_split(C.byref(U))
+    sizes = []
+    for c in range(1, 6):
+        pl = 1
+        for k in range(c):
+            pl *= [2, 2, 2, 2, 64, 64][k]
+        pr = 2 * 2 * 2 * 2 * 64 * 64 // pl
+        sizes.append((pl + pr) * [1, 2, 4, 4, 4, 4, 1][c])
+    assert s == 1 + sizes.index(min(sizes))
+    # d = 1 has no bond to cut; split outside [1, d-1]
+    D1 = _desc([7], [1, 1])
+    assert lib.tt_halves_split(C.byref(D1)) == L.TT_ERR_UNSUPPORTED
+    assert lib.tt_halves_bytes(C.byref(X), 0) == L.TT_ERR_ARG
+    assert lib.tt_halves_bytes(C.byref(X), 10) == L.TT_ERR_ARG
+    # a level over 2^30 rows
+    Big = _desc([4096] * 6, [1, 2, 2, 2, 2, 2, 1])
+    assert lib.tt_halves_bytes(C.byref(Big), 3) == L.TT_ERR_UNSUPPORTED
+    # missing or short table buffer, null idx, negative M
+    nb = lib.tt_halves_bytes(C.byref(X), 5)
+    assert lib.tt_halves_build(C.byref(X), 5, None, 0, None) == L.TT_ERR_WORKSPACE
+    assert lib.tt_halves_build(C.byref(X), 5, C.c_void_p(0x1000), nb - 1, None) == L.TT_ERR_WORKSPACE
+    assert lib.tt_halves_gather(C.byref(X), 5, C.c_void_p(0x1000), nb - 1, C.c_void_p(0x10), 4,
+                                C.c_void_p(0x10), None) == L.TT_ERR_WORKSPACE
+    assert lib.tt_halves_gather(C.byref(X), 5, C.c_void_p(0x1000), nb, None, 4, C.c_void_p(0x10),
+                                None) == L.TT_ERR_ARG
+    assert lib.tt_halves_gather(C.byref(X), 5, C.c_void_p(0x1000), nb, C.c_void_p(0x10), -1,
+                                C.c_void_p(0x10), None) == L.TT_ERR_ARG
+    # M = 0 is a no-op success
+    assert lib.tt_halves_gather(C.byref(X), 5, C.c_void_p(0x1000), nb, None, 0, None, None) == 0
