@@ -22,6 +22,7 @@
 // Every level is kept in the caller's table buffer (the levels shrink
 // geometrically, so the earlier ones add little).
 #include "common.h"
+#include "kernels.h"
 
 namespace ttgfx {
 
@@ -304,36 +305,20 @@ void launch_gather_lpe(const HalvesArgs &a, const int32_t *idx, long long M, flo
 
 }  // namespace
 
-}  // namespace ttgfx
-
-using namespace ttgfx;
-
-extern "C" {
-
-int32_t tt_halves_split(const tt_tensor *X) {
-  int rc = validate_tt(X, "X", TT_MAX_RANK);
+// Internal entry points (arguments validated by the caller).
+int halves_bytes(const tt_tensor *X, int split, size_t *bytes, long long *rows) {
+  HalvesLayout L;
+  int rc = halves_layout(X, split, L);
   if (rc) return rc;
-  if (X->d < 2) return set_error(TT_ERR_UNSUPPORTED, "halves: needs d >= 2 (d = %d)", X->d);
-  return halves_auto_split(X);
+  if (bytes) *bytes = L.total;
+  if (rows) *rows = L.lrows[split] + L.rrows[split];
+  return TT_OK;
 }
 
-int64_t tt_halves_bytes(const tt_tensor *X, int32_t split) {
-  int rc = halves_check(X, split);
-  if (rc) return rc;
+int halves_build(const tt_tensor *X, int split, void *tables, hipStream_t st) {
   HalvesLayout L;
-  if ((rc = halves_layout(X, split, L))) return rc;
-  return (int64_t)L.total;
-}
-
-int tt_halves_build(const tt_tensor *X, int32_t split, void *tables, size_t bytes, void *stream) {
-  int rc = halves_check(X, split);
+  int rc = halves_layout(X, split, L);
   if (rc) return rc;
-  HalvesLayout L;
-  if ((rc = halves_layout(X, split, L))) return rc;
-  if (!tables || bytes < L.total)
-    return set_error(TT_ERR_WORKSPACE, "halves_build: table buffer of %zu bytes given, %zu required",
-                     tables ? bytes : (size_t)0, L.total);
-  hipStream_t st = (hipStream_t)stream;
   char *base = (char *)tables;
   const int d = X->d, s = split;
   // step t of both chains in one launch: left level t (from level t-1,
@@ -381,19 +366,12 @@ int tt_halves_build(const tt_tensor *X, int32_t split, void *tables, size_t byte
   return TT_OK;
 }
 
-int tt_halves_gather(const tt_tensor *X, int32_t split, const void *tables, size_t bytes, const int32_t *idx,
-                     int64_t M, float *y, void *stream) {
-  int rc = halves_check(X, split);
-  if (rc) return rc;
-  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
-  if (M > 0 && (!idx || !y)) return set_error(TT_ERR_ARG, "halves_gather: null idx or y with M = %lld", (long long)M);
-  if (M > (int64_t)0x7fffffff) return set_error(TT_ERR_UNSUPPORTED, "M = %lld above 2^31-1", (long long)M);
-  HalvesLayout L;
-  if ((rc = halves_layout(X, split, L))) return rc;
-  if (!tables || bytes < L.total)
-    return set_error(TT_ERR_WORKSPACE, "halves_gather: table buffer of %zu bytes given, %zu required",
-                     tables ? bytes : (size_t)0, L.total);
+int halves_gather(const tt_tensor *X, int split, const void *tables, const int32_t *idx, int64_t M, float *y,
+                  hipStream_t st) {
   if (M == 0) return TT_OK;
+  HalvesLayout L;
+  int rc = halves_layout(X, split, L);
+  if (rc) return rc;
   HalvesArgs a;
   a.d = X->d;
   a.s = split;
@@ -401,7 +379,6 @@ int tt_halves_gather(const tt_tensor *X, int32_t split, const void *tables, size
   for (int k = 0; k < TT_MAX_D; ++k) a.n[k] = k < X->d ? X->n[k] : 1;
   a.lt = (const float *)((const char *)tables + L.loff[split]);
   a.rt = (const float *)((const char *)tables + L.roff[split]);
-  hipStream_t st = (hipStream_t)stream;
   timer_before(st);
   switch (a.rs) {
     case 4: launch_gather_lpe<1>(a, idx, M, y, st); break;
@@ -413,6 +390,55 @@ int tt_halves_gather(const tt_tensor *X, int32_t split, const void *tables, size
   }
   timer_after(st);
   return launch_check("halves gather");
+}
+
+int halves_split_of(const tt_tensor *X) { return halves_auto_split(X); }
+
+}  // namespace ttgfx
+
+using namespace ttgfx;
+
+extern "C" {
+
+int32_t tt_halves_split(const tt_tensor *X) {
+  int rc = validate_tt(X, "X", TT_MAX_RANK);
+  if (rc) return rc;
+  if (X->d < 2) return set_error(TT_ERR_UNSUPPORTED, "halves: needs d >= 2 (d = %d)", X->d);
+  return halves_auto_split(X);
+}
+
+int64_t tt_halves_bytes(const tt_tensor *X, int32_t split) {
+  int rc = halves_check(X, split);
+  if (rc) return rc;
+  size_t b = 0;
+  if ((rc = halves_bytes(X, split, &b, nullptr))) return rc;
+  return (int64_t)b;
+}
+
+int tt_halves_build(const tt_tensor *X, int32_t split, void *tables, size_t bytes, void *stream) {
+  int rc = halves_check(X, split);
+  if (rc) return rc;
+  size_t need = 0;
+  if ((rc = halves_bytes(X, split, &need, nullptr))) return rc;
+  if (!tables || bytes < need)
+    return set_error(TT_ERR_WORKSPACE, "halves_build: table buffer of %zu bytes given, %zu required",
+                     tables ? bytes : (size_t)0, need);
+  return halves_build(X, split, tables, (hipStream_t)stream);
+}
+
+int tt_halves_gather(const tt_tensor *X, int32_t split, const void *tables, size_t bytes, const int32_t *idx,
+                     int64_t M, float *y, void *stream) {
+  int rc = halves_check(X, split);
+  if (rc) return rc;
+  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
+  if (M > 0 && (!idx || !y)) return set_error(TT_ERR_ARG, "halves_gather: null idx or y with M = %lld", (long long)M);
+  if (M > (int64_t)0x7fffffff) return set_error(TT_ERR_UNSUPPORTED, "M = %lld above 2^31-1", (long long)M);
+  size_t need = 0;
+  if ((rc = halves_bytes(X, split, &need, nullptr))) return rc;
+  if (!tables || bytes < need)
+    return set_error(TT_ERR_WORKSPACE, "halves_gather: table buffer of %zu bytes given, %zu required",
+                     tables ? bytes : (size_t)0, need);
+  return halves_gather(X, split, tables, idx, M, y, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -3,9 +3,11 @@
 // observed entries come from the gather kernels, then
 //   out[0] = sum_m p_m^2,   out[1] = sum_m (y_m - t_m) p_m,
 // from which the minimiser of the linearised observed loss along -P is
-// out[1] / out[0].  Sums: per-thread partials over a fixed grid, wave and
-// block sums, then one wave adds the block partials in a fixed order, so
-// the result is deterministic.
+// out[1] / out[0].  The values p_m come from the prefix/suffix-table gather
+// when P's two tables have fewer rows than there are entries (and fit in
+// 1 GiB), else from the chain gather.  Sums: per-thread partials over a
+// fixed grid, wave and block sums, then one wave adds the block partials in
+// a fixed order, so the result is deterministic.
 #include "common.h"
 #include "kernels.h"
 
@@ -73,12 +75,26 @@ int ls_blocks(long long M) {
   return (int)(want < kLsBlocks ? want : kLsBlocks);
 }
 
+// Table gather for P at M entries: split and table bytes, or false.
+bool ls_halves(const tt_tensor *P, int64_t M, int &split, size_t &bytes) {
+  if (P->d < 2) return false;
+  split = halves_split_of(P);
+  long long rows = 0;
+  if (halves_bytes(P, split, &bytes, &rows) != TT_OK) return false;
+  return rows < M && bytes <= ((size_t)1 << 30);
+}
+
 }  // namespace
 
 size_t line_search_ws(const tt_tensor *P, int64_t M) {
   size_t b = arena_bytes<float>((size_t)M);
   b += arena_bytes<float>(2 * (size_t)kLsBlocks);
-  b += gather_dispatch_ws(P, M) + 256;
+  int split = 0;
+  size_t tb = 0;
+  if (ls_halves(P, M, split, tb))
+    b += arena_bytes<char>(tb);
+  else
+    b += gather_dispatch_ws(P, M) + 256;
   return b;
 }
 
@@ -87,13 +103,21 @@ int line_search(const tt_tensor *P, const int32_t *idx, int64_t M, const float *
   Arena ar(ws, ws_bytes);
   float *pv = ar.take<float>((size_t)M);
   float *part = ar.take<float>(2 * (size_t)kLsBlocks);
-  const size_t gws = gather_dispatch_ws(P, M);
+  int split = 0;
+  size_t tb = 0;
+  const bool tables = ls_halves(P, M, split, tb);
+  const size_t gws = tables ? tb : gather_dispatch_ws(P, M);
   void *gw = ar.take<char>(gws);
   if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "line search: workspace too small");
   const int nblk = M > 0 ? ls_blocks(M) : 0;
   int rc = TT_OK;
   if (M > 0) {
-    if ((rc = gather_dispatch(P, idx, M, pv, gw, gws, s))) return rc;
+    if (tables) {
+      if ((rc = halves_build(P, split, gw, s))) return rc;
+      if ((rc = halves_gather(P, split, gw, idx, M, pv, s))) return rc;
+    } else if ((rc = gather_dispatch(P, idx, M, pv, gw, gws, s))) {
+      return rc;
+    }
     hipLaunchKernelGGL(ls_partial_kernel, dim3(nblk), dim3(kLsThreads), 0, s, pv, y, t, (long long)M, part);
     if ((rc = launch_check("line search partials"))) return rc;
   }

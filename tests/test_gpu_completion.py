@@ -32,6 +32,9 @@ def _tt_rel(A, B):
 LS_CASES = [
     ([8] * 4, [1, 4, 4, 4, 1], 4096),
     ([10] * 10, W.canonical_ranks([10] * 10, 16), 70001),   # tangent rank 32, ragged tail
+    # P's prefix/suffix tables have fewer rows than M: the table gather
+    ([10] * 6, W.canonical_ranks([10] * 6, 16), 20011),      # split rank 32
+    ([10] * 8, W.canonical_ranks([10] * 8, 32), 30011),      # split rank 64
 ]
 
 
