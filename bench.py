@@ -158,6 +158,30 @@ def batched_leg(tt, W, reps=3):
             "speedup": round(plain_ms / graph_ms, 3)}
 
 
+def tables_leg(tt, W, reps=10):
+    """The gather of the headline workload (d=10, n=10, r=16, 2^20 entries)
+    from prefix/suffix tables, beside the chain gather: table build, table
+    gather, and the HBM rate of the table gather over the index and output
+    bytes (44 B per entry); the table rows come from the caches."""
+    import torch
+    p = W.gather_d10()
+    X = tt.TT.from_cores(p.cores)
+    idx = torch.from_numpy(p.idx).cuda()
+    split, tabs = tt.halves_tables(X)
+    tt.gather_halves(X, idx, tables=(split, tabs))
+    tt.gather(X, idx)
+    torch.cuda.synchronize()
+    build_ms = _event_ms(lambda: tt.halves_tables(X, split), reps)
+    gather_ms = _event_ms(lambda: tt.gather_halves(X, idx, tables=(split, tabs)), reps)
+    chain_ms = _event_ms(lambda: tt.gather(X, idx), reps)
+    return {"workload": "gather only, d=10 n=10 r=16, 2^20 uniform entries, tables cut at bond %d" % split,
+            "table_mb": round(tabs.numel() / 1e6, 2), "build_ms": round(build_ms, 4),
+            "gather_ms": round(gather_ms, 4), "chain_gather_ms": round(chain_ms, 4),
+            "gather_entries_per_s": round(p.M / (gather_ms * 1e-3), 1),
+            "build_plus_gather_entries_per_s": round(p.M / ((build_ms + gather_ms) * 1e-3), 1),
+            "gather_gb_per_s_44b": round(44.0 * p.M / (gather_ms * 1e-3) / 1e9, 1)}
+
+
 def gram_leg(tt, W, reps=3):
     """256 x 256 Gram matrix of the batched workload's tensors, ranks padded
     to 32 (12.65 MFLOP per pair, 32,896 unordered pairs)."""
@@ -327,6 +351,7 @@ def main():
     if not args.no_extras:
         # secondary measurements, each on its own workload after the timed region
         out["batched_vs_plain"] = batched_leg(tt, W)
+        out["gather_tables"] = tables_leg(tt, W)
         out["gram"] = gram_leg(tt, W)
         out["riemann_step"] = riemann_leg(tt, W)
         out["ttm_layer"] = ttm_leg(tt, W)
