@@ -352,3 +352,69 @@ def riemannian_completion(X0, idx, t, max_rank, iters, idx_test=None, t_test=Non
         hist.append(dict(loss=out["loss"], step=out["step"], test_rmse=rmse))
         X = out["Y"]
     return X, hist
+
+
+def cg_iteration(X, idx, t, max_rank, prev=None):
+    """One step of Riemannian conjugate gradients for tensor completion
+    (the nonlinear CG of Riemannian TT completion in the literature cited
+    with the Riemannian Geometry Operations section, Steinlechner 2016):
+      y = gather(X), L = mean((y - t)^2), g = 2 (y - t) / M,
+      xi = P_X(sum_m g_m e_{i^m})              (Riemannian gradient),
+      with the previous step's gradient xi' and direction eta' (tangent
+      TTs at the previous point) carried over by projection,
+        T xi' = P_X(xi'),  T eta' = P_X(eta'),
+      beta = max(0, <xi, xi - T xi'> / <xi', xi'>)      (Polak-Ribiere+),
+      eta = -xi + beta T eta', reset to -xi on the first step and whenever
+        <xi, eta> >= 0 (not a descent direction; beta is then 0),
+      a = -sum_m (y_m - t_m) eta(i^m) / sum_m eta(i^m)^2   (exact line
+        search of the linearised observed loss along eta),
+      Y = round(X + a eta, max_rank).
+    Inner products are exact TT inner products.  ``prev`` is the dict this
+    function returned for the previous step (None on the first).
+    Returns dict(loss, step, beta, Y, xi, eta, xi_sq): xi and eta as TTs at
+    X (rank-2r tangent TTs), xi_sq = <xi, xi>.
+    """
+    from .core import gather, inner, mse_loss_and_grad
+
+    y = gather(X, idx)
+    loss, g = mse_loss_and_grad(y, t)
+    xi, U, V, dG = project_sparse(X, idx, g, alpha=1.0, beta=0.0)
+    xi_sq = inner(xi, xi)
+    beta = 0.0
+    dE = [-c for c in dG]
+    if prev is not None and prev["xi_sq"] > 0.0:
+        Txi = project_tt(X, prev["xi"])[3]
+        Teta = project_tt(X, prev["eta"])[3]
+        Txi_tt = tangent_tt(U, V, Txi, 1.0, 0.0)
+        beta = max(0.0, (xi_sq - inner(xi, Txi_tt)) / prev["xi_sq"])
+        cand = [-a + beta * b for a, b in zip(dG, Teta)]
+        if inner(xi, tangent_tt(U, V, cand, 1.0, 0.0)) < 0.0:
+            dE = cand
+        else:
+            beta = 0.0
+    eta = tangent_tt(U, V, dE, 1.0, 0.0)
+    ev = gather(eta, idx)
+    a = -line_search_step(y, t, ev)
+    Y, _ = round_tt(tangent_tt(U, V, dE, a, 1.0), max_rank)
+    return dict(loss=loss, step=a, beta=beta, Y=Y, xi=xi, eta=eta, xi_sq=xi_sq)
+
+
+def riemannian_cg(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
+    """Riemannian conjugate gradients for tensor completion: ``iters`` steps
+    of ``cg_iteration`` from X0.  Returns (X, history) with history a list of
+    dict(loss, step, beta, test_rmse) per step (test_rmse of the iterate
+    before the step, when held-out entries are given)."""
+    from .core import gather
+
+    X = [np.asarray(c, dtype=np.float64) for c in X0]
+    hist = []
+    prev = None
+    for _ in range(iters):
+        rmse = None
+        if idx_test is not None:
+            e = gather(X, idx_test) - np.asarray(t_test, dtype=np.float64)
+            rmse = float(np.sqrt(np.mean(e * e)))
+        prev = cg_iteration(X, idx, t, max_rank, prev)
+        hist.append(dict(loss=prev["loss"], step=prev["step"], beta=prev["beta"], test_rmse=rmse))
+        X = prev["Y"]
+    return X, hist

@@ -403,3 +403,75 @@ def test_project_tt_identity_idempotence_linearity():
     lhs = oracle.full(R.project_tt(X, Ysum)[0])
     rhs = 2 * oracle.full(P1) - 3 * oracle.full(R.project_tt(X, Y2)[0])
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+# ------------------------------------------------------ conjugate gradients
+
+def _cg_problem():
+    from workloads import random_cores
+    ns = [8] * 4
+    rng = np.random.default_rng(21)
+    planted = random_cores(rng, ns, [1, 2, 2, 2, 1], 1 / np.sqrt(2))
+    X0 = [c.astype(np.float64) for c in random_cores(rng, ns, [1, 2, 2, 2, 1], 0.5)]
+    idx = random_indices(rng, ns, 2000)
+    t = oracle.gather(planted, idx)
+    idx_t = random_indices(rng, ns, 1000)
+    return X0, idx, t, idx_t, oracle.gather(planted, idx_t)
+
+
+def _tt_dist(A, B):
+    D = oracle.add(A, oracle.scale(B, -1.0))
+    return np.sqrt(max(oracle.inner(D, D), 0.0)) / np.sqrt(oracle.inner(B, B))
+
+
+def test_cg_first_step_is_gradient_descent():
+    """With no previous direction, eta = -P_X(grad): the CG step is the
+    gradient step (same step length along the opposite sign convention)."""
+    from oracle import riemannian as R
+    X0, idx, t, _, _ = _cg_problem()
+    cg = R.cg_iteration(X0, idx, t, 2)
+    gd = R.completion_iteration(X0, idx, t, 2)
+    assert cg["beta"] == 0.0
+    assert cg["step"] == pytest.approx(gd["step"], rel=1e-12)
+    assert _tt_dist(cg["Y"], gd["Y"]) < 1e-12
+
+
+def test_cg_direction_beta_and_line_search():
+    """Second step, checked with dense tensors: beta equals the
+    Polak-Ribiere+ quotient formed with the dense projector at the new point
+    (transport of the previous gradient), eta = -xi + beta P_X(eta') is a
+    tangent vector (P_X eta = eta) and a descent direction, and the step
+    zeroes the derivative of the linearised observed loss along eta."""
+    from oracle import riemannian as R
+    X0, idx, t, _, _ = _cg_problem()
+    s1 = R.cg_iteration(X0, idx, t, 2)
+    X1 = s1["Y"]
+    s2 = R.cg_iteration(X1, idx, t, 2, s1)
+    Pd = R.dense_projector(oracle.orthogonalize_lr(X1), oracle.orthogonalize_rl(X1))
+    xi = oracle.full(s2["xi"]).reshape(-1)
+    xi_prev = oracle.full(s1["xi"]).reshape(-1)
+    eta_prev = oracle.full(s1["eta"]).reshape(-1)
+    beta = max(0.0, float(xi @ (xi - Pd @ xi_prev)) / float(xi_prev @ xi_prev))
+    assert beta > 0.0
+    assert s2["beta"] == pytest.approx(beta, rel=1e-9)
+    eta = oracle.full(s2["eta"]).reshape(-1)
+    np.testing.assert_allclose(eta, -xi + beta * (Pd @ eta_prev), atol=1e-12 * np.abs(eta).max())
+    np.testing.assert_allclose(Pd @ eta, eta, atol=1e-12 * np.abs(eta).max())
+    assert float(xi @ eta) < 0.0
+    y = oracle.gather(X1, idx)
+    ev = oracle.gather(s2["eta"], idx)
+    assert abs(float(np.dot(y + s2["step"] * ev - t, ev))) <= 1e-10 * float(np.dot(ev, ev)) * abs(s2["step"])
+
+
+def test_cg_recovers_planted_tensor_faster_than_gd():
+    """The noiseless planted rank-2 problem: after 30 steps CG's held-out
+    RMSE is below 1e-8 and a hundred times below gradient descent's."""
+    from oracle import riemannian as R
+    X0, idx, t, idx_t, t_t = _cg_problem()
+    Xc, hc = R.riemannian_cg(X0, idx, t, 2, 30, idx_t, t_t)
+    Xg, _ = R.riemannian_completion(X0, idx, t, 2, 30, idx_t, t_t)
+    ec = oracle.gather(Xc, idx_t) - t_t
+    eg = oracle.gather(Xg, idx_t) - t_t
+    rc, rg = float(np.sqrt(np.mean(ec * ec))), float(np.sqrt(np.mean(eg * eg)))
+    assert rc < 1e-8 and rc < rg / 100
+    assert all(h["beta"] >= 0.0 for h in hc)
