@@ -232,6 +232,23 @@ int tt_project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y,
 int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha,
                        int add_x, tt_tensor *W, void *stream);
 
+/* Tangent-space algebra for tangent vectors at one point X (Riemannian
+ * Geometry Operations: elements of one tangent space add blockwise in the
+ * gauge-fixed parametrisation, and the metric is that of the ambient
+ * space).  A, B, W: tangent TTs in the block layout tt_project_sparse and
+ * tt_project_tt produce with add_x = 0, for the point whose left-orthonormal
+ * sweep is U (ranks 2 r_k of U's, same mode sizes).
+ *   tt_tangent_inner: out (dev, one float) = <A, B> = sum_k <dG_k^A, dG_k^B>
+ *     (exact under the gauge condition), summed in a fixed order.
+ *   tt_tangent_axpby: W = a A + b B (dG blocks combined, the other blocks
+ *     copied from A); W may alias A or B.
+ * Used by Riemannian conjugate gradients (direction update and
+ * Polak-Ribiere coefficient).  No workspace. */
+int tt_tangent_inner(const tt_tensor *U, const tt_tensor *A,
+                     const tt_tensor *B, float *out, void *stream);
+int tt_tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b,
+                     const tt_tensor *B, tt_tensor *W, void *stream);
+
 /* ------------------------------------------------------------------ A7 */
 /* TT rounding (t3f.round(x, max_tt_rank), Implementation Details): TT_RL
  * sweep, then left-to-right truncated SVDs of reshape(G^k, r_{k-1} n_k x r_k)

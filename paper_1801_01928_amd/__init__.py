@@ -25,6 +25,10 @@ from .tt import (  # noqa: F401
     project_tt,
     tangent_combine,
     completion_iteration,
+    cg_iteration,
+    riemannian_cg,
+    tangent_inner,
+    tangent_axpby,
     riemannian_completion,
     gram,
     BatchedPlan,

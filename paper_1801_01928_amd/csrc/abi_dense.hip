@@ -148,6 +148,35 @@ int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha, int 
   return tangent_combine(U, P, W, alpha, add_x, (hipStream_t)stream);
 }
 
+static int check_tangent(const tt_tensor *U, const tt_tensor *P, const char *name) {
+  int rc = validate_tt(P, name, 2 * TT_MAX_RANK);
+  if (rc) return rc;
+  if (!same_modes(U, P)) return set_error(TT_ERR_SHAPE, "%s must have U's mode sizes", name);
+  for (int k = 1; k < U->d; ++k)
+    if (P->r[k] != 2 * U->r[k])
+      return set_error(TT_ERR_SHAPE, "%s rank r[%d] = %d, expected %d", name, k, P->r[k], 2 * U->r[k]);
+  return TT_OK;
+}
+
+int tt_tangent_inner(const tt_tensor *U, const tt_tensor *A, const tt_tensor *B, float *out, void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "tangent_inner needs d >= 2");
+  if ((rc = check_tangent(U, A, "A")) || (rc = check_tangent(U, B, "B"))) return rc;
+  if (!out) return set_error(TT_ERR_ARG, "tangent_inner: null out");
+  return tangent_inner(U, A, B, out, (hipStream_t)stream);
+}
+
+int tt_tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, const tt_tensor *B, tt_tensor *W,
+                     void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "tangent_axpby needs d >= 2");
+  if ((rc = check_tangent(U, A, "A")) || (rc = check_tangent(U, B, "B")) || (rc = check_tangent(U, W, "W")))
+    return rc;
+  return tangent_axpby(U, a, A, b, B, W, (hipStream_t)stream);
+}
+
 int tt_round_ranks(const tt_tensor *Y, int32_t max_rank, int32_t *out_r) {
   int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
   if (rc) return rc;

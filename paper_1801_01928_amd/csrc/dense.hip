@@ -817,6 +817,64 @@ __global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDe
   }
 }
 
+// Offset, in core k of a tangent TT in the assembly's block layout, of the
+// dG block's element (a, s, b) (a < r_k, s < n_k, b < r_{k+1} of X): the
+// block sits at columns 0..r_{k+1} of the first core, at rows r_k.. of the
+// others (w1 = the tangent TT's rank r[k+1]).
+__device__ __forceinline__ long dg_offset(int k, int r0, int nk, int w1, int a, int s, int b) {
+  const int row = (k == 0) ? a : a + r0;
+  return ((long)row * nk + s) * w1 + b;
+}
+
+// <A, B> for two tangent vectors at the same point, both in the block
+// layout with add_x = 0.  Under the gauge condition the terms
+// U_<k dG_k V_>k are mutually orthogonal and the interfaces orthonormal, so
+// the inner product is sum_k <dG_k^A, dG_k^B> (tangent-space metric of the
+// Riemannian Geometry Operations section).  One workgroup; each thread
+// sums a fixed set of elements, then a fixed-order block sum.
+__global__ void __launch_bounds__(kThreads) tangent_inner_kernel(TTDev U, TTDev A, TTDev B, float *out) {
+  __shared__ Shared sh;
+  float acc = 0.f;
+  for (int k = 0; k < U.d; ++k) {
+    const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1], w1 = A.r[k + 1];
+    const float *Ak = A.data + A.off[k];
+    const float *Bk = B.data + B.off[k];
+    for (long e = threadIdx.x; e < (long)r0 * nk * r1; e += kThreads) {
+      const int b = (int)(e % r1), sl = (int)((e / r1) % nk), a = (int)(e / ((long)r1 * nk));
+      const long o = dg_offset(k, r0, nk, w1, a, sl, b);
+      acc = fmaf(Ak[o], Bk[o], acc);
+    }
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = acc;
+}
+
+// W = a A + b B for two tangent vectors at the same point in the block
+// layout with add_x = 0 (their V and U blocks are the same): the dG blocks
+// combine, the other blocks are copied from A.  One workgroup per core; W
+// may alias A or B (each element is read, then written, by one thread).
+__global__ void __launch_bounds__(kThreads) tangent_axpby_kernel(TTDev U, TTDev A, TTDev B, TTDev W, float ca,
+                                                                 float cb) {
+  const int k = blockIdx.x, d = U.d;
+  const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
+  const float *Ak = A.data + A.off[k];
+  const float *Bk = B.data + B.off[k];
+  float *Wk = W.data + W.off[k];
+  const int w0 = W.r[k], w1 = W.r[k + 1];
+  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
+    const int b = (int)(e % w1), a = (int)(e / ((long)w1 * nk));
+    bool dg;
+    if (k == 0)
+      dg = b < r1;
+    else if (k == d - 1)
+      dg = a >= r0;
+    else
+      dg = a >= r0 && b < r1;
+    const float va = Ak[e];
+    Wk[e] = dg ? fmaf(ca, va, cb * Bk[e]) : va;
+  }
+}
+
 // Projection of a TT tensor Y onto the tangent space at X (U left- and V
 // right-orthonormal cores of X).  Interfaces: Psi_0 = 1,
 // Psi_{k+1} = sum_i U_k[i]^T Psi_k Y_k[i] (left sweep, workgroup 0) and
@@ -1053,6 +1111,19 @@ int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float
                      b);
   if ((rc = launch_check("TT projection cores"))) return rc;
   return tangent_assemble(U, V, &Z, W, alpha, add_x, tw, tws, s);
+}
+
+int tangent_inner(const tt_tensor *U, const tt_tensor *A, const tt_tensor *B, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(tangent_inner_kernel, dim3(1), dim3(kThreads), 0, s, make_dev(U), make_dev(A), make_dev(B),
+                     out);
+  return launch_check("tangent inner product");
+}
+
+int tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, const tt_tensor *B, tt_tensor *W,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(tangent_axpby_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(A),
+                     make_dev(B), make_dev(W), a, b);
+  return launch_check("tangent axpby");
 }
 
 int tangent_combine(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, float alpha, int add_x,

@@ -348,6 +348,24 @@ def tangent_combine(U, P, alpha, add_x, out=None):
     return W
 
 
+def tangent_inner(U, A, B):
+    """<A, B> of two tangent TTs at the point with left sweep U, as a device
+    tensor of one float (tt_tangent_inner)."""
+    out = torch.empty(1, dtype=torch.float32, device=A.device)
+    L.check(L.load().tt_tangent_inner(C.byref(U.desc()), C.byref(A.desc()), C.byref(B.desc()), _ptr(out),
+                                      _stream(A.device)))
+    return out
+
+
+def tangent_axpby(U, a, A, b, B, out=None):
+    """a A + b B for two tangent TTs at the point with left sweep U
+    (tt_tangent_axpby); ``out`` may be A or B."""
+    W = out if out is not None else TT(A.ns, A.ranks, device=A.device)
+    L.check(L.load().tt_tangent_axpby(C.byref(U.desc()), C.c_float(a), C.byref(A.desc()), C.c_float(b),
+                                      C.byref(B.desc()), C.byref(W.desc()), _stream(A.device)))
+    return W
+
+
 def line_search_terms(P, idx, y, t):
     """Line-search terms (tt_line_search) as a device tensor of 2 floats:
     sum_m P(i^m)^2 and sum_m (y_m - t_m) P(i^m)."""
@@ -406,6 +424,68 @@ def riemannian_completion(X0, idx, t, max_rank, iters, idx_test=None, t_test=Non
         out = completion_iteration(X, idx, t, max_rank)
         hist.append(dict(loss=out["loss"], step=out["step"], test_rmse=rmse))
         X = out["Y"]
+    return X, hist
+
+
+def cg_iteration(X, idx, t, max_rank=None, prev=None):
+    """One step of Riemannian conjugate gradients for tensor completion:
+    xi = P_X(grad) from the fused pass and the sparse projection; with the
+    previous step's xi', eta' (``prev``), their transports P_X(xi'),
+    P_X(eta') by tt_project_tt; beta = max(0, <xi, xi - P_X xi'> /
+    <xi', xi'>) (Polak-Ribiere+, tt_tangent_inner); eta = -xi + beta
+    P_X(eta') (tt_tangent_axpby), reset to -xi when it is not a descent
+    direction; the exact linearised line search along eta (tt_line_search);
+    Y = round(X + a eta).  Host synchronisations: the inner products and the
+    step.  Returns dict(loss, step, beta, Y, xi, eta, xi_sq) (xi, eta:
+    tangent TTs at X, for the next step)."""
+    if max_rank is None:
+        max_rank = max(X.ranks)
+    idx = _idx(idx, X.d, X.device)
+    y, g, loss, _ = gather_mse_backward(X, idx, t, want_g=True)
+    U = orthogonalize(X, L.TT_LR)
+    V = orthogonalize(X, L.TT_RL)
+    xi = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
+    beta = 0.0
+    eta = None
+    if prev is not None and prev["xi_sq"] > 0.0:
+        Txi = project_tt(U, V, prev["xi"])
+        Teta = project_tt(U, V, prev["eta"])
+        xx, xt = (float(v) for v in torch.cat([tangent_inner(U, xi, xi), tangent_inner(U, xi, Txi)]).cpu())
+        beta = max(0.0, (xx - xt) / prev["xi_sq"])
+        eta = tangent_axpby(U, -1.0, xi, beta, Teta, out=Teta)
+        if float(tangent_inner(U, xi, eta).item()) >= 0.0:
+            eta, beta = None, 0.0
+    else:
+        xx = float(tangent_inner(U, xi, xi).item())
+    if eta is None:
+        eta = tangent_axpby(U, -1.0, xi, 0.0, xi)
+    pp, rp = (float(v) for v in line_search_terms(eta, idx, y, t).cpu())
+    a = -rp / pp if pp > 0.0 else 0.0
+    W = tangent_combine(U, eta, a, 1)  # X + a eta
+    Y, _ = round_tt(W, max_rank)
+    return dict(loss=float(loss.item()), step=a, beta=beta, Y=Y, xi=xi, eta=eta, xi_sq=xx)
+
+
+def riemannian_cg(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
+    """Riemannian conjugate gradients for tensor completion: ``iters`` steps
+    of ``cg_iteration`` from X0.  Returns (X, history), one dict(loss, step,
+    beta, test_rmse) per step (test_rmse of the iterate before the step)."""
+    X = X0
+    idx = _idx(idx, X.d, X.device)
+    t = _vec(t, idx.shape[1], X.device)
+    if idx_test is not None:
+        idx_test = _idx(idx_test, X.d, X.device)
+        t_test = _vec(t_test, idx_test.shape[1], X.device)
+    hist = []
+    prev = None
+    for _ in range(iters):
+        rmse = None
+        if idx_test is not None:
+            _, lt, _ = gather_mse_backward(X, idx_test, t_test, want_y=False)
+            rmse = float(lt.item()) ** 0.5
+        prev = cg_iteration(X, idx, t, max_rank, prev)
+        hist.append(dict(loss=prev["loss"], step=prev["step"], beta=prev["beta"], test_rmse=rmse))
+        X = prev["Y"]
     return X, hist
 
 
