@@ -233,7 +233,9 @@ def completion_leg(tt, W, iters=4):
     the linearised loss) on d=10, n=10, canonical rank 16, 2^20 observed
     entries of a planted rank-8 tensor plus noise: time per iteration (one
     host synchronisation per iteration, for the step size) and the loss and
-    held-out RMSE before and after."""
+    held-out RMSE before and after; then Riemannian conjugate gradients from
+    the same start for the same number of steps (time per iteration, loss,
+    beta, held-out RMSE)."""
     import torch
     p = W.completion_d10()
     X = tt.TT.from_cores(p.cores)
@@ -250,11 +252,25 @@ def completion_leg(tt, W, iters=4):
     Xn, h = tt.riemannian_completion(X1, idx, t, 16, iters)
     e1.record()
     torch.cuda.synchronize()
+    gd_ms = e0.elapsed_time(e1)
     _, hl = tt.riemannian_completion(Xn, idx, t, 16, 1, idx_t, t_t)
+    # conjugate gradients from the same start, the same number of steps
+    tt.riemannian_cg(X, idx, t, 16, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    Xc, hc = tt.riemannian_cg(X, idx, t, 16, iters + 1)
+    e1.record()
+    torch.cuda.synchronize()
+    _, lc, _ = tt.gather_mse_backward(Xc, idx_t, t_t, want_y=False)
+    _, lo, _ = tt.gather_mse_backward(Xc, idx, t, want_y=False)
     return {"workload": "d=10 n=10 canonical r=16, 2^20 observed planted-rank-8 entries + N(0, 0.01^2) noise",
-            "iteration_ms": round(e0.elapsed_time(e1) / iters, 3),
+            "iteration_ms": round(gd_ms / iters, 3),
             "loss": [round(h0[0]["loss"], 6)] + [round(x["loss"], 6) for x in h] + [round(hl[0]["loss"], 6)],
-            "test_rmse_first_last": [round(h0[0]["test_rmse"], 5), round(hl[0]["test_rmse"], 5)]}
+            "test_rmse_first_last": [round(h0[0]["test_rmse"], 5), round(hl[0]["test_rmse"], 5)],
+            "cg": {"iteration_ms": round(e0.elapsed_time(e1) / (iters + 1), 3),
+                   "loss": [round(x["loss"], 6) for x in hc] + [round(float(lo.item()), 6)],
+                   "beta": [round(x["beta"], 4) for x in hc],
+                   "test_rmse_first_last": [round(h0[0]["test_rmse"], 5), round(float(lc.item()) ** 0.5, 5)]}}
 
 
 def ttm_leg(tt, W, reps=3):
