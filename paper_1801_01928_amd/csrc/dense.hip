@@ -84,31 +84,6 @@ __device__ void blk_gemm(int M, int N, int K, const float *A, long ar, long ac, 
   }
 }
 
-// blk_gemm with four outputs per thread (independent FMA chains), K
-// unrolled; for products whose K is too long for the LDS-staged helpers.
-__device__ void blk_gemm4(int M, int N, int K, const float *A, long ar, long ac, const float *B,
-                          long br, long bc, float *C, long cr, long cc) {
-  const long tot = (long)M * N;
-  for (long e0 = threadIdx.x; e0 < tot; e0 += 4L * kThreads) {
-    int i[4], j[4];
-    float acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long e = e0 + q * kThreads < tot ? e0 + q * kThreads : e0;
-      i[q] = (int)(e / N);
-      j[q] = (int)(e % N);
-      acc[q] = 0.f;
-    }
-#pragma unroll 4
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = fmaf(A[i[q] * ar + k * ac], B[k * br + j[q] * bc], acc[q]);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (e0 + q * kThreads < tot) C[i[q] * cr + j[q] * cc] = acc[q];
-  }
-}
-
 // In-place Householder QR of the column-major m x c matrix W (ld = m).
 // On return the upper triangle holds R (diag >= 0) and column j below the
 // diagonal holds v_j (v_j[j] = 1 implied); tau[j] = beta_j.
@@ -877,49 +852,104 @@ __global__ void __launch_bounds__(kThreads) tangent_axpby_kernel(TTDev U, TTDev 
 
 // Projection of a TT tensor Y onto the tangent space at X (U left- and V
 // right-orthonormal cores of X).  Interfaces: Psi_0 = 1,
-// Psi_{k+1} = sum_i U_k[i]^T Psi_k Y_k[i] (left sweep, workgroup 0) and
-// Phi_d = 1, Phi_k = sum_i V_k[i] Phi_{k+1} Y_k[i]^T (right sweep,
-// workgroup 1), each a pair of row-major GEMMs per core through a scratch
-// T; then one workgroup per core forms Zhat_k[i] = Psi_k Y_k[i] Phi_{k+1}^T.
+// Psi_{k+1} = sum_i U_k[i]^T Psi_k Y_k[i] (left), Phi_d = 1,
+// Phi_k = sum_i V_k[i] Phi_{k+1} Y_k[i]^T (right); then one workgroup per
+// core forms Zhat_k[i] = Psi_k Y_k[i] Phi_{k+1}^T.
 struct ProjBufs {
   float *psi, *phi, *tmp;
   long pslot, tslot;
 };
 
-__global__ void __launch_bounds__(kThreads) proj_interfaces_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b) {
-  __shared__ Shared sh;
+// One step of both interface sweeps, launch t of d: the left side handles
+// k = t, the right side k = d-1-t.  A side's input interface (Psi_k, or
+// Phi_{k+1}) is [1] at the chain's start, else the sum, in slice order, of
+// the previous launch's per-slice partials; workgroup 0 of the side writes
+// it to its slot.  Then, unless the chain ends here, workgroup i forms the
+// slice-i term of the next interface:
+//   left  U_k[i]^T (Psi_k Y_k[i])          (r_{k+1} x s_{k+1}),
+//   right V_k[i] (Phi_{k+1} Y_k[i]^T)      (r_k x s_k),
+// both products in LDS.  Workgroups [0, lw) are left, the rest right.
+struct ProjStep {
+  int lk, rk;               // left k, right k
+  int lw;                   // left workgroups
+  const float *lin, *rin;   // previous partials ([n][pslot]) or null for [1]
+  int lnin, rnin;           // number of previous partials
+  float *lout, *rout;       // this step's partials
+};
+
+constexpr int kPs = kJac + 1;  // LDS row stride of the step's 64 x 64 tiles
+
+__global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b, ProjStep st) {
+  __shared__ float ta[kJac * kPs], tb[kJac * kPs], tc[kJac * kPs];
   const int d = U.d;
-  if (blockIdx.x == 0) {
-    float *T = b.tmp;
-    if (threadIdx.x == 0) b.psi[0] = 1.f;
-    __syncthreads();
-    for (int k = 0; k + 1 < d; ++k) {
-      const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
-      const long ns1 = (long)n * s1;
-      // T (r0 x n s1) = Psi_k (r0 x s0) Y_k (s0 x n s1), Y_k staged in LDS
-      const float *Pk = b.psi + k * b.pslot;
-      gemm_lds_a((int)r0, (int)ns1, s0, [&](int i, int l) { return Pk[i * s0 + l]; }, Y.data + Y.off[k], ns1, 1,
-                 T, ns1, 1, sh);
-      __syncthreads();
-      // Psi_{k+1} (r1 x s1) = U_k^T T, contracting the (r0 n) rows of both
-      blk_gemm4(r1, s1, r0 * n, U.data + U.off[k], 1, r1, T, s1, 1, b.psi + (k + 1) * b.pslot, s1, 1);
-      __syncthreads();
+  const bool left = (int)blockIdx.x < st.lw;
+  const int i = left ? (int)blockIdx.x : (int)blockIdx.x - st.lw;
+  const int k = left ? st.lk : st.rk;
+  // input interface: rows x cols, into ta
+  const int ir = left ? U.r[k] : V.r[k + 1], ic = left ? Y.r[k] : Y.r[k + 1];
+  const float *in = left ? st.lin : st.rin;
+  const int nin = left ? st.lnin : st.rnin;
+  for (int e = threadIdx.x; e < ir * ic; e += kThreads) {
+    float v = 1.f;  // the 1 x 1 start of a chain
+    if (in) {
+      v = 0.f;
+      for (int j = 0; j < nin; ++j) v += in[(long)j * b.pslot + e];
+    }
+    ta[(e / ic) * kPs + e % ic] = v;
+    if (i == 0) (left ? b.psi + (long)k * b.pslot : b.phi + (long)(k + 1) * b.pslot)[e] = v;
+  }
+  const bool more = left ? (k + 1 < d) : (k >= 1);
+  if (!more) return;
+  const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
+  // Y_k[i] (s0 x s1) into tb
+  const float *Yk = Y.data + Y.off[k];
+  for (int e = threadIdx.x; e < s0 * s1; e += kThreads) {
+    const int bb = e / s1, ee = e % s1;
+    tb[bb * kPs + ee] = Yk[((long)bb * n + i) * s1 + ee];
+  }
+  __syncthreads();
+  if (left) {
+    // tc = Psi_k Y_k[i] (r0 x s1)
+    for (int e = threadIdx.x; e < r0 * s1; e += kThreads) {
+      const int a = e / s1, ee = e % s1;
+      float acc = 0.f;
+      for (int l = 0; l < s0; ++l) acc = fmaf(ta[a * kPs + l], tb[l * kPs + ee], acc);
+      tc[a * kPs + ee] = acc;
     }
   } else {
-    float *T = b.tmp + b.tslot;
-    if (threadIdx.x == 0) b.phi[d * b.pslot] = 1.f;
-    __syncthreads();
-    for (int k = d - 1; k >= 1; --k) {
-      const int r0 = V.r[k], r1 = V.r[k + 1], n = V.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
-      const long ns1 = (long)n * s1;
-      // T ((r0 n) x s1) = V_k ((r0 n) x r1) Phi_{k+1} (r1 x s1), V_k staged in LDS
-      const float *Fk = b.phi + (k + 1) * b.pslot;
-      gemm_lds_b(r0 * n, s1, r1, V.data + V.off[k], r1, 1, [&](int l, int j) { return Fk[l * s1 + j]; }, T, s1,
-                 sh);
-      __syncthreads();
-      // Phi_k (r0 x s0) = T (r0 x n s1) Y_k^T (n s1 x s0)
-      blk_gemm4(r0, s0, (int)ns1, T, ns1, 1, Y.data + Y.off[k], 1, ns1, b.phi + k * b.pslot, s0, 1);
-      __syncthreads();
+    // tc = Phi_{k+1} Y_k[i]^T (r1 x s0)
+    for (int e = threadIdx.x; e < r1 * s0; e += kThreads) {
+      const int c = e / s0, bb = e % s0;
+      float acc = 0.f;
+      for (int l = 0; l < s1; ++l) acc = fmaf(ta[c * kPs + l], tb[bb * kPs + l], acc);
+      tc[c * kPs + bb] = acc;
+    }
+  }
+  __syncthreads();
+  // U_k[i] or V_k[i] (r0 x r1) into ta
+  const float *Gk = left ? U.data + U.off[k] : V.data + V.off[k];
+  for (int e = threadIdx.x; e < r0 * r1; e += kThreads) {
+    const int a = e / r1, c = e % r1;
+    ta[a * kPs + c] = Gk[((long)a * n + i) * r1 + c];
+  }
+  __syncthreads();
+  if (left) {
+    // partial of Psi_{k+1} (r1 x s1) = U_k[i]^T tc
+    float *out = st.lout + (long)i * b.pslot;
+    for (int e = threadIdx.x; e < r1 * s1; e += kThreads) {
+      const int c = e / s1, ee = e % s1;
+      float acc = 0.f;
+      for (int a = 0; a < r0; ++a) acc = fmaf(ta[a * kPs + c], tc[a * kPs + ee], acc);
+      out[e] = acc;
+    }
+  } else {
+    // partial of Phi_k (r0 x s0) = V_k[i] tc
+    float *out = st.rout + (long)i * b.pslot;
+    for (int e = threadIdx.x; e < r0 * s0; e += kThreads) {
+      const int a = e / s0, bb = e % s0;
+      float acc = 0.f;
+      for (int c = 0; c < r1; ++c) acc = fmaf(ta[a * kPs + c], tc[c * kPs + bb], acc);
+      out[e] = acc;
     }
   }
 }
@@ -1078,7 +1108,10 @@ size_t project_tt_ws(const tt_tensor *U, const tt_tensor *Y) {
   proj_slots(U, Y, &ps, &ts);
   long zel = 0;
   for (int k = 0; k < U->d; ++k) zel += (long)U->r[k] * U->n[k] * U->r[k + 1];
+  int nmax = 1;
+  for (int k = 0; k < U->d; ++k) nmax = U->n[k] > nmax ? U->n[k] : nmax;
   size_t b = 2 * arena_bytes<float>((size_t)(U->d + 1) * ps);
+  b += 4 * arena_bytes<float>((size_t)nmax * ps);
   b += arena_bytes<float>((size_t)(U->d + 2) * ts);
   b += arena_bytes<float>((size_t)zel);
   b += tangent_ws(U) + 256;
@@ -1091,8 +1124,12 @@ int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float
   proj_slots(U, Y, &ps, &ts);
   Arena ar(ws, bytes);
   ProjBufs b;
+  int nmax = 1;
+  for (int k = 0; k < U->d; ++k) nmax = U->n[k] > nmax ? U->n[k] : nmax;
   b.psi = ar.take<float>((size_t)(U->d + 1) * ps);
   b.phi = ar.take<float>((size_t)(U->d + 1) * ps);
+  float *lpart[2] = {ar.take<float>((size_t)nmax * ps), ar.take<float>((size_t)nmax * ps)};
+  float *rpart[2] = {ar.take<float>((size_t)nmax * ps), ar.take<float>((size_t)nmax * ps)};
   b.tmp = ar.take<float>((size_t)(U->d + 2) * ts);
   b.pslot = ps;
   b.tslot = ts;
@@ -1102,10 +1139,25 @@ int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float
   const size_t tws = tangent_ws(U);
   void *tw = ar.take<char>(tws);
   if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "project_tt: workspace too small");
-  hipLaunchKernelGGL(proj_interfaces_kernel, dim3(2), dim3(kThreads), 0, s, make_dev(U), make_dev(V), make_dev(Y),
-                     b);
-  int rc = launch_check("TT projection interfaces");
-  if (rc) return rc;
+  // interface sweeps: launch t runs left step k = t and right step k = d-1-t
+  const int d = U->d;
+  const TTDev Ud = make_dev(U), Vd = make_dev(V), Yd = make_dev(Y);
+  int rc = TT_OK;
+  for (int t = 0; t < d; ++t) {
+    ProjStep st;
+    st.lk = t;
+    st.rk = d - 1 - t;
+    st.lw = (st.lk + 1 < d) ? U->n[st.lk] : 1;
+    const int rw = (st.rk >= 1) ? U->n[st.rk] : 1;
+    st.lin = t == 0 ? nullptr : lpart[(t - 1) & 1];
+    st.lnin = t == 0 ? 0 : U->n[st.lk - 1];
+    st.rin = t == 0 ? nullptr : rpart[(t - 1) & 1];
+    st.rnin = t == 0 ? 0 : U->n[st.rk + 1];
+    st.lout = lpart[t & 1];
+    st.rout = rpart[t & 1];
+    hipLaunchKernelGGL(proj_step_kernel, dim3(st.lw + rw), dim3(kThreads), 0, s, Ud, Vd, Yd, b, st);
+    if ((rc = launch_check("TT projection interface step"))) return rc;
+  }
   tt_tensor Z = {U->d, U->n, U->r, nullptr, zbuf};
   hipLaunchKernelGGL(proj_cores_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(Y), make_dev(&Z),
                      b);
