@@ -201,21 +201,21 @@ def gram_leg(tt, W, reps=3):
 
 def riemann_leg(tt, W, reps=3):
     """One Riemannian step on d=10, n=10, r=32 (canonical ranks) with 2^20
-    observed N(0,1) gradient values: both QR sweeps, the sparse tangent
-    projection with assembly, and TT rounding back to rank 32; beside the
-    step, the projection of the rank-64 tangent TT onto the tangent space at
-    X (the transport of a search direction)."""
+    observed N(0,1) gradient values: both QR sweeps (one launch, a
+    workgroup per direction), the sparse tangent projection with assembly,
+    and TT rounding back to rank 32; beside the step, the projection of the
+    rank-64 tangent TT onto the tangent space at X (the transport of a
+    search direction)."""
     import torch
     p = W.riemann_d10()
     X = tt.TT.from_cores(p.cores)
     idx = torch.from_numpy(p.idx).cuda()
     z = torch.from_numpy(p.values).cuda()
-    U = tt.orthogonalize(X, tt.TT_LR)
-    V = tt.orthogonalize(X, tt.TT_RL)
+    U, V = tt.orthogonalize_both(X)
     Wt = tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1)
     tt.round_tt(Wt, 32)
     torch.cuda.synchronize()
-    orth_ms = _event_ms(lambda: (tt.orthogonalize(X, tt.TT_LR), tt.orthogonalize(X, tt.TT_RL)), reps)
+    orth_ms = _event_ms(lambda: tt.orthogonalize_both(X), reps)
     proj_ms = _event_ms(lambda: tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1), reps)
     round_ms = _event_ms(lambda: tt.round_tt(Wt, 32), reps)
     tt.project_tt(U, V, Wt)

@@ -190,6 +190,15 @@ int64_t tt_orthogonalize_workspace(const tt_tensor *X, int dir);
 int tt_orthogonalize(const tt_tensor *X, int dir, tt_tensor *out,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Both sweeps of one X in a single launch (two workgroups, each with its
+ * own half of the workspace): U receives the left-to-right result and V the
+ * right-to-left result, exactly as two tt_orthogonalize calls would write
+ * them (the same kernels; U and V at the ranks tt_orthogonalize_ranks gives
+ * for TT_LR and TT_RL).  The tangent-space operations need both. */
+int64_t tt_orthogonalize_both_workspace(const tt_tensor *X);
+int tt_orthogonalize_both(const tt_tensor *X, tt_tensor *U, tt_tensor *V,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* --------------------------------------------------------------- A5+A6 */
 /* Tangent projection of a sparse tensor (Riemannian Geometry Operations:
  * P_X Z, computed as project_sum of the M one-hot rank-1 tensors

@@ -18,6 +18,7 @@ from .tt import (  # noqa: F401
     tt_gather,
     KernelTimer,
     orthogonalize,
+    orthogonalize_both,
     project_sparse,
     round_tt,
     riemannian_step,

@@ -75,6 +75,8 @@ SIGNATURES = {
     "tt_line_search": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, SZ, VP]),
     "tt_orthogonalize_ranks": (C.c_int, [P_TT, C.c_int, PI32]),
     "tt_orthogonalize_workspace": (I64, [P_TT, C.c_int]),
+    "tt_orthogonalize_both_workspace": (I64, [P_TT]),
+    "tt_orthogonalize_both": (C.c_int, [P_TT, P_TT, P_TT, VP, SZ, VP]),
     "tt_orthogonalize": (C.c_int, [P_TT, C.c_int, P_TT, VP, SZ, VP]),
     "tt_project_sparse_workspace": (I64, [P_TT, I64]),
     "tt_project_sparse": (C.c_int, [P_TT, P_TT, VP, I64, VP, C.c_float, C.c_int, P_TT, VP, SZ, VP]),

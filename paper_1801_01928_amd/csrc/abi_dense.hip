@@ -63,6 +63,27 @@ int tt_orthogonalize(const tt_tensor *X, int dir, tt_tensor *out, void *ws, size
   return dense_orth(X, dir, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
+int64_t tt_orthogonalize_both_workspace(const tt_tensor *X) {
+  int rc = validate_tt(X, "X", DENSE_MAX_RANK);
+  if (rc) return rc;
+  return (int64_t)(2 * dense_ws(X));
+}
+
+int tt_orthogonalize_both(const tt_tensor *X, tt_tensor *U, tt_tensor *V, void *ws, size_t ws_bytes, void *stream) {
+  int rc = validate_tt(X, "X", DENSE_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = validate_tt(U, "U", DENSE_MAX_RANK))) return rc;
+  if ((rc = validate_tt(V, "V", DENSE_MAX_RANK))) return rc;
+  if (!same_modes(X, U) || !same_modes(X, V)) return set_error(TT_ERR_SHAPE, "U and V must have X's mode sizes");
+  int32_t want[TT_MAX_D + 1];
+  dense_orth_ranks(X, TT_LR, want);
+  if ((rc = check_ranks(U, want, "orthogonalize_both (U)"))) return rc;
+  dense_orth_ranks(X, TT_RL, want);
+  if ((rc = check_ranks(V, want, "orthogonalize_both (V)"))) return rc;
+  if ((rc = check_ws(ws, ws_bytes, 2 * dense_ws(X), "orthogonalize_both"))) return rc;
+  return dense_orth_both(X, U, V, ws, ws_bytes, (hipStream_t)stream);
+}
+
 int64_t tt_project_sparse_workspace(const tt_tensor *U, int64_t M) {
   int rc = validate_tt(U, "U", TT_MAX_RANK);
   if (rc) return rc;

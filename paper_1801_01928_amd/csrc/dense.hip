@@ -624,6 +624,23 @@ __global__ void __launch_bounds__(kThreads) orth_kernel(TTDev X, TTDev O, int di
   copy_out(w, X.d, n, r, O);
 }
 
+// Both sweeps at once: workgroup 0 runs the left-to-right sweep into OL,
+// workgroup 1 the right-to-left sweep into OR, each on its own buffers.
+__global__ void __launch_bounds__(kThreads) orth_both_kernel(TTDev X, TTDev OL, TTDev OR, DenseBufs bl,
+                                                             DenseBufs br) {
+  __shared__ Shared sh;
+  __shared__ int n[TT_MAX_D], r[TT_MAX_D + 1];
+  for (int k = threadIdx.x; k < X.d; k += kThreads) n[k] = X.n[k];
+  for (int k = threadIdx.x; k <= X.d; k += kThreads) r[k] = X.r[k];
+  const bool lr = blockIdx.x == 0;
+  const DenseBufs &b = lr ? bl : br;
+  WorkTT w{b.work, b.slot};
+  copy_in(X, w);
+  if (lr) sweep_lr(w, X.d, n, r, b.wm, b.q, b.tau, sh);
+  else sweep_rl(w, X.d, n, r, b.wm, b.q, b.tau, sh);
+  copy_out(w, X.d, n, r, lr ? OL : OR);
+}
+
 // TT rounding: right-to-left LQ sweep, then left-to-right truncated SVDs.
 __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int max_rank,
                                                          float *disc, DenseBufs b) {
@@ -1047,6 +1064,20 @@ int dense_orth(const tt_tensor *X, int dir, tt_tensor *O, void *ws, size_t bytes
   hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(kThreads), 0, s, make_dev(X), make_dev(O), dir, b);
   timer_after(s);
   return launch_check("orthogonalize");
+}
+
+int dense_orth_both(const tt_tensor *X, tt_tensor *OL, tt_tensor *OR, void *ws, size_t bytes, hipStream_t s) {
+  const size_t half = dense_ws(X);
+  if (bytes < 2 * half) return set_error(TT_ERR_WORKSPACE, "orthogonalize_both: workspace too small");
+  DenseBufs bl, br;
+  int rc = dense_bufs(X, ws, half, bl);
+  if (rc) return rc;
+  if ((rc = dense_bufs(X, (char *)ws + half, half, br))) return rc;
+  timer_before(s);
+  hipLaunchKernelGGL(orth_both_kernel, dim3(2), dim3(kThreads), 0, s, make_dev(X), make_dev(OL), make_dev(OR), bl,
+                     br);
+  timer_after(s);
+  return launch_check("orthogonalize both");
 }
 
 int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, void *ws, size_t bytes,

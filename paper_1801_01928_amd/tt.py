@@ -281,6 +281,18 @@ def orthogonalize(X, direction):
     return out
 
 
+def orthogonalize_both(X):
+    """(U, V) = (orthogonalize(X, LR), orthogonalize(X, RL)) in one launch
+    (tt_orthogonalize_both)."""
+    lib = L.load()
+    U = TT(X.ns, _ranks_call(lib.tt_orthogonalize_ranks, X, L.TT_LR), device=X.device)
+    V = TT(X.ns, _ranks_call(lib.tt_orthogonalize_ranks, X, L.TT_RL), device=X.device)
+    ws, nb = _workspace(L.check(lib.tt_orthogonalize_both_workspace(C.byref(X.desc()))), X.device)
+    L.check(lib.tt_orthogonalize_both(C.byref(X.desc()), C.byref(U.desc()), C.byref(V.desc()), _ptr(ws), nb,
+                                      _stream(X.device)))
+    return U, V
+
+
 def project_sparse(U, V, idx, z, alpha=1.0, add_x=0):
     """Tangent projection of the sparse tensor sum_m z[m] e_{i^m} at X, with
     U = orthogonalize(X, LR) and V = orthogonalize(X, RL); returns the rank-2r
@@ -320,8 +332,7 @@ def riemannian_step(X, idx, t, alpha=-0.1, max_rank=None):
     idx = _idx(idx, X.d, X.device)
     M = idx.shape[1]
     y, g, loss, grads = gather_mse_backward(X, idx, t, want_g=True)
-    U = orthogonalize(X, L.TT_LR)
-    V = orthogonalize(X, L.TT_RL)
+    U, V = orthogonalize_both(X)
     W = project_sparse(U, V, idx, g, alpha=alpha, add_x=1)
     Y, disc = round_tt(W, max_rank)
     return dict(y=y, loss=loss, grads=grads, U=U, V=V, W=W, Y=Y, disc_sq=disc)
@@ -394,8 +405,7 @@ def completion_iteration(X, idx, t, max_rank=None):
         max_rank = max(X.ranks)
     idx = _idx(idx, X.d, X.device)
     y, g, loss, _ = gather_mse_backward(X, idx, t, want_g=True)
-    U = orthogonalize(X, L.TT_LR)
-    V = orthogonalize(X, L.TT_RL)
+    U, V = orthogonalize_both(X)
     P = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
     pp, rp = (float(v) for v in line_search_terms(P, idx, y, t).cpu())
     a = rp / pp if pp > 0.0 else 0.0
@@ -442,8 +452,7 @@ def cg_iteration(X, idx, t, max_rank=None, prev=None):
         max_rank = max(X.ranks)
     idx = _idx(idx, X.d, X.device)
     y, g, loss, _ = gather_mse_backward(X, idx, t, want_g=True)
-    U = orthogonalize(X, L.TT_LR)
-    V = orthogonalize(X, L.TT_RL)
+    U, V = orthogonalize_both(X)
     xi = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
     beta = 0.0
     eta = None

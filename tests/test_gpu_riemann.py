@@ -62,6 +62,23 @@ def test_orthogonalize(gpu_lib, case):
             assert np.linalg.norm(g - r) <= 1e-4 * max(np.linalg.norm(r), 1e-30)
 
 
+@pytest.mark.parametrize("case", range(len(SHAPES)))
+def test_orthogonalize_both_equals_two_sweeps(gpu_lib, case):
+    """One launch with both sweeps writes exactly what two single-direction
+    calls write (the same arithmetic on separate buffers), on every shape
+    above, including the global-memory QR."""
+    tt = gpu_lib
+    ns, ranks = SHAPES[case]
+    print("orthogonalize_both", ns, ranks, flush=True)
+    X = tt.TT.from_cores(W.random_tt(150 + case, ns, ranks, std=1.0 / np.sqrt(max(ranks))))
+    U, V = tt.orthogonalize_both(X)
+    U1 = tt.orthogonalize(X, tt.TT_LR)
+    V1 = tt.orthogonalize(X, tt.TT_RL)
+    assert U.ranks == U1.ranks and V.ranks == V1.ranks
+    for a, b in zip(U.numpy_cores() + V.numpy_cores(), U1.numpy_cores() + V1.numpy_cores()):
+        np.testing.assert_array_equal(a, b)
+
+
 ROUND = [
     ([8, 8, 8, 8], [1, 8, 8, 8, 1], 4),
     ([10] * 6, [1, 10, 40, 40, 40, 10, 1], 16),
