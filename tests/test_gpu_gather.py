@@ -38,6 +38,9 @@ CASES = [
     (7, [13], [1, 1], 100),                       # d = 1
     (8, [6, 6, 6], [1, 40, 40, 1], 3001),         # rank above 32
     (9, [4, 4, 4, 4], [1, 4, 16, 4, 1], 1),       # a single entry
+    (12, [2] * 32, [1] + [3] * 31 + [1], 5000),   # d = TT_MAX_D (generic kernels)
+    (13, [4096, 3], [1, 5, 1], 20000),            # n = TT_MAX_N
+    (14, [40, 50, 30], [1, 8, 8, 1], 10000),      # modes above the MFMA classes' sizes
 ]
 
 
