@@ -107,6 +107,58 @@ def cpu_baseline(p, t, sample):
                       % (S, p.M, dt)}
 
 
+def _oracle_chunk(args):
+    """Worker of the all-core baseline: the oracle's gather, loss and adjoint
+    on one chunk of entries, single-threaded BLAS.  Returns the chunk's core
+    gradients (for the parent to sum) and its time."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(limits=1)
+    except ImportError:  # pragma: no cover
+        ctx = None
+    import oracle
+    cores, idx, ts, m_total = args
+    t0 = time.perf_counter()
+    y = oracle.gather(cores, idx)
+    _, g = oracle.mse_loss_and_grad(y, ts)
+    g = g * (len(ts) / float(m_total))  # the chunk's share of the mean over all entries
+    grads = oracle.gather_backward(cores, idx, g)
+    dt = time.perf_counter() - t0
+    del ctx  # the worker exits after the pool; its BLAS limit need not be restored
+    return grads, dt
+
+
+def cpu_baseline_all_cores(p, t, sample, workers):
+    """The same oracle pass over `workers` processes (spawned, one BLAS thread
+    each), each on its own chunk of the first workers * sample entries; the
+    parent sums the chunk gradients.  Wall time from the first chunk handed
+    out to the last gradient summed, after a warm-up that starts every
+    worker.  Bounded waits; the pool is terminated on any failure."""
+    import multiprocessing as mp
+    import numpy as np
+    S = min(sample * workers, p.M)
+    cores = [c.astype(np.float64) for c in p.cores]
+    ts = t[:S].astype(np.float64)
+    bounds = np.linspace(0, S, workers + 1).astype(int)
+    jobs = [(cores, p.idx[:, a:b], ts[a:b], S) for a, b in zip(bounds[:-1], bounds[1:])]
+    pool = mp.get_context("spawn").Pool(workers)
+    try:
+        pool.map_async(_oracle_chunk, [(cores, p.idx[:, :64], ts[:64], S)] * workers, chunksize=1).get(timeout=60)
+        t0 = time.perf_counter()
+        res = pool.map_async(_oracle_chunk, jobs, chunksize=1).get(timeout=120)
+        total = res[0][0]
+        for grads, _ in res[1:]:
+            total = [a + b for a, b in zip(total, grads)]
+        dt = time.perf_counter() - t0
+    finally:
+        pool.terminate()
+        pool.join()
+    return {"value": S / dt, "unit": "entries/s", "cores": workers, "kind": "oracle",
+            "sample": "first %d of the %d observed entries over %d processes (gather + MSE + adjoint, "
+                      "float64, %.1f s)" % (S, p.M, workers, dt)}
+
+
 def _event_ms(fn, reps, stream=None):
     """Average milliseconds of fn() over reps calls, HIP events on the stream."""
     import torch
@@ -373,7 +425,14 @@ def main():
         out["ttm_layer"] = ttm_leg(tt, W)
         out["completion_loop"] = completion_leg(tt, W)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, t.cpu().numpy(), args.cpu_sample)
+        th = t.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(p, th, args.cpu_sample)
+        workers = max(1, min(16, os.cpu_count() or 1))
+        if workers > 1:
+            try:
+                out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(p, th, args.cpu_sample // 2, workers)
+            except Exception as e:  # reported, never fatal to the JSON line
+                out["cpu_baseline_all_cores"] = {"error": "%s: %s" % (type(e).__name__, e)}
     print(json.dumps(out), flush=True)
 
 
