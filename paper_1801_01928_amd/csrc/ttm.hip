@@ -213,6 +213,11 @@ template <int BF16, int VT, int VV>
 __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   __shared__ float ts[kSlab][kLd];
   __shared__ float vs[kSlab][kLd];
+  // bfloat16 slabs reuse the same memory as [row][k] tables
+  constexpr int kLdb = kSlab + 4;
+  static_assert(TTM_MAX_FUSED * kLdb * 2 <= kSlab * kLd * 4, "bf16 slab fits");
+  uint16_t *tsb = (uint16_t *)&ts[0][0];
+  uint16_t *vsb = (uint16_t *)&vs[0][0];
   __shared__ long long roff[TTM_MAX_FUSED], coffs[TTM_MAX_FUSED];
   const int ROWS = g.rT * g.n, COLS = g.m * g.rV;
   const int RT = (ROWS + 15) / 16, CT = (COLS + 15) / 16;
@@ -298,23 +303,63 @@ __global__ void __launch_bounds__(kThreads) ttm_grad_kernel(GradArgs g) {
   int sl = 0;
   for (long long kb = k0; kb < k1; kb += kSlab, ++sl) {
     __syncthreads();  // the previous slab is consumed
+    if constexpr (BF16) {
+      // bfloat16 slabs, K fastest: tsb[row][k], vsb[col][k] (the values
+      // came from bfloat16, so the conversion back is exact)
 #pragma unroll
-    for (int u = 0; u < kPerT; ++u) {
-      const int e = ET * (tid + u * kThreads);
+      for (int u = 0; u < kPerT; ++u) {
+        const int e = ET * (tid + u * kThreads);
 #pragma unroll
-      for (int x = 0; x < ET; ++x)
-        if (e < kSlab * ROWS) ts[e / ROWS][e % ROWS + x] = tr[u][x];
-    }
+        for (int x = 0; x < ET; ++x)
+          if (e < kSlab * ROWS) tsb[(e % ROWS + x) * kLdb + e / ROWS] = f32_to_bf16(tr[u][x]);
+      }
 #pragma unroll
-    for (int u = 0; u < kPerV; ++u) {
-      const int e = EV * (tid + u * kThreads);
+      for (int u = 0; u < kPerV; ++u) {
+        const int e = EV * (tid + u * kThreads);
 #pragma unroll
-      for (int x = 0; x < EV; ++x)
-        if (e < kSlab * COLS) vs[e / COLS][e % COLS + x] = vr[u][x];
+        for (int x = 0; x < EV; ++x)
+          if (e < kSlab * COLS) vsb[(e % COLS + x) * kLdb + e / COLS] = f32_to_bf16(vr[u][x]);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kPerT; ++u) {
+        const int e = ET * (tid + u * kThreads);
+#pragma unroll
+        for (int x = 0; x < ET; ++x)
+          if (e < kSlab * ROWS) ts[e / ROWS][e % ROWS + x] = tr[u][x];
+      }
+#pragma unroll
+      for (int u = 0; u < kPerV; ++u) {
+        const int e = EV * (tid + u * kThreads);
+#pragma unroll
+        for (int x = 0; x < EV; ++x)
+          if (e < kSlab * COLS) vs[e / COLS][e % COLS + x] = vr[u][x];
+      }
     }
     bases(kb + kSlab, (sl + 1) & 1);
     __syncthreads();
     if (kb + kSlab < k1) fetch((sl + 1) & 1);
+    if constexpr (BF16) {
+      // bfloat16 MFMA, 16 K values per product: lane (q4, c16) holds K
+      // values 4 q4 .. 4 q4 + 3 of its row (A) and of its column (B), one
+      // 8-byte LDS read each; the D layout is that of the fp32 product
+#pragma unroll
+      for (int kg = 0; kg < kSlab / 16; ++kg) {
+        const int kl = 16 * kg + 4 * q4;
+        v4s a4[RPW];
+#pragma unroll
+        for (int u = 0; u < RPW; ++u) a4[u] = *(const v4s *)(tsb + (16 * (wave + 4 * u) + c16) * kLdb + kl);
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) {
+          if (t >= CT) continue;
+          const v4s b4 = *(const v4s *)(vsb + (16 * t + c16) * kLdb + kl);
+#pragma unroll
+          for (int u = 0; u < RPW; ++u)
+            if (wave + 4 * u < RT) acc[u][t] = mfma_bf16(a4[u], b4, acc[u][t]);
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int ks = 0; ks < kSlab / 4; ++ks) {
       const int kl = 4 * ks + q4;  // K slot q4 of this lane
