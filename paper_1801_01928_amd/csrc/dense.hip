@@ -36,8 +36,13 @@ struct Shared {
   int rotated;
   float hv[2][64 * 10];     // register QR: broadcast Householder vector (double-buffered)
   float stg[64 * 65];       // staging chunk of the large GEMM operand
+  float sm[64 * 65];        // the small GEMM factor, staged (row stride 65)
   float hb[kJac];           // register QR: reflector coefficients
 };
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -428,87 +433,96 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
   return 40;
 }
 
+// The two GEMM helpers below run on the fp32 matrix cores
+// (v_mfma_f32_16x16x4f32).  Each 64 x 64 block of C is 16 tiles of 16 x 16;
+// wave w takes row tile w % 4 and column tiles w / 4 and w / 4 + 2.  MFMA
+// operands, lane (q4, c16) = (lane / 16, lane % 16): A(row c16, k q4),
+// B(k q4, column c16); the result lane holds C(rows 4 q4 .. 4 q4 + 3,
+// column c16).  Both factors sit in LDS as zero-padded 64 x 64 tables of
+// row stride 65: the small one (read through its accessor) in sh.sm, the
+// large one (staged from global memory in 64-row or 64-column chunks) in
+// sh.stg.
+
+// One 64 x 64 block: C(i, j) = sum_l A(i, l) B(l, j) for l < K, with A at
+// ta[i * 65 + l] and B at tb[l * 65 + j]; K rounded up to 4 (the tables are
+// zero past K).  out(i, j, value) stores the block's elements.
+template <class Out>
+__device__ __forceinline__ void mfma_block(const float *ta, const float *tb, int K, Out out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c16 = lane & 15, q4 = lane >> 4;
+  const int rt = wave & 3, ct0 = wave >> 2;
+  v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const float av = ta[(16 * rt + c16) * 65 + k0 + q4];
+    const float b0 = tb[(k0 + q4) * 65 + 16 * ct0 + c16];
+    const float b1 = tb[(k0 + q4) * 65 + 16 * (ct0 + 2) + c16];
+    acc0 = mfma4(av, b0, acc0);
+    acc1 = mfma4(av, b1, acc1);
+  }
+  __syncthreads();  // every read of the staged tables precedes the stores
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    out(16 * rt + 4 * q4 + v, 16 * ct0 + c16, acc0[v]);
+    out(16 * rt + 4 * q4 + v, 16 * (ct0 + 2) + c16, acc1[v]);
+  }
+}
+
 // C (M x N) = A (M x K) * B (K x N) for K <= 64, the small factor A read
-// from LDS through aop(i, l), B in global memory (element (l, j) at
-// B[l*br + j*bc]).  B is staged through sh.stg in chunks of 64 columns, so
-// every global element is read once and coalesced.  C may alias B: the
-// columns of a chunk are written only after that chunk was staged
-// (element (i, j) of C at C[i*cr + j*cc]).
+// through aop(i, l) (consecutive l on consecutive lanes when staged), B in
+// global memory (element (l, j) at B[l*br + j*bc]), staged in chunks of 64
+// columns.  C may alias B: a chunk's columns are written only after the
+// whole chunk was staged (element (i, j) of C at C[i*cr + j*cc]).
 template <class AOp>
 __device__ void gemm_lds_a(int M, int N, int K, AOp aop, const float *B, long br, long bc, float *C, long cr,
                            long cc, Shared &sh) {
-  for (int j0 = 0; j0 < N; j0 += 64) {
-    const int nc = (N - j0) < 64 ? (N - j0) : 64;
-    for (int e = threadIdx.x; e < K * 64; e += kThreads) {
-      const int l = e >> 6, jj = e & 63;
-      sh.stg[l * 65 + jj] = (jj < nc) ? B[(long)l * br + (long)(j0 + jj) * bc] : 0.f;
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    const int mr = (M - i0) < 64 ? (M - i0) : 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
+      const int i = e >> 6, l = e & 63;
+      sh.sm[i * 65 + l] = (i < mr && l < K) ? aop(i0 + i, l) : 0.f;
     }
-    __syncthreads();
-    // four outputs per thread at a time (independent FMA chains), K unrolled
-    const int tot = M * nc;
-    for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * kThreads) {
-      int i[4], jj[4];
-      float acc[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = e0 + q * kThreads < tot ? e0 + q * kThreads : e0;
-        i[q] = e / nc;
-        jj[q] = e % nc;
-        acc[q] = 0.f;
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      const int nc = (N - j0) < 64 ? (N - j0) : 64;
+      for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
+        const int l = e >> 6, jj = e & 63;
+        sh.stg[l * 65 + jj] = (jj < nc && l < K) ? B[(long)l * br + (long)(j0 + jj) * bc] : 0.f;
       }
-#pragma unroll 4
-      for (int l = 0; l < K; ++l)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = fmaf(aop(i[q], l), sh.stg[l * 65 + jj[q]], acc[q]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (e0 + q * kThreads < tot) C[(long)i[q] * cr + (long)(j0 + jj[q]) * cc] = acc[q];
+      __syncthreads();
+      mfma_block(sh.sm, sh.stg, K, [&](int i, int jj, float v) {
+        if (i < mr && jj < nc) C[(long)(i0 + i) * cr + (long)(j0 + jj) * cc] = v;
+      });
     }
     __syncthreads();
   }
 }
 
-// C (M x N) = A (M x K) * B (K x N) for K <= 64, A in global memory
-// (element (i, l) at A[i*ar + l*ac]) staged in chunks of 64 rows, the small
-// factor B read from LDS through bop(l, j).  C may alias A when row i of C
-// (C[i*ldc + j]) never reaches past row i of A, i.e. ldc <= A's row stride.
-// ROWS_ON_LANES: the lanes of a wave take the rows of one column (bop is
-// then read at one address per wave), for factors whose elements of one
-// row l sit in a single LDS bank across columns; otherwise lanes take
-// consecutive columns of a row (coalesced stores).
+// C (M x N) = A (M x K) * B (K x N) for K <= 64 and N <= 64, A in global
+// memory (element (i, l) at A[i*ar + l*ac]) staged in chunks of 64 rows,
+// the small factor B read through bop(l, j).  ROWS_ON_LANES: bop is read
+// with consecutive l on consecutive lanes (for factors whose elements of
+// one row l are 64 floats apart), else with consecutive j.  C may alias A
+// when row i of C (C[i*ldc + j]) never reaches past row i of A, i.e. ldc <=
+// A's row stride: a chunk's rows are written after the chunk was staged.
 template <bool ROWS_ON_LANES = false, class BOp>
 __device__ void gemm_lds_b(int M, int N, int K, const float *A, long ar, long ac, BOp bop, float *C, long ldc,
                            Shared &sh) {
+  for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
+    const int l = ROWS_ON_LANES ? (e & 63) : (e >> 6), j = ROWS_ON_LANES ? (e >> 6) : (e & 63);
+    sh.sm[l * 65 + j] = (l < K && j < N) ? bop(l, j) : 0.f;
+  }
   for (int i0 = 0; i0 < M; i0 += 64) {
     const int mr = (M - i0) < 64 ? (M - i0) : 64;
     // consecutive threads walk the unit-stride index of A (coalesced loads)
-    for (int e = threadIdx.x; e < 64 * K; e += kThreads) {
-      const int ii = (ar == 1) ? (e & 63) : e / K, l = (ar == 1) ? (e >> 6) : e % K;
-      sh.stg[ii * 65 + l] = (ii < mr) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
+    for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
+      const int ii = (ar == 1) ? (e & 63) : (e >> 6), l = (ar == 1) ? (e >> 6) : (e & 63);
+      sh.stg[ii * 65 + l] = (ii < mr && l < K) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
     }
     __syncthreads();
-    // four outputs per thread at a time (independent FMA chains), K unrolled
-    const int tot = (ROWS_ON_LANES ? 64 : mr) * N;
-    for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * kThreads) {
-      int ii[4], j[4];
-      float acc[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = e0 + q * kThreads < tot ? e0 + q * kThreads : e0;
-        ii[q] = ROWS_ON_LANES ? (e & 63) : e / N;
-        j[q] = ROWS_ON_LANES ? (e >> 6) : e % N;
-        acc[q] = 0.f;
-      }
-#pragma unroll 4
-      for (int l = 0; l < K; ++l)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = fmaf(sh.stg[ii[q] * 65 + l], bop(l, j[q]), acc[q]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (e0 + q * kThreads < tot && ii[q] < mr) C[(long)(i0 + ii[q]) * ldc + j[q]] = acc[q];
-    }
-    __syncthreads();
+    mfma_block(sh.stg, sh.sm, K, [&](int ii, int j, float v) {
+      if (ii < mr && j < N) C[(long)(i0 + ii) * ldc + j] = v;
+    });
   }
+  __syncthreads();
 }
 
 // Cores of the working TT in the workspace: each core has its own slot of
@@ -984,7 +998,8 @@ __global__ void __launch_bounds__(kThreads) proj_cores_kernel(TTDev U, TTDev Y, 
   __syncthreads();
   // Zhat_k ((r0 n) x r1) = T ((r0 n) x s1) Phi_{k+1}^T (s1 x r1)
   const float *Fk = b.phi + (k + 1) * b.pslot;
-  gemm_lds_b(r0 * n, r1, s1, T, s1, 1, [&](int l, int j) { return Fk[j * s1 + l]; }, Z.data + Z.off[k], r1, sh);
+  gemm_lds_b<true>(r0 * n, r1, s1, T, s1, 1, [&](int l, int j) { return Fk[j * s1 + l]; }, Z.data + Z.off[k], r1,
+                   sh);
 }
 
 long slot_of(const int *n, const int *r, int d) {
