@@ -45,6 +45,8 @@ def parse():
                     help="observed entries the oracle processes for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--tables-only", action="store_true",
+                    help="run only the table gather leg (for its kernel trace and HBM counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (batched plan, Riemannian step, Gram, TT-matrix)")
     return ap.parse_args()
@@ -365,6 +367,12 @@ def main():
     import workloads as W
     import paper_1801_01928_amd as tt
 
+    if args.tables_only:
+        import paper_1801_01928_amd as tt
+        import workloads as W
+        tt.load()
+        print(json.dumps({"gather_tables": tables_leg(tt, W)}), flush=True)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
