@@ -62,7 +62,11 @@ __device__ __forceinline__ void load8_bf16(const void *p, long long i, float (&o
 }
 
 constexpr int kThreads = 256;  // 4 waves
-constexpr int kRows = 64;      // rows per workgroup iteration, 16 per wave
+// The step kernel stages the whole core in LDS (64 KB in fp32 at the
+// largest fused sizes), so its workgroups are 8 waves: two of them per CU
+// still give 4 waves per SIMD.
+constexpr int kStepThreads = 512;
+constexpr int kStepRows = 16 * (kStepThreads / 64);
 constexpr int kMaxTiles = TTM_MAX_FUSED / 16;
 
 struct Step {
@@ -83,7 +87,7 @@ struct Step {
 // multiple of 4, so the 4 K values of a lane are contiguous and load as
 // one vector.
 template <int BF16, int VEC>
-__global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32) {
+__global__ void __launch_bounds__(kStepThreads) ttm_step_kernel(Step s, int out_f32) {
   extern __shared__ __align__(16) char smem[];
   const int K = s.nin * s.rin, N = s.mout * s.rout;
   const int KC = (K + 15) / 16, NT = (N + 15) / 16;
@@ -92,9 +96,9 @@ __global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32)
   long long *koff = (long long *)smem;  // [KC * 16], -1 past K
   char *bsm = smem + 16 * ((KC * 16 * 8 + 15) / 16);
   const long long jstride = s.Q * s.rin;
-  for (int kk = tid; kk < KC * 16; kk += kThreads) koff[kk] = kk < K ? (kk / s.rin) * jstride + kk % s.rin : -1;
+  for (int kk = tid; kk < KC * 16; kk += kStepThreads) koff[kk] = kk < K ? (kk / s.rin) * jstride + kk % s.rin : -1;
   // chunk x (16 K values), tile t: lane (q4, c16) holds B[16x + 4q4 + v][16t + c16]
-  for (int e = tid; e < KC * NT * 256; e += kThreads) {
+  for (int e = tid; e < KC * NT * 256; e += kStepThreads) {
     const int v = e & 3, ln = (e >> 2) & 63, xt = e >> 8;
     const int x = xt / NT, t = xt % NT;
     const int kk = 16 * x + 4 * (ln >> 4) + v, nn = 16 * t + (ln & 15);
@@ -113,7 +117,7 @@ __global__ void __launch_bounds__(kThreads) ttm_step_kernel(Step s, int out_f32)
   }
   __syncthreads();
   const long long rows = s.P * s.Q;
-  for (long long r0 = (long long)blockIdx.x * kRows; r0 < rows; r0 += (long long)gridDim.x * kRows) {
+  for (long long r0 = (long long)blockIdx.x * kStepRows; r0 < rows; r0 += (long long)gridDim.x * kStepRows) {
     const long long row = r0 + wave * 16 + c16;  // A-operand row of this lane
     const bool rvalid = row < rows;
     const long long p = rvalid ? row / s.Q : 0, q = rvalid ? row % s.Q : 0;
@@ -435,13 +439,13 @@ int launch_step(const Step &s, int bf16, int out_f32, hipStream_t st) {
   const long long rows = s.P * s.Q;
   // enough workgroups to fill the chip a few times over; each one stages the
   // core once and then walks many row blocks
-  long long nb = (rows + kRows - 1) / kRows;
+  long long nb = (rows + kStepRows - 1) / kStepRows;
   nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
   // vector loads need the 4 K values of a lane contiguous: a bond of IN
   // that is a multiple of 4 and an IN pointer aligned to 4 elements
   const size_t esize = bf16 ? 2 : 4;
   const bool vec = (s.rin % 4 == 0) && ((uintptr_t)s.in % (4 * esize) == 0);
-  const dim3 g((unsigned)nb), blk(kThreads);
+  const dim3 g((unsigned)nb), blk(kStepThreads);
   if (bf16 && vec) hipLaunchKernelGGL((ttm_step_kernel<1, 1>), g, blk, shm, st, s, out_f32);
   else if (bf16) hipLaunchKernelGGL((ttm_step_kernel<1, 0>), g, blk, shm, st, s, out_f32);
   else if (vec) hipLaunchKernelGGL((ttm_step_kernel<0, 1>), g, blk, shm, st, s, out_f32);
