@@ -9,7 +9,7 @@
 //     chosen so that diag(R) >= 0, thin Q by backward accumulation;
 //   * SVD of the small R factor by one-sided (Hestenes) Jacobi rotations in
 //     round-robin order, one wave per column pair;
-//   * small GEMMs, one output element per thread.
+//   * small GEMMs (one factor at most 64 x 64) on the fp32 matrix cores.
 // Matrices live in a global workspace (they stay in L2); the Jacobi state
 // lives in LDS.  All arithmetic is float32.
 #include "common.h"
@@ -75,18 +75,6 @@ __device__ float block_sum(float v, Shared &sh) {
   float s = 0.f;
   for (int w = 0; w < kWaves; ++w) s += sh.red[w];
   return s;
-}
-
-// C (M x N) = A (M x K) * B (K x N); element (i, j) of X at X[i*xr + j*xc].
-__device__ void blk_gemm(int M, int N, int K, const float *A, long ar, long ac, const float *B,
-                         long br, long bc, float *C, long cr, long cc) {
-  for (long e = threadIdx.x; e < (long)M * N; e += kThreads) {
-    const int i = (int)(e / N), j = (int)(e % N);
-    float s = 0.f;
-#pragma unroll 8
-    for (int k = 0; k < K; ++k) s = fmaf(A[i * ar + k * ac], B[k * br + j * bc], s);
-    C[i * cr + j * cc] = s;
-  }
 }
 
 // In-place Householder QR of the column-major m x c matrix W (ld = m).
@@ -752,6 +740,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
 __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTDev Z, TTDev W,
                                                            float alpha, float addx, float *scratch,
                                                            long scratch_stride) {
+  __shared__ Shared sh;
   const int k = blockIdx.x, d = U.d;
   const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
   const int m = r0 * nk;
@@ -760,17 +749,35 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
   float *dG = scratch + (long)k * scratch_stride;   // m x r1 (row-major)
   float *C = dG + (long)m * r1;                     // r1 x r1
   if (k < d - 1) {
-    // C = U^T Z  (r1 x r1), K = m
-    blk_gemm(r1, r1, m, Uk, 1, r1, Zk, r1, 1, C, r1, 1);
-    __syncthreads();
-    // dG = Z - U C
-    for (long e = threadIdx.x; e < (long)m * r1; e += kThreads) {
-      const int i = (int)(e / r1), j = (int)(e % r1);
-      float s = 0.f;
-#pragma unroll 8
-      for (int l = 0; l < r1; ++l) s = fmaf(Uk[(long)i * r1 + l], C[l * r1 + j], s);
-      dG[e] = Zk[e] - s;
+    // C = U^T Z (r1 x r1), K = m, on the matrix cores: wave w takes the
+    // 16 x 16 output tiles w, w + 8, ...; operand lane (q4, c16) reads
+    // U[k0 + q4][16 ti + c16] and Z[k0 + q4][16 tj + c16] (rows of r1
+    // floats, 16 consecutive per quarter-wave)
+    {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const int c16 = lane & 15, q4 = lane >> 4;
+      const int nt = (r1 + 15) / 16;
+      for (int tile = wave; tile < nt * nt; tile += kWaves) {
+        const int ti = tile / nt, tj = tile % nt;
+        const int ci = 16 * ti + c16, cj = 16 * tj + c16;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < m; k0 += 4) {
+          const int kr = k0 + q4;
+          const float av = (kr < m && ci < r1) ? Uk[(long)kr * r1 + ci] : 0.f;
+          const float bv = (kr < m && cj < r1) ? Zk[(long)kr * r1 + cj] : 0.f;
+          acc = mfma4(av, bv, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * ti + 4 * q4 + v;
+          if (row < r1 && cj < r1) C[row * r1 + cj] = acc[v];
+        }
+      }
     }
+    __syncthreads();
+    // dG = Z - U C: U C on the matrix cores, then the difference
+    gemm_lds_b(m, r1, r1, Uk, r1, 1, [&](int l, int j) { return C[l * r1 + j]; }, dG, r1, sh);
+    for (long e = threadIdx.x; e < (long)m * r1; e += kThreads) dG[e] = Zk[e] - dG[e];
   } else {
     for (long e = threadIdx.x; e < (long)m * r1; e += kThreads) dG[e] = Zk[e];
   }
