@@ -186,3 +186,32 @@ def test_halves_host_logic(lib):
                                 C.c_void_p(0x10), None) == L.TT_ERR_ARG
     # M = 0 is a no-op success
     assert lib.tt_halves_gather(C.byref(X), 5, C.c_void_p(0x1000), nb, None, 0, None, None) == 0
+
+
+def test_tangent_algebra_and_orthogonalize_both_validation(lib):
+    """Shape and argument checks of tt_tangent_inner, tt_tangent_axpby and
+    tt_orthogonalize_both, all on the host before any device work."""
+    from paper_1801_01928_amd import _lib as L
+    U = _desc([3, 4, 5], [1, 2, 2, 1])
+    P = _desc([3, 4, 5], [1, 4, 4, 1])
+    bad = _desc([3, 4, 5], [1, 4, 3, 1])
+    other = _desc([3, 4, 6], [1, 4, 4, 1])
+    out = C.c_void_p(0x10)
+    assert lib.tt_tangent_inner(C.byref(U), C.byref(P), C.byref(bad), out, None) == L.TT_ERR_SHAPE
+    assert lib.tt_tangent_inner(C.byref(U), C.byref(other), C.byref(P), out, None) == L.TT_ERR_SHAPE
+    assert lib.tt_tangent_inner(C.byref(U), C.byref(P), C.byref(P), None, None) == L.TT_ERR_ARG
+    one = _desc([3], [1, 1])
+    assert lib.tt_tangent_inner(C.byref(one), C.byref(one), C.byref(one), out, None) == L.TT_ERR_ARG
+    assert lib.tt_tangent_axpby(C.byref(U), 1.0, C.byref(P), 2.0, C.byref(P), C.byref(bad), None) == L.TT_ERR_SHAPE
+    assert lib.tt_tangent_axpby(C.byref(U), 1.0, C.byref(bad), 2.0, C.byref(P), C.byref(P), None) == L.TT_ERR_SHAPE
+    # orthogonalize_both: output ranks must be the reduced ones of each direction
+    X = _desc([3, 4, 5], [1, 3, 5, 1])       # LR ranks (1, 3, 5, 1); RL ranks (1, 3, 5, 1)
+    Xs = _desc([3, 4, 5], [1, 3, 4, 1])
+    assert lib.tt_orthogonalize_both_workspace(C.byref(X)) > 0
+    assert lib.tt_orthogonalize_both(C.byref(X), C.byref(Xs), C.byref(X), C.c_void_p(0x1000), 1 << 30,
+                                     None) == L.TT_ERR_SHAPE
+    assert lib.tt_orthogonalize_both(C.byref(X), C.byref(X), C.byref(Xs), C.c_void_p(0x1000), 1 << 30,
+                                     None) == L.TT_ERR_SHAPE
+    assert lib.tt_orthogonalize_both(C.byref(X), C.byref(X), C.byref(X), None, 0, None) == L.TT_ERR_WORKSPACE
+    assert lib.tt_orthogonalize_both(C.byref(X), C.byref(X), C.byref(other), C.c_void_p(0x1000), 1 << 30,
+                                     None) == L.TT_ERR_SHAPE
