@@ -418,3 +418,16 @@ def riemannian_cg(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
         hist.append(dict(loss=prev["loss"], step=prev["step"], beta=prev["beta"], test_rmse=rmse))
         X = prev["Y"]
     return X, hist
+
+
+def project_sum(X, As, c, alpha=1.0, beta=0.0):
+    """``project_sum`` (Riemannian Geometry Operations): the tangent vector
+    beta*X + alpha * sum_i c_i P_X(A_i), for a batch of TT tensors A_i.  The
+    projection is linear, so this is P_X of the weighted TT sum
+    sum_i c_i A_i (formed by TT addition, ranks adding up).  Returns
+    (W, U, V, dG) as ``project_tt``."""
+    from .core import add, scale
+    Y = scale([np.asarray(g, dtype=np.float64) for g in As[0]], float(c[0]))
+    for A, ci in zip(As[1:], c[1:]):
+        Y = add(Y, scale([np.asarray(g, dtype=np.float64) for g in A], float(ci)))
+    return project_tt(X, Y, alpha, beta)

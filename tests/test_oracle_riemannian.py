@@ -475,3 +475,21 @@ def test_cg_recovers_planted_tensor_faster_than_gd():
     rc, rg = float(np.sqrt(np.mean(ec * ec))), float(np.sqrt(np.mean(eg * eg)))
     assert rc < 1e-8 and rc < rg / 100
     assert all(h["beta"] >= 0.0 for h in hc)
+
+
+def test_project_sum_linearity_and_dense_projector():
+    """project_sum of a batch equals the weighted sum of the single
+    projections, and the dense projector applied to the dense weighted sum,
+    with X added for beta = 1."""
+    from oracle import riemannian as R
+    ns = [3, 4, 3, 2]
+    X = _X(31, ns, 3)
+    As = [_X(40 + i, ns, 2) for i in range(3)]
+    c = [0.7, -1.3, 0.4]
+    W = R.project_sum(X, As, c, alpha=0.5, beta=1.0)[0]
+    single = [R.project_tt(X, A)[0] for A in As]
+    dense = oracle.full(X) + 0.5 * sum(ci * oracle.full(S) for ci, S in zip(c, single))
+    np.testing.assert_allclose(oracle.full(W), dense, atol=1e-12)
+    P = R.dense_projector(oracle.orthogonalize_lr(X), oracle.orthogonalize_rl(X))
+    z = sum(ci * oracle.full(A).reshape(-1) for ci, A in zip(c, As))
+    np.testing.assert_allclose(oracle.full(W).reshape(-1), oracle.full(X).reshape(-1) + 0.5 * (P @ z), atol=1e-12)
