@@ -259,7 +259,7 @@ def riemann_leg(tt, W, reps=3):
     workgroup per direction), the sparse tangent projection with assembly,
     and TT rounding back to rank 32; beside the step, the projection of the
     rank-64 tangent TT onto the tangent space at X (the transport of a
-    search direction)."""
+    search direction) and project_sum of 100 rank-10 TTs."""
     import torch
     p = W.riemann_d10()
     X = tt.TT.from_cores(p.cores)
@@ -275,11 +275,21 @@ def riemann_leg(tt, W, reps=3):
     tt.project_tt(U, V, Wt)
     torch.cuda.synchronize()
     transport_ms = _event_ms(lambda: tt.project_tt(U, V, Wt), reps)
+    # project_sum of a batch of 100 random rank-10 TTs at X
+    import numpy as np
+    rng = np.random.default_rng(9)
+    As = [tt.TT.from_cores(W.random_cores(rng, p.ns, W.uniform_ranks(len(p.ns), 10), 1 / np.sqrt(10)))
+          for _ in range(100)]
+    cw = rng.standard_normal(100)
+    tt.project_sum(U, V, As, cw)
+    torch.cuda.synchronize()
+    psum_ms = _event_ms(lambda: tt.project_sum(U, V, As, cw), reps)
     return {"workload": "d=10 n=10 r=32 (canonical), 2^20 entries", "orthogonalize_both_ms": round(orth_ms, 3),
             "project_sparse_ms": round(proj_ms, 3),
             "project_entries_per_s": round(p.M / (proj_ms * 1e-3), 1),
             "round_ms": round(round_ms, 3), "step_ms": round(orth_ms + proj_ms + round_ms, 3),
-            "project_tt_rank64_ms": round(transport_ms, 3)}
+            "project_tt_rank64_ms": round(transport_ms, 3),
+            "project_sum_100_rank10_ms": round(psum_ms, 3)}
 
 
 def completion_leg(tt, W, iters=4):

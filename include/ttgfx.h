@@ -231,6 +231,19 @@ int tt_project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y,
                   float alpha, int add_x, tt_tensor *W,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* project_sum of a batch (Riemannian Geometry Operations):
+ *   W = add_x X + alpha sum_i c[i] P_X(A_i),
+ * one projection per batch member computed together.  The core
+ * contractions are linear in A_i, so the weighted contractions are summed
+ * (in batch order) before one gauge fix and assembly.  A: b >= 1 TTs with
+ * X's mode sizes and one shape (equal ranks and core offsets; ranks up to
+ * 64), cores anywhere in device memory; c: (host) [b] weights; U, V, W as
+ * for tt_project_tt.  Launches process up to 64 members at a time. */
+int64_t tt_project_sum_workspace(const tt_tensor *U, const tt_batch *A);
+int tt_project_sum(const tt_tensor *U, const tt_tensor *V, const tt_batch *A,
+                   const float *c, float alpha, int add_x, tt_tensor *W,
+                   void *ws, size_t ws_bytes, void *stream);
+
 /* Re-weighting of a tangent TT (Riemannian Geometry Operations: the
  * tangent vector is linear in its gauge-fixed cores).  P: the tangent TT
  * tt_project_sparse returned with alpha = 1, add_x = 0 for the point whose

@@ -24,6 +24,7 @@ from .tt import (  # noqa: F401
     riemannian_step,
     line_search_terms,
     project_tt,
+    project_sum,
     tangent_combine,
     completion_iteration,
     cg_iteration,

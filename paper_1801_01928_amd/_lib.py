@@ -80,6 +80,8 @@ SIGNATURES = {
     "tt_orthogonalize": (C.c_int, [P_TT, C.c_int, P_TT, VP, SZ, VP]),
     "tt_project_sparse_workspace": (I64, [P_TT, I64]),
     "tt_project_sparse": (C.c_int, [P_TT, P_TT, VP, I64, VP, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
+    "tt_project_sum_workspace": (I64, [P_TT, P_BATCH]),
+    "tt_project_sum": (C.c_int, [P_TT, P_TT, P_BATCH, VP, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_tangent_inner": (C.c_int, [P_TT, P_TT, P_TT, VP, VP]),
     "tt_tangent_axpby": (C.c_int, [P_TT, C.c_float, P_TT, C.c_float, P_TT, P_TT, VP]),
     "tt_tangent_combine": (C.c_int, [P_TT, P_TT, C.c_float, C.c_int, P_TT, VP]),

@@ -153,6 +153,47 @@ int tt_project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, fl
   return project_tt(U, V, Y, alpha, add_x, W, ws, ws_bytes, (hipStream_t)stream);
 }
 
+static int validate_project_sum(const tt_tensor *U, const tt_tensor *V, const tt_batch *A, const float *c) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if (V && (rc = validate_tt(V, "V", TT_MAX_RANK))) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "project_sum needs d >= 2");
+  if (V && !same_shape(U, V))
+    return set_error(TT_ERR_SHAPE, "U and V must have the same modes and ranks (X at feasible ranks)");
+  if (!A || A->b < 1 || !A->tt) return set_error(TT_ERR_ARG, "project_sum: empty batch");
+  for (int i = 0; i < A->b; ++i) {
+    if ((rc = validate_tt(&A->tt[i], "A[i]", DENSE_MAX_RANK))) return rc;
+    if (!same_modes(U, &A->tt[i])) return set_error(TT_ERR_SHAPE, "A[%d] must have X's mode sizes", i);
+    if (!same_shape(&A->tt[0], &A->tt[i]))
+      return set_error(TT_ERR_SHAPE, "A[%d] must have the ranks of A[0] (one shape per batch)", i);
+    for (int k = 0; k < A->tt[i].d; ++k)
+      if (core_off(&A->tt[i], k) != core_off(&A->tt[0], k))
+        return set_error(TT_ERR_SHAPE, "A[%d] must have the core offsets of A[0]", i);
+  }
+  if (!c) return set_error(TT_ERR_ARG, "project_sum: null weights");
+  return TT_OK;
+}
+
+int64_t tt_project_sum_workspace(const tt_tensor *U, const tt_batch *A) {
+  int rc = validate_project_sum(U, nullptr, A, (const float *)1);
+  if (rc) return rc;
+  return (int64_t)project_sum_ws(U, &A->tt[0], A->b);
+}
+
+int tt_project_sum(const tt_tensor *U, const tt_tensor *V, const tt_batch *A, const float *c, float alpha,
+                   int add_x, tt_tensor *W, void *ws, size_t ws_bytes, void *stream) {
+  int rc = validate_project_sum(U, V, A, c);
+  if (rc) return rc;
+  if ((rc = validate_tt(W, "W", 2 * TT_MAX_RANK))) return rc;
+  if (!same_modes(U, W)) return set_error(TT_ERR_SHAPE, "W must have U's mode sizes");
+  for (int k = 1; k < U->d; ++k)
+    if (W->r[k] != 2 * U->r[k])
+      return set_error(TT_ERR_SHAPE, "W rank r[%d] = %d, expected %d", k, W->r[k], 2 * U->r[k]);
+  if (add_x != 0 && add_x != 1) return set_error(TT_ERR_ARG, "add_x must be 0 or 1");
+  if ((rc = check_ws(ws, ws_bytes, project_sum_ws(U, &A->tt[0], A->b), "project_sum"))) return rc;
+  return project_sum(U, V, A->tt, A->b, c, alpha, add_x, W, ws, ws_bytes, (hipStream_t)stream);
+}
+
 int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha, int add_x, tt_tensor *W,
                        void *stream) {
   int rc = validate_tt(U, "U", TT_MAX_RANK);

@@ -24,6 +24,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kJac = DENSE_MAX_RANK;  // Jacobi matrices are at most 64 x 64
+constexpr int kProjBatch = 64;        // tensors per launch of a batched projection
 
 struct Shared {
   float red[kWaves];
@@ -830,6 +831,19 @@ __global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDe
   }
 }
 
+// z[e] = (acc ? z[e] : 0) + sum_{i < nb} c[i] zp[i * stride + e], in order.
+struct ZWeights {
+  float c[kProjBatch];
+};
+__global__ void __launch_bounds__(256) zsum_kernel(const float *__restrict__ zp, long long stride, int nb, ZWeights w,
+                                                   long long cnt, int acc, float *__restrict__ z) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= cnt) return;
+  float v = acc ? z[e] : 0.f;
+  for (int i = 0; i < nb; ++i) v = fmaf(w.c[i], zp[(long long)i * stride + e], v);
+  z[e] = v;
+}
+
 // Offset, in core k of a tangent TT in the assembly's block layout, of the
 // dG block's element (a, s, b) (a < r_k, s < n_k, b < r_{k+1} of X): the
 // block sits at columns 0..r_{k+1} of the first core, at rows r_k.. of the
@@ -917,8 +931,29 @@ struct ProjStep {
 
 constexpr int kPs = kJac + 1;  // LDS row stride of the step's 64 x 64 tiles
 
-__global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b, ProjStep st) {
+// A batch of TTs of one shape projected at once (project_sum): tensor
+// blockIdx.y has its cores at ydata[blockIdx.y] (offsets of the shared
+// shape) and its own interface, partial, scratch and Zhat blocks, `stride`
+// floats apart for each kind.  A single projection is the batch of one.
+struct ProjBatch {
+  const float *ydata[kProjBatch];
+  long long psi_stride, part_stride, tmp_stride, z_stride;
+};
+
+__global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b, ProjStep st,
+                                                             ProjBatch pb) {
   __shared__ float ta[kJac * kPs], tb[kJac * kPs], tc[kJac * kPs];
+  {
+    // this tensor's blocks
+    const int bi = blockIdx.y;
+    Y.data = (float *)pb.ydata[bi];
+    b.psi += bi * pb.psi_stride;
+    b.phi += bi * pb.psi_stride;
+    if (st.lin) st.lin += bi * pb.part_stride;
+    if (st.rin) st.rin += bi * pb.part_stride;
+    st.lout += bi * pb.part_stride;
+    st.rout += bi * pb.part_stride;
+  }
   const int d = U.d;
   const bool left = (int)blockIdx.x < st.lw;
   const int i = left ? (int)blockIdx.x : (int)blockIdx.x - st.lw;
@@ -992,9 +1027,17 @@ __global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, T
   }
 }
 
-__global__ void __launch_bounds__(kThreads) proj_cores_kernel(TTDev U, TTDev Y, TTDev Z, ProjBufs b) {
+__global__ void __launch_bounds__(kThreads) proj_cores_kernel(TTDev U, TTDev Y, TTDev Z, ProjBufs b, ProjBatch pb) {
   __shared__ Shared sh;
   const int k = blockIdx.x;
+  {
+    const int bi = blockIdx.y;
+    Y.data = (float *)pb.ydata[bi];
+    b.psi += bi * pb.psi_stride;
+    b.phi += bi * pb.psi_stride;
+    b.tmp += bi * pb.tmp_stride;
+    Z.data += bi * pb.z_stride;
+  }
   const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
   const long ns1 = (long)n * s1;
   float *T = b.tmp + (2 + k) * b.tslot;
@@ -1156,44 +1199,62 @@ static void proj_slots(const tt_tensor *U, const tt_tensor *Y, long *pslot, long
   *tslot = ts;
 }
 
-size_t project_tt_ws(const tt_tensor *U, const tt_tensor *Y) {
-  long ps, ts;
-  proj_slots(U, Y, &ps, &ts);
+// Workspace of `nb` projections of TTs of Y's shape run together: per tensor
+// the interfaces, the step partials (two ping-pong pairs), the core-step
+// scratch and its Zhat.
+struct ProjWs {
+  ProjBufs b;
+  float *lpart[2], *rpart[2], *zpart;
+  ProjBatch pb;
+};
+
+static long proj_zel(const tt_tensor *U) {
   long zel = 0;
   for (int k = 0; k < U->d; ++k) zel += (long)U->r[k] * U->n[k] * U->r[k + 1];
+  return zel;
+}
+
+static int proj_nmax(const tt_tensor *U) {
   int nmax = 1;
   for (int k = 0; k < U->d; ++k) nmax = U->n[k] > nmax ? U->n[k] : nmax;
-  size_t b = 2 * arena_bytes<float>((size_t)(U->d + 1) * ps);
-  b += 4 * arena_bytes<float>((size_t)nmax * ps);
-  b += arena_bytes<float>((size_t)(U->d + 2) * ts);
-  b += arena_bytes<float>((size_t)zel);
-  b += tangent_ws(U) + 256;
+  return nmax;
+}
+
+static size_t proj_batch_bytes(const tt_tensor *U, const tt_tensor *Y, int nb) {
+  long ps, ts;
+  proj_slots(U, Y, &ps, &ts);
+  size_t b = 2 * arena_bytes<float>((size_t)nb * (U->d + 1) * ps);
+  b += 4 * arena_bytes<float>((size_t)nb * proj_nmax(U) * ps);
+  b += arena_bytes<float>((size_t)nb * (U->d + 2) * ts);
+  b += arena_bytes<float>((size_t)nb * proj_zel(U));
   return b;
 }
 
-int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float alpha, int add_x, tt_tensor *W,
-               void *ws, size_t bytes, hipStream_t s) {
+static void proj_batch_take(Arena &ar, const tt_tensor *U, const tt_tensor *Y, int nb, ProjWs &w) {
   long ps, ts;
   proj_slots(U, Y, &ps, &ts);
-  Arena ar(ws, bytes);
-  ProjBufs b;
-  int nmax = 1;
-  for (int k = 0; k < U->d; ++k) nmax = U->n[k] > nmax ? U->n[k] : nmax;
-  b.psi = ar.take<float>((size_t)(U->d + 1) * ps);
-  b.phi = ar.take<float>((size_t)(U->d + 1) * ps);
-  float *lpart[2] = {ar.take<float>((size_t)nmax * ps), ar.take<float>((size_t)nmax * ps)};
-  float *rpart[2] = {ar.take<float>((size_t)nmax * ps), ar.take<float>((size_t)nmax * ps)};
-  b.tmp = ar.take<float>((size_t)(U->d + 2) * ts);
-  b.pslot = ps;
-  b.tslot = ts;
-  long zel = 0;
-  for (int k = 0; k < U->d; ++k) zel += (long)U->r[k] * U->n[k] * U->r[k + 1];
-  float *zbuf = ar.take<float>((size_t)zel);
-  const size_t tws = tangent_ws(U);
-  void *tw = ar.take<char>(tws);
-  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "project_tt: workspace too small");
-  // interface sweeps: launch t runs left step k = t and right step k = d-1-t
+  const long nmax = proj_nmax(U), zel = proj_zel(U);
+  w.b.psi = ar.take<float>((size_t)nb * (U->d + 1) * ps);
+  w.b.phi = ar.take<float>((size_t)nb * (U->d + 1) * ps);
+  for (int i = 0; i < 2; ++i) w.lpart[i] = ar.take<float>((size_t)nb * nmax * ps);
+  for (int i = 0; i < 2; ++i) w.rpart[i] = ar.take<float>((size_t)nb * nmax * ps);
+  w.b.tmp = ar.take<float>((size_t)nb * (U->d + 2) * ts);
+  w.b.pslot = ps;
+  w.b.tslot = ts;
+  w.zpart = ar.take<float>((size_t)nb * zel);
+  w.pb.psi_stride = (long long)(U->d + 1) * ps;
+  w.pb.part_stride = (long long)nmax * ps;
+  w.pb.tmp_stride = (long long)(U->d + 2) * ts;
+  w.pb.z_stride = zel;
+}
+
+// Zhat of each of the nb tensors (cores at ydata[i], Y's shape) into
+// w.zpart + i * zel: d interface launches (left step t and right step
+// d-1-t, a workgroup per slice and tensor), then the core step.
+static int proj_batch_run(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, const float *const *ydata,
+                          int nb, ProjWs &w, hipStream_t s) {
   const int d = U->d;
+  for (int i = 0; i < nb; ++i) w.pb.ydata[i] = ydata[i];
   const TTDev Ud = make_dev(U), Vd = make_dev(V), Yd = make_dev(Y);
   int rc = TT_OK;
   for (int t = 0; t < d; ++t) {
@@ -1202,19 +1263,70 @@ int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float
     st.rk = d - 1 - t;
     st.lw = (st.lk + 1 < d) ? U->n[st.lk] : 1;
     const int rw = (st.rk >= 1) ? U->n[st.rk] : 1;
-    st.lin = t == 0 ? nullptr : lpart[(t - 1) & 1];
+    st.lin = t == 0 ? nullptr : w.lpart[(t - 1) & 1];
     st.lnin = t == 0 ? 0 : U->n[st.lk - 1];
-    st.rin = t == 0 ? nullptr : rpart[(t - 1) & 1];
+    st.rin = t == 0 ? nullptr : w.rpart[(t - 1) & 1];
     st.rnin = t == 0 ? 0 : U->n[st.rk + 1];
-    st.lout = lpart[t & 1];
-    st.rout = rpart[t & 1];
-    hipLaunchKernelGGL(proj_step_kernel, dim3(st.lw + rw), dim3(kThreads), 0, s, Ud, Vd, Yd, b, st);
+    st.lout = w.lpart[t & 1];
+    st.rout = w.rpart[t & 1];
+    hipLaunchKernelGGL(proj_step_kernel, dim3(st.lw + rw, nb), dim3(kThreads), 0, s, Ud, Vd, Yd, w.b, st, w.pb);
     if ((rc = launch_check("TT projection interface step"))) return rc;
   }
-  tt_tensor Z = {U->d, U->n, U->r, nullptr, zbuf};
-  hipLaunchKernelGGL(proj_cores_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(Y), make_dev(&Z),
-                     b);
-  if ((rc = launch_check("TT projection cores"))) return rc;
+  tt_tensor Z = {U->d, U->n, U->r, nullptr, w.zpart};
+  hipLaunchKernelGGL(proj_cores_kernel, dim3(U->d, nb), dim3(kThreads), 0, s, Ud, Yd, make_dev(&Z), w.b, w.pb);
+  return launch_check("TT projection cores");
+}
+
+size_t project_tt_ws(const tt_tensor *U, const tt_tensor *Y) {
+  return proj_batch_bytes(U, Y, 1) + tangent_ws(U) + 256;
+}
+
+int project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y, float alpha, int add_x, tt_tensor *W,
+               void *ws, size_t bytes, hipStream_t s) {
+  Arena ar(ws, bytes);
+  ProjWs w;
+  proj_batch_take(ar, U, Y, 1, w);
+  const size_t tws = tangent_ws(U);
+  void *tw = ar.take<char>(tws);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "project_tt: workspace too small");
+  const float *yd = Y->data;
+  int rc = proj_batch_run(U, V, Y, &yd, 1, w, s);
+  if (rc) return rc;
+  tt_tensor Z = {U->d, U->n, U->r, nullptr, w.zpart};
+  return tangent_assemble(U, V, &Z, W, alpha, add_x, tw, tws, s);
+}
+
+size_t project_sum_ws(const tt_tensor *U, const tt_tensor *A0, int nb) {
+  const int chunk = nb < kProjBatch ? nb : kProjBatch;
+  return proj_batch_bytes(U, A0, chunk) + arena_bytes<float>((size_t)proj_zel(U)) + tangent_ws(U) + 256;
+}
+
+int project_sum(const tt_tensor *U, const tt_tensor *V, const tt_tensor *A, int nb, const float *c, float alpha,
+                int add_x, tt_tensor *W, void *ws, size_t bytes, hipStream_t s) {
+  const int chunk = nb < kProjBatch ? nb : kProjBatch;
+  Arena ar(ws, bytes);
+  ProjWs w;
+  proj_batch_take(ar, U, &A[0], chunk, w);
+  const long zel = proj_zel(U);
+  float *zsum = ar.take<float>((size_t)zel);
+  const size_t tws = tangent_ws(U);
+  void *tw = ar.take<char>(tws);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "project_sum: workspace too small");
+  int rc = TT_OK;
+  for (int i0 = 0; i0 < nb; i0 += chunk) {
+    const int m = (nb - i0) < chunk ? (nb - i0) : chunk;
+    const float *yd[kProjBatch];
+    ZWeights zw;
+    for (int i = 0; i < m; ++i) {
+      yd[i] = A[i0 + i].data;
+      zw.c[i] = c[i0 + i];
+    }
+    if ((rc = proj_batch_run(U, V, &A[0], yd, m, w, s))) return rc;
+    hipLaunchKernelGGL(zsum_kernel, dim3((unsigned)((zel + 255) / 256)), dim3(256), 0, s, w.zpart,
+                       (long long)zel, m, zw, (long long)zel, i0 > 0 ? 1 : 0, zsum);
+    if ((rc = launch_check("project_sum weighted sum"))) return rc;
+  }
+  tt_tensor Z = {U->d, U->n, U->r, nullptr, zsum};
   return tangent_assemble(U, V, &Z, W, alpha, add_x, tw, tws, s);
 }
 

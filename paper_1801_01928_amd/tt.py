@@ -359,6 +359,20 @@ def tangent_combine(U, P, alpha, add_x, out=None):
     return W
 
 
+def project_sum(U, V, As, c, alpha=1.0, add_x=0):
+    """project_sum (tt_project_sum): the rank-2r TT  add_x * X +
+    alpha * sum_i c[i] P_X(As[i])  for TTs As of one shape, with U, V the
+    two sweeps of X."""
+    lib = L.load()
+    c = (C.c_float * len(As))(*[float(x) for x in c])
+    A, keep = _batch(As)
+    W = TT(U.ns, [1] + [2 * r for r in U.ranks[1:-1]] + [1], device=U.device)
+    ws, nb = _workspace(L.check(lib.tt_project_sum_workspace(C.byref(U.desc()), C.byref(A))), U.device)
+    L.check(lib.tt_project_sum(C.byref(U.desc()), C.byref(V.desc()), C.byref(A), c, C.c_float(alpha), int(add_x),
+                               C.byref(W.desc()), _ptr(ws), nb, _stream(U.device)))
+    return W
+
+
 def tangent_inner(U, A, B):
     """<A, B> of two tangent TTs at the point with left sweep U, as a device
     tensor of one float (tt_tangent_inner)."""

@@ -215,3 +215,30 @@ def test_tangent_algebra_and_orthogonalize_both_validation(lib):
     assert lib.tt_orthogonalize_both(C.byref(X), C.byref(X), C.byref(X), None, 0, None) == L.TT_ERR_WORKSPACE
     assert lib.tt_orthogonalize_both(C.byref(X), C.byref(X), C.byref(other), C.c_void_p(0x1000), 1 << 30,
                                      None) == L.TT_ERR_SHAPE
+
+
+def test_project_sum_validation_before_device(lib):
+    """tt_project_sum rejects empty batches, mixed shapes, wrong output
+    ranks and a missing weight array before any device work."""
+    from paper_1801_01928_amd import _lib as L
+    U = _desc([3, 4, 5], [1, 2, 2, 1])
+    W = _desc([3, 4, 5], [1, 4, 4, 1])
+    a1 = _desc([3, 4, 5], [1, 3, 3, 1])
+    a2 = _desc([3, 4, 5], [1, 3, 2, 1])
+    arr = (L.tt_tensor * 2)(a1, a2)
+    mixed = L.tt_batch(2, arr)
+    same = L.tt_batch(1, arr)
+    empty = L.tt_batch(0, arr)
+    c = (C.c_float * 2)(1.0, 2.0)
+    ws = C.c_void_p(0x1000)
+    assert lib.tt_project_sum(C.byref(U), C.byref(U), C.byref(empty), c, 1.0, 0, C.byref(W), ws, 1 << 30,
+                              None) == L.TT_ERR_ARG
+    assert lib.tt_project_sum(C.byref(U), C.byref(U), C.byref(mixed), c, 1.0, 0, C.byref(W), ws, 1 << 30,
+                              None) == L.TT_ERR_SHAPE
+    assert lib.tt_project_sum(C.byref(U), C.byref(U), C.byref(same), None, 1.0, 0, C.byref(W), ws, 1 << 30,
+                              None) == L.TT_ERR_ARG
+    assert lib.tt_project_sum(C.byref(U), C.byref(U), C.byref(same), c, 1.0, 0, C.byref(a1), ws, 1 << 30,
+                              None) == L.TT_ERR_SHAPE
+    assert lib.tt_project_sum(C.byref(U), C.byref(U), C.byref(same), c, 1.0, 0, C.byref(W), None, 0,
+                              None) == L.TT_ERR_WORKSPACE
+    assert lib.tt_project_sum_workspace(C.byref(U), C.byref(same)) > 0

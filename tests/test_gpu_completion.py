@@ -254,3 +254,46 @@ def test_cg_recovers_planted_tensor(gpu_lib):
     assert h[0]["test_rmse"] > 0.1
     assert float(np.sqrt(np.mean(e * e))) < 1e-4
     assert any(x["beta"] > 0.0 for x in h)
+
+
+SUM_CASES = [
+    # (seed, ns, X rank, batch rank, batch size): one launch chunk, and 70
+    # members across two chunks of 64
+    (80, [3, 4, 3, 2], 3, 2, 3),
+    (81, [8] * 5, 6, 4, 9),
+    (82, [10] * 8, 12, 4, 70),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SUM_CASES)))
+def test_project_sum_matches_oracle(gpu_lib, case):
+    """project_sum of a batch (tt_project_sum) against the FP64 oracle, as
+    tensors through exact inner products, with and without X added."""
+    tt = gpu_lib
+    seed, ns, r, ra, b = SUM_CASES[case]
+    print("project_sum", ns, r, ra, b, flush=True)
+    rng = np.random.default_rng(seed)
+    Xc = W.random_cores(rng, ns, W.canonical_ranks(ns, r), 1 / np.sqrt(r))
+    As = [W.random_cores(rng, ns, W.uniform_ranks(len(ns), ra), 1 / np.sqrt(ra)) for _ in range(b)]
+    c = rng.standard_normal(b)
+    X = tt.TT.from_cores(Xc)
+    U, V = tt.orthogonalize_both(X)
+    At = [tt.TT.from_cores(a) for a in As]
+    for alpha, add_x in ((1.0, 0), (-0.3, 1)):
+        got = tt.project_sum(U, V, At, c, alpha=alpha, add_x=add_x).numpy_cores()
+        want = R.project_sum(Xc, As, c.astype(np.float32), alpha=alpha, beta=float(add_x))[0]
+        assert _tt_rel(got, want) <= 1e-4
+
+
+def test_project_sum_of_one_is_project_tt(gpu_lib):
+    """A batch of one with weight 1 gives exactly the single projection."""
+    import torch
+    tt = gpu_lib
+    rng = np.random.default_rng(83)
+    ns = [8] * 5
+    X = tt.TT.from_cores(W.random_cores(rng, ns, W.canonical_ranks(ns, 6), 0.4))
+    Y = tt.TT.from_cores(W.random_cores(rng, ns, [1, 7, 12, 12, 5, 1], 0.3))
+    U, V = tt.orthogonalize_both(X)
+    a = tt.project_sum(U, V, [Y], [1.0], alpha=-0.7, add_x=1)
+    b = tt.project_tt(U, V, Y, alpha=-0.7, add_x=1)
+    assert torch.equal(a.data, b.data)
