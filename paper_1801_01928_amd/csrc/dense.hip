@@ -943,24 +943,21 @@ struct ProjBatch {
 __global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, TTDev Y, ProjBufs b, ProjStep st,
                                                              ProjBatch pb) {
   __shared__ float ta[kJac * kPs], tb[kJac * kPs], tc[kJac * kPs];
-  {
-    // this tensor's blocks
-    const int bi = blockIdx.y;
-    Y.data = (float *)pb.ydata[bi];
-    b.psi += bi * pb.psi_stride;
-    b.phi += bi * pb.psi_stride;
-    if (st.lin) st.lin += bi * pb.part_stride;
-    if (st.rin) st.rin += bi * pb.part_stride;
-    st.lout += bi * pb.part_stride;
-    st.rout += bi * pb.part_stride;
-  }
+  // this tensor's blocks (locals: the by-value arguments stay unmodified,
+  // so they are read from the argument segment, not copied to scratch)
+  const int bi = blockIdx.y;
+  const float *ydat = pb.ydata[bi];
+  float *psi = b.psi + bi * pb.psi_stride, *phi = b.phi + bi * pb.psi_stride;
+  const float *lin = st.lin ? st.lin + bi * pb.part_stride : nullptr;
+  const float *rin = st.rin ? st.rin + bi * pb.part_stride : nullptr;
+  float *lout = st.lout + bi * pb.part_stride, *rout = st.rout + bi * pb.part_stride;
   const int d = U.d;
   const bool left = (int)blockIdx.x < st.lw;
   const int i = left ? (int)blockIdx.x : (int)blockIdx.x - st.lw;
   const int k = left ? st.lk : st.rk;
   // input interface: rows x cols, into ta
   const int ir = left ? U.r[k] : V.r[k + 1], ic = left ? Y.r[k] : Y.r[k + 1];
-  const float *in = left ? st.lin : st.rin;
+  const float *in = left ? lin : rin;
   const int nin = left ? st.lnin : st.rnin;
   for (int e = threadIdx.x; e < ir * ic; e += kThreads) {
     float v = 1.f;  // the 1 x 1 start of a chain
@@ -969,13 +966,13 @@ __global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, T
       for (int j = 0; j < nin; ++j) v += in[(long)j * b.pslot + e];
     }
     ta[(e / ic) * kPs + e % ic] = v;
-    if (i == 0) (left ? b.psi + (long)k * b.pslot : b.phi + (long)(k + 1) * b.pslot)[e] = v;
+    if (i == 0) (left ? psi + (long)k * b.pslot : phi + (long)(k + 1) * b.pslot)[e] = v;
   }
   const bool more = left ? (k + 1 < d) : (k >= 1);
   if (!more) return;
   const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
   // Y_k[i] (s0 x s1) into tb
-  const float *Yk = Y.data + Y.off[k];
+  const float *Yk = ydat + Y.off[k];
   for (int e = threadIdx.x; e < s0 * s1; e += kThreads) {
     const int bb = e / s1, ee = e % s1;
     tb[bb * kPs + ee] = Yk[((long)bb * n + i) * s1 + ee];
@@ -1008,7 +1005,7 @@ __global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, T
   __syncthreads();
   if (left) {
     // partial of Psi_{k+1} (r1 x s1) = U_k[i]^T tc
-    float *out = st.lout + (long)i * b.pslot;
+    float *out = lout + (long)i * b.pslot;
     for (int e = threadIdx.x; e < r1 * s1; e += kThreads) {
       const int c = e / s1, ee = e % s1;
       float acc = 0.f;
@@ -1017,7 +1014,7 @@ __global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, T
     }
   } else {
     // partial of Phi_k (r0 x s0) = V_k[i] tc
-    float *out = st.rout + (long)i * b.pslot;
+    float *out = rout + (long)i * b.pslot;
     for (int e = threadIdx.x; e < r0 * s0; e += kThreads) {
       const int a = e / s0, bb = e % s0;
       float acc = 0.f;
@@ -1030,25 +1027,21 @@ __global__ void __launch_bounds__(kThreads) proj_step_kernel(TTDev U, TTDev V, T
 __global__ void __launch_bounds__(kThreads) proj_cores_kernel(TTDev U, TTDev Y, TTDev Z, ProjBufs b, ProjBatch pb) {
   __shared__ Shared sh;
   const int k = blockIdx.x;
-  {
-    const int bi = blockIdx.y;
-    Y.data = (float *)pb.ydata[bi];
-    b.psi += bi * pb.psi_stride;
-    b.phi += bi * pb.psi_stride;
-    b.tmp += bi * pb.tmp_stride;
-    Z.data += bi * pb.z_stride;
-  }
+  const int bi = blockIdx.y;
+  const float *ydat = pb.ydata[bi];
+  const float *psi = b.psi + bi * pb.psi_stride, *phi = b.phi + bi * pb.psi_stride;
+  float *tmp = b.tmp + bi * pb.tmp_stride, *zdat = Z.data + bi * pb.z_stride;
   const int r0 = U.r[k], r1 = U.r[k + 1], n = U.n[k], s0 = Y.r[k], s1 = Y.r[k + 1];
   const long ns1 = (long)n * s1;
-  float *T = b.tmp + (2 + k) * b.tslot;
+  float *T = tmp + (2 + k) * b.tslot;
   // T (r0 x n s1) = Psi_k Y_k
-  const float *Pk = b.psi + k * b.pslot;
-  gemm_lds_a(r0, (int)ns1, s0, [&](int i, int l) { return Pk[i * s0 + l]; }, Y.data + Y.off[k], ns1, 1, T, ns1, 1,
+  const float *Pk = psi + k * b.pslot;
+  gemm_lds_a(r0, (int)ns1, s0, [&](int i, int l) { return Pk[i * s0 + l]; }, ydat + Y.off[k], ns1, 1, T, ns1, 1,
              sh);
   __syncthreads();
   // Zhat_k ((r0 n) x r1) = T ((r0 n) x s1) Phi_{k+1}^T (s1 x r1)
-  const float *Fk = b.phi + (k + 1) * b.pslot;
-  gemm_lds_b<true>(r0 * n, r1, s1, T, s1, 1, [&](int l, int j) { return Fk[j * s1 + l]; }, Z.data + Z.off[k], r1,
+  const float *Fk = phi + (k + 1) * b.pslot;
+  gemm_lds_b<true>(r0 * n, r1, s1, T, s1, 1, [&](int l, int j) { return Fk[j * s1 + l]; }, zdat + Z.off[k], r1,
                    sh);
 }
 
