@@ -635,13 +635,19 @@ __global__ void __launch_bounds__(kThreads) orth_both_kernel(TTDev X, TTDev OL, 
   __shared__ int n[TT_MAX_D], r[TT_MAX_D + 1];
   for (int k = threadIdx.x; k < X.d; k += kThreads) n[k] = X.n[k];
   for (int k = threadIdx.x; k <= X.d; k += kThreads) r[k] = X.r[k];
-  const bool lr = blockIdx.x == 0;
-  const DenseBufs &b = lr ? bl : br;
-  WorkTT w{b.work, b.slot};
-  copy_in(X, w);
-  if (lr) sweep_lr(w, X.d, n, r, b.wm, b.q, b.tau, sh);
-  else sweep_rl(w, X.d, n, r, b.wm, b.q, b.tau, sh);
-  copy_out(w, X.d, n, r, lr ? OL : OR);
+  // Branch on the workgroup rather than select between the by-value
+  // parameters: a selected reference would force them into private memory.
+  if (blockIdx.x == 0) {
+    WorkTT w{bl.work, bl.slot};
+    copy_in(X, w);
+    sweep_lr(w, X.d, n, r, bl.wm, bl.q, bl.tau, sh);
+    copy_out(w, X.d, n, r, OL);
+  } else {
+    WorkTT w{br.work, br.slot};
+    copy_in(X, w);
+    sweep_rl(w, X.d, n, r, br.wm, br.q, br.tau, sh);
+    copy_out(w, X.d, n, r, OR);
+  }
 }
 
 // TT rounding: right-to-left LQ sweep, then left-to-right truncated SVDs.
