@@ -262,6 +262,9 @@ SUM_CASES = [
     (80, [3, 4, 3, 2], 3, 2, 3),
     (81, [8] * 5, 6, 4, 9),
     (82, [10] * 8, 12, 4, 70),
+    (84, [5, 7], 3, 5, 65),               # d = 2; a last chunk of one member
+    (85, [5, 7, 3, 9, 4], 4, 64, 3),      # ragged modes; members of rank 64 at X rank 4
+    (86, [4] * 4, 3, 2, 64),              # exactly one full chunk
 ]
 
 
@@ -283,6 +286,22 @@ def test_project_sum_matches_oracle(gpu_lib, case):
         got = tt.project_sum(U, V, At, c, alpha=alpha, add_x=add_x).numpy_cores()
         want = R.project_sum(Xc, As, c.astype(np.float32), alpha=alpha, beta=float(add_x))[0]
         assert _tt_rel(got, want) <= 1e-4
+
+
+def test_project_sum_cancelling_weights(gpu_lib):
+    """Weights that cancel (A with 0.5 and -0.5, B with 0) leave only X:
+    the result is X itself as a tangent TT."""
+    tt = gpu_lib
+    rng = np.random.default_rng(87)
+    ns = [6, 5, 7, 4]
+    Xc = W.random_cores(rng, ns, W.canonical_ranks(ns, 5), 0.4)
+    A = W.random_cores(rng, ns, W.uniform_ranks(4, 7), 0.3)
+    B = W.random_cores(rng, ns, W.uniform_ranks(4, 7), 0.3)
+    X = tt.TT.from_cores(Xc)
+    U, V = tt.orthogonalize_both(X)
+    At = [tt.TT.from_cores(a) for a in (A, A, B)]
+    got = tt.project_sum(U, V, At, [0.5, -0.5, 0.0], alpha=2.0, add_x=1).numpy_cores()
+    assert _tt_rel(got, Xc) <= 1e-5
 
 
 def test_project_sum_of_one_is_project_tt(gpu_lib):
