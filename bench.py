@@ -259,7 +259,8 @@ def riemann_leg(tt, W, reps=3):
     workgroup per direction), the sparse tangent projection with assembly,
     and TT rounding back to rank 32; beside the step, the projection of the
     rank-64 tangent TT onto the tangent space at X (the transport of a
-    search direction) and project_sum of 100 rank-10 TTs."""
+    search direction), project_sum of 100 rank-10 TTs, and the Gram matrix
+    of their 100 projections at a rank-10 point."""
     import torch
     p = W.riemann_d10()
     X = tt.TT.from_cores(p.cores)
@@ -284,12 +285,21 @@ def riemann_leg(tt, W, reps=3):
     tt.project_sum(U, V, As, cw)
     torch.cuda.synchronize()
     psum_ms = _event_ms(lambda: tt.project_sum(U, V, As, cw), reps)
+    # Gram matrix of 100 tangent vectors at a rank-10 point (the projections
+    # of the same 100 TTs)
+    X10 = tt.TT.from_cores(W.random_cores(rng, p.ns, W.canonical_ranks(p.ns, 10), 1 / np.sqrt(10)))
+    U10, V10 = tt.orthogonalize_both(X10)
+    Ts = [tt.project_tt(U10, V10, A) for A in As]
+    tt.tangent_gram(U10, Ts)
+    torch.cuda.synchronize()
+    tgram_ms = _event_ms(lambda: tt.tangent_gram(U10, Ts), reps)
     return {"workload": "d=10 n=10 r=32 (canonical), 2^20 entries", "orthogonalize_both_ms": round(orth_ms, 3),
             "project_sparse_ms": round(proj_ms, 3),
             "project_entries_per_s": round(p.M / (proj_ms * 1e-3), 1),
             "round_ms": round(round_ms, 3), "step_ms": round(orth_ms + proj_ms + round_ms, 3),
             "project_tt_rank64_ms": round(transport_ms, 3),
-            "project_sum_100_rank10_ms": round(psum_ms, 3)}
+            "project_sum_100_rank10_ms": round(psum_ms, 3),
+            "tangent_gram_100_rank10_ms": round(tgram_ms, 3)}
 
 
 def completion_leg(tt, W, iters=4):

@@ -271,6 +271,19 @@ int tt_tangent_inner(const tt_tensor *U, const tt_tensor *A,
 int tt_tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b,
                      const tt_tensor *B, tt_tensor *W, void *stream);
 
+/* Gram matrix of a batch of tangent vectors at one point X (Riemannian
+ * Geometry Operations: the metric of the tangent space is that of the
+ * ambient space; Table 1 lists the Gram matrix among the timed
+ * operations).  A: b >= 1 tangent TTs in the block layout of
+ * tt_tangent_inner, one shape and one set of core offsets for the whole
+ * batch; U: the left-orthonormal sweep of X.  G (dev, b x b, row-major)
+ * receives G[i][j] = <A_i, A_j> = sum_k <dG_k^i, dG_k^j>, exactly
+ * symmetric, each entry summed in a fixed order.  The workspace holds the
+ * b x S matrix of dG blocks (S = sum_k r_k n_k r_{k+1} over U's ranks). */
+int64_t tt_tangent_gram_workspace(const tt_tensor *U, const tt_batch *A);
+int tt_tangent_gram(const tt_tensor *U, const tt_batch *A, float *G,
+                    void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ A7 */
 /* TT rounding (t3f.round(x, max_tt_rank), Implementation Details): TT_RL
  * sweep, then left-to-right truncated SVDs of reshape(G^k, r_{k-1} n_k x r_k)

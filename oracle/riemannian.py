@@ -431,3 +431,17 @@ def project_sum(X, As, c, alpha=1.0, beta=0.0):
     for A, ci in zip(As[1:], c[1:]):
         Y = add(Y, scale([np.asarray(g, dtype=np.float64) for g in A], float(ci)))
     return project_tt(X, Y, alpha, beta)
+
+
+def tangent_gram(Ws):
+    """Gram matrix of tangent vectors given as TTs (Riemannian Geometry
+    Operations: the tangent space carries the ambient inner product; Table 1
+    times the Gram matrix): G[i][j] = <W_i, W_j> by exact TT inner products."""
+    from .core import inner
+    b = len(Ws)
+    W64 = [[np.asarray(g, dtype=np.float64) for g in W] for W in Ws]
+    G = np.empty((b, b))
+    for i in range(b):
+        for j in range(b):
+            G[i, j] = inner(W64[i], W64[j])
+    return G

@@ -30,6 +30,7 @@ from .tt import (  # noqa: F401
     cg_iteration,
     riemannian_cg,
     tangent_inner,
+    tangent_gram,
     tangent_axpby,
     riemannian_completion,
     gram,

@@ -83,6 +83,8 @@ SIGNATURES = {
     "tt_project_sum_workspace": (I64, [P_TT, P_BATCH]),
     "tt_project_sum": (C.c_int, [P_TT, P_TT, P_BATCH, VP, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_tangent_inner": (C.c_int, [P_TT, P_TT, P_TT, VP, VP]),
+    "tt_tangent_gram_workspace": (I64, [P_TT, P_BATCH]),
+    "tt_tangent_gram": (C.c_int, [P_TT, P_BATCH, VP, VP, SZ, VP]),
     "tt_tangent_axpby": (C.c_int, [P_TT, C.c_float, P_TT, C.c_float, P_TT, P_TT, VP]),
     "tt_tangent_combine": (C.c_int, [P_TT, P_TT, C.c_float, C.c_int, P_TT, VP]),
     "tt_project_tt_workspace": (I64, [P_TT, P_TT]),

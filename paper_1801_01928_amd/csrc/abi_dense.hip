@@ -239,6 +239,34 @@ int tt_tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, c
   return tangent_axpby(U, a, A, b, B, W, (hipStream_t)stream);
 }
 
+static int validate_tangent_gram(const tt_tensor *U, const tt_batch *A) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "tangent_gram needs d >= 2");
+  if (!A || A->b < 1 || !A->tt) return set_error(TT_ERR_ARG, "tangent_gram: empty batch");
+  for (int i = 0; i < A->b; ++i) {
+    if ((rc = check_tangent(U, &A->tt[i], "A[i]"))) return rc;
+    for (int k = 0; k < U->d; ++k)
+      if (core_off(&A->tt[i], k) != core_off(&A->tt[0], k))
+        return set_error(TT_ERR_SHAPE, "A[%d] must have the core offsets of A[0]", i);
+  }
+  return TT_OK;
+}
+
+int64_t tt_tangent_gram_workspace(const tt_tensor *U, const tt_batch *A) {
+  int rc = validate_tangent_gram(U, A);
+  if (rc) return rc;
+  return (int64_t)tangent_gram_ws(U, A->b);
+}
+
+int tt_tangent_gram(const tt_tensor *U, const tt_batch *A, float *G, void *ws, size_t ws_bytes, void *stream) {
+  int rc = validate_tangent_gram(U, A);
+  if (rc) return rc;
+  if (!G) return set_error(TT_ERR_ARG, "tangent_gram: null G");
+  if ((rc = check_ws(ws, ws_bytes, tangent_gram_ws(U, A->b), "tangent_gram"))) return rc;
+  return tangent_gram(U, A->tt, A->b, G, ws, ws_bytes, (hipStream_t)stream);
+}
+
 int tt_round_ranks(const tt_tensor *Y, int32_t max_rank, int32_t *out_r) {
   int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
   if (rc) return rc;

@@ -25,6 +25,8 @@ int project_sum(const tt_tensor *U, const tt_tensor *V, const tt_tensor *A, int 
 int tangent_inner(const tt_tensor *U, const tt_tensor *A, const tt_tensor *B, float *out, hipStream_t s);
 int tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, const tt_tensor *B, tt_tensor *W,
                   hipStream_t s);
+size_t tangent_gram_ws(const tt_tensor *U, int nb);
+int tangent_gram(const tt_tensor *U, const tt_tensor *A, int nb, float *G, void *ws, size_t bytes, hipStream_t s);
 int tangent_assemble(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Z, tt_tensor *W,
                      float alpha, int add_x, void *ws, size_t bytes, hipStream_t s);
 

@@ -908,6 +908,95 @@ __global__ void __launch_bounds__(kThreads) tangent_axpby_kernel(TTDev U, TTDev 
   }
 }
 
+// Gram matrix of a batch of tangent vectors at one point.  Under the gauge
+// condition <A, B> = sum_k <dG_k^A, dG_k^B>, so the Gram matrix is D D^T
+// for the matrix D whose row j lists member j's dG blocks (S elements:
+// sum_k r_k n_k r_{k+1} over X's ranks).  A pack launch copies the blocks of
+// up to 64 members into rows of D; the Gram launch forms 8 x 8 tiles of
+// D D^T.
+constexpr int kGramTile = 8;
+struct MemberPtrs {
+  const float *p[kProjBatch];
+};
+
+// grid (ceil(S / 256), members); row i0 + blockIdx.y of D receives the dG
+// blocks of member blockIdx.y (core offsets and ranks of A0, shared by the
+// batch) in core order, each block in (a, s, b) order.
+__global__ void __launch_bounds__(256) tangent_pack_kernel(TTDev U, TTDev A0, MemberPtrs mp, int i0, long long S,
+                                                           float *__restrict__ D) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= S) return;
+  const float *src = mp.p[blockIdx.y];
+  long long base = 0;
+  int k = 0;
+  for (; k + 1 < U.d; ++k) {
+    const long long sz = (long long)U.r[k] * U.n[k] * U.r[k + 1];
+    if (e < base + sz) break;
+    base += sz;
+  }
+  const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
+  const long long l = e - base;
+  const int b = (int)(l % r1), sl = (int)((l / r1) % nk), a = (int)(l / ((long long)r1 * nk));
+  D[(long long)(i0 + blockIdx.y) * S + e] = src[A0.off[k] + dg_offset(k, r0, nk, A0.r[k + 1], a, sl, b)];
+}
+
+// One workgroup per tile pair (ta <= tb) of 8 x 8 members: each thread sums
+// its strided share of the S columns for all 64 pairs, then a fixed-order
+// reduction (waves, then the four wave sums in order).  The tile (tb, ta)
+// is the transpose, written from the same sums, so G is exactly symmetric.
+__global__ void __launch_bounds__(256) tangent_gram_kernel(const float *__restrict__ D, int nb, long long S,
+                                                           float *__restrict__ G) {
+  __shared__ float red[4][kGramTile * kGramTile];
+  int t = blockIdx.x, tb = 0;
+  while (t > tb) {
+    t -= tb + 1;
+    ++tb;
+  }
+  const int ta = t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float *Da[kGramTile], *Db[kGramTile];
+#pragma unroll
+  for (int i = 0; i < kGramTile; ++i) {
+    const int ra = ta * kGramTile + i, rb = tb * kGramTile + i;
+    Da[i] = D + (long long)(ra < nb ? ra : 0) * S;
+    Db[i] = D + (long long)(rb < nb ? rb : 0) * S;
+  }
+  float acc[kGramTile][kGramTile];
+#pragma unroll
+  for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+    for (int j = 0; j < kGramTile; ++j) acc[i][j] = 0.f;
+  for (long long e = threadIdx.x; e < S; e += 256) {
+    float xa[kGramTile], xb[kGramTile];
+#pragma unroll
+    for (int i = 0; i < kGramTile; ++i) {
+      xa[i] = Da[i][e];
+      xb[i] = Db[i][e];
+    }
+#pragma unroll
+    for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+      for (int j = 0; j < kGramTile; ++j) acc[i][j] = fmaf(xa[i], xb[j], acc[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+    for (int j = 0; j < kGramTile; ++j) {
+      const float v = wave_sum(acc[i][j]);
+      if (lane == 0) red[wave][i * kGramTile + j] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < kGramTile * kGramTile) {
+    const int i = threadIdx.x / kGramTile, j = threadIdx.x % kGramTile;
+    const int ra = ta * kGramTile + i, rb = tb * kGramTile + j;
+    if (ra < nb && rb < nb) {
+      const float v = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+      G[(long long)ra * nb + rb] = v;
+      if (ta != tb) G[(long long)rb * nb + ra] = v;
+    }
+  }
+}
+
 // Projection of a TT tensor Y onto the tangent space at X (U left- and V
 // right-orthonormal cores of X).  Interfaces: Psi_0 = 1,
 // Psi_{k+1} = sum_i U_k[i]^T Psi_k Y_k[i] (left), Phi_d = 1,
@@ -1333,6 +1422,36 @@ int tangent_inner(const tt_tensor *U, const tt_tensor *A, const tt_tensor *B, fl
   hipLaunchKernelGGL(tangent_inner_kernel, dim3(1), dim3(kThreads), 0, s, make_dev(U), make_dev(A), make_dev(B),
                      out);
   return launch_check("tangent inner product");
+}
+
+static long long tangent_dg_count(const tt_tensor *U) {
+  long long S = 0;
+  for (int k = 0; k < U->d; ++k) S += (long long)U->r[k] * U->n[k] * U->r[k + 1];
+  return S;
+}
+
+size_t tangent_gram_ws(const tt_tensor *U, int nb) {
+  return arena_bytes<float>((size_t)nb * (size_t)tangent_dg_count(U));
+}
+
+int tangent_gram(const tt_tensor *U, const tt_tensor *A, int nb, float *G, void *ws, size_t bytes, hipStream_t s) {
+  const long long S = tangent_dg_count(U);
+  Arena ar(ws, bytes);
+  float *D = ar.take<float>((size_t)nb * (size_t)S);
+  if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "tangent_gram: workspace too small");
+  const TTDev ud = make_dev(U), a0 = make_dev(&A[0]);
+  const unsigned gx = (unsigned)((S + 255) / 256);
+  for (int i0 = 0; i0 < nb; i0 += kProjBatch) {
+    const int m = (nb - i0) < kProjBatch ? (nb - i0) : kProjBatch;
+    MemberPtrs mp{};
+    for (int i = 0; i < m; ++i) mp.p[i] = A[i0 + i].data;
+    hipLaunchKernelGGL(tangent_pack_kernel, dim3(gx, (unsigned)m), dim3(256), 0, s, ud, a0, mp, i0, S, D);
+    int rc = launch_check("tangent gram pack");
+    if (rc) return rc;
+  }
+  const long long nt = (nb + kGramTile - 1) / kGramTile;
+  hipLaunchKernelGGL(tangent_gram_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, D, nb, S, G);
+  return launch_check("tangent gram");
 }
 
 int tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, const tt_tensor *B, tt_tensor *W,

@@ -382,6 +382,17 @@ def tangent_inner(U, A, B):
     return out
 
 
+def tangent_gram(U, As):
+    """Gram matrix G[i][j] = <As[i], As[j]> of tangent TTs at the point with
+    left sweep U (tt_tangent_gram), as a (b, b) device tensor."""
+    lib = L.load()
+    A, keep = _batch(As)
+    G = torch.empty((len(As), len(As)), dtype=torch.float32, device=U.device)
+    ws, nb = _workspace(L.check(lib.tt_tangent_gram_workspace(C.byref(U.desc()), C.byref(A))), U.device)
+    L.check(lib.tt_tangent_gram(C.byref(U.desc()), C.byref(A), _ptr(G), _ptr(ws), nb, _stream(U.device)))
+    return G
+
+
 def tangent_axpby(U, a, A, b, B, out=None):
     """a A + b B for two tangent TTs at the point with left sweep U
     (tt_tangent_axpby); ``out`` may be A or B."""

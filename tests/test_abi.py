@@ -242,3 +242,27 @@ def test_project_sum_validation_before_device(lib):
     assert lib.tt_project_sum(C.byref(U), C.byref(U), C.byref(same), c, 1.0, 0, C.byref(W), None, 0,
                               None) == L.TT_ERR_WORKSPACE
     assert lib.tt_project_sum_workspace(C.byref(U), C.byref(same)) > 0
+
+
+def test_tangent_gram_validation_before_device(lib):
+    """tt_tangent_gram rejects empty batches, members that are not tangent
+    TTs of U's shape, a missing output and a short workspace before any
+    device work; the workspace is the b x S matrix of dG blocks."""
+    from paper_1801_01928_amd import _lib as L
+    U = _desc([3, 4, 5], [1, 2, 2, 1])
+    t1 = _desc([3, 4, 5], [1, 4, 4, 1])
+    bad = _desc([3, 4, 5], [1, 3, 3, 1])
+    arr = (L.tt_tensor * 3)(t1, t1, bad)
+    two = L.tt_batch(2, arr)
+    mixed = L.tt_batch(3, arr)
+    empty = L.tt_batch(0, arr)
+    G = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x1000)
+    assert lib.tt_tangent_gram(C.byref(U), C.byref(empty), G, ws, 1 << 30, None) == L.TT_ERR_ARG
+    assert lib.tt_tangent_gram(C.byref(U), C.byref(mixed), G, ws, 1 << 30, None) == L.TT_ERR_SHAPE
+    assert lib.tt_tangent_gram(C.byref(U), C.byref(two), None, ws, 1 << 30, None) == L.TT_ERR_ARG
+    assert lib.tt_tangent_gram(C.byref(U), C.byref(two), G, None, 0, None) == L.TT_ERR_WORKSPACE
+    S = 3 * 2 + 2 * 4 * 2 + 2 * 5
+    need = lib.tt_tangent_gram_workspace(C.byref(U), C.byref(two))
+    assert need >= 2 * S * 4
+    assert lib.tt_tangent_gram_workspace(C.byref(U), C.byref(mixed)) == L.TT_ERR_SHAPE

@@ -304,6 +304,37 @@ def test_project_sum_cancelling_weights(gpu_lib):
     assert _tt_rel(got, Xc) <= 1e-5
 
 
+GRAM_CASES = [
+    # (seed, ns, X rank, Y rank, members)
+    (90, [6, 5, 7, 4], 5, 3, 70),     # two pack chunks, a ragged 8 x 8 tile
+    (91, [5, 7], 3, 2, 1),            # d = 2, one member
+    (92, [10] * 10, 10, 10, 9),       # d = 10, n = 10, rank 10
+]
+
+
+@pytest.mark.parametrize("case", range(len(GRAM_CASES)))
+def test_tangent_gram_matches_oracle(gpu_lib, case):
+    """tt_tangent_gram on tangent TTs that the oracle projected (cast to
+    float32) against the oracle's Gram matrix of the same TTs, entrywise
+    relative to sqrt(G_ii G_jj); the result is exactly symmetric."""
+    import torch
+    tt = gpu_lib
+    seed, ns, r, ry, b = GRAM_CASES[case]
+    print("tangent_gram", ns, r, ry, b, flush=True)
+    rng = np.random.default_rng(seed)
+    Xc = W.random_cores(rng, ns, W.canonical_ranks(ns, r), 1 / np.sqrt(r))
+    outs = [R.project_tt(Xc, W.random_cores(rng, ns, W.uniform_ranks(len(ns), ry), 1 / np.sqrt(ry)))
+            for _ in range(b)]
+    U = tt.TT.from_cores([u.astype(np.float32) for u in outs[0][1]])
+    Ws = [[g.astype(np.float32) for g in o[0]] for o in outs]
+    G = tt.tangent_gram(U, [tt.TT.from_cores(w) for w in Ws])
+    assert torch.equal(G, G.t())
+    got = G.cpu().numpy().astype(np.float64)
+    want = R.tangent_gram(Ws)
+    scale = np.sqrt(np.outer(np.diag(want), np.diag(want)))
+    assert np.all(np.abs(got - want) <= 1e-5 * scale)
+
+
 def test_project_sum_of_one_is_project_tt(gpu_lib):
     """A batch of one with weight 1 gives exactly the single projection."""
     import torch

@@ -493,3 +493,21 @@ def test_project_sum_linearity_and_dense_projector():
     P = R.dense_projector(oracle.orthogonalize_lr(X), oracle.orthogonalize_rl(X))
     z = sum(ci * oracle.full(A).reshape(-1) for ci, A in zip(c, As))
     np.testing.assert_allclose(oracle.full(W).reshape(-1), oracle.full(X).reshape(-1) + 0.5 * (P @ z), atol=1e-12)
+
+
+def test_tangent_gram_dense_and_block_identity():
+    """The tangent Gram matrix equals the Gram matrix of the dense tensors,
+    and the sum of the dG block inner products (the gauge condition makes
+    the tangent terms orthogonal); it is symmetric positive semidefinite."""
+    from oracle import riemannian as R
+    ns = [3, 4, 3, 2]
+    X = _X(61, ns, 3)
+    outs = [R.project_tt(X, _X(70 + i, ns, 2)) for i in range(4)]
+    Ws = [o[0] for o in outs]
+    G = R.tangent_gram(Ws)
+    F = np.stack([oracle.full(W).reshape(-1) for W in Ws])
+    np.testing.assert_allclose(G, F @ F.T, atol=1e-12)
+    blocks = np.array([[sum(np.vdot(a, b) for a, b in zip(oi[3], oj[3])) for oj in outs] for oi in outs])
+    np.testing.assert_allclose(G, blocks, atol=1e-12)
+    assert np.array_equal(G, G.T) or np.allclose(G, G.T, atol=1e-14)
+    assert np.linalg.eigvalsh(G).min() > -1e-12
