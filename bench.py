@@ -347,6 +347,39 @@ def completion_leg(tt, W, iters=4):
                    "test_rmse_first_last": [round(h0[0]["test_rmse"], 5), round(float(lc.item()) ** 0.5, 5)]}}
 
 
+def matvec_leg(tt, W, reps=5):
+    """TT-matrix by TT-vector products in the TT format at Table 1's shape:
+    W of size 10^10 x 10^10 (d=10, modes 10 x 10, rank 10) times 100 TT
+    vectors of rank 10, giving 100 exact products of rank 100.  The outputs
+    are allocated before timing; HBM bandwidth counts the bytes written and
+    read once."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from paper_1801_01928_amd import _lib as L
+    from paper_1801_01928_amd.tt import _batch
+    lib = L.load()
+    rng = np.random.default_rng(11)
+    d, b = 10, 100
+    Wm = tt.TTMatrix.from_cores([rng.standard_normal((1 if k == 0 else 10, 10, 10, 1 if k == d - 1 else 10))
+                                 .astype(np.float32) * 0.3 for k in range(d)])
+    xs = [tt.TT.from_cores(W.random_cores(rng, [10] * d, W.uniform_ranks(d, 10), 0.3)) for _ in range(b)]
+    ys = tt.tt_matvec(Wm, xs)
+    xb, keepx = _batch(xs)
+    yb, keepy = _batch(ys)
+    stream = torch.cuda.current_stream()
+    call = lambda: L.check(lib.tt_matvec(C.byref(Wm.desc()), C.byref(xb), C.byref(yb),
+                                         C.c_void_p(stream.cuda_stream)))
+    call()
+    torch.cuda.synchronize()
+    ms = _event_ms(call, reps)
+    nbytes = 4 * (sum(y.data.numel() for y in ys) + sum(x.data.numel() for x in xs) + Wm.data.numel())
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": "y_j = W x_j in TT format, W 10^10 x 10^10 (d=10, modes 10x10, rank 10), 100 TT vectors "
+                        "of rank 10, outputs of rank 100", "ms": round(ms, 4), "bytes": nbytes,
+            "gb_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / 8000.0, 3)}
+
+
 def ttm_leg(tt, W, reps=3):
     """TT-matrix layer 1024 x 1024 (modes 4^5, r=32) on a batch of 4096 rows:
     forward and adjoint, float32 and bf16 (float32 accumulation)."""
@@ -451,6 +484,7 @@ def main():
         out["gram"] = gram_leg(tt, W)
         out["riemann_step"] = riemann_leg(tt, W)
         out["ttm_layer"] = ttm_leg(tt, W)
+        out["matvec"] = matvec_leg(tt, W)
         out["completion_loop"] = completion_leg(tt, W)
     if not args.no_cpu_baseline:
         th = t.cpu().numpy()

@@ -43,7 +43,7 @@ extern "C" {
 
 #define TTGFX_VERSION 1
 #define TT_MAX_D 32       /* modes per tensor */
-#define TT_MAX_RANK 64    /* largest bond rank any entry point accepts */
+#define TT_MAX_RANK 64    /* largest input bond rank (tt_matvec's outputs: products of two) */
 #define TT_MAX_N 4096     /* largest mode size */
 
 enum {
@@ -364,6 +364,17 @@ int tt_matmul(const tt_matrix *W, const void *X, int64_t B, float *Y, int dtype,
 int tt_matmul_backward(const tt_matrix *W, const void *X, int64_t B,
                        const void *dY, float *dX, float *dWdata, int dtype,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* TT-matrix by TT-vector product in the TT format (Implementation Details:
+ * matrix-by-vector products of TT objects; Table 1 times it as matvec).
+ * W: float32 TT-matrix, cores r_k x m_k x n_k x r_{k+1} (tt_matrix above;
+ * no limit on prod m or prod n).  X: b >= 1 TT vectors of modes n_k, one
+ * shape and one set of core offsets for the batch.  Y: b TT vectors (dev,
+ * caller-owned) of modes m_k and ranks r_k s_k (s = X's ranks; up to
+ * TT_MAX_RANK^2), receiving y_j = W x_j exactly (no rounding):
+ *   Y_k[(a, b), i, (a', b')] = sum_j W_k[a, i, j, a'] X_k[b, j, b'],
+ * with the bond index a s_k + b.  Every element is written; no workspace. */
+int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, void *stream);
 
 /* ---------------------------------------------------------------- misc */
 const char *tt_last_error(void);   /* thread-local message of the last failure */

@@ -52,4 +52,5 @@ from .ttmatrix import (  # noqa: F401
     ttm_full,
     ttm_forward,
     ttm_backward,
+    tt_matvec,
 )

@@ -81,3 +81,19 @@ def ttm_backward(X, cores, dY):
         g = np.tensordot(g, Rk.T, axes=([2], [0]))           # (r_k, mk, r_{k+1})
         grads.append(g.reshape(cores[k].shape))
     return dX, grads
+
+
+def tt_matvec(W, x):
+    """The TT-matrix by TT-vector product in the TT format (Implementation
+    Details: products of TT objects; Table 1 times it as matvec): for W
+    cores (r_k, m_k, n_k, r_{k+1}) and x cores (s_k, n_k, s_{k+1}), the cores
+    y_k[(a, b), i, (a', b')] = sum_j W_k[a, i, j, a'] x_k[b, j, b'], bond
+    index a s_k + b.  Exact; the ranks multiply."""
+    out = []
+    for Wk, xk in zip(W, x):
+        Wk = np.asarray(Wk, dtype=np.float64)
+        xk = np.asarray(xk, dtype=np.float64)
+        r0, m, n, r1 = Wk.shape
+        s0, _, s1 = xk.shape
+        out.append(np.einsum("aijc,bjd->abicd", Wk, xk).reshape(r0 * s0, m, r1 * s1))
+    return out

@@ -37,6 +37,7 @@ from .tt import (  # noqa: F401
     BatchedPlan,
     TTMatrix,
     ttm_matmul,
+    tt_matvec,
     ttm_matmul_backward,
     tt_linear,
 )

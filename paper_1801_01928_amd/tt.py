@@ -663,6 +663,20 @@ def _ttm_input(W, X, cols):
     return X
 
 
+def tt_matvec(W, xs):
+    """y_j = W x_j in the TT format (tt_matvec) for a float32 TTMatrix W and
+    TT vectors xs of one shape: exact products of ranks r_k s_k."""
+    if W.dtype_code != 0:
+        raise ValueError("tt_matvec takes a float32 TT-matrix")
+    lib = L.load()
+    ranks = [a * b for a, b in zip(W.ranks, xs[0].ranks)]
+    ys = [TT(W.ms, ranks, device=xs[0].device) for _ in xs]
+    X, keepx = _batch(xs)
+    Y, keepy = _batch(ys)
+    L.check(lib.tt_matvec(C.byref(W.desc()), C.byref(X), C.byref(Y), _stream(xs[0].device)))
+    return ys
+
+
 def ttm_matmul(W, X):
     """Y = X W^T (float32) for a batch of rows X (B x prod n), X in W's dtype."""
     lib = L.load()

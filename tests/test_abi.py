@@ -266,3 +266,26 @@ def test_tangent_gram_validation_before_device(lib):
     need = lib.tt_tangent_gram_workspace(C.byref(U), C.byref(two))
     assert need >= 2 * S * 4
     assert lib.tt_tangent_gram_workspace(C.byref(U), C.byref(mixed)) == L.TT_ERR_SHAPE
+
+
+def test_matvec_validation_before_device(lib):
+    """tt_matvec rejects an empty batch, mismatched batch sizes, a vector
+    whose modes are not W's column modes, and outputs whose ranks are not
+    the products, before any device work."""
+    from paper_1801_01928_amd import _lib as L
+    m = (C.c_int32 * 2)(2, 3)
+    n = (C.c_int32 * 2)(3, 4)
+    r = (C.c_int32 * 3)(1, 2, 1)
+    W = L.tt_matrix(2, m, n, r, None, C.c_void_p(0x3000))
+    x = _desc([3, 4], [1, 3, 1])
+    xbad = _desc([3, 5], [1, 3, 1])
+    y = _desc([2, 3], [1, 6, 1])
+    ybad = _desc([2, 3], [1, 5, 1])
+    xs = (L.tt_tensor * 2)(x, xbad)
+    ys = (L.tt_tensor * 2)(y, ybad)
+    one_x, one_y = L.tt_batch(1, xs), L.tt_batch(1, ys)
+    assert lib.tt_matvec(C.byref(W), C.byref(L.tt_batch(0, xs)), C.byref(one_y), None) == L.TT_ERR_ARG
+    assert lib.tt_matvec(C.byref(W), C.byref(one_x), C.byref(L.tt_batch(2, ys)), None) == L.TT_ERR_ARG
+    assert lib.tt_matvec(C.byref(W), C.byref(L.tt_batch(2, xs)), C.byref(L.tt_batch(2, ys)), None) == L.TT_ERR_SHAPE
+    ys2 = (L.tt_tensor * 1)(ybad)
+    assert lib.tt_matvec(C.byref(W), C.byref(one_x), C.byref(L.tt_batch(1, ys2)), None) == L.TT_ERR_SHAPE

@@ -181,3 +181,35 @@ def test_ttm_layer_full_size_bf16(gpu_lib):
     got = tt.TTMatrix(p.row_modes, p.col_modes, p.ranks, dG).numpy_cores()
     for g, r in zip(got, rdG):
         assert rel(g, r) <= tol
+
+
+MATVEC_CASES = [
+    # (seed, row modes, column modes, W ranks, x ranks, vectors)
+    (40, [2, 3, 5], [3, 4, 2], [1, 3, 4, 1], [1, 2, 5, 1], 3),     # ragged modes and ranks
+    (41, [7], [5], [1, 1], [1, 1], 2),                              # d = 1: a dense matvec
+    (42, [3, 2, 2], [2, 2, 3], [1, 2, 2, 1], [1, 2, 3, 1], 65),     # two launches of 64 + 1
+    (43, [10] * 10, [10] * 10, [1] + [10] * 9 + [1], [1] + [10] * 9 + [1], 2),  # d=10, rank 10 x 10
+]
+
+
+@pytest.mark.parametrize("case", range(len(MATVEC_CASES)))
+def test_tt_matvec_matches_oracle(gpu_lib, case):
+    """tt_matvec against the oracle's TT-format product, core by core: every
+    element within 1e-5 of the same sum taken over absolute values."""
+    tt = gpu_lib
+    seed, ms, ns, rw, rx, b = MATVEC_CASES[case]
+    print("matvec", ms, ns, rw, rx, b, flush=True)
+    rng = np.random.default_rng(seed)
+    Wc = [rng.standard_normal((rw[k], ms[k], ns[k], rw[k + 1])).astype(np.float32) for k in range(len(ms))]
+    xs = [[rng.standard_normal((rx[k], ns[k], rx[k + 1])).astype(np.float32) for k in range(len(ms))]
+          for _ in range(b)]
+    W = tt.TTMatrix.from_cores(Wc)
+    ys = tt.tt_matvec(W, [tt.TT.from_cores(x) for x in xs])
+    absW = [np.abs(c) for c in Wc]
+    for x, y in zip(xs, ys):
+        want = oracle.tt_matvec(Wc, x)
+        bound = oracle.tt_matvec(absW, [np.abs(c) for c in x])
+        got = y.numpy_cores()
+        assert [g.shape for g in got] == [w.shape for w in want]
+        for g, w, bd in zip(got, want, bound):
+            assert np.all(np.abs(g.astype(np.float64) - w) <= 1e-5 * bd + 1e-30)

@@ -93,3 +93,21 @@ def test_backward_exact_fd_euler_and_sparse_adjoint():
     for k in range(3):
         np.testing.assert_allclose(ga[k].reshape(cores[k].shape), dG[k], rtol=1e-11, atol=1e-12)
     assert W.shape == (12, 12)
+
+
+def test_tt_matvec_dense_product_and_identity():
+    """The TT-format product equals the dense matrix-vector product, its
+    ranks multiply, and an identity TT-matrix (rank-1 eye cores) returns the
+    vector's own cores."""
+    import oracle
+    rng = np.random.default_rng(5)
+    ms, ns, rw, rx = [2, 3, 2], [3, 2, 4], [1, 2, 3, 1], [1, 3, 2, 1]
+    Wc = [rng.standard_normal((rw[k], ms[k], ns[k], rw[k + 1])) for k in range(3)]
+    xc = [rng.standard_normal((rx[k], ns[k], rx[k + 1])) for k in range(3)]
+    y = oracle.tt_matvec(Wc, xc)
+    assert [c.shape for c in y] == [(1, 2, 6), (6, 3, 6), (6, 2, 1)]
+    np.testing.assert_allclose(oracle.full(y).reshape(-1), oracle.ttm_full(Wc) @ oracle.full(xc).reshape(-1),
+                               rtol=1e-12, atol=1e-12)
+    eye = [np.eye(n).reshape(1, n, n, 1) for n in ns]
+    for a, b in zip(oracle.tt_matvec(eye, xc), xc):
+        assert np.array_equal(a, b)
