@@ -7,8 +7,9 @@
 // of ranks r_k s_k (bond index a s_k + b) and modes m_k (Implementation
 // Details: the TT-matrix by TT-vector product; Table 1 times it as matvec).
 // No rounding: the product is exact and its ranks multiply.  Every output
-// element is one n_k-term sum, so the kernel is bound by writing y; W_k and
-// x_k are small and stay in the caches.
+// element is one n_k-term sum over W_k and x_k, which are small and stay in
+// the caches; the bytes that must move are those of y.  This kernel gathers
+// both factors per lane, which, not the bytes, limits it.
 #include "common.h"
 
 namespace ttgfx {
@@ -16,6 +17,7 @@ namespace {
 
 constexpr int kMvBatch = 64;  // vectors per launch
 constexpr int kMvThreads = 256;
+constexpr int kMvPerThread = 8;  // fewer, fuller workgroups: dispatch is not the limit
 
 struct MatDev {
   int d;
@@ -29,26 +31,30 @@ struct MvIO {
   float *y[kMvBatch];
 };
 
-// grid (ceil(max output core / 256), d, members): thread e of core k writes
-// element e of y_k for member blockIdx.z, with e = (row m_k + i) R' + col,
-// row = a s_k + b, col = a' s_{k+1} + b', R' = r_{k+1} s_{k+1}.
+// grid (g, d, members), grid-stride over the elements of y_k for member
+// blockIdx.z (g sized for about kMvPerThread elements per thread of the
+// largest core): element e = (row m_k + i) R' + col, row = a s_k + b,
+// col = a' s_{k+1} + b', R' = r_{k+1} s_{k+1}.
 __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, TTDev X0, TTDev Y0, MvIO io) {
   const int k = blockIdx.y;
   const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
   const int mk = W.m[k], nk = W.n[k];
-  const int R1 = r1 * s1;
-  const long long cnt = (long long)r0 * s0 * mk * R1;
-  const long long e = (long long)blockIdx.x * kMvThreads + threadIdx.x;
-  if (e >= cnt) return;
-  const int col = (int)(e % R1);
-  const long long t = e / R1;
-  const int i = (int)(t % mk), row = (int)(t / mk);
-  const int a = row / s0, b = row % s0, ap = col / s1, bp = col % s1;
-  const float *wk = W.data + W.off[k] + (((long long)a * mk + i) * nk) * r1 + ap;
-  const float *xk = io.x[blockIdx.z] + X0.off[k] + (long long)b * nk * s1 + bp;
-  float acc = 0.f;
-  for (int j = 0; j < nk; ++j) acc = fmaf(wk[(long long)j * r1], xk[(long long)j * s1], acc);
-  io.y[blockIdx.z][Y0.off[k] + e] = acc;
+  // the host keeps every output core below 2^31 elements: 32-bit index
+  // arithmetic
+  const unsigned R1 = (unsigned)(r1 * s1);
+  const unsigned cnt = (unsigned)r0 * s0 * mk * R1;
+  const float *xm = io.x[blockIdx.z] + X0.off[k];
+  float *yk = io.y[blockIdx.z] + Y0.off[k];
+  for (unsigned e = blockIdx.x * kMvThreads + threadIdx.x; e < cnt; e += gridDim.x * kMvThreads) {
+    const unsigned t = e / R1, col = e - t * R1;
+    const unsigned row = t / mk, i = t - row * mk;
+    const unsigned a = row / s0, b = row - a * s0, ap = col / s1, bp = col - ap * s1;
+    const float *wk = W.data + W.off[k] + (((long long)a * mk + i) * nk) * r1 + ap;
+    const float *xk = xm + (long long)b * nk * s1 + bp;
+    float acc = 0.f;
+    for (int j = 0; j < nk; ++j) acc = fmaf(wk[(long long)j * r1], xk[(long long)j * s1], acc);
+    yk[e] = acc;
+  }
 }
 
 int validate_matvec(const tt_matrix *W, const tt_batch *X, const tt_batch *Y, MatDev *md) {
@@ -114,8 +120,8 @@ extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, voi
     const long long c = core_elems(&Y->tt[0], k);
     maxcnt = c > maxcnt ? c : maxcnt;
   }
-  const long long gx = (maxcnt + kMvThreads - 1) / kMvThreads;
-  if (gx > 0x7fffffffLL) return set_error(TT_ERR_UNSUPPORTED, "matvec: an output core above 2^39 elements");
+  const long long gx = (maxcnt + (long long)kMvThreads * kMvPerThread - 1) / ((long long)kMvThreads * kMvPerThread);
+  if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "matvec: an output core of 2^31 or more elements");
   for (int j0 = 0; j0 < X->b; j0 += kMvBatch) {
     const int m = (X->b - j0) < kMvBatch ? (X->b - j0) : kMvBatch;
     MvIO io{};
