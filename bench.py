@@ -375,9 +375,16 @@ def matvec_leg(tt, W, reps=5):
     ms = _event_ms(call, reps)
     nbytes = 4 * (sum(y.data.numel() for y in ys) + sum(x.data.numel() for x in xs) + Wm.data.numel())
     gbs = nbytes / (ms * 1e-3) / 1e9
+    # one TT-matrix product W W2 at the same shape (output rank 100)
+    W2 = tt.TTMatrix.from_cores([rng.standard_normal((1 if k == 0 else 10, 10, 10, 1 if k == d - 1 else 10))
+                                 .astype(np.float32) * 0.3 for k in range(d)])
+    tt.tt_matmat(Wm, W2)
+    torch.cuda.synchronize()
+    mm_ms = _event_ms(lambda: tt.tt_matmat(Wm, W2), reps)
     return {"workload": "y_j = W x_j in TT format, W 10^10 x 10^10 (d=10, modes 10x10, rank 10), 100 TT vectors "
                         "of rank 10, outputs of rank 100", "ms": round(ms, 4), "bytes": nbytes,
-            "gb_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / 8000.0, 3)}
+            "gb_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / 8000.0, 3),
+            "matmat_ms": round(mm_ms, 4)}
 
 
 def ttm_leg(tt, W, reps=3):

@@ -375,6 +375,13 @@ int tt_matmul_backward(const tt_matrix *W, const void *X, int64_t B,
  *   Y_k[(a, b), i, (a', b')] = sum_j W_k[a, i, j, a'] X_k[b, j, b'],
  * with the bond index a s_k + b.  Every element is written; no workspace. */
 int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, void *stream);
+/* TT-matrix by TT-matrix product C = A B in the TT format (Table 1's
+ * matmul).  A: m_k x n_k modes, B: n_k x l_k modes (both float32, ranks up
+ * to TT_MAX_RANK); C (dev, caller-owned, float32): modes m_k x l_k, ranks
+ * r^A_k r^B_k, offsets from C->off or packed.  Exact:
+ *   C_k[(a, b), i, l, (a', b')] = sum_j A_k[a, i, j, a'] B_k[b, j, l, b'],
+ * bond index a r^B_k + b.  Every element is written; no workspace. */
+int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *C, void *stream);
 
 /* ---------------------------------------------------------------- misc */
 const char *tt_last_error(void);   /* thread-local message of the last failure */

@@ -53,4 +53,5 @@ from .ttmatrix import (  # noqa: F401
     ttm_forward,
     ttm_backward,
     tt_matvec,
+    tt_matmat,
 )

@@ -97,3 +97,18 @@ def tt_matvec(W, x):
         s0, _, s1 = xk.shape
         out.append(np.einsum("aijc,bjd->abicd", Wk, xk).reshape(r0 * s0, m, r1 * s1))
     return out
+
+
+def tt_matmat(A, B):
+    """The TT-matrix by TT-matrix product in the TT format (Table 1 times it
+    as matmul): for A cores (r_k, m_k, n_k, r_{k+1}) and B cores
+    (s_k, n_k, l_k, s_{k+1}), C_k[(a, b), i, l, (a', b')] =
+    sum_j A_k[a, i, j, a'] B_k[b, j, l, b'], bond index a s_k + b."""
+    out = []
+    for Ak, Bk in zip(A, B):
+        Ak = np.asarray(Ak, dtype=np.float64)
+        Bk = np.asarray(Bk, dtype=np.float64)
+        r0, m, n, r1 = Ak.shape
+        s0, _, lk, s1 = Bk.shape
+        out.append(np.einsum("aijc,bjld->abilcd", Ak, Bk).reshape(r0 * s0, m, lk, r1 * s1))
+    return out

@@ -38,6 +38,7 @@ from .tt import (  # noqa: F401
     TTMatrix,
     ttm_matmul,
     tt_matvec,
+    tt_matmat,
     ttm_matmul_backward,
     tt_linear,
 )

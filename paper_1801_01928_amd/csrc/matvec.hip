@@ -26,6 +26,16 @@ struct MatDev {
   const float *data;
 };
 
+// The right factor: a TT vector (L_k = 1) or a TT-matrix with cores
+// s_k x n_k x L_k x s_{k+1}; and the output's core offsets.
+struct RightDev {
+  int r[TT_MAX_D + 1], L[TT_MAX_D];
+  long long off[TT_MAX_D];
+};
+struct OutDev {
+  long long off[TT_MAX_D];
+};
+
 struct MvIO {
   const float *x[kMvBatch];
   float *y[kMvBatch];
@@ -33,31 +43,33 @@ struct MvIO {
 
 // grid (g, d, members), grid-stride over the elements of y_k for member
 // blockIdx.z (g sized for about kMvPerThread elements per thread of the
-// largest core): element e = (row m_k + i) R' + col, row = a s_k + b,
-// col = a' s_{k+1} + b', R' = r_{k+1} s_{k+1}.
-__global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, TTDev X0, TTDev Y0, MvIO io) {
+// largest core): element e = ((row m_k + i) L_k + l) R' + col, with
+// row = a s_k + b, col = a' s_{k+1} + b', R' = r_{k+1} s_{k+1}.
+__global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, RightDev X0, OutDev Y0, MvIO io) {
   const int k = blockIdx.y;
   const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
-  const int mk = W.m[k], nk = W.n[k];
+  const int mk = W.m[k], nk = W.n[k], lk = X0.L[k];
   // the host keeps every output core below 2^31 elements: 32-bit index
   // arithmetic
   const unsigned R1 = (unsigned)(r1 * s1);
-  const unsigned cnt = (unsigned)r0 * s0 * mk * R1;
+  const unsigned cnt = (unsigned)r0 * s0 * mk * lk * R1;
   const float *xm = io.x[blockIdx.z] + X0.off[k];
   float *yk = io.y[blockIdx.z] + Y0.off[k];
+  const long long xs = (long long)lk * s1;  // x stride along j
   for (unsigned e = blockIdx.x * kMvThreads + threadIdx.x; e < cnt; e += gridDim.x * kMvThreads) {
     const unsigned t = e / R1, col = e - t * R1;
-    const unsigned row = t / mk, i = t - row * mk;
+    const unsigned t2 = t / lk, l = t - t2 * lk;
+    const unsigned row = t2 / mk, i = t2 - row * mk;
     const unsigned a = row / s0, b = row - a * s0, ap = col / s1, bp = col - ap * s1;
     const float *wk = W.data + W.off[k] + (((long long)a * mk + i) * nk) * r1 + ap;
-    const float *xk = xm + (long long)b * nk * s1 + bp;
+    const float *xk = xm + ((long long)b * nk * lk + l) * s1 + bp;
     float acc = 0.f;
-    for (int j = 0; j < nk; ++j) acc = fmaf(wk[(long long)j * r1], xk[(long long)j * s1], acc);
+    for (int j = 0; j < nk; ++j) acc = fmaf(wk[(long long)j * r1], xk[j * xs], acc);
     yk[e] = acc;
   }
 }
 
-int validate_matvec(const tt_matrix *W, const tt_batch *X, const tt_batch *Y, MatDev *md) {
+int validate_matrix(const tt_matrix *W, MatDev *md) {
   if (!W) return set_error(TT_ERR_ARG, "W: null descriptor");
   if (W->d < 1 || W->d > TT_MAX_D) return set_error(TT_ERR_ARG, "W: d = %d outside [1, %d]", W->d, TT_MAX_D);
   if (!W->m || !W->n || !W->r) return set_error(TT_ERR_ARG, "W: null m, n or r array");
@@ -82,9 +94,14 @@ int validate_matvec(const tt_matrix *W, const tt_batch *X, const tt_batch *Y, Ma
     md->off[k] = W->off ? W->off[k] : o;
     o += (long long)W->r[k] * W->m[k] * W->n[k] * W->r[k + 1];
   }
+  return TT_OK;
+}
+
+int validate_matvec(const tt_matrix *W, const tt_batch *X, const tt_batch *Y, MatDev *md) {
+  int rc = validate_matrix(W, md);
+  if (rc) return rc;
   if (!X || X->b < 1 || !X->tt) return set_error(TT_ERR_ARG, "matvec: empty batch of vectors");
   if (!Y || Y->b != X->b || !Y->tt) return set_error(TT_ERR_ARG, "matvec: Y must hold as many TTs as X");
-  int rc;
   const tt_tensor *x0 = &X->tt[0], *y0 = &Y->tt[0];
   for (int j = 0; j < X->b; ++j) {
     const tt_tensor *x = &X->tt[j], *y = &Y->tt[j];
@@ -114,7 +131,15 @@ extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, voi
   MatDev md;
   int rc = validate_matvec(W, X, Y, &md);
   if (rc) return rc;
-  const TTDev x0 = make_dev(&X->tt[0]), y0 = make_dev(&Y->tt[0]);
+  RightDev x0{};
+  OutDev y0{};
+  for (int k = 0; k < md.d; ++k) {
+    x0.r[k] = X->tt[0].r[k];
+    x0.L[k] = 1;
+    x0.off[k] = core_off(&X->tt[0], k);
+    y0.off[k] = core_off(&Y->tt[0], k);
+  }
+  x0.r[md.d] = 1;
   long long maxcnt = 0;
   for (int k = 0; k < md.d; ++k) {
     const long long c = core_elems(&Y->tt[0], k);
@@ -134,4 +159,45 @@ extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, voi
     if ((rc = launch_check("matvec"))) return rc;
   }
   return TT_OK;
+}
+
+// C = A B for two TT-matrices (A: m x n modes, B: n x l modes): the cores
+// C_k[(a, b), i, l, (a', b')] = sum_j A_k[a, i, j, a'] B_k[b, j, l, b'].
+extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, void *stream) {
+  MatDev ma, mb, mc;
+  int rc;
+  if ((rc = validate_matrix(A, &ma)) || (rc = validate_matrix(B, &mb))) return rc;
+  if (!Cm) return set_error(TT_ERR_ARG, "C: null descriptor");
+  if (!Cm->m || !Cm->n || !Cm->r || !Cm->data) return set_error(TT_ERR_ARG, "C: null array or data pointer");
+  if (B->d != A->d || Cm->d != A->d) return set_error(TT_ERR_SHAPE, "A, B and C must have the same d");
+  for (int k = 0; k < A->d; ++k) {
+    if (B->m[k] != A->n[k]) return set_error(TT_ERR_SHAPE, "B: row mode %d = %d, expected A's column mode %d", k, B->m[k], A->n[k]);
+    if (Cm->m[k] != A->m[k] || Cm->n[k] != B->n[k])
+      return set_error(TT_ERR_SHAPE, "C: modes of core %d must be A's rows and B's columns", k);
+  }
+  for (int k = 0; k <= A->d; ++k)
+    if (Cm->r[k] != A->r[k] * B->r[k])
+      return set_error(TT_ERR_SHAPE, "C: r[%d] = %d, expected %d", k, Cm->r[k], A->r[k] * B->r[k]);
+  RightDev x0{};
+  OutDev y0{};
+  long long oc = 0, maxcnt = 0;
+  for (int k = 0; k < A->d; ++k) {
+    if (Cm->off && Cm->off[k] < 0) return set_error(TT_ERR_ARG, "C: negative offset for core %d", k);
+    x0.r[k] = B->r[k];
+    x0.L[k] = B->n[k];
+    x0.off[k] = mb.off[k];
+    y0.off[k] = Cm->off ? Cm->off[k] : oc;
+    const long long c = (long long)Cm->r[k] * Cm->m[k] * Cm->n[k] * Cm->r[k + 1];
+    oc += c;
+    maxcnt = c > maxcnt ? c : maxcnt;
+  }
+  x0.r[A->d] = 1;
+  if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "matmat: an output core of 2^31 or more elements");
+  const long long gx = (maxcnt + (long long)kMvThreads * kMvPerThread - 1) / ((long long)kMvThreads * kMvPerThread);
+  MvIO io{};
+  io.x[0] = mb.data;
+  io.y[0] = (float *)Cm->data;
+  hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)gx, (unsigned)ma.d, 1u), dim3(kMvThreads), 0,
+                     (hipStream_t)stream, ma, x0, y0, io);
+  return launch_check("matmat");
 }

@@ -677,6 +677,19 @@ def tt_matvec(W, xs):
     return ys
 
 
+def tt_matmat(A, B):
+    """C = A B in the TT format (tt_matmat) for float32 TTMatrix objects:
+    exact, modes A.ms x B.ns, ranks the products of A's and B's."""
+    if A.dtype_code != 0 or B.dtype_code != 0:
+        raise ValueError("tt_matmat takes float32 TT-matrices")
+    ranks = [a * b for a, b in zip(A.ranks, B.ranks)]
+    n = sum(ranks[k] * A.ms[k] * B.ns[k] * ranks[k + 1] for k in range(A.d))
+    Cm = TTMatrix(A.ms, B.ns, ranks, torch.empty(n, dtype=torch.float32, device=A.data.device))
+    L.check(L.load().tt_matmat(C.byref(A.desc()), C.byref(B.desc()), C.byref(Cm.desc()),
+                               _stream(A.data.device)))
+    return Cm
+
+
 def ttm_matmul(W, X):
     """Y = X W^T (float32) for a batch of rows X (B x prod n), X in W's dtype."""
     lib = L.load()

@@ -289,3 +289,20 @@ def test_matvec_validation_before_device(lib):
     assert lib.tt_matvec(C.byref(W), C.byref(L.tt_batch(2, xs)), C.byref(L.tt_batch(2, ys)), None) == L.TT_ERR_SHAPE
     ys2 = (L.tt_tensor * 1)(ybad)
     assert lib.tt_matvec(C.byref(W), C.byref(one_x), C.byref(L.tt_batch(1, ys2)), None) == L.TT_ERR_SHAPE
+
+
+def test_matmat_validation_before_device(lib):
+    """tt_matmat rejects mismatched inner modes and output ranks that are
+    not the products before any device work."""
+    from paper_1801_01928_amd import _lib as L
+    def mat(m, n, r, ptr):
+        arrs = ((C.c_int32 * len(m))(*m), (C.c_int32 * len(n))(*n), (C.c_int32 * len(r))(*r))
+        return L.tt_matrix(len(m), arrs[0], arrs[1], arrs[2], None, C.c_void_p(ptr)), arrs
+    A, ka = mat([2, 3], [3, 4], [1, 2, 1], 0x1000)
+    B, kb = mat([3, 4], [2, 2], [1, 3, 1], 0x2000)
+    Bbad, kbb = mat([3, 5], [2, 2], [1, 3, 1], 0x2000)
+    Cg, kc = mat([2, 3], [2, 2], [1, 6, 1], 0x3000)
+    Cbad, kcb = mat([2, 3], [2, 2], [1, 5, 1], 0x3000)
+    assert lib.tt_matmat(C.byref(A), C.byref(Bbad), C.byref(Cg), None) == L.TT_ERR_SHAPE
+    assert lib.tt_matmat(C.byref(A), C.byref(B), C.byref(Cbad), None) == L.TT_ERR_SHAPE
+    assert lib.tt_matmat(C.byref(A), C.byref(B), None, None) == L.TT_ERR_ARG

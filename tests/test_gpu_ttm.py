@@ -213,3 +213,30 @@ def test_tt_matvec_matches_oracle(gpu_lib, case):
         assert [g.shape for g in got] == [w.shape for w in want]
         for g, w, bd in zip(got, want, bound):
             assert np.all(np.abs(g.astype(np.float64) - w) <= 1e-5 * bd + 1e-30)
+
+
+MATMAT_CASES = [
+    # (seed, row modes, inner modes, column modes, A ranks, B ranks)
+    (44, [2, 3, 5], [3, 4, 2], [2, 1, 3], [1, 3, 4, 1], [1, 2, 5, 1]),
+    (45, [10] * 4, [10] * 4, [10] * 4, [1, 10, 10, 10, 1], [1, 10, 10, 10, 1]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(MATMAT_CASES)))
+def test_tt_matmat_matches_oracle(gpu_lib, case):
+    """tt_matmat against the oracle's TT-format product, core by core, each
+    element within 1e-5 of its absolute-value sum."""
+    tt = gpu_lib
+    seed, ms, ns, ls, ra, rb = MATMAT_CASES[case]
+    print("matmat", ms, ns, ls, ra, rb, flush=True)
+    rng = np.random.default_rng(seed)
+    d = len(ms)
+    A = [rng.standard_normal((ra[k], ms[k], ns[k], ra[k + 1])).astype(np.float32) for k in range(d)]
+    B = [rng.standard_normal((rb[k], ns[k], ls[k], rb[k + 1])).astype(np.float32) for k in range(d)]
+    Cm = tt.tt_matmat(tt.TTMatrix.from_cores(A), tt.TTMatrix.from_cores(B))
+    flat = Cm.data.cpu().numpy().astype(np.float64)
+    want = oracle.tt_matmat(A, B)
+    bound = oracle.tt_matmat([np.abs(c) for c in A], [np.abs(c) for c in B])
+    for k in range(d):
+        got = flat[Cm.offs[k]:Cm.offs[k + 1]].reshape(want[k].shape)
+        assert np.all(np.abs(got - want[k]) <= 1e-5 * bound[k] + 1e-30)

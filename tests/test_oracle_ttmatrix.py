@@ -111,3 +111,20 @@ def test_tt_matvec_dense_product_and_identity():
     eye = [np.eye(n).reshape(1, n, n, 1) for n in ns]
     for a, b in zip(oracle.tt_matvec(eye, xc), xc):
         assert np.array_equal(a, b)
+
+
+def test_tt_matmat_dense_product_and_matvec():
+    """The TT-format matrix product equals the dense product of the dense
+    matrices; with a one-column right factor it is the matvec."""
+    import oracle
+    rng = np.random.default_rng(6)
+    ms, ns, ls, ra, rb = [2, 3, 2], [3, 2, 2], [2, 1, 3], [1, 2, 3, 1], [1, 3, 2, 1]
+    A = [rng.standard_normal((ra[k], ms[k], ns[k], ra[k + 1])) for k in range(3)]
+    B = [rng.standard_normal((rb[k], ns[k], ls[k], rb[k + 1])) for k in range(3)]
+    Cc = oracle.tt_matmat(A, B)
+    assert [c.shape for c in Cc] == [(1, 2, 2, 6), (6, 3, 1, 6), (6, 2, 3, 1)]
+    np.testing.assert_allclose(oracle.ttm_full(Cc), oracle.ttm_full(A) @ oracle.ttm_full(B), rtol=1e-12, atol=1e-12)
+    x = [rng.standard_normal((rb[k], ns[k], rb[k + 1])) for k in range(3)]
+    as_mat = oracle.tt_matmat(A, [c.reshape(c.shape[0], c.shape[1], 1, c.shape[2]) for c in x])
+    for a, b in zip(as_mat, oracle.tt_matvec(A, x)):
+        np.testing.assert_array_equal(a[:, :, 0, :], b)
