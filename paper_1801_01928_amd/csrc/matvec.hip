@@ -8,8 +8,9 @@
 // Details: the TT-matrix by TT-vector product; Table 1 times it as matvec).
 // No rounding: the product is exact and its ranks multiply.  Every output
 // element is one n_k-term sum over W_k and x_k, which are small and stay in
-// the caches; the bytes that must move are those of y.  This kernel gathers
-// both factors per lane, which, not the bytes, limits it.
+// the caches; the bytes that must move are those of y.  The LDS path stages
+// both factors' slices per workgroup; the grid-stride fallback gathers them
+// per lane.
 #include "common.h"
 
 namespace ttgfx {
@@ -67,6 +68,71 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, RightDev X
     for (int j = 0; j < nk; ++j) acc = fmaf(wk[(long long)j * r1], xk[j * xs], acc);
     yk[e] = acc;
   }
+}
+
+// LDS path: one workgroup per (a, i, l) of core k and member blockIdx.z.
+// W_k[a, i, :, :] (n_k x r_{k+1}) and the l-slice of the right factor's
+// core (s_k x n_k x s_{k+1}) are staged in LDS once; the workgroup then
+// writes the s_k rows (a, b) at (i, l), each a contiguous run of
+// r_{k+1} s_{k+1} elements.  The host takes this path when both slices fit
+// in kMvLdsFloats for every core.
+constexpr int kMvLdsFloats = 16384;  // 64 KB of dynamic LDS
+__global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev W, RightDev X0, OutDev Y0, MvIO io) {
+  extern __shared__ float lds[];
+  const int k = blockIdx.y;
+  const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
+  const int mk = W.m[k], nk = W.n[k], lk = X0.L[k];
+  const unsigned pairs = (unsigned)r0 * mk * lk;
+  if (blockIdx.x >= pairs) return;  // uniform over the workgroup, before any barrier
+  const unsigned t = blockIdx.x / lk, l = blockIdx.x - t * lk;
+  const unsigned a = t / mk, i = t - a * mk;
+  float *ws = lds, *xs = lds + nk * r1;
+  const float *wsrc = W.data + W.off[k] + ((long long)a * mk + i) * nk * r1;
+  for (int e = threadIdx.x; e < nk * r1; e += kMvThreads) ws[e] = wsrc[e];
+  const float *xm = io.x[blockIdx.z] + X0.off[k];
+  const int xn = s0 * nk * s1;
+  for (int e = threadIdx.x; e < xn; e += kMvThreads) {
+    const int bp = e % s1, u = e / s1;  // u = b n_k + j
+    xs[e] = xm[((long long)u * lk + l) * s1 + bp];
+  }
+  __syncthreads();
+  const int R1 = r1 * s1;
+  float *yk = io.y[blockIdx.z] + Y0.off[k];
+  for (int o = threadIdx.x; o < s0 * R1; o += kMvThreads) {
+    const int b = o / R1, col = o - b * R1;
+    const int ap = col / s1, bp = col - ap * s1;
+    const float *xb = xs + b * nk * s1 + bp;
+    float acc = 0.f;
+    for (int j = 0; j < nk; ++j) acc = fmaf(ws[j * r1 + ap], xb[j * s1], acc);
+    const long long row = (long long)a * s0 + b;
+    yk[((row * mk + i) * lk + l) * R1 + col] = acc;
+  }
+}
+
+// Launches the product kernels for `members` right factors: the LDS path
+// when every core's two slices fit, else the grid-stride kernel.
+int launch_products(const MatDev &md, const RightDev &x0, const OutDev &y0, const MvIO &io, int members,
+                    hipStream_t s) {
+  long long maxcnt = 0, maxpairs = 0, maxlds = 0;
+  for (int k = 0; k < md.d; ++k) {
+    const long long r0 = md.r[k], r1 = md.r[k + 1], s0 = x0.r[k], s1 = x0.r[k + 1];
+    const long long c = r0 * s0 * md.m[k] * x0.L[k] * r1 * s1;
+    const long long p = r0 * md.m[k] * x0.L[k];
+    const long long f = (long long)md.n[k] * r1 + s0 * md.n[k] * s1;
+    maxcnt = c > maxcnt ? c : maxcnt;
+    maxpairs = p > maxpairs ? p : maxpairs;
+    maxlds = f > maxlds ? f : maxlds;
+  }
+  if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "product: an output core of 2^31 or more elements");
+  if (maxlds <= kMvLdsFloats && maxpairs <= 0x7fffffffLL) {
+    hipLaunchKernelGGL(matvec_lds_kernel, dim3((unsigned)maxpairs, (unsigned)md.d, (unsigned)members),
+                       dim3(kMvThreads), (size_t)maxlds * sizeof(float), s, md, x0, y0, io);
+  } else {
+    const long long gx = (maxcnt + (long long)kMvThreads * kMvPerThread - 1) / ((long long)kMvThreads * kMvPerThread);
+    hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)gx, (unsigned)md.d, (unsigned)members), dim3(kMvThreads), 0,
+                       s, md, x0, y0, io);
+  }
+  return launch_check("TT-matrix product");
 }
 
 int validate_matrix(const tt_matrix *W, MatDev *md) {
@@ -140,13 +206,6 @@ extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, voi
     y0.off[k] = core_off(&Y->tt[0], k);
   }
   x0.r[md.d] = 1;
-  long long maxcnt = 0;
-  for (int k = 0; k < md.d; ++k) {
-    const long long c = core_elems(&Y->tt[0], k);
-    maxcnt = c > maxcnt ? c : maxcnt;
-  }
-  const long long gx = (maxcnt + (long long)kMvThreads * kMvPerThread - 1) / ((long long)kMvThreads * kMvPerThread);
-  if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "matvec: an output core of 2^31 or more elements");
   for (int j0 = 0; j0 < X->b; j0 += kMvBatch) {
     const int m = (X->b - j0) < kMvBatch ? (X->b - j0) : kMvBatch;
     MvIO io{};
@@ -154,9 +213,7 @@ extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, voi
       io.x[j] = X->tt[j0 + j].data;
       io.y[j] = Y->tt[j0 + j].data;
     }
-    hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)gx, (unsigned)md.d, (unsigned)m), dim3(kMvThreads), 0,
-                       (hipStream_t)stream, md, x0, y0, io);
-    if ((rc = launch_check("matvec"))) return rc;
+    if ((rc = launch_products(md, x0, y0, io, m, (hipStream_t)stream))) return rc;
   }
   return TT_OK;
 }
@@ -164,7 +221,7 @@ extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, voi
 // C = A B for two TT-matrices (A: m x n modes, B: n x l modes): the cores
 // C_k[(a, b), i, l, (a', b')] = sum_j A_k[a, i, j, a'] B_k[b, j, l, b'].
 extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, void *stream) {
-  MatDev ma, mb, mc;
+  MatDev ma, mb;
   int rc;
   if ((rc = validate_matrix(A, &ma)) || (rc = validate_matrix(B, &mb))) return rc;
   if (!Cm) return set_error(TT_ERR_ARG, "C: null descriptor");
@@ -180,7 +237,7 @@ extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, 
       return set_error(TT_ERR_SHAPE, "C: r[%d] = %d, expected %d", k, Cm->r[k], A->r[k] * B->r[k]);
   RightDev x0{};
   OutDev y0{};
-  long long oc = 0, maxcnt = 0;
+  long long oc = 0;
   for (int k = 0; k < A->d; ++k) {
     if (Cm->off && Cm->off[k] < 0) return set_error(TT_ERR_ARG, "C: negative offset for core %d", k);
     x0.r[k] = B->r[k];
@@ -189,15 +246,10 @@ extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, 
     y0.off[k] = Cm->off ? Cm->off[k] : oc;
     const long long c = (long long)Cm->r[k] * Cm->m[k] * Cm->n[k] * Cm->r[k + 1];
     oc += c;
-    maxcnt = c > maxcnt ? c : maxcnt;
   }
   x0.r[A->d] = 1;
-  if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "matmat: an output core of 2^31 or more elements");
-  const long long gx = (maxcnt + (long long)kMvThreads * kMvPerThread - 1) / ((long long)kMvThreads * kMvPerThread);
   MvIO io{};
   io.x[0] = mb.data;
   io.y[0] = (float *)Cm->data;
-  hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)gx, (unsigned)ma.d, 1u), dim3(kMvThreads), 0,
-                     (hipStream_t)stream, ma, x0, y0, io);
-  return launch_check("matmat");
+  return launch_products(ma, x0, y0, io, 1, (hipStream_t)stream);
 }

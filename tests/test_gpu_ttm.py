@@ -189,6 +189,7 @@ MATVEC_CASES = [
     (41, [7], [5], [1, 1], [1, 1], 2),                              # d = 1: a dense matvec
     (42, [3, 2, 2], [2, 2, 3], [1, 2, 2, 1], [1, 2, 3, 1], 65),     # two launches of 64 + 1
     (43, [10] * 10, [10] * 10, [1] + [10] * 9 + [1], [1] + [10] * 9 + [1], 2),  # d=10, rank 10 x 10
+    (46, [3, 3, 3], [8, 8, 8], [1, 2, 2, 1], [1, 64, 64, 1], 2),   # x core 64x8x64: beyond LDS, grid-stride path
 ]
 
 
