@@ -381,10 +381,14 @@ def matvec_leg(tt, W, reps=5):
     tt.tt_matmat(Wm, W2)
     torch.cuda.synchronize()
     mm_ms = _event_ms(lambda: tt.tt_matmat(Wm, W2), reps)
+    # norms of the 100 rank-10 vectors
+    tt.norms(xs)
+    torch.cuda.synchronize()
+    nrm_ms = _event_ms(lambda: tt.norms(xs), reps)
     return {"workload": "y_j = W x_j in TT format, W 10^10 x 10^10 (d=10, modes 10x10, rank 10), 100 TT vectors "
                         "of rank 10, outputs of rank 100", "ms": round(ms, 4), "bytes": nbytes,
             "gb_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / 8000.0, 3),
-            "matmat_ms": round(mm_ms, 4)}
+            "matmat_ms": round(mm_ms, 4), "norms_100_rank10_ms": round(nrm_ms, 4)}
 
 
 def ttm_leg(tt, W, reps=3):

@@ -382,6 +382,11 @@ int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, void *stream);
  *   C_k[(a, b), i, l, (a', b')] = sum_j A_k[a, i, j, a'] B_k[b, j, l, b'],
  * bond index a r^B_k + b.  Every element is written; no workspace. */
 int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *C, void *stream);
+/* Frobenius norms of a batch of TT tensors (Table 1's norm): out (dev, [b])
+ * receives ||A_j|| = sqrt(<A_j, A_j>), by the chain of r_k x r_k
+ * interface matrices.  A: b >= 1 TTs of one shape and one set of core
+ * offsets, ranks up to TT_MAX_RANK.  No workspace. */
+int tt_norms(const tt_batch *A, float *out, void *stream);
 
 /* ---------------------------------------------------------------- misc */
 const char *tt_last_error(void);   /* thread-local message of the last failure */

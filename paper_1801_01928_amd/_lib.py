@@ -104,6 +104,7 @@ SIGNATURES = {
     "tt_matmul": (C.c_int, [P_TTM, VP, I64, VP, C.c_int, VP, SZ, VP]),
     "tt_matvec": (C.c_int, [P_TTM, P_BATCH, P_BATCH, VP]),
     "tt_matmat": (C.c_int, [P_TTM, P_TTM, P_TTM, VP]),
+    "tt_norms": (C.c_int, [P_BATCH, VP, VP]),
     "tt_matmul_backward": (C.c_int, [P_TTM, VP, I64, VP, VP, VP, C.c_int, VP, SZ, VP]),
     "tt_timer_start": (C.c_int, []),
     "tt_timer_stop": (C.c_int, [C.POINTER(C.c_float), PI32]),

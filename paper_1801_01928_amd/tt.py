@@ -382,6 +382,15 @@ def tangent_inner(U, A, B):
     return out
 
 
+def norms(As):
+    """Frobenius norms of TT tensors of one shape (tt_norms), as a device
+    tensor of len(As) floats."""
+    A, keep = _batch(As)
+    out = torch.empty(len(As), dtype=torch.float32, device=As[0].device)
+    L.check(L.load().tt_norms(C.byref(A), _ptr(out), _stream(As[0].device)))
+    return out
+
+
 def tangent_gram(U, As):
     """Gram matrix G[i][j] = <As[i], As[j]> of tangent TTs at the point with
     left sweep U (tt_tangent_gram), as a (b, b) device tensor."""

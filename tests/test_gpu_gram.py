@@ -61,3 +61,26 @@ def test_gram_batched_workload_sampled(gpu_lib):
         ref = oracle.inner(cores[a], cores[b])
         assert abs(G[a, b] - ref) <= 1e-5 * np.sqrt(diag[a] * diag[b])
     assert np.array_equal(G, G.T)
+
+
+NORM_CASES = [
+    # (seed, ns, ranks, members)
+    (50, [7], [1, 1], 3),                                   # d = 1
+    (51, [5, 7, 3, 9, 4], [1, 3, 11, 6, 2, 1], 70),         # ragged; two launches of 64 + 6
+    (52, [4, 4, 4], [1, 4, 64, 1], 2),                      # rank 64 (the limit)
+    (53, [10] * 10, [1] + [10] * 9 + [1], 100),             # d=10, rank 10, batch 100
+]
+
+
+@pytest.mark.parametrize("case", range(len(NORM_CASES)))
+def test_norms_match_oracle(gpu_lib, case):
+    """tt_norms against the oracle's norm (exact inner product in FP64),
+    relative 1e-4: fp32 sums along d steps of r-term products."""
+    tt = gpu_lib
+    seed, ns, ranks, b = NORM_CASES[case]
+    print("norms", ns, ranks, b, flush=True)
+    rng = np.random.default_rng(seed)
+    As = [W.random_cores(rng, ns, ranks, 1.0 / np.sqrt(max(ranks))) for _ in range(b)]
+    got = tt.norms([tt.TT.from_cores(a) for a in As]).cpu().numpy().astype(np.float64)
+    want = np.array([oracle.norm(a) for a in As])
+    assert np.all(np.abs(got - want) <= 1e-4 * want)
