@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import adjoint_bound, assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -47,20 +48,26 @@ def _oracle(insts):
     out = []
     for cores, idx, t in insts:
         if idx.shape[1] == 0:
-            out.append((0.0, [np.zeros(c.shape) for c in cores]))
+            out.append((0.0, [np.zeros(c.shape) for c in cores], [np.zeros(c.shape) for c in cores]))
             continue
         y = oracle.gather(cores, idx)
         loss, g = oracle.mse_loss_and_grad(y, t)
-        out.append((loss, oracle.gather_backward(cores, idx, g)))
+        out.append((loss, oracle.gather_backward(cores, idx, g), adjoint_bound(cores, cores, idx, g)))
     return out
 
 
 def _check(plan, ref):
+    """Per tensor: the loss (1e-5 relative), each core normwise (1e-5) and
+    each gradient element within 1e-5 of its absolute-value bound."""
     loss = plan.loss.cpu().numpy()
-    for j, (lr, gr) in enumerate(ref):
+    for j, item in enumerate(ref):
+        lr, gr = item[0], item[1]
         assert abs(loss[j] - lr) <= TOL * max(lr, 1e-30), (j, loss[j], lr)
-        for k, c in enumerate(plan.grads[j].numpy_cores()):
+        got = plan.grads[j].numpy_cores()
+        for k, c in enumerate(got):
             assert _rel(c, gr[k]) <= TOL, (j, k, _rel(c, gr[k]))
+            if len(item) > 2:
+                assert_elementwise(c, gr[k], item[2][k], TOL, "tensor %d core %d" % (j, k))
 
 
 def test_batched_and_plain_match_oracle(gpu_lib):
@@ -137,14 +144,22 @@ def test_batched_workload_256(gpu_lib):
     for j in range(len(inst)):
         assert abs(loss_b[j] - loss_p[j]) <= TOL * loss_p[j]
         assert _rel(grads_b[j], plan.grads[j].data.cpu().numpy()) <= TOL, j
+    # against the oracle: the three smallest tensors, the largest, and for
+    # every rank the tensor of median entry count among that rank's tensors
     by_m = sorted(range(len(inst)), key=lambda j: inst[j].M)
-    r32 = [j for j in by_m if inst[j].meta["rank"] == 32][:1]
-    for j in by_m[:3] + r32:
+    picks = by_m[:3] + by_m[-1:]
+    for r in (4, 8, 16, 32):
+        of_r = [j for j in by_m if inst[j].meta["rank"] == r]
+        picks.append(of_r[len(of_r) // 2])
+    for j in picks:
         cores, i, tj = packed[j]
+        print("oracle check: tensor %d, rank %d, %d entries" % (j, inst[j].meta["rank"], inst[j].M), flush=True)
         y = oracle.gather(cores, i)
         lr, g = oracle.mse_loss_and_grad(y, tj)
         gr = oracle.gather_backward(cores, i, g)
         assert abs(loss_b[j] - lr) <= TOL * lr
         flat = np.concatenate([x.reshape(-1) for x in gr])
         assert _rel(grads_b[j], flat) <= TOL, j
+        bound = np.concatenate([x.reshape(-1) for x in adjoint_bound(cores, cores, i, g)])
+        assert_elementwise(grads_b[j], flat, bound, TOL, "tensor %d" % j)
     plan.close()

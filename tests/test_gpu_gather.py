@@ -1,10 +1,14 @@
 """GPU parity of the gather, its adjoint and the fused MSE pass against the
-FP64 oracle (tolerances: 1e-5 relative, normwise)."""
+FP64 oracle: 1e-5 relative normwise, and every element within 1e-5 of its
+absolute-value bound (each entry against the product of its absolute
+slices, each gradient element against the sum of |w| |L| |R| over its
+entries)."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
+from parity import assert_adjoint, assert_elementwise, assert_gather, adjoint_bound, gather_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -59,11 +63,13 @@ def test_gather_and_backward_parity(gpu_lib, case):
     y = tt.gather(X, idx).cpu().numpy()
     yr = oracle.gather(cores, idx)
     assert _rel(y, yr) <= TOL
+    assert_gather(y, yr, cores, idx, TOL)
     gX = tt.gather_backward(X, idx, torch.from_numpy(g))
     gr = oracle.gather_backward(cores, idx, g)
     got = gX.numpy_cores()
     for k in range(len(ns)):
         assert _rel(got[k], gr[k]) <= TOL, (k, _rel(got[k], gr[k]))
+    assert_adjoint(got, gr, cores, cores, idx, g, TOL)
 
 
 def test_empty_entries(gpu_lib):
@@ -93,6 +99,7 @@ def test_duplicates_and_repeatability(gpu_lib):
     gr = oracle.gather_backward(cores, idx, g)
     for k, c in enumerate(a.numpy_cores()):
         assert _rel(c, gr[k]) <= TOL
+    assert_adjoint(a.numpy_cores(), gr, cores, cores, idx, g, TOL)
 
 
 @pytest.mark.parametrize("M", [4096, 100003])
@@ -105,10 +112,12 @@ def test_fused_mse_parity(gpu_lib, M):
     yr = oracle.gather(p.cores, p.idx)
     lr, gr = oracle.mse_loss_and_grad(yr, t)
     assert _rel(y.cpu().numpy(), yr) <= TOL
+    assert_gather(y.cpu().numpy(), yr, p.cores, p.idx, TOL)
     assert abs(float(loss.item()) - lr) <= TOL * lr
     grr = oracle.gather_backward(p.cores, p.idx, gr)
     for k, c in enumerate(gX.numpy_cores()):
         assert _rel(c, grr[k]) <= TOL, k
+    assert_adjoint(gX.numpy_cores(), grr, p.cores, p.cores, p.idx, gr, TOL, "fused MSE")
 
 
 def test_autograd_function(gpu_lib):
@@ -122,6 +131,8 @@ def test_autograd_function(gpu_lib):
     gr = oracle.gather_backward(cores, idx, g)
     flat = np.concatenate([x.reshape(-1) for x in gr])
     assert _rel(X.data.grad.cpu().numpy(), flat) <= TOL
+    bound = np.concatenate([x.reshape(-1) for x in adjoint_bound(cores, cores, idx, g)])
+    assert_elementwise(X.data.grad.cpu().numpy(), flat, bound, TOL, "autograd")
 
 
 @pytest.fixture(scope="module")
@@ -132,28 +143,32 @@ def full_d10():
     yr = oracle.gather(p.cores, p.idx)
     lr, gr = oracle.mse_loss_and_grad(yr, t)
     grads = oracle.gather_backward(p.cores, p.idx, gr)
-    return p, t, yr, lr, grads
+    ybound = gather_bound(p.cores, p.idx)
+    gbound = adjoint_bound(p.cores, p.cores, p.idx, gr)
+    return p, t, yr, lr, grads, ybound, gbound
 
 
 def test_full_size_d10_r16(gpu_lib, full_d10):
     """Full size (2^20 entries) in the launch configuration the benchmark
     times: every output compared with the oracle."""
     tt = gpu_lib
-    p, t, yr, lr, grads = full_d10
+    p, t, yr, lr, grads, ybound, gbound = full_d10
     print("full d10 r16 M=2^20", flush=True)
     X = tt.TT.from_cores(p.cores)
     y, loss, gX = tt.gather_mse_backward(X, p.idx, t)
     assert _rel(y.cpu().numpy(), yr) <= TOL
+    assert_elementwise(y.cpu().numpy(), yr, ybound, TOL, "y")
     assert abs(float(loss.item()) - lr) <= TOL * lr
     for k, c in enumerate(gX.numpy_cores()):
         assert _rel(c, grads[k]) <= TOL, (k, _rel(c, grads[k]))
+        assert_elementwise(c, grads[k], gbound[k], TOL, "core %d" % k)
 
 
 def test_full_size_finite_differences(gpu_lib, full_d10):
     """64 random core entries: exact central differences of the FP64 loss
     agree with the GPU gradient."""
     tt = gpu_lib
-    p, t, yr, lr, grads = full_d10
+    p, t, yr, lr, grads, ybound, gbound = full_d10
     X = tt.TT.from_cores(p.cores)
     _, _, gX = tt.gather_mse_backward(X, p.idx, t)
     got = np.concatenate([c.reshape(-1) for c in gX.numpy_cores()])
@@ -186,7 +201,12 @@ def test_full_size_finite_differences(gpu_lib, full_d10):
         fd.append((vals[0] - vals[1]) / (2 * h))
         an.append(gsub[j])
     assert _rel(an, fd) <= 1e-8          # the oracle gradient is exact
-    assert _rel(got[pick], np.concatenate([c.reshape(-1) for c in grads])[pick]) <= 1e-4
+    ref = np.concatenate([c.reshape(-1) for c in grads])
+    bnd = np.concatenate([c.reshape(-1) for c in gbound])
+    assert _rel(got[pick], ref[pick]) <= TOL
+    # each picked entry on its own, against the full-set oracle gradient
+    for j in pick:
+        assert abs(got[j] - ref[j]) <= TOL * bnd[j], (int(j), got[j], ref[j], bnd[j])
 
 
 def test_fused_pass_graph_replays(gpu_lib):
@@ -233,6 +253,7 @@ def test_fused_pass_graph_replays(gpu_lib):
         got = tt.TT(ns, ranks, gX.data).numpy_cores()
         for a, b in zip(got, ref):
             assert _rel(a, b) <= TOL
+        assert_adjoint(got, ref, cores, cores, p.idx, g, TOL, "replay %d" % rep)
 
 
 RANK64_CASES = [
@@ -256,4 +277,6 @@ def test_gather_rank64_class(gpu_lib, case):
     idx = W.random_indices(rng, ns, M)
     X = tt.TT.from_cores(cores)
     y = tt.gather(X, torch.as_tensor(idx).cuda()).cpu().numpy()
-    assert _rel(y, oracle.gather(cores, idx)) <= TOL
+    yr = oracle.gather(cores, idx)
+    assert _rel(y, yr) <= TOL
+    assert_gather(y, yr, cores, idx, TOL)

@@ -8,8 +8,74 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import absolute, assert_elementwise, gather_bound
 
 pytestmark = pytest.mark.gpu
+
+
+def tangent_blocks(Wc, ranks):
+    """Blocks of an assembled tangent TT (ranks 2r): per core the alpha*dG
+    block, and the U and V blocks where the core has them.  Layout: W_1 =
+    [alpha dG_1, U_1]; W_k = [[V_k, 0], [alpha dG_k, U_k]];
+    W_d = [[V_d], [beta S_d + alpha dG_d]]."""
+    d = len(Wc)
+    out = []
+    for k, c in enumerate(Wc):
+        c = np.asarray(c, np.float64)
+        r0, r1 = ranks[k], ranks[k + 1]
+        if k == 0:
+            out.append({"dG": c[:, :, :r1], "U": c[:, :, r1:]})
+        elif k == d - 1:
+            out.append({"V": c[:r0], "dG": c[r0:]})
+        else:
+            out.append({"V": c[:r0, :, :r1], "dG": c[r0:, :, :r1], "U": c[r0:, :, r1:], "zero": c[:r0, :, r1:]})
+    return out
+
+
+def tangent_core_bounds(U, V, idx, z, alpha):
+    """Per element of alpha*dG_k: |alpha| (|Zhat|_abs + |U_k| (|U_k|^T |Zhat|_abs)),
+    where |Zhat|_abs is the sparse contraction over |U|, |V| and |z| (the sum
+    of the absolute terms of Zhat, then of the gauge fix dG = Zhat - U U^T Zhat)."""
+    Za = oracle.sparse_adjoint(absolute(U), absolute(V), idx, np.abs(np.asarray(z, np.float64)))
+    out = []
+    d = len(U)
+    for k in range(d):
+        if k < d - 1:
+            r0, n, r1 = U[k].shape
+            UL = np.abs(np.asarray(U[k], np.float64)).reshape(r0 * n, r1)
+            ZL = Za[k].reshape(r0 * n, r1)
+            out.append(abs(alpha) * (ZL + UL @ (UL.T @ ZL)).reshape(r0, n, r1))
+        else:
+            out.append(abs(alpha) * Za[k])
+    return out
+
+
+def assert_tangent_elementwise(Wg, ref, idx, z, alpha, beta, tol=1e-4):
+    """Element-by-element comparison of an assembled tangent TT with the
+    oracle's: the alpha*dG blocks within ``tol`` of their absolute-value
+    bounds (plus, in the last core with beta != 0, tol times the largest
+    element of S_d), the orthonormal U and V blocks within ``tol``
+    absolutely (their columns have unit norm), the zero blocks exactly zero."""
+    Wr, Uo, Vo, dGo = ref
+    ranks = oracle.ranks_of(Uo)
+    bounds = tangent_core_bounds(Uo, Vo, idx, z, alpha)
+    gb = tangent_blocks(Wg, ranks)
+    rb = tangent_blocks(Wr, ranks)
+    d = len(Wg)
+    for k in range(d):
+        g, r = gb[k], rb[k]
+        bd = bounds[k]
+        if k == d - 1 and beta != 0.0:
+            # beta S_d + alpha dG_d: the part of S_d (the last core of the
+            # left-to-right sweep) is held to tol times its largest element
+            bd = bd + abs(beta) * float(np.abs(np.asarray(Uo[k], np.float64)).max())
+        assert_elementwise(g["dG"], r["dG"], bd, tol, "dG block of core %d" % k)
+        for key in ("U", "V"):
+            if key in g:
+                err = float(np.abs(g[key] - r[key]).max())
+                assert err <= tol, (k, key, err)
+        if "zero" in g:
+            assert not np.any(g["zero"]), k
 
 
 def rel_tt(A, B):
@@ -143,8 +209,9 @@ def test_project_sparse(gpu_lib, case, alpha, add_x):
     U = tt.orthogonalize(X, tt.TT_LR)
     V = tt.orthogonalize(X, tt.TT_RL)
     Wg = tt.project_sparse(U, V, idx, z, alpha=alpha, add_x=add_x)
-    Wr = oracle.project_sparse(cores, idx, z, alpha=alpha, beta=float(add_x))[0]
-    assert rel_tt(Wg.numpy_cores(), Wr) <= 1e-4
+    ref = oracle.project_sparse(cores, idx, z, alpha=alpha, beta=float(add_x))
+    assert rel_tt(Wg.numpy_cores(), ref[0]) <= 1e-4
+    assert_tangent_elementwise(Wg.numpy_cores(), ref, idx, z, alpha, float(add_x))
 
 
 def test_completion_step_small(gpu_lib):
@@ -202,3 +269,39 @@ def test_riemann_d10_full_size_properties(gpu_lib):
     err2 = oracle.inner(oracle.add(Wc, oracle.scale(Yc, -1.0)), oracle.add(Wc, oracle.scale(Yc, -1.0)))
     assert abs(err2 - float(disc.double().sum())) <= 1e-3 * err2 + 1e-5 * oracle.inner(Wc, Wc)
     assert _orth_err(Yc[:-1], True) <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def riemann_full():
+    """The d=10, n=10, canonical rank-32 workload at 2^20 entries and the
+    oracle's retraction input X - 0.1 P_X(Z) (with U, V and dG)."""
+    p = W.riemann_d10()
+    ref = oracle.project_sparse([c.astype(np.float64) for c in p.cores], p.idx, p.values, alpha=-0.1, beta=1.0)
+    return p, ref
+
+
+@pytest.mark.timeout(900)
+def test_riemann_d10_full_size_oracle(gpu_lib, riemann_full):
+    """Full size against the oracle's projection, in the launch
+    configuration the benchmark times: the exact TT-difference norm of the
+    retraction input X - 0.1 P_X(Z) (1e-4), every tangent core element
+    within 1e-4 of its absolute-value bound, and the values at a seeded
+    sample of 2^17 observed entries plus 4096 uniform probes (1e-4 normwise
+    and per entry against the product of the absolute slices)."""
+    tt = gpu_lib
+    p, ref = riemann_full
+    print("riemann d10 r32 M=2^20 against the oracle", flush=True)
+    X = tt.TT.from_cores(p.cores)
+    U, V = tt.orthogonalize_both(X)
+    Wg = tt.project_sparse(U, V, p.idx, p.values, alpha=-0.1, add_x=1).numpy_cores()
+    Wr = ref[0]
+    assert [c.shape for c in Wg] == [c.shape for c in Wr]
+    assert rel_tt(Wg, Wr) <= 1e-4
+    assert_tangent_elementwise(Wg, ref, p.idx, p.values, -0.1, 1.0)
+    rng = np.random.default_rng(33)
+    sample = np.sort(rng.choice(p.M, size=1 << 17, replace=False))
+    probes = np.concatenate([p.idx[:, sample], W.random_indices(rng, p.ns, 4096)], axis=1)
+    vg = oracle.gather(Wg, probes)
+    vr = oracle.gather(Wr, probes)
+    assert np.linalg.norm(vg - vr) <= 1e-4 * np.linalg.norm(vr)
+    assert_elementwise(vg, vr, gather_bound(Wr, probes), 1e-4, "tangent values")

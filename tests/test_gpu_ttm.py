@@ -13,6 +13,7 @@ import torch
 
 import oracle
 import workloads as W
+from parity import assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -155,12 +156,19 @@ def test_ttm_layer_full_size(gpu_lib):
     assert rel(Y, rY) <= 1e-5
     rdX, rdG = oracle.ttm_backward(p.X, p.cores, p.dY)
     assert rel(dX.cpu().numpy(), rdX) <= 1e-5
+    # absolute-value sums of the same products bound every element
+    aX, aC, adY = np.abs(p.X), [np.abs(c) for c in p.cores], np.abs(p.dY)
+    bY = oracle.ttm_forward(aX, aC)
+    bdX, bdG = oracle.ttm_backward(aX, aC, adY)
+    assert_elementwise(Y, rY, bY, 1e-5, "Y")
+    assert_elementwise(dX.cpu().numpy(), rdX, bdX, 1e-5, "dX")
     got = tt.TTMatrix(p.row_modes, p.col_modes, p.ranks, dG).numpy_cores()
     L0 = float(np.sum(p.dY.astype(np.float64) * rY))
     for k, (g, r) in enumerate(zip(got, rdG)):
-        assert rel(g, r) <= 1e-4, k
+        assert rel(g, r) <= 1e-5, (k, rel(g, r))
+        assert_elementwise(g, r, bdG[k], 1e-5, "dG core %d" % k)
         euler = float(np.sum(g.astype(np.float64) * p.cores[k]))
-        assert abs(euler - L0) <= 1e-4 * np.linalg.norm(g) * np.linalg.norm(p.cores[k])
+        assert abs(euler - L0) <= 1e-5 * np.linalg.norm(g) * np.linalg.norm(p.cores[k])
 
 
 def test_ttm_layer_full_size_bf16(gpu_lib):
