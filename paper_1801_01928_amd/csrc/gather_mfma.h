@@ -6,31 +6,22 @@ namespace ttgfx {
 
 #define MF_MAX_D 16
 
-// Per rank class: entries per tile, largest mode size, permutation capacity.
+// Per rank class: largest mode size (slice values per sort count row).
 template <int R>
 struct MfTraits;
 template <>
 struct MfTraits<16> {
-  static constexpr int T = 1024;
-  static constexpr int THREADS = 768;
   static constexpr int MAX_N = 16;
-  static constexpr int PERM_CAP = 16384;
 };
 template <>
 struct MfTraits<32> {
-  static constexpr int T = 512;
-  static constexpr int THREADS = 512;
   static constexpr int MAX_N = 32;
-  static constexpr int PERM_CAP = 16384;
 };
 // Gather only (no adjoint): ranks 33..64, e.g. tangent vectors of rank-32
-// points; entry rows of 68 floats keep the tile at 256 entries.
+// points.
 template <>
 struct MfTraits<64> {
-  static constexpr int T = 256;
-  static constexpr int THREADS = 512;
   static constexpr int MAX_N = 16;
-  static constexpr int PERM_CAP = 8192;
 };
 
 // One tensor of the slice-grouped kernels (kernel argument or batch table).
@@ -54,6 +45,8 @@ struct MfInst {
 };
 
 #define MF_BATCH_THREADS 512
+#define MF_BATCH_T16 1024  // entries per tile of the batched kernel, rank class 16
+#define MF_BATCH_T32 512   // and rank class 32
 
 // Work item of the batched kernel: `ntile` consecutive tiles of one tensor.
 struct MfWorkItem {
@@ -73,9 +66,9 @@ struct MfBatchArgs {
   int nb16, nb32;          // blocks-per-mode capacities of the two classes
 };
 
-size_t mfma_batch_lds();
+size_t mfma_batch_lds(int d, const int *n);  // LDS bytes of the batched kernel for these modes
 int mfma_batch_prepare();
-int mfma_batch_launch(const MfBatchArgs &a, int nwg, hipStream_t s);
+int mfma_batch_launch(const MfBatchArgs &a, int nwg, size_t lds, hipStream_t s);
 int mfma_device_cus();
 
 // True when every descriptor fits the MFMA kernels (2 <= d <= 16, ranks <= 32,

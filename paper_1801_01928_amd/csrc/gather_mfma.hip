@@ -34,6 +34,8 @@
 // The per-tile work is one device function shared by the single-tensor
 // kernel (tiles in grid-stride order) and the batched persistent kernel
 // (work items from an atomic queue).
+#include <stdlib.h>
+
 #include <type_traits>
 
 #include "common.h"
@@ -42,6 +44,15 @@
 namespace ttgfx {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int a16(int x) { return (x + 15) & ~15; }
+
+enum { ACC_SLAB = 0, ACC_DIRECT = 1 };
+
+// Byte offsets of the LDS regions of one tile (see mf_layout).
+struct MfLayout {
+  int rows, slab, edges, sflag, wsum, perm, bslc, nblk, total, nmax;
+};
 
 namespace {
 
@@ -60,7 +71,6 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 enum { MODE_GATHER = 0, MODE_ADJOINT = 1, MODE_MSE = 2 };
-enum { ACC_SLAB = 0, ACC_DIRECT = 1 };
 
 template <int T>
 __device__ __forceinline__ int pbase_of(const MfInst &p, int k) {
@@ -76,30 +86,45 @@ __device__ __forceinline__ int bbase_of(const MfInst &p, int k) {
   return s;
 }
 
-// LDS layout (bytes), in this order:
+// LDS layout (bytes), in this order, sized for the tensor's d and mode sizes:
 //   rows   float [T + 2][R + 4]  (row T: zeros, row T+1: write sink)
-//   slab   float [MAX_N][R][R + 4]    (SLAB: per-slice sums)
+//   slab   float [nmax][R][R + 4]     (SLAB: per-slice sums)
 //   edges  float [waves][R][R + 4]    (SLAB: runs continuing the previous wave's slice)
-//   sflag  int   [MAX_N + 16]         (SLAB: slice has a stored run; edge slice ids)
+//   sflag  int   [nmax + 16]          (SLAB: slice has a stored run; edge slice ids)
 //   wsum   float [T + 2]              (per-entry weight g_e; [T] = 0)
-//   perm   uint16 [PERM_CAP]
-//   bslc   uint8  [PERM_CAP / 16 + d]
+//   perm   uint16 [sum_k (T + 16 n_k)]
+//   bslc   uint8  [sum_k ((T + 16 n_k) / 16 + 1)]
 //   nblk   int   [MF_MAX_D]
-template <int R, int T, int NTHR, int ACC>
-struct Lds {
-  static constexpr int NMAX = (ACC == ACC_SLAB) ? MfTraits<R>::MAX_N : 0;
-  static constexpr int PCAP = MfTraits<R>::PERM_CAP;
-  static constexpr size_t rows = 0;
-  static constexpr size_t slab = rows + (sizeof(float) * (T + 2) * (R + 4) + 15) / 16 * 16;
-  static constexpr size_t edges = slab + sizeof(float) * NMAX * R * (R + 4);
-  static constexpr size_t sflag = edges + (ACC == ACC_SLAB ? sizeof(float) * (NTHR / 64) * R * (R + 4) : 0);
-  static constexpr size_t wsum = sflag + (ACC == ACC_SLAB ? sizeof(int) * (NMAX + 16) : 0);
-  static constexpr size_t perm = wsum + (sizeof(float) * (T + 2) + 15) / 16 * 16;
-  static constexpr size_t bslc = perm + sizeof(uint16_t) * PCAP;
-  static constexpr size_t nblk = bslc + (PCAP / 16 + MF_MAX_D + 16) / 16 * 16;
-  static constexpr size_t total = nblk + sizeof(int) * MF_MAX_D + 64;
-  static_assert(total <= 160 * 1024, "LDS budget");
-};
+__host__ __device__ inline MfLayout mf_layout(int R, int T, int NTHR, int ACC, int d, const int *n) {
+  const int W = NTHR / 64;
+  int nmax = 1, pcap = 0, bcap = 0;
+  for (int k = 0; k < d; ++k) {
+    nmax = n[k] > nmax ? n[k] : nmax;
+    pcap += T + 16 * n[k];
+    bcap += (T + 16 * n[k]) / 16 + 1;
+  }
+  MfLayout L;
+  int o = 0;
+  L.rows = o;
+  o += a16(4 * (T + 2) * (R + 4));
+  L.slab = o;
+  if (ACC == ACC_SLAB) o += 4 * nmax * R * (R + 4);
+  L.edges = o;
+  if (ACC == ACC_SLAB) o += 4 * W * R * (R + 4);
+  L.sflag = o;
+  if (ACC == ACC_SLAB) o += a16(4 * (nmax + 16));
+  L.wsum = o;
+  o += a16(4 * (T + 2));
+  L.perm = o;
+  o += a16(2 * pcap);
+  L.bslc = o;
+  o += a16(bcap + 16);
+  L.nblk = o;
+  o += 4 * MF_MAX_D;
+  L.total = o + 64;
+  L.nmax = nmax;
+  return L;
+}
 
 // One tile of T entries starting at entry e0 (cnt of them valid): sort,
 // right sweep, residual, left sweep.  `accg` is the workgroup accumulator
@@ -113,16 +138,16 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   constexpr int SS = R + 4;       // slab/edge row stride (conflict-free D stores)
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
-  using L = Lds<R, T, NTHR, ACC>;
-  float *rows = (float *)(smem + L::rows);
-  float *slab = (float *)(smem + L::slab);
-  float *edges = (float *)(smem + L::edges);
-  int *sflag = (int *)(smem + L::sflag);
-  int *eslice = sflag + L::NMAX;
-  float *wsum = (float *)(smem + L::wsum);
-  uint16_t *perm = (uint16_t *)(smem + L::perm);
-  uint8_t *bslc = (uint8_t *)(smem + L::bslc);
-  int *nblk = (int *)(smem + L::nblk);
+  const MfLayout L = mf_layout(R, T, NTHR, ACC, p.d, p.n);
+  float *rows = (float *)(smem + L.rows);
+  float *slab = (float *)(smem + L.slab);
+  float *edges = (float *)(smem + L.edges);
+  int *sflag = (int *)(smem + L.sflag);
+  int *eslice = sflag + L.nmax;
+  float *wsum = (float *)(smem + L.wsum);
+  uint16_t *perm = (uint16_t *)(smem + L.perm);
+  uint8_t *bslc = (uint8_t *)(smem + L.bslc);
+  int *nblk = (int *)(smem + L.nblk);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -392,7 +417,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   // slice of the previous wave stores that run into its edge buffer.  The
   // flush adds slab and edges in a fixed order: no atomics, deterministic.
   // The accumulator values of the flush load at mode start.
-  constexpr int FLN = (ACC == ACC_SLAB) ? (L::NMAX * R * R / 4 + NTHR - 1) / NTHR : 1;
+  constexpr int FLN = (ACC == ACC_SLAB) ? (MfTraits<R>::MAX_N * R * R / 4 + NTHR - 1) / NTHR : 1;
   for (int k = 0; k < d; ++k) {
     const int nk = p.n[k];
     if constexpr (ACC == ACC_SLAB) {
@@ -595,9 +620,8 @@ struct Grid {
   float *loss_acc;         // per workgroup squared-residual sums
 };
 
-template <int R, int T, int MODE, int ACC>
-__global__ void __launch_bounds__(MfTraits<R>::THREADS) fused_kernel(MfInst p, Grid g) {
-  constexpr int NTHR = MfTraits<R>::THREADS;
+template <int R, int T, int NTHR, int MODE, int ACC>
+__global__ void __launch_bounds__(NTHR) fused_kernel(MfInst p, Grid g) {
   extern __shared__ __align__(16) char smem[];
   float *stash = g.stash + (long long)blockIdx.x * g.stash_stride;
   float *accg = g.acc ? g.acc + (long long)blockIdx.x * g.acc_stride : nullptr;
@@ -645,13 +669,13 @@ __global__ void __launch_bounds__(MF_BATCH_THREADS) batched_kernel(MfBatchArgs a
     for (int t = 0; t < w.ntile; ++t) {
       float lp = 0.f;
       if (w.rclass == 16) {
-        constexpr int T = MfTraits<16>::T;
+        constexpr int T = MF_BATCH_T16;
         const long long e0 = (long long)(w.tile0 + t) * T;
         const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
         run_tile<16, T, MF_BATCH_THREADS, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb16, nullptr,
                                                                 false, lp);
       } else {
-        constexpr int T = MfTraits<32>::T;
+        constexpr int T = MF_BATCH_T32;
         const long long e0 = (long long)(w.tile0 + t) * T;
         const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
         run_tile<32, T, MF_BATCH_THREADS, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb32, nullptr,
@@ -763,48 +787,121 @@ int device_cus() {
 
 constexpr int acc_of(int R) { return R == 16 ? ACC_SLAB : ACC_DIRECT; }
 
+// Tile shapes of the single-tensor kernels (entries per tile, threads per
+// workgroup), two per rank class; shape 0 is the default.  At rank class 16
+// the larger tile pads fewer entries (slice groups round up to 16 entries)
+// while the smaller one keeps a tile's LDS under half of a CU's 160 KiB, so
+// two workgroups share a CU.  Measured at d=10, n=10, r=16, 2^20 entries:
+// 0.41 ms and 0.43 ms; at rank class 32 (projection, d=10, rank 32):
+// 1.41 ms and 2.10 ms.
+struct TileShape {
+  int T, threads;
+};
+constexpr TileShape kShapes16[2] = {{1024, 768}, {512, 512}};
+constexpr TileShape kShapes32[2] = {{512, 512}, {256, 256}};
+constexpr TileShape kShape64 = {256, 512};
+constexpr int kLdsBytes = 160 * 1024;
+constexpr int kBatchStaticLds = 1024;
+
+int g_variant[2] = {-1, -1};  // per rank class 16 / 32; -1: not chosen yet
+
+int variant_of(int R) {
+  if (R == 64) return 0;
+  int &v = g_variant[R == 16 ? 0 : 1];
+  if (v < 0) {
+    v = 0;
+    const char *e = getenv(R == 16 ? "TTGFX_TILE16" : "TTGFX_TILE32");
+    if (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) v = e[0] - '0';
+  }
+  return v;
+}
+
+TileShape shape_of(int R) {
+  if (R == 16) return kShapes16[variant_of(16)];
+  if (R == 32) return kShapes32[variant_of(32)];
+  return kShape64;
+}
+
+int device_id() {
+  int dev = 0;
+  return hipGetDevice(&dev) == hipSuccess ? dev : -1;
+}
+
 struct Geometry {
-  int R, T, nb_max, total_slices, ntiles, nwg;
+  int R, T, threads, nb_max, total_slices, ntiles, nwg, lds;
   long long stash_stride, acc_stride;
 };
+
+// Workgroups per CU the LDS allows (the kernels' register use admits at
+// least two 8-wave workgroups per CU).
+int wgs_per_cu(int lds, int threads) {
+  int by_lds = kLdsBytes / (lds > 0 ? lds : 1);
+  int by_waves = 32 / (threads / 64);  // 8 waves per SIMD at most
+  int w = by_lds < by_waves ? by_lds : by_waves;
+  return w < 1 ? 1 : w;
+}
 
 Geometry geometry(const tt_tensor *X, int R, int64_t M) {
   Geometry g;
   g.R = R;
-  g.T = (R == 16) ? MfTraits<16>::T : (R == 32 ? MfTraits<32>::T : MfTraits<64>::T);
+  const TileShape sh = shape_of(R);
+  g.T = sh.T;
+  g.threads = sh.threads;
   int nmax = 1;
   g.total_slices = 0;
   for (int k = 0; k < X->d; ++k) {
     nmax = X->n[k] > nmax ? X->n[k] : nmax;
     g.total_slices += X->n[k];
   }
+  g.lds = mf_layout(R, g.T, g.threads, acc_of(R), X->d, X->n).total;
   g.nb_max = g.T / 16 + nmax;
   g.ntiles = (int)((M + g.T - 1) / g.T);
-  const int cus = device_cus();
-  g.nwg = g.ntiles < cus ? g.ntiles : cus;
+  const int slots = device_cus() * wgs_per_cu(g.lds, g.threads);
+  g.nwg = g.ntiles < slots ? g.ntiles : slots;
   if (g.nwg < 1) g.nwg = 1;
   g.stash_stride = (long long)(X->d > 1 ? X->d - 1 : 1) * g.nb_max * 64 * (R / 4);
   g.acc_stride = (R == 16) ? (long long)g.total_slices * R * R : 0;
   return g;
 }
 
-template <int R, int MODE>
-int launch_fused(const MfInst &p, const Grid &g, int nwg, hipStream_t s) {
-  constexpr int T = MfTraits<R>::T;
+template <int R, int T, int NTHR, int MODE>
+int launch_fused(const MfInst &p, const Grid &g, int nwg, int lds, hipStream_t s) {
   constexpr int ACC = acc_of(R);
-  using L = Lds<R, T, MfTraits<R>::THREADS, ACC>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<R, T, MODE, ACC>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::total);
+  static int attr_dev = -2;
+  const int dev = device_id();
+  if (attr_dev != dev) {
+    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<R, T, NTHR, MODE, ACC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (e != hipSuccess) return hip_check(e, "fused kernel LDS attribute");
-    attr_set = true;
+    attr_dev = dev;
   }
   timer_before(s);
-  hipLaunchKernelGGL((fused_kernel<R, T, MODE, ACC>), dim3(nwg), dim3(MfTraits<R>::THREADS), L::total, s,
-                     p, g);
+  hipLaunchKernelGGL((fused_kernel<R, T, NTHR, MODE, ACC>), dim3(nwg), dim3(NTHR), lds, s, p, g);
   timer_after(s);
   return launch_check("fused MFMA kernel");
+}
+
+template <int R, int T, int NTHR>
+int launch_mode(int mode, const MfInst &p, const Grid &g, int nwg, int lds, hipStream_t s) {
+  if (mode == MODE_GATHER) return launch_fused<R, T, NTHR, MODE_GATHER>(p, g, nwg, lds, s);
+  if constexpr (R <= 32) {
+    if (mode == MODE_ADJOINT) return launch_fused<R, T, NTHR, MODE_ADJOINT>(p, g, nwg, lds, s);
+    return launch_fused<R, T, NTHR, MODE_MSE>(p, g, nwg, lds, s);
+  }
+  return set_error(TT_ERR_UNSUPPORTED, "rank class 64 serves the gather only");
+}
+
+int launch_geometry(int mode, const Geometry &ge, const MfInst &p, const Grid &g, hipStream_t s) {
+  const TileShape sh{ge.T, ge.threads};
+  if (ge.R == 16) {
+    if (sh.T == kShapes16[0].T) return launch_mode<16, kShapes16[0].T, kShapes16[0].threads>(mode, p, g, ge.nwg, ge.lds, s);
+    return launch_mode<16, kShapes16[1].T, kShapes16[1].threads>(mode, p, g, ge.nwg, ge.lds, s);
+  }
+  if (ge.R == 32) {
+    if (sh.T == kShapes32[0].T) return launch_mode<32, kShapes32[0].T, kShapes32[0].threads>(mode, p, g, ge.nwg, ge.lds, s);
+    return launch_mode<32, kShapes32[1].T, kShapes32[1].threads>(mode, p, g, ge.nwg, ge.lds, s);
+  }
+  return launch_mode<64, kShape64.T, kShape64.threads>(mode, p, g, ge.nwg, ge.lds, s);
 }
 
 }  // namespace
@@ -812,12 +909,29 @@ int launch_fused(const MfInst &p, const Grid &g, int nwg, hipStream_t s) {
 template <int R>
 static bool fits_class(const tt_tensor *X) {
   if (X->d < 2 || X->d > MF_MAX_D) return false;
-  int pcap = 0;
-  for (int k = 0; k < X->d; ++k) {
+  for (int k = 0; k < X->d; ++k)
     if (X->n[k] > MfTraits<R>::MAX_N) return false;
-    pcap += MfTraits<R>::T + 16 * X->n[k];
+  // every tile shape of the class (and the batched kernel's) fits the LDS,
+  // so the choice of shape never changes which kernel serves a tensor
+  TileShape shapes[3];
+  int ns = 0;
+  if (R == 16) {
+    shapes[ns++] = kShapes16[0];
+    shapes[ns++] = kShapes16[1];
+    shapes[ns++] = {MF_BATCH_T16, MF_BATCH_THREADS};
+  } else if (R == 32) {
+    shapes[ns++] = kShapes32[0];
+    shapes[ns++] = kShapes32[1];
+    shapes[ns++] = {MF_BATCH_T32, MF_BATCH_THREADS};
+  } else {
+    shapes[ns++] = kShape64;
   }
-  return pcap <= MfTraits<R>::PERM_CAP;
+  for (int i = 0; i < ns; ++i) {
+    const int acc = (i < 2 && R == 16) ? ACC_SLAB : ACC_DIRECT;
+    const int cap = (i == 2) ? kLdsBytes - kBatchStaticLds : kLdsBytes;
+    if (mf_layout(R, shapes[i].T, shapes[i].threads, acc, X->d, X->n).total > cap) return false;
+  }
+  return true;
 }
 
 int mfma_rank_class(const tt_tensor *L, const tt_tensor *R) {
@@ -938,17 +1052,7 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
     if ((rc = fill_zero(grad, (long long)g.total_slices * R * R, s))) return rc;
   }
   if (M > 0) {
-    if (R == 64) {
-      rc = launch_fused<64, MODE_GATHER>(p, gr, g.nwg, s);
-    } else if (R == 16) {
-      if (mode == MODE_GATHER) rc = launch_fused<16, MODE_GATHER>(p, gr, g.nwg, s);
-      else if (mode == MODE_ADJOINT) rc = launch_fused<16, MODE_ADJOINT>(p, gr, g.nwg, s);
-      else rc = launch_fused<16, MODE_MSE>(p, gr, g.nwg, s);
-    } else {
-      if (mode == MODE_GATHER) rc = launch_fused<32, MODE_GATHER>(p, gr, g.nwg, s);
-      else if (mode == MODE_ADJOINT) rc = launch_fused<32, MODE_ADJOINT>(p, gr, g.nwg, s);
-      else rc = launch_fused<32, MODE_MSE>(p, gr, g.nwg, s);
-    }
+    rc = launch_geometry(mode, g, p, gr, s);
     if (rc) return rc;
   }
   if (!adjoint) return TT_OK;
@@ -980,27 +1084,29 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
   return TT_OK;
 }
 
-size_t mfma_batch_lds() {
-  constexpr size_t a = Lds<16, MfTraits<16>::T, MF_BATCH_THREADS, ACC_DIRECT>::total;
-  constexpr size_t b = Lds<32, MfTraits<32>::T, MF_BATCH_THREADS, ACC_DIRECT>::total;
-  return a > b ? a : b;
+size_t mfma_batch_lds(int d, const int *n) {
+  const int a = mf_layout(16, MF_BATCH_T16, MF_BATCH_THREADS, ACC_DIRECT, d, n).total;
+  const int b = mf_layout(32, MF_BATCH_T32, MF_BATCH_THREADS, ACC_DIRECT, d, n).total;
+  return (size_t)(a > b ? a : b);
 }
 
 int mfma_batch_prepare() {
-  static bool done = false;
-  if (done) return TT_OK;
+  static int done_dev = -2;
+  const int dev = device_id();
+  if (done_dev == dev) return TT_OK;
+  // the kernel also holds a few static LDS words (work item, loss partials)
   hipError_t e = hipFuncSetAttribute((const void *)batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)mfma_batch_lds());
+                                     kLdsBytes - kBatchStaticLds);
   if (e != hipSuccess) return hip_check(e, "batched kernel LDS attribute");
-  done = true;
+  done_dev = dev;
   return TT_OK;
 }
 
-int mfma_batch_launch(const MfBatchArgs &a, int nwg, hipStream_t s) {
+int mfma_batch_launch(const MfBatchArgs &a, int nwg, size_t lds, hipStream_t s) {
   int rc = mfma_batch_prepare();
   if (rc) return rc;
   timer_before(s);
-  hipLaunchKernelGGL(batched_kernel, dim3(nwg), dim3(MF_BATCH_THREADS), mfma_batch_lds(), s, a);
+  hipLaunchKernelGGL(batched_kernel, dim3(nwg), dim3(MF_BATCH_THREADS), lds, s, a);
   timer_after(s);
   return launch_check("batched kernel");
 }

@@ -148,7 +148,7 @@ int build_items(tt_plan *P) {
   for (int j = 0; j < P->b; ++j) {
     const long long M = P->entry_off[j + 1] - P->entry_off[j];
     const int R = P->rclass[j];
-    const int T = (R == 16) ? MfTraits<16>::T : MfTraits<32>::T;
+    const int T = (R == 16) ? MF_BATCH_T16 : MF_BATCH_T32;
     const int ntiles = (int)((M + T - 1) / T);
     for (int t0 = 0; t0 < ntiles; t0 += P->chunk) {
       const int nt = std::min(P->chunk, ntiles - t0);
@@ -186,7 +186,7 @@ int issue(tt_plan *P, hipStream_t s) {
   a.stash_stride = P->stash_stride;
   a.nb16 = P->nb16;
   a.nb32 = P->nb32;
-  if (P->nitems > 0 && (rc = mfma_batch_launch(a, P->nwg, s))) return rc;
+  if (P->nitems > 0 && (rc = mfma_batch_launch(a, P->nwg, mfma_batch_lds(P->md.d, P->md.n), s))) return rc;
   hipLaunchKernelGGL(unpad_batch_kernel, dim3(P->md.d, P->b), dim3(256), 0, s, P->dmeta, P->md, P->gp);
   return launch_check("plan: unpad gradients");
 }
@@ -255,8 +255,8 @@ int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t, const 
   P->entry_off.assign(entry_off, entry_off + X->b + 1);
   int nmax = 1;
   for (int k = 0; k < ref->d; ++k) nmax = std::max(nmax, ref->n[k]);
-  P->nb16 = MfTraits<16>::T / 16 + nmax;
-  P->nb32 = MfTraits<32>::T / 16 + nmax;
+  P->nb16 = MF_BATCH_T16 / 16 + nmax;
+  P->nb32 = MF_BATCH_T32 / 16 + nmax;
   P->stash_stride = std::max((long long)(ref->d - 1) * P->nb16 * 64 * 4, (long long)(ref->d - 1) * P->nb32 * 64 * 8);
   P->nwg = mfma_device_cus();
 
@@ -313,7 +313,7 @@ int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t, const 
   // upper bound on work items (chunk = 1)
   long long maxit = 0;
   for (int j = 0; j < X->b; ++j) {
-    const int T = (meta[j].R == 16) ? MfTraits<16>::T : MfTraits<32>::T;
+    const int T = (meta[j].R == 16) ? MF_BATCH_T16 : MF_BATCH_T32;
     maxit += (P->entry_off[j + 1] - P->entry_off[j] + T - 1) / T;
   }
   P->max_items = (int)std::max(1LL, maxit);
