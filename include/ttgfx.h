@@ -144,6 +144,25 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
                            tt_tensor *gX, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* --------------------------------------- A1+A2+A3 without a workspace */
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * fused pass above with the same arguments and results (the same kernels),
+ * minus ws/ws_bytes.  Its workspace is a fixed device array of
+ * tt_gather_mse_noalloc_limit() bytes (256 MiB) held by every GPU the
+ * library runs on until the process ends; the first call on a device looks
+ * up that device's copy.  Shapes whose tt_gather_mse_workspace exceeds the
+ * limit fail with TT_ERR_WORKSPACE before any device work.  Calls share
+ * the array: calls that overlap in time on one GPU (different streams or
+ * host threads without ordering) race and give undefined results; calls
+ * ordered on one stream are safe.  Nothing in the array needs to start at
+ * zero (the kernels initialise what they accumulate into). */
+int64_t tt_gather_mse_noalloc_limit(void);
+int tt_gather_mse_backward_noalloc(const tt_tensor *X, const int32_t *idx,
+                                   int64_t M, const float *t, float *y,
+                                   float *g, float *loss, tt_tensor *gX,
+                                   void *stream);
+
 /* ---------------------------------------------- completion line search */
 /* Terms of the exact line search of Riemannian tensor completion (the
  * completion use case of the Introduction with the Riemannian gradient of

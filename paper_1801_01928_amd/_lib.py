@@ -66,6 +66,8 @@ SIGNATURES = {
     "tt_gather_backward": (C.c_int, [P_TT, VP, I64, VP, P_TT, VP, SZ, VP]),
     "tt_gather_mse_workspace": (I64, [P_TT, I64]),
     "tt_gather_mse_backward": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, P_TT, VP, SZ, VP]),
+    "tt_gather_mse_noalloc_limit": (I64, []),
+    "tt_gather_mse_backward_noalloc": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, P_TT, VP]),
     "tt_check_indices": (C.c_int, [P_TT, VP, I64, VP, VP]),
     "tt_halves_split": (C.c_int32, [P_TT]),
     "tt_halves_bytes": (I64, [P_TT, C.c_int32]),

@@ -220,6 +220,33 @@ def gather_mse_backward(X, idx, t, want_y=True, ws=None, out=None, loss=None, wa
     return y, loss, gX
 
 
+def gather_mse_backward_noalloc(X, idx, t, want_y=True, out=None, loss=None, want_g=False):
+    """``gather_mse_backward`` through the entry point that allocates nothing
+    on the device (its workspace is the library's fixed scratch array).
+    ``out`` and ``loss`` may be given, as may ``idx`` and ``t`` as device
+    tensors, so that a caller allocates nothing per call either."""
+    lib = L.load()
+    idx = _idx(idx, X.d, X.device)
+    _checked(X, idx)
+    M = idx.shape[1]
+    t = _vec(t, M, X.device)
+    y = torch.empty(M, dtype=torch.float32, device=X.device) if want_y else None
+    g = torch.empty(M, dtype=torch.float32, device=X.device) if want_g else None
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    gX = out if out is not None else X.empty_like()
+    L.check(lib.tt_gather_mse_backward_noalloc(C.byref(X.desc()), _ptr(idx), M, _ptr(t), _ptr(y), _ptr(g),
+                                               _ptr(loss), C.byref(gX.desc()), _stream(X.device)))
+    if want_g:
+        return y, g, loss, gX
+    return y, loss, gX
+
+
+def gather_mse_noalloc_limit():
+    """Bytes of the fixed scratch array behind ``gather_mse_backward_noalloc``."""
+    return int(L.load().tt_gather_mse_noalloc_limit())
+
+
 class KernelTimer:
     """Times the library's dominant kernels with HIP events recorded on the
     launch stream (tt_timer_start / tt_timer_stop)."""

@@ -306,3 +306,22 @@ def test_matmat_validation_before_device(lib):
     assert lib.tt_matmat(C.byref(A), C.byref(Bbad), C.byref(Cg), None) == L.TT_ERR_SHAPE
     assert lib.tt_matmat(C.byref(A), C.byref(B), C.byref(Cbad), None) == L.TT_ERR_SHAPE
     assert lib.tt_matmat(C.byref(A), C.byref(B), None, None) == L.TT_ERR_ARG
+
+
+def test_noalloc_rejects_shapes_beyond_its_scratch(lib):
+    """The no-allocation fused pass refuses, on the host and before any
+    device work, a shape whose workspace exceeds its fixed scratch array."""
+    from paper_1801_01928_amd import _lib as L
+    limit = lib.tt_gather_mse_noalloc_limit()
+    assert limit == 256 << 20
+    X = _desc([32] * 16, [1] + [32] * 15 + [1])
+    M = 1 << 20
+    assert lib.tt_gather_mse_workspace(C.byref(X), M) > limit
+    rc = lib.tt_gather_mse_backward_noalloc(C.byref(X), C.c_void_p(0x10), M, C.c_void_p(0x10), None, None,
+                                            None, C.byref(X), None)
+    assert rc == L.TT_ERR_WORKSPACE
+    assert "scratch" in L.last_error()
+    # invalid descriptors are still reported as such
+    B = _desc([3, 4], [2, 2, 1])
+    assert lib.tt_gather_mse_backward_noalloc(C.byref(B), C.c_void_p(0x10), 5, C.c_void_p(0x10), None, None,
+                                              None, C.byref(B), None) == L.TT_ERR_SHAPE
