@@ -24,22 +24,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "observed entries/s, TT gather fwd+bwd (d=10,n=10,r=16) + % roofline, batched vs plain"
-# Algorithmic work of the fused pass per observed entry (d=10, r=16, first
-# and last cores 1 x r and r x 1): right sweep 8 (1x16)(16x16) products plus
-# one 16-dot = 4128 flop (it yields y), left sweep 8 products = 4096 flop,
-# outer products g * lambda (x) rho for all 10 modes = 2 * (16 + 8*256 + 16)
-# = 4160 flop.  The forward is not recomputed by the adjoint.
-FLOP_PER_ENTRY = 4128 + 4096 + 4160
+# Algorithmic work of one gather forward + backward per observed entry at
+# d=10, r=16 (first and last cores 1 x r and r x 1), the count of the scope
+# table: forward 8 (1x16)(16x16) products plus one 16-dot = 4,128 flop;
+# backward = both partial-product chains (4,128 + 4,096) and the outer
+# products of all 10 modes, 2 (16 + 8*256 + 16) = 4,160: 12,352 flop.
+FLOP_PER_ENTRY = 4128 + 12352
+# What the fused kernel executes: the adjoint reuses the forward's right
+# partials instead of recomputing them (4,128 + 4,096 + 4,160).
+FLOP_EXECUTED = 4128 + 4096 + 4160
+# The sparse tangent projection at d=10, canonical ranks (1,10,32,...,32,10,1):
+# both interface chains and the 10 outer products per entry.
+PROJ_FLOP_PER_ENTRY = 40744
+# Batched workload (d=8, uniform rank r per tensor): forward + backward flop
+# per entry by rank, and bytes per entry (8 indices, target, output weight,
+# with the stash of one partial per mode counted once).
+BATCH_FLOP = {4: 792, 8: 3120, 16: 12384, 32: 49344}
+BATCH_BYTES_PER_ENTRY = 76
 PEAK_MFMA_F32_TFLOPS = 157.3
+PEAK_MFMA_BF16_TFLOPS = 2500.0
+PEAK_VALU_F32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["gather_mfma.hip", "gather_mfma.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_gather_d10_r16.json")
+
+
+def batch_flop_per_entry(d, r):
+    """Forward + backward flop per entry of a d-mode TT of uniform rank r
+    with boundary ranks 1: forward (d-2) r x r products and one r-dot;
+    backward both chains and the d outer products (the counts above)."""
+    fwd = 2 * r * r * (d - 2) + 2 * r
+    bwd = 2 * 2 * r * r * (d - 2) + 2 * (2 * r + (d - 2) * r * r)
+    return fwd + bwd
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-peaks", action="store_true", help="skip the peak microbenchmarks")
+    ap.add_argument("--no-oracle-workloads", action="store_true",
+                    help="skip the oracle timings of the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="observed entries the oracle processes for the CPU baseline")
@@ -161,6 +187,67 @@ def cpu_baseline_all_cores(p, t, sample, workers):
                       "float64, %.1f s)" % (S, p.M, workers, dt)}
 
 
+def oracle_workloads(W):
+    """The FP64 oracle timed on the other workloads, single-threaded BLAS,
+    on bounded samples (each a few seconds): a full completion step of the
+    small workload; the sparse projection (both sweeps, contraction, gauge,
+    assembly) on the first 2^16 of the 2^20 entries of the rank-32 workload
+    and its rounding; gather + MSE + adjoint of the first 8 of the 256
+    batched tensors and 64 entries of their Gram matrix; the TT-matrix layer
+    forward and backward on its full 4096-row batch."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle
+    out = {}
+    f64 = lambda cs: [np.asarray(c, np.float64) for c in cs]
+    with threadpool_limits(limits=1):
+        p = W.small_step()
+        t = oracle.gather(p.planted, p.idx) + p.noise
+        cores = f64(p.cores)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            oracle.completion_step(cores, p.idx, t, alpha=-0.1, max_rank=4)
+            ts.append(time.perf_counter() - t0)
+        out["small_step"] = {"us_per_step": round(sorted(ts)[2] * 1e6, 1), "cores": 1,
+                             "sample": "the whole workload (d=4 n=8 r=4, 4096 entries), median of 5"}
+        q = W.riemann_d10()
+        S = 1 << 16
+        cq = f64(q.cores)
+        t0 = time.perf_counter()
+        Wt = oracle.project_sparse(cq, q.idx[:, :S], q.values[:S], alpha=-0.1, beta=1.0)[0]
+        t1 = time.perf_counter()
+        oracle.round_tt(Wt, 32)
+        t2 = time.perf_counter()
+        out["riemann_step"] = {"project_entries_per_s": round(S / (t1 - t0), 1), "round_ms": round((t2 - t1) * 1e3, 2),
+                               "cores": 1, "sample": "first %d of the %d entries (projection %.1f s)" % (S, q.M, t1 - t0)}
+        inst = W.batched()[:8]
+        t0 = time.perf_counter()
+        M = 0
+        for b in inst:
+            y = oracle.gather(b.cores, b.idx)
+            _, g = oracle.mse_loss_and_grad(y, b.noise)
+            oracle.gather_backward(b.cores, b.idx, g)
+            M += b.M
+        t1 = time.perf_counter()
+        cs = [f64(b.cores) for b in inst]
+        for a in range(8):
+            for c in range(8):
+                oracle.inner(cs[a], cs[c])
+        t2 = time.perf_counter()
+        out["batched"] = {"entries_per_s": round(M / (t1 - t0), 1), "gram_pairs_per_s": round(64 / (t2 - t1), 1),
+                          "cores": 1, "sample": "tensors 0-7 of 256 (%d entries, %.1f s); 64 Gram entries" % (M, t1 - t0)}
+        r = W.ttm_layer()
+        t0 = time.perf_counter()
+        oracle.ttm_forward(r.X, r.cores)
+        t1 = time.perf_counter()
+        oracle.ttm_backward(r.X, r.cores, r.dY)
+        t2 = time.perf_counter()
+        out["ttm_layer"] = {"fwd_ms": round((t1 - t0) * 1e3, 1), "bwd_ms": round((t2 - t1) * 1e3, 1), "cores": 1,
+                            "sample": "the whole batch of 4096 rows (W materialised densely)"}
+    return out
+
+
 def _event_ms(fn, reps, stream=None):
     """Average milliseconds of fn() over reps calls, HIP events on the stream."""
     import torch
@@ -174,6 +261,65 @@ def _event_ms(fn, reps, stream=None):
         e1.record(stream)
     stream.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def _percentiles(ms):
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"p10": round(float(np.percentile(a, 10)), 4), "p50": round(float(np.percentile(a, 50)), 4),
+            "p90": round(float(np.percentile(a, 90)), 4), "reps": int(a.size)}
+
+
+def _per_call_ms(fn, reps, stream=None):
+    """Milliseconds of each of `reps` calls of fn(), each bracketed by its own
+    pair of HIP events on the stream."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    with torch.cuda.stream(stream):
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+    stream.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def peaks_leg(tt):
+    """Measured peaks of one MI355X beside the datasheet's: a plain 1 GiB
+    device copy (HBM, bytes read + written), and the library's
+    microbenchmark kernels for the fp32 and bf16 matrix cores, fp32 vector
+    FMA and LDS reads (median of 5 launches each)."""
+    import ctypes as C
+    import torch
+    from paper_1801_01928_amd import _lib as L
+    lib = L.load()
+    out = {}
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ms = sorted(_per_call_ms(lambda: b.copy_(a), 7))[3]
+    out["hbm_copy_gb_s"] = round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    stream = torch.cuda.current_stream()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = 8 * cus
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    for kind, name, iters, unit in ((0, "mfma_f32_tflops", 1000, 1e12), (1, "mfma_bf16_tflops", 1000, 1e12),
+                                    (2, "valu_f32_tflops", 4000, 1e12), (3, "lds_tb_s", 1000, 1e12)):
+        launch = lambda: L.check(lib.tt_peak_launch(kind, blocks, iters, C.c_void_p(sink.data_ptr()),
+                                                    C.c_void_p(stream.cuda_stream)))
+        launch()
+        torch.cuda.synchronize()
+        ms = sorted(_per_call_ms(launch, 5))[2]
+        out[name] = round(lib.tt_peak_work(kind, blocks, iters) / (ms * 1e-3) / unit, 2)
+    out["datasheet"] = {"hbm_gb_s": PEAK_HBM_GBS, "mfma_f32_tflops": PEAK_MFMA_F32_TFLOPS,
+                        "mfma_bf16_tflops": PEAK_MFMA_BF16_TFLOPS, "valu_f32_packed_tflops": PEAK_VALU_F32_TFLOPS,
+                        "valu_f32_unpacked_tflops": PEAK_VALU_F32_TFLOPS / 2,
+                        "lds_tb_s_at_128B_per_clk": round(cus * 128 * 2.4e9 / 1e12, 1)}
+    return out
 
 
 def batched_leg(tt, W, reps=3):
@@ -203,8 +349,15 @@ def batched_leg(tt, W, reps=3):
     s.synchronize()
     plain_ms = _event_ms(lambda: plan.run_plain(s), reps, s)
     plan.close()
+    # roofline: every tensor at the larger of its matrix-core and HBM times
+    ideal_s = sum(max(q.M * BATCH_FLOP[q.meta["rank"]] / (PEAK_MFMA_F32_TFLOPS * 1e12),
+                      q.M * BATCH_BYTES_PER_ENTRY / (PEAK_HBM_GBS * 1e9)) for q in inst)
+    flop = sum(q.M * BATCH_FLOP[q.meta["rank"]] for q in inst)
     return {"workload": "256 TT tensors d=8 n=16, ranks U{4,8,16,32}, lognormal(ln 5e4, 0.8) entries "
                         "clipped to [1e4, 2e5], planted targets",
+            "roofline": {"bound": "mfma (per tensor: max of flop/157.3 TF and 76 B/entry / 8 TB/s)",
+                         "ideal_ms": round(ideal_s * 1e3, 4), "algorithmic_gflop": round(flop / 1e9, 2),
+                         "frac": round(ideal_s * 1e3 / graph_ms, 4)},
             "entries": int(M), "autotuned_chunk": chunk,
             "graph_ms": round(graph_ms, 3), "plain_ms": round(plain_ms, 3),
             "graph_entries_per_s": round(M / (graph_ms * 1e-3), 1),
@@ -272,6 +425,12 @@ def riemann_leg(tt, W, reps=3):
     torch.cuda.synchronize()
     orth_ms = _event_ms(lambda: tt.orthogonalize_both(X), reps)
     proj_ms = _event_ms(lambda: tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1), reps)
+    with tt.KernelTimer() as kt:
+        for _ in range(reps):
+            tt.project_sparse(U, V, idx, z, alpha=-0.1, add_x=1)
+        torch.cuda.synchronize()
+    proj_kernel_ms = kt.ms / max(kt.launches, 1)
+    proj_tf = PROJ_FLOP_PER_ENTRY * p.M / (proj_kernel_ms * 1e-3) / 1e12
     round_ms = _event_ms(lambda: tt.round_tt(Wt, 32), reps)
     tt.project_tt(U, V, Wt)
     torch.cuda.synchronize()
@@ -296,6 +455,10 @@ def riemann_leg(tt, W, reps=3):
     return {"workload": "d=10 n=10 r=32 (canonical), 2^20 entries", "orthogonalize_both_ms": round(orth_ms, 3),
             "project_sparse_ms": round(proj_ms, 3),
             "project_entries_per_s": round(p.M / (proj_ms * 1e-3), 1),
+            "project_roofline": {"bound": "mfma", "kernel": "fused_kernel<32,512,ADJOINT>",
+                                 "kernel_ms": round(proj_kernel_ms, 4), "flop_per_entry": PROJ_FLOP_PER_ENTRY,
+                                 "achieved": round(proj_tf, 3), "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(proj_tf / PEAK_MFMA_F32_TFLOPS, 4)},
             "round_ms": round(round_ms, 3), "step_ms": round(orth_ms + proj_ms + round_ms, 3),
             "project_tt_rank64_ms": round(transport_ms, 3),
             "project_sum_100_rank10_ms": round(psum_ms, 3),
@@ -411,8 +574,14 @@ def ttm_leg(tt, W, reps=3):
         torch.cuda.synchronize()
         f = _event_ms(lambda: tt.ttm_matmul(Wm, X), reps)
         b = _event_ms(lambda: tt.ttm_matmul_backward(Wm, X, dY), reps)
+        peak = PEAK_MFMA_F32_TFLOPS if name == "f32" else PEAK_MFMA_BF16_TFLOPS
+        # forward + backward: the backward is dX (one chain) and every dG^k
+        # (the chain of T_k and V_{k+1} contractions): 3x the forward chain
+        tf = 3 * fwd_flop / ((f + b) * 1e-3) / 1e12
         out[name] = {"fwd_ms": round(f, 3), "bwd_ms": round(b, 3),
-                     "fwd_chain_tflops": round(fwd_flop / (f * 1e-3) / 1e12, 2)}
+                     "fwd_chain_tflops": round(fwd_flop / (f * 1e-3) / 1e12, 2),
+                     "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                                  "frac": round(tf / peak, 4), "flop_fwd_bwd": round(3 * fwd_flop / 1e9, 1)}}
     return out
 
 
@@ -472,12 +641,17 @@ def main():
     value = p.M * args.steps / (total_ms * 1e-3)
 
     kernel_ms = kt.ms / max(kt.launches, 1)
+    # per-step distribution over separate event pairs (after the timed region)
+    steps_ms = _per_call_ms(step, max(100, args.steps))
     achieved = FLOP_PER_ENTRY * p.M / (kernel_ms * 1e-3) / 1e12
+    executed = FLOP_EXECUTED * p.M / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_MFMA_F32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_MFMA_F32_TFLOPS, 4),
                 "traffic": traffic_bytes(),
-                "kernel": "fused_kernel<16,1024,MSE>", "kernel_ms": round(kernel_ms, 4),
-                "flop_per_entry": FLOP_PER_ENTRY}
+                "kernel": "fused_kernel<16,1024,768,MSE>", "kernel_ms": round(kernel_ms, 4),
+                "flop_per_entry": FLOP_PER_ENTRY,
+                "executed_flop_per_entry": FLOP_EXECUTED,
+                "executed_frac": round(executed / PEAK_MFMA_F32_TFLOPS, 4)}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "entries/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -487,7 +661,12 @@ def main():
                                   "2^20 uniform observed entries, planted rank-8 targets",
                       "d": 10, "n": 10, "r": 16, "M": p.M, "global_batch": p.M},
            "roofline": roofline,
+           "step_ms": _percentiles(steps_ms),
            "loss": float(loss.item())}
+    if not args.no_peaks:
+        pk = peaks_leg(tt)
+        out["peaks"] = pk
+        roofline["frac_of_measured_peak"] = round(achieved / pk["mfma_f32_tflops"], 4)
     if not args.no_extras:
         # secondary measurements, each on its own workload after the timed region
         out["batched_vs_plain"] = batched_leg(tt, W)
@@ -497,6 +676,8 @@ def main():
         out["ttm_layer"] = ttm_leg(tt, W)
         out["matvec"] = matvec_leg(tt, W)
         out["completion_loop"] = completion_leg(tt, W)
+    if not args.no_cpu_baseline and not args.no_oracle_workloads:
+        out["cpu_baseline_workloads"] = oracle_workloads(W)
     if not args.no_cpu_baseline:
         th = t.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(p, th, args.cpu_sample)

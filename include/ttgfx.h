@@ -408,6 +408,19 @@ int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *C, void *stream
 int tt_norms(const tt_batch *A, float *out, void *stream);
 
 /* ---------------------------------------------------------------- misc */
+/* ---------------------------------------------------------- measurement */
+/* Microbenchmarks of the peaks that bound the kernels above, for reporting
+ * fractions against measured as well as datasheet peaks.  kind: 0 fp32
+ * matrix core (v_mfma_f32_16x16x4_f32), 1 bf16 matrix core
+ * (v_mfma_f32_16x16x32_bf16), 2 fp32 vector FMA (unpacked), 3 LDS reads of
+ * 16 bytes per lane, conflict-free.  tt_peak_launch queues one kernel of
+ * `blocks` workgroups of 256 threads, each running `iters` iterations, on
+ * `stream`; out: (dev) float [blocks * 256] (sink values).  tt_peak_work
+ * returns the flop (kinds 0-2) or bytes (kind 3) of that launch, or a
+ * negative value for an unknown kind. */
+double tt_peak_work(int kind, int32_t blocks, int32_t iters);
+int tt_peak_launch(int kind, int32_t blocks, int32_t iters, float *out, void *stream);
+
 const char *tt_last_error(void);   /* thread-local message of the last failure */
 int tt_version(void);              /* TTGFX_VERSION                            */
 

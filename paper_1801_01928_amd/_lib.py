@@ -108,6 +108,8 @@ SIGNATURES = {
     "tt_matmat": (C.c_int, [P_TTM, P_TTM, P_TTM, VP]),
     "tt_norms": (C.c_int, [P_BATCH, VP, VP]),
     "tt_matmul_backward": (C.c_int, [P_TTM, VP, I64, VP, VP, VP, C.c_int, VP, SZ, VP]),
+    "tt_peak_work": (C.c_double, [C.c_int, I32, I32]),
+    "tt_peak_launch": (C.c_int, [C.c_int, I32, I32, VP, VP]),
     "tt_timer_start": (C.c_int, []),
     "tt_timer_stop": (C.c_int, [C.POINTER(C.c_float), PI32]),
     "tt_last_error": (C.c_char_p, []),
