@@ -173,8 +173,10 @@ int tt_gather_mse_backward_noalloc(const tt_tensor *X, const int32_t *idx,
  * out: (dev) float [2], written asynchronously:
  *   out[0] = sum_m P(i^m)^2,   out[1] = sum_m (y_m - t_m) P(i^m);
  * the observed loss of the first-order model X - a P is smallest at
- * a = out[1] / out[0].  Sums are in a fixed order (deterministic).
- * M = 0 writes {0, 0}. */
+ * a = out[1] / out[0], which is written to out[2] (0 when out[0] = 0), so
+ * that the step can feed tt_tangent_combine_dev without a host round trip.
+ * out: (dev) float [3].  Sums are in a fixed order (deterministic).
+ * M = 0 writes {0, 0, 0}. */
 int64_t tt_line_search_workspace(const tt_tensor *P, int64_t M);
 int tt_line_search(const tt_tensor *P, const int32_t *idx, int64_t M,
                    const float *y, const float *t, float *out,
@@ -272,6 +274,12 @@ int tt_project_sum(const tt_tensor *U, const tt_tensor *V, const tt_batch *A,
  * Needs no workspace. */
 int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha,
                        int add_x, tt_tensor *W, void *stream);
+/* The same with the coefficient read on the device: alpha = scale * (*alpha)
+ * (alpha: (dev) one float, e.g. out + 2 of tt_line_search with scale = -1
+ * for the completion step X - a P). */
+int tt_tangent_combine_dev(const tt_tensor *U, const tt_tensor *P,
+                           const float *alpha, float scale, int add_x,
+                           tt_tensor *W, void *stream);
 
 /* Tangent-space algebra for tangent vectors at one point X (Riemannian
  * Geometry Operations: elements of one tangent space add blockwise in the
@@ -289,6 +297,25 @@ int tt_tangent_inner(const tt_tensor *U, const tt_tensor *A,
                      const tt_tensor *B, float *out, void *stream);
 int tt_tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b,
                      const tt_tensor *B, tt_tensor *W, void *stream);
+
+/* Direction update of Riemannian conjugate gradients (the nonlinear CG of
+ * Riemannian TT completion in the literature the paper cites, with the
+ * Riemannian gradient of the Riemannian Geometry Operations section), all
+ * scalars on the device.  xi: the projected gradient at X; Txi, Teta: the
+ * previous step's gradient and direction transported to X (tt_project_tt),
+ * or both NULL on the first step; prev_xi_sq: (dev) one float, <xi', xi'>
+ * of the previous step (read only with Txi).  Writes eta (may alias Teta,
+ * not xi or Txi) and scalars: (dev) float [5]:
+ *   [0] <xi, xi>;
+ *   [1] beta = max(0, (<xi, xi> - <xi, Txi>) / <xi', xi'>) (Polak-Ribiere+;
+ *       0 on the first step or when <xi', xi'> <= 0);
+ *   [2] 1 when eta = -xi + beta Teta was not a descent direction and was
+ *       reset to -xi (beta then 0), else 0;
+ *   [3] <xi, eta> before the reset;  [4] <xi, Txi> (scratch).
+ * Tangent TTs as for tt_tangent_inner.  No workspace; sums in a fixed order. */
+int tt_cg_direction(const tt_tensor *U, const tt_tensor *xi, const tt_tensor *Txi,
+                    const tt_tensor *Teta, const float *prev_xi_sq,
+                    tt_tensor *eta, float *scalars, void *stream);
 
 /* Gram matrix of a batch of tangent vectors at one point X (Riemannian
  * Geometry Operations: the metric of the tangent space is that of the

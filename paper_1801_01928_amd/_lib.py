@@ -89,6 +89,8 @@ SIGNATURES = {
     "tt_tangent_gram": (C.c_int, [P_TT, P_BATCH, VP, VP, SZ, VP]),
     "tt_tangent_axpby": (C.c_int, [P_TT, C.c_float, P_TT, C.c_float, P_TT, P_TT, VP]),
     "tt_tangent_combine": (C.c_int, [P_TT, P_TT, C.c_float, C.c_int, P_TT, VP]),
+    "tt_tangent_combine_dev": (C.c_int, [P_TT, P_TT, VP, C.c_float, C.c_int, P_TT, VP]),
+    "tt_cg_direction": (C.c_int, [P_TT, P_TT, P_TT, P_TT, VP, P_TT, VP, VP]),
     "tt_project_tt_workspace": (I64, [P_TT, P_TT]),
     "tt_project_tt": (C.c_int, [P_TT, P_TT, P_TT, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_round_ranks": (C.c_int, [P_TT, I32, PI32]),

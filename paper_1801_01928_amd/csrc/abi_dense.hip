@@ -210,6 +210,23 @@ int tt_tangent_combine(const tt_tensor *U, const tt_tensor *P, float alpha, int 
   return tangent_combine(U, P, W, alpha, add_x, (hipStream_t)stream);
 }
 
+int tt_tangent_combine_dev(const tt_tensor *U, const tt_tensor *P, const float *alpha, float scale, int add_x,
+                           tt_tensor *W, void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = validate_tt(P, "P", 2 * TT_MAX_RANK))) return rc;
+  if ((rc = validate_tt(W, "W", 2 * TT_MAX_RANK))) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "tangent_combine_dev needs d >= 2");
+  if (!alpha) return set_error(TT_ERR_ARG, "tangent_combine_dev: null alpha");
+  if (!same_shape(P, W)) return set_error(TT_ERR_SHAPE, "W must have P's shape");
+  if (!same_modes(U, P)) return set_error(TT_ERR_SHAPE, "P must have U's mode sizes");
+  for (int k = 1; k < U->d; ++k)
+    if (P->r[k] != 2 * U->r[k])
+      return set_error(TT_ERR_SHAPE, "P rank r[%d] = %d, expected %d", k, P->r[k], 2 * U->r[k]);
+  if (add_x != 0 && add_x != 1) return set_error(TT_ERR_ARG, "add_x must be 0 or 1");
+  return tangent_combine_dev(U, P, W, alpha, scale, add_x, (hipStream_t)stream);
+}
+
 static int check_tangent(const tt_tensor *U, const tt_tensor *P, const char *name) {
   int rc = validate_tt(P, name, 2 * TT_MAX_RANK);
   if (rc) return rc;
@@ -237,6 +254,29 @@ int tt_tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, c
   if ((rc = check_tangent(U, A, "A")) || (rc = check_tangent(U, B, "B")) || (rc = check_tangent(U, W, "W")))
     return rc;
   return tangent_axpby(U, a, A, b, B, W, (hipStream_t)stream);
+}
+
+int tt_cg_direction(const tt_tensor *U, const tt_tensor *xi, const tt_tensor *Txi, const tt_tensor *Teta,
+                    const float *prev_xi_sq, tt_tensor *eta, float *scalars, void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "cg_direction needs d >= 2");
+  if ((rc = check_tangent(U, xi, "xi")) || (rc = check_tangent(U, eta, "eta"))) return rc;
+  if (!same_shape(xi, eta)) return set_error(TT_ERR_SHAPE, "eta must have xi's shape");
+  if (!scalars) return set_error(TT_ERR_ARG, "cg_direction: null scalars");
+  if ((Txi == nullptr) != (Teta == nullptr))
+    return set_error(TT_ERR_ARG, "cg_direction: Txi and Teta must both be given or both be NULL");
+  if (Txi) {
+    if ((rc = check_tangent(U, Txi, "Txi")) || (rc = check_tangent(U, Teta, "Teta"))) return rc;
+    if (!same_shape(xi, Txi) || !same_shape(xi, Teta))
+      return set_error(TT_ERR_SHAPE, "Txi and Teta must have xi's shape");
+    if (!prev_xi_sq) return set_error(TT_ERR_ARG, "cg_direction: null prev_xi_sq");
+    if (eta->data == Txi->data || eta->data == xi->data)
+      return set_error(TT_ERR_ARG, "cg_direction: eta may alias Teta only");
+  } else if (eta->data == xi->data) {
+    return set_error(TT_ERR_ARG, "cg_direction: eta must not alias xi");
+  }
+  return cg_direction(U, xi, Txi, Teta, prev_xi_sq, eta, scalars, (hipStream_t)stream);
 }
 
 static int validate_tangent_gram(const tt_tensor *U, const tt_batch *A) {

@@ -22,6 +22,12 @@ int tangent_combine(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, float 
 size_t project_sum_ws(const tt_tensor *U, const tt_tensor *A0, int nb);
 int project_sum(const tt_tensor *U, const tt_tensor *V, const tt_tensor *A, int nb, const float *c, float alpha,
                 int add_x, tt_tensor *W, void *ws, size_t bytes, hipStream_t s);
+int tangent_combine_dev(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, const float *alpha, float scale,
+                        int add_x, hipStream_t s);
+// One direction update of nonlinear CG (txi = teta = NULL on the first step);
+// sc: (dev) float [5] scalars (see cg_beta_kernel).
+int cg_direction(const tt_tensor *U, const tt_tensor *xi, const tt_tensor *txi, const tt_tensor *teta,
+                 const float *prev_sq, tt_tensor *eta, float *sc, hipStream_t s);
 int tangent_inner(const tt_tensor *U, const tt_tensor *A, const tt_tensor *B, float *out, hipStream_t s);
 int tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, const tt_tensor *B, tt_tensor *W,
                   hipStream_t s);

@@ -816,8 +816,9 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
 // workgroup per core; W may alias P (each element is read, then written, by
 // one thread).
 __global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDev P, TTDev W, float alpha,
-                                                                   float addx) {
+                                                                   const float *alpha_dev, float addx) {
   const int k = blockIdx.x, d = U.d;
+  if (alpha_dev) alpha *= alpha_dev[0];  // coefficient computed on the device (the line-search step)
   const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
   const float *Uk = U.data + U.off[k];
   const float *Pk = P.data + P.off[k];
@@ -905,6 +906,75 @@ __global__ void __launch_bounds__(kThreads) tangent_axpby_kernel(TTDev U, TTDev 
       dg = a >= r0 && b < r1;
     const float va = Ak[e];
     Wk[e] = dg ? fmaf(ca, va, cb * Bk[e]) : va;
+  }
+}
+
+// Nonlinear conjugate gradients on tangent vectors (the Riemannian CG of
+// the TT-completion literature the paper cites), with every scalar kept on
+// the device in sc[]: sc[0] = <xi, xi>, sc[1] = beta, sc[2] = 1 when the
+// direction was reset to -xi, sc[3] = <xi, eta>, sc[4] = <xi, T xi'>.
+// Polak-Ribiere+: beta = max(0, (<xi, xi> - <xi, T xi'>) / <xi', xi'>),
+// 0 on the first step or when <xi', xi'> is not positive.
+__global__ void cg_beta_kernel(const float *prev_sq, float *sc) {
+  if (threadIdx.x != 0) return;
+  float beta = 0.f;
+  if (prev_sq) {
+    const float q = prev_sq[0];
+    if (q > 0.f) beta = fmaxf(0.f, (sc[0] - sc[4]) / q);
+  }
+  sc[1] = beta;
+  sc[2] = 0.f;
+}
+
+// eta = -xi + sc[0] * T (dG blocks; the V and U blocks are xi's); one
+// workgroup per core.  T may be xi itself (first step, coefficient 0).
+__global__ void __launch_bounds__(kThreads) cg_axpby_kernel(TTDev U, TTDev A, TTDev T, TTDev W, const float *cb) {
+  const int k = blockIdx.x, d = U.d;
+  const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
+  const float b = cb[0];
+  const float *Ak = A.data + A.off[k];
+  const float *Tk = T.data + T.off[k];
+  float *Wk = W.data + W.off[k];
+  const int w0 = W.r[k], w1 = W.r[k + 1];
+  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
+    const int bb = (int)(e % w1), a = (int)(e / ((long)w1 * nk));
+    bool dg;
+    if (k == 0)
+      dg = bb < r1;
+    else if (k == d - 1)
+      dg = a >= r0;
+    else
+      dg = a >= r0 && bb < r1;
+    const float va = Ak[e];
+    Wk[e] = dg ? fmaf(-1.f, va, b * Tk[e]) : va;
+  }
+}
+
+// When eta is not a descent direction (<xi, eta> >= 0), reset it to -xi:
+// beta = 0, sc[2] = 1.  Every workgroup reads the same sc[3]; workgroup 0
+// writes the scalars.
+__global__ void __launch_bounds__(kThreads) cg_restart_kernel(TTDev U, TTDev A, TTDev W, float *sc) {
+  if (!(sc[3] >= 0.f)) return;
+  const int k = blockIdx.x, d = U.d;
+  const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
+  const float *Ak = A.data + A.off[k];
+  float *Wk = W.data + W.off[k];
+  const int w0 = W.r[k], w1 = W.r[k + 1];
+  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
+    const int bb = (int)(e % w1), a = (int)(e / ((long)w1 * nk));
+    bool dg;
+    if (k == 0)
+      dg = bb < r1;
+    else if (k == d - 1)
+      dg = a >= r0;
+    else
+      dg = a >= r0 && bb < r1;
+    const float va = Ak[e];
+    Wk[e] = dg ? -va : va;
+  }
+  if (k == 0 && threadIdx.x == 0) {
+    sc[1] = 0.f;
+    sc[2] = 1.f;
   }
 }
 
@@ -1464,8 +1534,38 @@ int tangent_axpby(const tt_tensor *U, float a, const tt_tensor *A, float b, cons
 int tangent_combine(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, float alpha, int add_x,
                     hipStream_t s) {
   hipLaunchKernelGGL(tangent_combine_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(P),
-                     make_dev(W), alpha, add_x ? 1.f : 0.f);
+                     make_dev(W), alpha, (const float *)nullptr, add_x ? 1.f : 0.f);
   return launch_check("tangent combine");
+}
+
+int tangent_combine_dev(const tt_tensor *U, const tt_tensor *P, tt_tensor *W, const float *alpha, float scale,
+                        int add_x, hipStream_t s) {
+  hipLaunchKernelGGL(tangent_combine_kernel, dim3(U->d), dim3(kThreads), 0, s, make_dev(U), make_dev(P),
+                     make_dev(W), scale, alpha, add_x ? 1.f : 0.f);
+  return launch_check("tangent combine (device coefficient)");
+}
+
+int cg_direction(const tt_tensor *U, const tt_tensor *xi, const tt_tensor *txi, const tt_tensor *teta,
+                 const float *prev_sq, tt_tensor *eta, float *sc, hipStream_t s) {
+  const TTDev ud = make_dev(U), xd = make_dev(xi), ed = make_dev(eta);
+  hipLaunchKernelGGL(tangent_inner_kernel, dim3(1), dim3(kThreads), 0, s, ud, xd, xd, sc + 0);
+  int rc = launch_check("cg: <xi, xi>");
+  if (rc) return rc;
+  const bool first = (txi == nullptr);
+  if (!first) {
+    hipLaunchKernelGGL(tangent_inner_kernel, dim3(1), dim3(kThreads), 0, s, ud, xd, make_dev(txi), sc + 4);
+    if ((rc = launch_check("cg: <xi, T xi'>"))) return rc;
+  }
+  hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(64), 0, s, first ? nullptr : prev_sq, sc);
+  if ((rc = launch_check("cg: beta"))) return rc;
+  // eta = -xi + beta T eta' (first step: -xi)
+  const TTDev td = first ? xd : make_dev(teta);
+  hipLaunchKernelGGL(cg_axpby_kernel, dim3(U->d), dim3(kThreads), 0, s, ud, xd, td, ed, sc + 1);
+  if ((rc = launch_check("cg: direction"))) return rc;
+  hipLaunchKernelGGL(tangent_inner_kernel, dim3(1), dim3(kThreads), 0, s, ud, xd, ed, sc + 3);
+  if ((rc = launch_check("cg: <xi, eta>"))) return rc;
+  hipLaunchKernelGGL(cg_restart_kernel, dim3(U->d), dim3(kThreads), 0, s, ud, xd, ed, sc);
+  return launch_check("cg: restart");
 }
 
 }  // namespace ttgfx

@@ -67,6 +67,7 @@ __global__ void ls_final_kernel(const float *__restrict__ part, int nblk, float 
   if (lane == 0) {
     out[0] = a;
     out[1] = b;
+    out[2] = (a > 0.f) ? b / a : 0.f;  // minimiser of the linearised loss along -P
   }
 }
 

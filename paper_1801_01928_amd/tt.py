@@ -377,6 +377,30 @@ def project_tt(U, V, Y, alpha=1.0, add_x=0):
     return W
 
 
+def tangent_combine_dev(U, P, alpha, scale, add_x, out=None):
+    """``tangent_combine`` with the coefficient scale * alpha[0] read on the
+    device (alpha: a one-element device tensor), so no host round trip."""
+    W = out if out is not None else TT(P.ns, P.ranks, device=P.device)
+    L.check(L.load().tt_tangent_combine_dev(C.byref(U.desc()), C.byref(P.desc()), _ptr(alpha), C.c_float(scale),
+                                            int(add_x), C.byref(W.desc()), _stream(P.device)))
+    return W
+
+
+def cg_direction(U, xi, Txi, Teta, prev_xi_sq, eta, scalars):
+    """Direction update of Riemannian CG on the device (tt_cg_direction):
+    eta = -xi + beta Teta with the Polak-Ribiere+ beta, reset to -xi when it
+    is not a descent direction; Txi = Teta = None on the first step.
+    scalars (5 device floats) receives <xi, xi>, beta, the reset flag,
+    <xi, eta> and <xi, Txi>."""
+    first = Txi is None
+    L.check(L.load().tt_cg_direction(C.byref(U.desc()), C.byref(xi.desc()),
+                                     None if first else C.byref(Txi.desc()),
+                                     None if first else C.byref(Teta.desc()),
+                                     C.c_void_p(0) if first else _ptr(prev_xi_sq), C.byref(eta.desc()),
+                                     _ptr(scalars), _stream(U.device)))
+    return eta
+
+
 def tangent_combine(U, P, alpha, add_x, out=None):
     """add_x X + alpha P_X(Z) from P = project_sparse(U, V, idx, z, 1, 0)
     (tt_tangent_combine); ``out`` may be P itself."""
@@ -439,15 +463,16 @@ def tangent_axpby(U, a, A, b, B, out=None):
 
 
 def line_search_terms(P, idx, y, t):
-    """Line-search terms (tt_line_search) as a device tensor of 2 floats:
-    sum_m P(i^m)^2 and sum_m (y_m - t_m) P(i^m)."""
+    """Line-search terms (tt_line_search) as a device tensor of 3 floats:
+    sum_m P(i^m)^2, sum_m (y_m - t_m) P(i^m) and their quotient (the step
+    a of X - a P; 0 when the first is 0)."""
     lib = L.load()
     idx = _idx(idx, P.d, P.device)
     _checked(P, idx)
     M = idx.shape[1]
     y = _vec(y, M, P.device)
     t = _vec(t, M, P.device)
-    out = torch.empty(2, dtype=torch.float32, device=P.device)
+    out = torch.empty(3, dtype=torch.float32, device=P.device)
     ws, nb = _workspace(L.check(lib.tt_line_search_workspace(C.byref(P.desc()), M)), P.device)
     L.check(lib.tt_line_search(C.byref(P.desc()), _ptr(idx), M, _ptr(y), _ptr(t), _ptr(out), _ptr(ws), nb,
                                _stream(P.device)))
@@ -458,43 +483,57 @@ def completion_iteration(X, idx, t, max_rank=None):
     """One step of Riemannian gradient descent for tensor completion with the
     exact line search on the linearised observed loss: g = dL/dy of the
     fused pass, P = P_X(sum_m g_m e_{i^m}), step a = sum (y - t) P(i) /
-    sum P(i)^2 from tt_line_search, Y = round(X - a P, max_rank) with X - a P
-    re-weighted from P by tt_tangent_combine.  The step size is the one
-    host-side quotient (one synchronisation per step).
-    Returns dict(loss, step, Y)."""
+    sum P(i)^2 (tt_line_search, on the device), Y = round(X - a P,
+    max_rank) with X - a P re-weighted from P by tt_tangent_combine_dev,
+    which reads a on the device.  No host synchronisation.
+    Returns dict(loss, ls, Y): loss (one device float) and ls (three device
+    floats: the two line-search sums and a)."""
     if max_rank is None:
         max_rank = max(X.ranks)
     idx = _idx(idx, X.d, X.device)
     y, g, loss, _ = gather_mse_backward(X, idx, t, want_g=True)
     U, V = orthogonalize_both(X)
     P = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
-    pp, rp = (float(v) for v in line_search_terms(P, idx, y, t).cpu())
-    a = rp / pp if pp > 0.0 else 0.0
-    W = tangent_combine(U, P, -a, 1, out=P)  # X - a P, without a second projection
+    ls = line_search_terms(P, idx, y, t)
+    W = tangent_combine_dev(U, P, ls[2:3], -1.0, 1, out=P)  # X - a P, without a second projection
     Y, _ = round_tt(W, max_rank)
-    return dict(loss=float(loss.item()), step=a, Y=Y)
+    return dict(loss=loss, ls=ls, Y=Y)
+
+
+def _history(rows, keys):
+    """Device scalars of a run's steps to floats, in one transfer."""
+    if not rows:
+        return []
+    flat = torch.cat([torch.cat([r[k].reshape(-1)[:1] for k in keys]) for r in rows]).cpu().tolist()
+    n = len(keys)
+    return [dict(zip(keys, flat[i * n:(i + 1) * n])) for i in range(len(rows))]
 
 
 def riemannian_completion(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
     """Riemannian gradient descent for tensor completion: ``iters`` steps of
-    ``completion_iteration`` from X0.  Returns (X, history), one
-    dict(loss, step, test_rmse) per step; test_rmse is the held-out RMSE of
-    the iterate before the step (from the fused pass on the test entries)."""
+    ``completion_iteration`` from X0, with no host synchronisation inside
+    the loop.  Returns (X, history), one dict(loss, step, test_rmse) per
+    step; test_rmse is the held-out RMSE of the iterate before the step
+    (from the fused pass on the test entries), None without test entries."""
     X = X0
     idx = _idx(idx, X.d, X.device)
     t = _vec(t, idx.shape[1], X.device)
     if idx_test is not None:
         idx_test = _idx(idx_test, X.d, X.device)
         t_test = _vec(t_test, idx_test.shape[1], X.device)
-    hist = []
+    rows = []
     for _ in range(iters):
-        rmse = None
+        row = {}
         if idx_test is not None:
-            _, lt, _ = gather_mse_backward(X, idx_test, t_test, want_y=False)
-            rmse = float(lt.item()) ** 0.5
+            _, row["test_mse"], _ = gather_mse_backward(X, idx_test, t_test, want_y=False)
         out = completion_iteration(X, idx, t, max_rank)
-        hist.append(dict(loss=out["loss"], step=out["step"], test_rmse=rmse))
+        row["loss"], row["step"] = out["loss"], out["ls"][2:3]
+        rows.append(row)
         X = out["Y"]
+    keys = ["loss", "step"] + (["test_mse"] if idx_test is not None else [])
+    hist = _history(rows, keys)
+    for h in hist:
+        h["test_rmse"] = max(h.pop("test_mse"), 0.0) ** 0.5 if "test_mse" in h else None
     return X, hist
 
 
@@ -502,60 +541,68 @@ def cg_iteration(X, idx, t, max_rank=None, prev=None):
     """One step of Riemannian conjugate gradients for tensor completion:
     xi = P_X(grad) from the fused pass and the sparse projection; with the
     previous step's xi', eta' (``prev``), their transports P_X(xi'),
-    P_X(eta') by tt_project_tt; beta = max(0, <xi, xi - P_X xi'> /
-    <xi', xi'>) (Polak-Ribiere+, tt_tangent_inner); eta = -xi + beta
-    P_X(eta') (tt_tangent_axpby), reset to -xi when it is not a descent
-    direction; the exact linearised line search along eta (tt_line_search);
-    Y = round(X + a eta).  Host synchronisations: the inner products and the
-    step.  Returns dict(loss, step, beta, Y, xi, eta, xi_sq) (xi, eta:
-    tangent TTs at X, for the next step)."""
+    P_X(eta') by tt_project_tt; the direction eta = -xi + beta P_X(eta')
+    with the Polak-Ribiere+ beta, reset to -xi when it is not a descent
+    direction (tt_cg_direction); the exact linearised line search along eta
+    (tt_line_search), Y = round(X + a eta) with a = -ls[2] read on the
+    device.  No host synchronisation.  Returns dict(loss, ls, scalars, Y,
+    xi, eta): loss, ls (as for completion_iteration, along eta) and the five
+    CG scalars of tt_cg_direction are device tensors; xi, eta are tangent
+    TTs at X for the next step.  ``cg_values`` turns them into floats."""
     if max_rank is None:
         max_rank = max(X.ranks)
     idx = _idx(idx, X.d, X.device)
     y, g, loss, _ = gather_mse_backward(X, idx, t, want_g=True)
     U, V = orthogonalize_both(X)
     xi = project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
-    beta = 0.0
-    eta = None
-    if prev is not None and prev["xi_sq"] > 0.0:
+    sc = torch.empty(5, dtype=torch.float32, device=X.device)
+    if prev is not None:
         Txi = project_tt(U, V, prev["xi"])
         Teta = project_tt(U, V, prev["eta"])
-        xx, xt = (float(v) for v in torch.cat([tangent_inner(U, xi, xi), tangent_inner(U, xi, Txi)]).cpu())
-        beta = max(0.0, (xx - xt) / prev["xi_sq"])
-        eta = tangent_axpby(U, -1.0, xi, beta, Teta, out=Teta)
-        if float(tangent_inner(U, xi, eta).item()) >= 0.0:
-            eta, beta = None, 0.0
+        eta = cg_direction(U, xi, Txi, Teta, prev["scalars"][0:1], Teta, sc)
     else:
-        xx = float(tangent_inner(U, xi, xi).item())
-    if eta is None:
-        eta = tangent_axpby(U, -1.0, xi, 0.0, xi)
-    pp, rp = (float(v) for v in line_search_terms(eta, idx, y, t).cpu())
-    a = -rp / pp if pp > 0.0 else 0.0
-    W = tangent_combine(U, eta, a, 1)  # X + a eta
+        eta = cg_direction(U, xi, None, None, None, TT(xi.ns, xi.ranks, device=xi.device), sc)
+    ls = line_search_terms(eta, idx, y, t)
+    W = tangent_combine_dev(U, eta, ls[2:3], -1.0, 1)  # X + a eta, a = -ls[2]
     Y, _ = round_tt(W, max_rank)
-    return dict(loss=float(loss.item()), step=a, beta=beta, Y=Y, xi=xi, eta=eta, xi_sq=xx)
+    return dict(loss=loss, ls=ls, scalars=sc, Y=Y, xi=xi, eta=eta)
+
+
+def cg_values(out):
+    """Floats of one CG step for reporting: loss, step a (Y = round(X + a
+    eta)), beta, whether the direction was reset, and <xi, xi>."""
+    v = torch.cat([out["loss"].reshape(1), out["ls"], out["scalars"]]).cpu().tolist()
+    return dict(loss=v[0], step=-v[3], beta=v[5], restarted=bool(v[6] > 0.5), xi_sq=v[4])
 
 
 def riemannian_cg(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
     """Riemannian conjugate gradients for tensor completion: ``iters`` steps
-    of ``cg_iteration`` from X0.  Returns (X, history), one dict(loss, step,
-    beta, test_rmse) per step (test_rmse of the iterate before the step)."""
+    of ``cg_iteration`` from X0, with no host synchronisation inside the
+    loop.  Returns (X, history), one dict(loss, step, beta, restarted,
+    test_rmse) per step (test_rmse of the iterate before the step)."""
     X = X0
     idx = _idx(idx, X.d, X.device)
     t = _vec(t, idx.shape[1], X.device)
     if idx_test is not None:
         idx_test = _idx(idx_test, X.d, X.device)
         t_test = _vec(t_test, idx_test.shape[1], X.device)
-    hist = []
+    rows = []
     prev = None
     for _ in range(iters):
-        rmse = None
+        row = {}
         if idx_test is not None:
-            _, lt, _ = gather_mse_backward(X, idx_test, t_test, want_y=False)
-            rmse = float(lt.item()) ** 0.5
+            _, row["test_mse"], _ = gather_mse_backward(X, idx_test, t_test, want_y=False)
         prev = cg_iteration(X, idx, t, max_rank, prev)
-        hist.append(dict(loss=prev["loss"], step=prev["step"], beta=prev["beta"], test_rmse=rmse))
+        row.update(loss=prev["loss"], step=prev["ls"][2:3], beta=prev["scalars"][1:2],
+                   restarted=prev["scalars"][2:3])
+        rows.append(row)
         X = prev["Y"]
+    keys = ["loss", "step", "beta", "restarted"] + (["test_mse"] if idx_test is not None else [])
+    hist = _history(rows, keys)
+    for h in hist:
+        h["step"] = -h["step"]
+        h["restarted"] = bool(h["restarted"] > 0.5)
+        h["test_rmse"] = max(h.pop("test_mse"), 0.0) ** 0.5 if "test_mse" in h else None
     return X, hist
 
 

@@ -59,6 +59,8 @@ def test_line_search_terms_match_oracle(gpu_lib, case):
     want = [float(np.dot(pv, pv)), float(np.dot(yv - t, pv))]
     assert abs(got[0] - want[0]) <= 1e-5 * abs(want[0])
     assert abs(got[1] - want[1]) <= 1e-5 * np.sqrt(np.dot(yv - t, yv - t) * want[0])
+    # the step quotient, computed on the device
+    assert abs(got[2] - want[1] / want[0]) <= 2e-5 * np.sqrt(np.dot(yv - t, yv - t) / want[0])
 
 
 def test_line_search_empty(gpu_lib):
@@ -66,7 +68,7 @@ def test_line_search_empty(gpu_lib):
     X = tt.TT([4, 4], [1, 2, 1])
     e = torch.zeros((2, 0), dtype=torch.int32, device="cuda")
     z = torch.zeros(0, device="cuda")
-    assert tt.line_search_terms(X, e, z, z).cpu().tolist() == [0.0, 0.0]
+    assert tt.line_search_terms(X, e, z, z).cpu().tolist() == [0.0, 0.0, 0.0]
 
 
 def test_completion_iterations_match_oracle(gpu_lib):
@@ -84,8 +86,9 @@ def test_completion_iterations_match_oracle(gpu_lib):
         Xc = [c.astype(np.float64) for c in X.numpy_cores()]
         ref = R.completion_iteration(Xc, p.idx, t.astype(np.float32), 4)
         out = tt.completion_iteration(X, idxg, tg, 4)
-        assert abs(out["loss"] - ref["loss"]) <= 1e-5 * ref["loss"]
-        assert abs(out["step"] - ref["step"]) <= 1e-4 * abs(ref["step"])
+        loss, step = float(out["loss"]), float(out["ls"][2])
+        assert abs(loss - ref["loss"]) <= 1e-5 * ref["loss"]
+        assert abs(step - ref["step"]) <= 1e-4 * abs(ref["step"])
         assert _tt_rel(out["Y"].numpy_cores(), ref["Y"]) <= 1e-4
         X = out["Y"]
 
@@ -227,13 +230,45 @@ def test_cg_iterations_match_oracle(gpu_lib):
                                                [c.astype(np.float64) for c in prev_gpu["xi"].numpy_cores()]))
         ref = R.cg_iteration(Xc, p.idx, t.astype(np.float32), 4, prev_ref)
         out = tt.cg_iteration(X, idxg, tg, 4, prev_gpu)
-        assert abs(out["loss"] - ref["loss"]) <= 1e-5 * ref["loss"]
-        assert abs(out["beta"] - ref["beta"]) <= 1e-3 * max(ref["beta"], 1e-3)
+        v = tt.cg_values(out)
+        assert abs(v["loss"] - ref["loss"]) <= 1e-5 * ref["loss"]
+        assert abs(v["beta"] - ref["beta"]) <= 1e-3 * max(ref["beta"], 1e-3)
         saw_beta = saw_beta or ref["beta"] > 0.0
-        assert abs(out["step"] - ref["step"]) <= 1e-4 * abs(ref["step"])
+        assert abs(v["step"] - ref["step"]) <= 1e-4 * abs(ref["step"])
         assert _tt_rel(out["Y"].numpy_cores(), ref["Y"]) <= 1e-4
         X, prev_gpu = out["Y"], out
     assert saw_beta
+
+
+def test_cg_iterations_match_oracle_d10(gpu_lib):
+    """Three CG steps at the completion workload's shape (d=10, n=10,
+    canonical rank 16, planted rank 8) on 2^16 of its observed entries:
+    loss, beta, restart decision and step against the oracle's step run on
+    the GPU's own iterate, previous gradient and direction."""
+    tt = gpu_lib
+    p = W.completion_d10(M=1 << 16)
+    t = (oracle.gather(p.planted, p.idx) + p.noise).astype(np.float32)
+    X = tt.TT.from_cores(p.cores)
+    idxg = torch.as_tensor(p.idx).cuda()
+    tg = torch.as_tensor(t).cuda()
+    prev_gpu = prev_ref = None
+    for it in range(3):
+        print("cg d10 iteration", it, flush=True)
+        Xc = [c.astype(np.float64) for c in X.numpy_cores()]
+        if prev_gpu is not None:
+            xi = [c.astype(np.float64) for c in prev_gpu["xi"].numpy_cores()]
+            prev_ref = dict(xi=xi, eta=[c.astype(np.float64) for c in prev_gpu["eta"].numpy_cores()],
+                            xi_sq=oracle.inner(xi, xi))
+        ref = R.cg_iteration(Xc, p.idx, t, 16, prev_ref)
+        out = tt.cg_iteration(X, idxg, tg, 16, prev_gpu)
+        v = tt.cg_values(out)
+        print("  loss %.6g/%.6g beta %.6g/%.6g step %.6g/%.6g" % (v["loss"], ref["loss"], v["beta"], ref["beta"],
+                                                                 v["step"], ref["step"]), flush=True)
+        assert abs(v["loss"] - ref["loss"]) <= 1e-5 * ref["loss"]
+        assert abs(v["beta"] - ref["beta"]) <= 1e-3 * max(ref["beta"], 1e-3)
+        assert abs(v["step"] - ref["step"]) <= 1e-4 * abs(ref["step"])
+        assert _tt_rel(out["Y"].numpy_cores(), ref["Y"]) <= 1e-4
+        X, prev_gpu = out["Y"], out
 
 
 def test_cg_recovers_planted_tensor(gpu_lib):
