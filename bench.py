@@ -340,7 +340,8 @@ def batched_leg(tt, W, reps=3):
     off = np.concatenate([[0], np.cumsum([p.M for p in inst])])
     plan = tt.BatchedPlan(Xs, idx, t, off)
     s = torch.cuda.Stream()
-    chunk = plan.autotune(s)
+    plan.autotune(s)
+    plan_cfg = plan.config()
     plan.capture(s)
     plan.run(s)
     s.synchronize()
@@ -358,7 +359,7 @@ def batched_leg(tt, W, reps=3):
             "roofline": {"bound": "mfma (per tensor: max of flop/157.3 TF and 76 B/entry / 8 TB/s)",
                          "ideal_ms": round(ideal_s * 1e3, 4), "algorithmic_gflop": round(flop / 1e9, 2),
                          "frac": round(ideal_s * 1e3 / graph_ms, 4)},
-            "entries": int(M), "autotuned_chunk": chunk,
+            "entries": int(M), "autotuned": plan_cfg,
             "graph_ms": round(graph_ms, 3), "plain_ms": round(plain_ms, 3),
             "graph_entries_per_s": round(M / (graph_ms * 1e-3), 1),
             "plain_entries_per_s": round(M / (plain_ms * 1e-3), 1),

@@ -341,6 +341,12 @@ int tt_round_ranks(const tt_tensor *Y, int32_t max_rank, int32_t *out_r /*(host)
 int64_t tt_round_workspace(const tt_tensor *Y, int32_t max_rank);
 int tt_round(const tt_tensor *Y, int32_t max_rank, tt_tensor *out,
              float *disc_sq, void *ws, size_t ws_bytes, void *stream);
+/* tt_round with a convergence report: status: (dev) int32 [1] or NULL,
+ * receives the number of bonds whose one-sided Jacobi SVD did not converge
+ * within its 40 sweeps (their factors are then used as they stand). */
+int tt_round_status(const tt_tensor *Y, int32_t max_rank, tt_tensor *out,
+                    float *disc_sq, int32_t *status, void *ws, size_t ws_bytes,
+                    void *stream);
 
 /* ------------------------------------------------------------------ A8 */
 /* Gram matrix of two batches (Riemannian Geometry Operations; Table 1
@@ -371,10 +377,22 @@ int tt_gram(const tt_batch *A, const tt_batch *B, float *G,
  *   Do not run tt_timer_start() across a capture.
  * tt_plan_run_plain: the same results by b plain tt_gather_mse_backward
  *   launch sequences (the reference that the batched form is compared with).
- * tt_plan_autotune: times the tile-chunk size of the work list (1..16) and
- *   keeps the fastest; *chosen receives it.  With the environment variable
- *   TTGFX_TUNE_CACHE naming a file, choices are read from / appended to it
- *   (keyed by the batch's shape signature).  Drops a captured graph. */
+ * tt_plan_autotune: times every tile shape of the batched kernel (entries
+ *   per tile of the rank-16 and rank-32 classes and threads per workgroup:
+ *   1024/512/512, 512/512/512, 512/256/256, 1024/512/768) with every
+ *   work-item chunk (1, 2, 4, 8, 16 tiles) and keeps the fastest pair;
+ *   *chosen receives the chunk, tt_plan_config the whole choice.  With the
+ *   environment variable TTGFX_TUNE_CACHE naming a file, choices are read
+ *   from / appended to it, keyed by device architecture, CU count, d, mode
+ *   sizes, tensors per rank class and the entry count's power-of-two
+ *   bucket.  Drops a captured graph.
+ * tt_plan_config: cfg (host) [4] = chunk, entries per tile at rank class
+ *   16, at rank class 32, threads per workgroup of the plan's current
+ *   launch.
+ * tt_plan_set_config: sets that launch from cfg (host) [4] in the same
+ *   order (the shape must be one of the four above; TT_ERR_UNSUPPORTED
+ *   otherwise).  Rewrites the plan's work list with a synchronous copy:
+ *   call it with no run of the plan in flight.  Drops a captured graph. */
 typedef struct tt_plan tt_plan;
 int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t,
                    const int64_t *entry_off, const tt_batch *grads, float *loss,
@@ -383,6 +401,8 @@ int tt_plan_run(tt_plan *plan, void *stream);
 int tt_plan_capture(tt_plan *plan, void *stream);
 int tt_plan_run_plain(tt_plan *plan, void *stream);
 int tt_plan_autotune(tt_plan *plan, void *stream, int32_t *chosen);
+int tt_plan_config(const tt_plan *plan, int32_t *cfg);
+int tt_plan_set_config(tt_plan *plan, const int32_t *cfg);
 void tt_plan_destroy(tt_plan *plan);
 
 /* ----------------------------------------------------------------- A10 */

@@ -96,6 +96,7 @@ SIGNATURES = {
     "tt_round_ranks": (C.c_int, [P_TT, I32, PI32]),
     "tt_round_workspace": (I64, [P_TT, I32]),
     "tt_round": (C.c_int, [P_TT, I32, P_TT, VP, VP, SZ, VP]),
+    "tt_round_status": (C.c_int, [P_TT, I32, P_TT, VP, VP, VP, SZ, VP]),
     "tt_gram_workspace": (I64, [P_BATCH, P_BATCH]),
     "tt_gram": (C.c_int, [P_BATCH, P_BATCH, VP, VP, SZ, VP]),
     "tt_plan_create": (C.c_int, [P_BATCH, VP, VP, PI64, P_BATCH, VP, C.POINTER(VP)]),
@@ -103,6 +104,8 @@ SIGNATURES = {
     "tt_plan_capture": (C.c_int, [VP, VP]),
     "tt_plan_run_plain": (C.c_int, [VP, VP]),
     "tt_plan_autotune": (C.c_int, [VP, VP, PI32]),
+    "tt_plan_config": (C.c_int, [VP, PI32]),
+    "tt_plan_set_config": (C.c_int, [VP, PI32]),
     "tt_plan_destroy": (None, [VP]),
     "tt_matmul_workspace": (I64, [P_TTM, I64, C.c_int]),
     "tt_matmul": (C.c_int, [P_TTM, VP, I64, VP, C.c_int, VP, SZ, VP]),

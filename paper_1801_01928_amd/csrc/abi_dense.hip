@@ -324,6 +324,11 @@ int64_t tt_round_workspace(const tt_tensor *Y, int32_t max_rank) {
 
 int tt_round(const tt_tensor *Y, int32_t max_rank, tt_tensor *out, float *disc_sq, void *ws,
              size_t ws_bytes, void *stream) {
+  return tt_round_status(Y, max_rank, out, disc_sq, nullptr, ws, ws_bytes, stream);
+}
+
+int tt_round_status(const tt_tensor *Y, int32_t max_rank, tt_tensor *out, float *disc_sq, int32_t *status,
+                    void *ws, size_t ws_bytes, void *stream) {
   int rc = validate_tt(Y, "Y", DENSE_MAX_RANK);
   if (rc) return rc;
   if (max_rank < 1) return set_error(TT_ERR_ARG, "max_rank must be >= 1");
@@ -333,7 +338,7 @@ int tt_round(const tt_tensor *Y, int32_t max_rank, tt_tensor *out, float *disc_s
   dense_round_ranks(Y, max_rank, want);
   if ((rc = check_ranks(out, want, "round"))) return rc;
   if ((rc = check_ws(ws, ws_bytes, dense_ws(Y), "round"))) return rc;
-  return dense_round(Y, max_rank, out, disc_sq, ws, ws_bytes, (hipStream_t)stream);
+  return dense_round(Y, max_rank, out, disc_sq, status, ws, ws_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -11,7 +11,7 @@ int dense_round_ranks(const tt_tensor *Y, int max_rank, int32_t *out);
 size_t dense_ws(const tt_tensor *X);
 int dense_orth(const tt_tensor *X, int dir, tt_tensor *O, void *ws, size_t bytes, hipStream_t s);
 int dense_orth_both(const tt_tensor *X, tt_tensor *OL, tt_tensor *OR, void *ws, size_t bytes, hipStream_t s);
-int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, void *ws, size_t bytes,
+int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, int *status, void *ws, size_t bytes,
                 hipStream_t s);
 size_t tangent_ws(const tt_tensor *U);
 size_t project_tt_ws(const tt_tensor *U, const tt_tensor *Y);

@@ -419,7 +419,7 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
     __syncthreads();
     if (!any) return sweep + 1;
   }
-  return 40;
+  return -1;  // not converged within 40 sweeps
 }
 
 // The two GEMM helpers below run on the fp32 matrix cores
@@ -652,10 +652,11 @@ __global__ void __launch_bounds__(kThreads) orth_both_kernel(TTDev X, TTDev OL, 
 
 // TT rounding: right-to-left LQ sweep, then left-to-right truncated SVDs.
 __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int max_rank,
-                                                         float *disc, DenseBufs b) {
+                                                         float *disc, int *status, DenseBufs b) {
   __shared__ Shared sh;
   __shared__ int n[TT_MAX_D], r[TT_MAX_D + 1];
   const int d = Y.d;
+  int unconverged = 0;  // bonds whose Jacobi SVD hit the sweep limit (thread 0's count)
   for (int k = threadIdx.x; k < d; k += kThreads) n[k] = Y.n[k];
   for (int k = threadIdx.x; k <= d; k += kThreads) r[k] = Y.r[k];
   WorkTT w{b.work, b.slot};
@@ -678,7 +679,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       sh.jb[e] = (l < c && j < p && l >= j) ? b.wm[(long)l * m + j] : 0.f;
     }
     __syncthreads();
-    blk_jacobi(c, p, sh);
+    if (blk_jacobi(c, p, sh) < 0) ++unconverged;
     // singular values (column norms of B V) and their descending order
     for (int j = wave; j < p; j += kWaves) {
       const float x = lane < c ? sh.jb[j * kJac + lane] : 0.f;
@@ -738,6 +739,7 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
     __syncthreads();
   }
   copy_out(w, d, n, r, O);
+  if (status && threadIdx.x == 0) status[0] = unconverged;
 }
 
 // Tangent cores and the rank-2r tangent TT (one workgroup per mode):
@@ -1303,14 +1305,14 @@ int dense_orth_both(const tt_tensor *X, tt_tensor *OL, tt_tensor *OR, void *ws, 
   return launch_check("orthogonalize both");
 }
 
-int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, void *ws, size_t bytes,
+int dense_round(const tt_tensor *Y, int max_rank, tt_tensor *O, float *disc, int *status, void *ws, size_t bytes,
                 hipStream_t s) {
   DenseBufs b;
   int rc = dense_bufs(Y, ws, bytes, b);
   if (rc) return rc;
   timer_before(s);
   hipLaunchKernelGGL(round_kernel, dim3(1), dim3(kThreads), 0, s, make_dev(Y), make_dev(O), max_rank,
-                     disc, b);
+                     disc, status, b);
   timer_after(s);
   return launch_check("round");
 }

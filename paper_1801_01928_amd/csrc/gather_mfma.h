@@ -44,9 +44,14 @@ struct MfInst {
   int rclass;              // 16 or 32
 };
 
-#define MF_BATCH_THREADS 512
-#define MF_BATCH_T16 1024  // entries per tile of the batched kernel, rank class 16
-#define MF_BATCH_T32 512   // and rank class 32
+// Tile shape of the batched kernel: entries per tile of rank classes 16
+// and 32, threads per workgroup.
+struct MfBatchShape {
+  int t16, t32, threads;
+};
+#define MF_BATCH_SHAPES 4
+#define MF_BATCH_MIN_T16 512  // smallest tiles over the shapes (work-list bound)
+#define MF_BATCH_MIN_T32 256
 
 // Work item of the batched kernel: `ntile` consecutive tiles of one tensor.
 struct MfWorkItem {
@@ -66,9 +71,11 @@ struct MfBatchArgs {
   int nb16, nb32;          // blocks-per-mode capacities of the two classes
 };
 
-size_t mfma_batch_lds(int d, const int *n);  // LDS bytes of the batched kernel for these modes
+MfBatchShape mfma_batch_shape(int shape);
+size_t mfma_batch_lds(int shape, int d, const int *n);  // dynamic LDS bytes of the batched kernel
+int mfma_batch_wgs_per_cu(int shape, int d, const int *n);
 int mfma_batch_prepare();
-int mfma_batch_launch(const MfBatchArgs &a, int nwg, size_t lds, hipStream_t s);
+int mfma_batch_launch(const MfBatchArgs &a, int shape, int nwg, size_t lds, hipStream_t s);
 int mfma_device_cus();
 
 // True when every descriptor fits the MFMA kernels (2 <= d <= 16, ranks <= 32,

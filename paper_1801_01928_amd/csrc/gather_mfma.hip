@@ -652,11 +652,14 @@ __global__ void __launch_bounds__(NTHR) fused_kernel(MfInst p, Grid g) {
 // count) items from an atomic counter (items are in decreasing-cost order)
 // until the list is exhausted; both rank classes share the launch.  Per
 // tensor: gradients accumulate into its zeroed padded buffer (DIRECT), the
-// loss into loss[b] (mean over that tensor's entries).
-__global__ void __launch_bounds__(MF_BATCH_THREADS) batched_kernel(MfBatchArgs a) {
+// loss into loss[b] (mean over that tensor's entries).  T16 and T32 are the
+// entries per tile of the two rank classes, NTHR the threads per workgroup
+// (the tile shape the plan's autotuner chooses).
+template <int T16, int T32, int NTHR>
+__global__ void __launch_bounds__(NTHR) batched_kernel(MfBatchArgs a) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int item_sh;
-  __shared__ float red[MF_BATCH_THREADS / 64];
+  __shared__ float red[NTHR / 64];
   float *stash = a.stash + (long long)blockIdx.x * a.stash_stride;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(a.counter, 1);
@@ -669,17 +672,13 @@ __global__ void __launch_bounds__(MF_BATCH_THREADS) batched_kernel(MfBatchArgs a
     for (int t = 0; t < w.ntile; ++t) {
       float lp = 0.f;
       if (w.rclass == 16) {
-        constexpr int T = MF_BATCH_T16;
-        const long long e0 = (long long)(w.tile0 + t) * T;
-        const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
-        run_tile<16, T, MF_BATCH_THREADS, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb16, nullptr,
-                                                                false, lp);
+        const long long e0 = (long long)(w.tile0 + t) * T16;
+        const int cnt = (int)((p.M - e0) < T16 ? (p.M - e0) : T16);
+        run_tile<16, T16, NTHR, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb16, nullptr, false, lp);
       } else {
-        constexpr int T = MF_BATCH_T32;
-        const long long e0 = (long long)(w.tile0 + t) * T;
-        const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
-        run_tile<32, T, MF_BATCH_THREADS, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb32, nullptr,
-                                                                false, lp);
+        const long long e0 = (long long)(w.tile0 + t) * T32;
+        const int cnt = (int)((p.M - e0) < T32 ? (p.M - e0) : T32);
+        run_tile<32, T32, NTHR, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb32, nullptr, false, lp);
       }
       // this tile's share of the tensor's mean squared residual
       for (int off = 32; off > 0; off >>= 1) lp += __shfl_xor(lp, off);
@@ -687,7 +686,7 @@ __global__ void __launch_bounds__(MF_BATCH_THREADS) batched_kernel(MfBatchArgs a
       __syncthreads();
       if (threadIdx.x == 0) {
         float s = 0.f;
-        for (int wv = 0; wv < MF_BATCH_THREADS / 64; ++wv) s += red[wv];
+        for (int wv = 0; wv < NTHR / 64; ++wv) s += red[wv];
         unsafeAtomicAdd(p.loss, s * p.inv_m);
       }
       __syncthreads();
@@ -800,6 +799,11 @@ struct TileShape {
 constexpr TileShape kShapes16[2] = {{1024, 768}, {512, 512}};
 constexpr TileShape kShapes32[2] = {{512, 512}, {256, 256}};
 constexpr TileShape kShape64 = {256, 512};
+
+// Tile shapes of the batched kernel: entries per tile of rank class 16 and
+// 32, threads per workgroup.  The plan's autotuner picks one.
+constexpr MfBatchShape kBatchShapes[MF_BATCH_SHAPES] = {
+    {1024, 512, 512}, {512, 512, 512}, {512, 256, 256}, {1024, 512, 768}};
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kBatchStaticLds = 1024;
 
@@ -913,22 +917,24 @@ static bool fits_class(const tt_tensor *X) {
     if (X->n[k] > MfTraits<R>::MAX_N) return false;
   // every tile shape of the class (and the batched kernel's) fits the LDS,
   // so the choice of shape never changes which kernel serves a tensor
-  TileShape shapes[3];
+  TileShape shapes[2 + MF_BATCH_SHAPES];
   int ns = 0;
   if (R == 16) {
     shapes[ns++] = kShapes16[0];
     shapes[ns++] = kShapes16[1];
-    shapes[ns++] = {MF_BATCH_T16, MF_BATCH_THREADS};
   } else if (R == 32) {
     shapes[ns++] = kShapes32[0];
     shapes[ns++] = kShapes32[1];
-    shapes[ns++] = {MF_BATCH_T32, MF_BATCH_THREADS};
   } else {
     shapes[ns++] = kShape64;
   }
+  const int nsingle = ns;
+  if (R <= 32)
+    for (int i = 0; i < MF_BATCH_SHAPES; ++i)
+      shapes[ns++] = {R == 16 ? kBatchShapes[i].t16 : kBatchShapes[i].t32, kBatchShapes[i].threads};
   for (int i = 0; i < ns; ++i) {
-    const int acc = (i < 2 && R == 16) ? ACC_SLAB : ACC_DIRECT;
-    const int cap = (i == 2) ? kLdsBytes - kBatchStaticLds : kLdsBytes;
+    const int acc = (i < nsingle && R == 16) ? ACC_SLAB : ACC_DIRECT;
+    const int cap = (i >= nsingle) ? kLdsBytes - kBatchStaticLds : kLdsBytes;
     if (mf_layout(R, shapes[i].T, shapes[i].threads, acc, X->d, X->n).total > cap) return false;
   }
   return true;
@@ -1084,29 +1090,58 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
   return TT_OK;
 }
 
-size_t mfma_batch_lds(int d, const int *n) {
-  const int a = mf_layout(16, MF_BATCH_T16, MF_BATCH_THREADS, ACC_DIRECT, d, n).total;
-  const int b = mf_layout(32, MF_BATCH_T32, MF_BATCH_THREADS, ACC_DIRECT, d, n).total;
+MfBatchShape mfma_batch_shape(int shape) { return kBatchShapes[shape]; }
+
+size_t mfma_batch_lds(int shape, int d, const int *n) {
+  const MfBatchShape &sh = kBatchShapes[shape];
+  const int a = mf_layout(16, sh.t16, sh.threads, ACC_DIRECT, d, n).total;
+  const int b = mf_layout(32, sh.t32, sh.threads, ACC_DIRECT, d, n).total;
   return (size_t)(a > b ? a : b);
 }
+
+int mfma_batch_wgs_per_cu(int shape, int d, const int *n) {
+  return wgs_per_cu((int)mfma_batch_lds(shape, d, n) + kBatchStaticLds, kBatchShapes[shape].threads);
+}
+
+namespace {
+template <int S>
+const void *batch_fn() {
+  constexpr MfBatchShape sh = kBatchShapes[S];
+  return (const void *)batched_kernel<sh.t16, sh.t32, sh.threads>;
+}
+template <int S>
+void batch_launch(const MfBatchArgs &a, int nwg, size_t lds, hipStream_t s) {
+  constexpr MfBatchShape sh = kBatchShapes[S];
+  hipLaunchKernelGGL((batched_kernel<sh.t16, sh.t32, sh.threads>), dim3(nwg), dim3(sh.threads), lds, s, a);
+}
+}  // namespace
 
 int mfma_batch_prepare() {
   static int done_dev = -2;
   const int dev = device_id();
   if (done_dev == dev) return TT_OK;
-  // the kernel also holds a few static LDS words (work item, loss partials)
-  hipError_t e = hipFuncSetAttribute((const void *)batched_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     kLdsBytes - kBatchStaticLds);
-  if (e != hipSuccess) return hip_check(e, "batched kernel LDS attribute");
+  static_assert(MF_BATCH_SHAPES == 4, "one entry per shape below");
+  const void *fns[MF_BATCH_SHAPES] = {batch_fn<0>(), batch_fn<1>(), batch_fn<2>(), batch_fn<3>()};
+  for (const void *f : fns) {
+    // the kernel also holds a few static LDS words (work item, loss partials)
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kBatchStaticLds);
+    if (e != hipSuccess) return hip_check(e, "batched kernel LDS attribute");
+  }
   done_dev = dev;
   return TT_OK;
 }
 
-int mfma_batch_launch(const MfBatchArgs &a, int nwg, size_t lds, hipStream_t s) {
+int mfma_batch_launch(const MfBatchArgs &a, int shape, int nwg, size_t lds, hipStream_t s) {
   int rc = mfma_batch_prepare();
   if (rc) return rc;
+  if (shape < 0 || shape >= MF_BATCH_SHAPES) return set_error(TT_ERR_ARG, "batched kernel: shape %d", shape);
   timer_before(s);
-  hipLaunchKernelGGL(batched_kernel, dim3(nwg), dim3(MF_BATCH_THREADS), lds, s, a);
+  switch (shape) {
+    case 0: batch_launch<0>(a, nwg, lds, s); break;
+    case 1: batch_launch<1>(a, nwg, lds, s); break;
+    case 2: batch_launch<2>(a, nwg, lds, s); break;
+    default: batch_launch<3>(a, nwg, lds, s); break;
+  }
   timer_after(s);
   return launch_check("batched kernel");
 }

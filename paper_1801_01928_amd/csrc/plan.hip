@@ -129,8 +129,8 @@ struct tt_plan {
   long long grad_begin = 0, grad_floats = 0;
   float *stash = nullptr;
   long long stash_stride = 0;
-  int nb16 = 0, nb32 = 0;
-  int nwg = 0;
+  int nmax = 1;                 // largest mode size
+  int shape = 0;                // tile shape of the batched kernel (mfma_batch_shape)
   int chunk = 4;
   int nitems = 0;
   int max_items = 0;
@@ -142,13 +142,32 @@ struct tt_plan {
 
 namespace {
 
+// Launch geometry of the batched kernel for one tile shape: stash blocks per
+// mode of each rank class, stash floats per workgroup, workgroups.
+struct ShapeGeo {
+  int nb16, nb32, nwg;
+  long long stash_stride;
+};
+
+ShapeGeo shape_geo(const tt_plan *P, int shape) {
+  const MfBatchShape sh = mfma_batch_shape(shape);
+  ShapeGeo g;
+  g.nb16 = sh.t16 / 16 + P->nmax;
+  g.nb32 = sh.t32 / 16 + P->nmax;
+  const long long dm1 = P->md.d > 1 ? P->md.d - 1 : 1;
+  g.stash_stride = std::max(dm1 * g.nb16 * 64 * 4, dm1 * g.nb32 * 64 * 8);
+  g.nwg = mfma_device_cus() * mfma_batch_wgs_per_cu(shape, P->md.d, P->md.n);
+  return g;
+}
+
 int build_items(tt_plan *P) {
   std::vector<MfWorkItem> items;
   std::vector<long long> cost;
+  const MfBatchShape sh = mfma_batch_shape(P->shape);
   for (int j = 0; j < P->b; ++j) {
     const long long M = P->entry_off[j + 1] - P->entry_off[j];
     const int R = P->rclass[j];
-    const int T = (R == 16) ? MF_BATCH_T16 : MF_BATCH_T32;
+    const int T = (R == 16) ? sh.t16 : sh.t32;
     const int ntiles = (int)((M + T - 1) / T);
     for (int t0 = 0; t0 < ntiles; t0 += P->chunk) {
       const int nt = std::min(P->chunk, ntiles - t0);
@@ -182,11 +201,14 @@ int issue(tt_plan *P, hipStream_t s) {
   a.items = P->ditems;
   a.nitems = P->nitems;
   a.counter = P->counter;
+  const ShapeGeo g = shape_geo(P, P->shape);
   a.stash = P->stash;
-  a.stash_stride = P->stash_stride;
-  a.nb16 = P->nb16;
-  a.nb32 = P->nb32;
-  if (P->nitems > 0 && (rc = mfma_batch_launch(a, P->nwg, mfma_batch_lds(P->md.d, P->md.n), s))) return rc;
+  a.stash_stride = g.stash_stride;
+  a.nb16 = g.nb16;
+  a.nb32 = g.nb32;
+  if (P->nitems > 0 &&
+      (rc = mfma_batch_launch(a, P->shape, g.nwg, mfma_batch_lds(P->shape, P->md.d, P->md.n), s)))
+    return rc;
   hipLaunchKernelGGL(unpad_batch_kernel, dim3(P->md.d, P->b), dim3(256), 0, s, P->dmeta, P->md, P->gp);
   return launch_check("plan: unpad gradients");
 }
@@ -197,15 +219,28 @@ void drop_graph(tt_plan *P) {
   P->graph_stream = nullptr;
 }
 
+// Tuning-cache key: device architecture and CU count, d, the mode sizes'
+// sum, the tensor count per rank class and the total entry count rounded
+// to a power of two.
 std::string signature(const tt_plan *P) {
-  char buf[256];
+  char buf[320];
   long long total = P->entry_off[P->b];
   int c16 = 0, c32 = 0;
   for (int j = 0; j < P->b; ++j) (P->rclass[j] == 16 ? c16 : c32)++;
   int nsum = 0;
   for (int k = 0; k < P->md.d; ++k) nsum += P->md.n[k];
-  snprintf(buf, sizeof buf, "d%d_n%d_b%d_r16x%d_r32x%d_M%lld_cus%d", P->md.d, nsum, P->b, c16, c32, total,
-           P->nwg);
+  int mlog = 0;
+  while ((1LL << mlog) < total) ++mlog;
+  char arch[64] = "gfx";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char *c = arch; *c; ++c)
+      if (*c == ':' || *c == ' ') *c = '_';
+  }
+  snprintf(buf, sizeof buf, "%s_cus%d_d%d_n%d_b%d_r16x%d_r32x%d_M2^%d", arch, mfma_device_cus(), P->md.d, nsum,
+           P->b, c16, c32, mlog);
   return buf;
 }
 
@@ -253,12 +288,13 @@ int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t, const 
   P->t = t;
   P->loss = loss;
   P->entry_off.assign(entry_off, entry_off + X->b + 1);
-  int nmax = 1;
-  for (int k = 0; k < ref->d; ++k) nmax = std::max(nmax, ref->n[k]);
-  P->nb16 = MF_BATCH_T16 / 16 + nmax;
-  P->nb32 = MF_BATCH_T32 / 16 + nmax;
-  P->stash_stride = std::max((long long)(ref->d - 1) * P->nb16 * 64 * 4, (long long)(ref->d - 1) * P->nb32 * 64 * 8);
-  P->nwg = mfma_device_cus();
+  for (int k = 0; k < ref->d; ++k) P->nmax = std::max(P->nmax, ref->n[k]);
+  // stash for the largest of the shapes' needs
+  long long stash_floats = 0;
+  for (int sh = 0; sh < MF_BATCH_SHAPES; ++sh) {
+    const ShapeGeo g = shape_geo(P, sh);
+    stash_floats = std::max(stash_floats, g.stash_stride * g.nwg);
+  }
 
   // host tables
   std::vector<PadMeta> meta(X->b);
@@ -313,7 +349,7 @@ int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t, const 
   // upper bound on work items (chunk = 1)
   long long maxit = 0;
   for (int j = 0; j < X->b; ++j) {
-    const int T = (meta[j].R == 16) ? MF_BATCH_T16 : MF_BATCH_T32;
+    const int T = (meta[j].R == 16) ? MF_BATCH_MIN_T16 : MF_BATCH_MIN_T32;
     maxit += (P->entry_off[j + 1] - P->entry_off[j] + T - 1) / T;
   }
   P->max_items = (int)std::max(1LL, maxit);
@@ -331,7 +367,7 @@ int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t, const 
   if (!rc) rc = hip_check(hipMalloc((void **)&P->dtable, sizeof(MfInst) * X->b), "plan: table");
   if (!rc) rc = hip_check(hipMalloc((void **)&P->ditems, sizeof(MfWorkItem) * P->max_items), "plan: items");
   if (!rc) rc = hip_check(hipMalloc((void **)&P->counter, 256), "plan: counter");
-  if (!rc) rc = hip_check(hipMalloc((void **)&P->stash, sizeof(float) * (size_t)P->stash_stride * P->nwg), "plan: stash");
+  if (!rc) rc = hip_check(hipMalloc((void **)&P->stash, sizeof(float) * (size_t)stash_floats), "plan: stash");
   if (!rc && pw) rc = hip_check(hipMalloc(&P->plain_ws, pw), "plan: plain workspace");
   if (rc) {
     tt_plan_destroy(P);
@@ -401,44 +437,56 @@ int tt_plan_run_plain(tt_plan *plan, void *stream) {
 int tt_plan_autotune(tt_plan *plan, void *stream, int32_t *chosen) {
   if (!plan) return set_error(TT_ERR_ARG, "null plan");
   hipStream_t s = (hipStream_t)stream;
+  // build_items rewrites the device work list with a synchronous copy that
+  // is not ordered against work already queued on s: let that work finish
+  int rc0 = hip_check(hipStreamSynchronize(s), "autotune: drain the stream");
+  if (rc0) return rc0;
   const char *cache = getenv("TTGFX_TUNE_CACHE");
   const std::string sig = signature(plan);
-  int best = -1;
+  int best = -1, best_shape = 0;
   if (cache) {
     FILE *f = fopen(cache, "r");
     if (f) {
-      char key[256];
-      int val;
-      while (fscanf(f, "%255s %d", key, &val) == 2)
-        if (sig == key) best = val;
+      char key[320];
+      int sh, ch;
+      while (fscanf(f, "%319s %d %d", key, &sh, &ch) == 3)
+        if (sig == key && sh >= 0 && sh < MF_BATCH_SHAPES && ch >= 1) {
+          best_shape = sh;
+          best = ch;
+        }
       fclose(f);
     }
   }
   if (best < 0) {
+    // every tile shape of the batched kernel with every work-item chunk
     const int cands[] = {1, 2, 4, 8, 16};
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     int rc = hip_check(hipEventCreate(&e0), "autotune event");
     if (rc) return rc;
     if ((rc = hip_check(hipEventCreate(&e1), "autotune event"))) return rc;
-    for (int c : cands) {
-      plan->chunk = c;
-      if ((rc = build_items(plan))) break;
-      if ((rc = issue(plan, s))) break;  // warm-up
-      float ms_best = 1e30f;
-      for (int rep = 0; rep < 3 && !rc; ++rep) {
-        rc = hip_check(hipEventRecord(e0, s), "autotune record");
-        if (!rc) rc = issue(plan, s);
-        if (!rc) rc = hip_check(hipEventRecord(e1, s), "autotune record");
-        if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
-        float ms = 0.f;
-        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune time");
-        if (!rc) ms_best = std::min(ms_best, ms);
-      }
-      if (rc) break;
-      if (ms_best < best_ms) {
-        best_ms = ms_best;
-        best = c;
+    for (int sh = 0; sh < MF_BATCH_SHAPES && !rc; ++sh) {
+      for (int c : cands) {
+        plan->shape = sh;
+        plan->chunk = c;
+        if ((rc = build_items(plan))) break;
+        if ((rc = issue(plan, s))) break;  // warm-up
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+          rc = hip_check(hipEventRecord(e0, s), "autotune record");
+          if (!rc) rc = issue(plan, s);
+          if (!rc) rc = hip_check(hipEventRecord(e1, s), "autotune record");
+          if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
+          float ms = 0.f;
+          if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune time");
+          if (!rc) ms_best = std::min(ms_best, ms);
+        }
+        if (rc) break;
+        if (ms_best < best_ms) {
+          best_ms = ms_best;
+          best = c;
+          best_shape = sh;
+        }
       }
     }
     (void)hipEventDestroy(e0);
@@ -447,16 +495,43 @@ int tt_plan_autotune(tt_plan *plan, void *stream, int32_t *chosen) {
     if (cache) {
       FILE *f = fopen(cache, "a");
       if (f) {
-        fprintf(f, "%s %d\n", sig.c_str(), best);
+        fprintf(f, "%s %d %d\n", sig.c_str(), best_shape, best);
         fclose(f);
       }
     }
   }
   drop_graph(plan);
+  plan->shape = best_shape;
   plan->chunk = best;
   int rc = build_items(plan);
   if (rc) return rc;
   if (chosen) *chosen = best;
+  return TT_OK;
+}
+
+int tt_plan_set_config(tt_plan *plan, const int32_t *cfg) {
+  if (!plan || !cfg) return set_error(TT_ERR_ARG, "plan_set_config: null argument");
+  if (cfg[0] < 1) return set_error(TT_ERR_ARG, "plan_set_config: chunk %d < 1", cfg[0]);
+  int shape = -1;
+  for (int i = 0; i < MF_BATCH_SHAPES; ++i) {
+    const MfBatchShape sh = mfma_batch_shape(i);
+    if (sh.t16 == cfg[1] && sh.t32 == cfg[2] && sh.threads == cfg[3]) shape = i;
+  }
+  if (shape < 0)
+    return set_error(TT_ERR_UNSUPPORTED, "plan_set_config: no tile shape %d/%d/%d", cfg[1], cfg[2], cfg[3]);
+  drop_graph(plan);
+  plan->shape = shape;
+  plan->chunk = cfg[0];
+  return build_items(plan);
+}
+
+int tt_plan_config(const tt_plan *plan, int32_t *cfg) {
+  if (!plan || !cfg) return set_error(TT_ERR_ARG, "plan_config: null argument");
+  const MfBatchShape sh = mfma_batch_shape(plan->shape);
+  cfg[0] = plan->chunk;
+  cfg[1] = sh.t16;
+  cfg[2] = sh.t32;
+  cfg[3] = sh.threads;
   return TT_OK;
 }
 

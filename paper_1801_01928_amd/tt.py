@@ -337,16 +337,21 @@ def project_sparse(U, V, idx, z, alpha=1.0, add_x=0):
     return W
 
 
-def round_tt(Y, max_rank):
+def round_tt(Y, max_rank, with_status=False):
     """TT rounding to ranks <= max_rank (t3f.round); returns (TT, disc_sq)
-    with disc_sq[k] the discarded squared singular values at bond k+1."""
+    with disc_sq[k] the discarded squared singular values at bond k+1, and
+    with ``with_status`` also a device int32 holding the number of bonds
+    whose Jacobi SVD did not converge (tt_round_status)."""
     lib = L.load()
     ranks = _ranks_call(lib.tt_round_ranks, Y, int(max_rank))
     out = TT(Y.ns, ranks, device=Y.device)
     disc = torch.zeros(max(Y.d - 1, 1), dtype=torch.float32, device=Y.device)
+    status = torch.full((1,), -1, dtype=torch.int32, device=Y.device) if with_status else None
     ws, nb = _workspace(L.check(lib.tt_round_workspace(C.byref(Y.desc()), int(max_rank))), Y.device)
-    L.check(lib.tt_round(C.byref(Y.desc()), int(max_rank), C.byref(out.desc()), _ptr(disc), _ptr(ws), nb,
-                         _stream(Y.device)))
+    L.check(lib.tt_round_status(C.byref(Y.desc()), int(max_rank), C.byref(out.desc()), _ptr(disc), _ptr(status),
+                                _ptr(ws), nb, _stream(Y.device)))
+    if with_status:
+        return out, disc[:max(Y.d - 1, 0)], status
     return out, disc[:max(Y.d - 1, 0)]
 
 
@@ -670,6 +675,20 @@ class BatchedPlan:
         chosen = C.c_int32(0)
         L.check(L.load().tt_plan_autotune(self._plan, s, C.byref(chosen)))
         return int(chosen.value)
+
+    def config(self):
+        """The plan's launch: dict(chunk, tile16, tile32, threads) (entries
+        per tile of the two rank classes, threads per workgroup)."""
+        cfg = (C.c_int32 * 4)()
+        L.check(L.load().tt_plan_config(self._plan, cfg))
+        return dict(chunk=cfg[0], tile16=cfg[1], tile32=cfg[2], threads=cfg[3])
+
+    def set_config(self, chunk, tile16, tile32, threads):
+        """Set the launch (one of the autotuner's tile shapes); synchronizes
+        the device first, since the work list is rewritten."""
+        torch.cuda.synchronize(self.device)
+        cfg = (C.c_int32 * 4)(int(chunk), int(tile16), int(tile32), int(threads))
+        L.check(L.load().tt_plan_set_config(self._plan, cfg))
 
     def close(self):
         if self._plan:

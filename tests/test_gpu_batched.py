@@ -120,9 +120,44 @@ def test_autotune_keeps_results(gpu_lib):
     plan = tt.BatchedPlan(Xs, idx, t, off)
     chunk = plan.autotune()
     assert chunk in (1, 2, 4, 8, 16)
+    cfg = plan.config()
+    assert cfg["chunk"] == chunk
+    assert (cfg["tile16"], cfg["tile32"], cfg["threads"]) in ((1024, 512, 512), (512, 512, 512), (512, 256, 256),
+                                                              (1024, 512, 768))
     plan.run()
     _check(plan, _oracle(insts))
     plan.close()
+
+
+SHAPES = [(1024, 512, 512), (512, 512, 512), (512, 256, 256), (1024, 512, 768)]
+
+
+@pytest.mark.parametrize("shape", range(len(SHAPES)))
+def test_every_tile_shape_matches_oracle(gpu_lib, shape):
+    """Each tile shape the autotuner can choose gives the oracle's losses and
+    gradients (element by element), with chunks of 1 and 3 tiles, and
+    survives a graph capture and replay."""
+    import torch
+    tt = gpu_lib
+    ns, insts = _small_batch()
+    idx, t, off = _pack(insts)
+    ref = _oracle(insts)
+    for chunk in (1, 3):
+        print("batched tile shape", SHAPES[shape], "chunk", chunk, flush=True)
+        Xs = [tt.TT.from_cores(c) for c, _, _ in insts]
+        plan = tt.BatchedPlan(Xs, idx, t, off)
+        plan.set_config(chunk, *SHAPES[shape])
+        assert plan.config() == dict(chunk=chunk, tile16=SHAPES[shape][0], tile32=SHAPES[shape][1],
+                                     threads=SHAPES[shape][2])
+        plan.run()
+        _check(plan, ref)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            plan.capture(s)
+            plan.run(s)
+        s.synchronize()
+        _check(plan, ref)
+        plan.close()
 
 
 def test_batched_workload_256(gpu_lib):

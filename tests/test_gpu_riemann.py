@@ -173,6 +173,29 @@ def test_round(gpu_lib, case):
     assert _orth_err(got[:-1], True) <= 1e-4
 
 
+def test_round_ill_conditioned_converges(gpu_lib):
+    """Rounding of a TT whose bond singular values fall over six decades
+    (each core's right bond scaled by 10^(-6 j / r)): the Jacobi SVD of every
+    bond converges (status 0) and the result matches the oracle's rounding."""
+    tt = gpu_lib
+    ns, r, rmax = [6] * 6, 24, 12
+    ranks = W.canonical_ranks(ns, r)
+    cores = W.random_tt(310, ns, ranks, std=1.0 / np.sqrt(r))
+    graded = []
+    for k, c in enumerate(cores):
+        c = c.astype(np.float64)
+        if k < len(cores) - 1:
+            rr = c.shape[2]
+            c = c * (10.0 ** (-6.0 * np.arange(rr) / rr))[None, None, :]
+        graded.append(c.astype(np.float32))
+    O, disc, status = tt.round_tt(tt.TT.from_cores(graded), rmax, with_status=True)
+    assert int(status.item()) == 0
+    ref, dref = oracle.round_tt(graded, rmax)
+    assert rel_tt(O.numpy_cores(), ref) <= 1e-4
+    ny2 = oracle.inner(graded, graded)
+    assert np.abs(disc.cpu().numpy() - dref).max() <= 1e-4 * ny2
+
+
 def test_round_exact_sum(gpu_lib):
     """round(X + X, r) represents 2X exactly (ranks suffice)."""
     tt = gpu_lib
