@@ -47,6 +47,8 @@ from .riemannian import (  # noqa: F401
     left_interface,
     right_interface,
     dense_projector,
+    observed_loss,
+    riemannian_grad_dense,
 )
 from .ttmatrix import (  # noqa: F401
     ttm_full,

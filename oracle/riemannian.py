@@ -445,3 +445,49 @@ def tangent_gram(Ws):
         for j in range(b):
             G[i, j] = inner(W64[i], W64[j])
     return G
+
+
+def observed_loss(y, t, kind, delta=1.0):
+    """A loss over the observed entries, L = (1/M) sum_m phi(y_m, t_m), and
+    its gradient g_m = dL/dy_m = phi'(y_m, t_m) / M, for the completion use
+    case of the Introduction with other per-entry losses than the squared
+    residual (the Riemannian gradient of the Riemannian Geometry Operations
+    section is then P_X(sum_m g_m e_{i^m})).  kind:
+      'squared'   phi = (y - t)^2,                  phi' = 2 (y - t);
+      'huber'     r = y - t; phi = r^2 / 2 for |r| <= delta, else
+                  delta (|r| - delta / 2);         phi' = r, else delta sign(r);
+      'logistic'  labels t in {-1, +1}; phi = log(1 + exp(-t y)),
+                  phi' = -t / (1 + exp(t y)).
+    The definitions written out, in float64."""
+    y = np.asarray(y, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    M = y.shape[0]
+    if M == 0:
+        return 0.0, np.zeros(0)
+    if kind == "squared":
+        r = y - t
+        phi, dphi = r * r, 2.0 * r
+    elif kind == "huber":
+        r = y - t
+        small = np.abs(r) <= delta
+        phi = np.where(small, 0.5 * r * r, delta * (np.abs(r) - 0.5 * delta))
+        dphi = np.where(small, r, delta * np.sign(r))
+    elif kind == "logistic":
+        z = t * y
+        phi = np.log1p(np.exp(-z))
+        dphi = -t / (1.0 + np.exp(z))
+    else:
+        raise ValueError("unknown loss kind %r" % (kind,))
+    return float(np.sum(phi) / M), dphi / M
+
+
+def riemannian_grad_dense(X, G):
+    """P_X G for a dense tensor G (tiny sizes only): the Riemannian gradient
+    of a function whose Euclidean gradient at X is G (Riemannian Geometry
+    Operations: the Riemannian gradient is the projection of the Euclidean
+    one onto the tangent space).  The dense projector of ``dense_projector``
+    applied to vec(G); returns a dense tensor of G's shape."""
+    U = orthogonalize_lr(X)
+    V = orthogonalize_rl(X)
+    G = np.asarray(G, dtype=np.float64)
+    return (dense_projector(U, V) @ G.reshape(-1)).reshape(G.shape)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import riemannian as R
 from workloads import random_tt, random_indices, canonical_ranks, small_step
 
 
@@ -511,3 +512,82 @@ def test_tangent_gram_dense_and_block_identity():
     np.testing.assert_allclose(G, blocks, atol=1e-12)
     assert np.array_equal(G, G.T) or np.allclose(G, G.T, atol=1e-14)
     assert np.linalg.eigvalsh(G).min() > -1e-12
+
+
+@pytest.mark.parametrize("kind", ["squared", "huber", "logistic"])
+def test_observed_loss_gradient_is_the_derivative(kind):
+    """Central differences of the observed loss in each y_m match g_m (the
+    losses are smooth away from Huber's two kinks, which the draw avoids)."""
+    rng = np.random.default_rng(71)
+    M = 40
+    y = rng.standard_normal(M) * 1.5
+    t = np.sign(rng.standard_normal(M)) if kind == "logistic" else rng.standard_normal(M)
+    delta = 0.7
+    if kind == "huber":
+        r = y - t
+        keep = np.abs(np.abs(r) - delta) > 1e-2
+        y, t = y[keep], t[keep]
+    L, g = R.observed_loss(y, t, kind, delta)
+    h = 1e-6
+    for m in range(len(y)):
+        yp, ym = y.copy(), y.copy()
+        yp[m] += h
+        ym[m] -= h
+        fd = (R.observed_loss(yp, t, kind, delta)[0] - R.observed_loss(ym, t, kind, delta)[0]) / (2 * h)
+        assert abs(fd - g[m]) <= 1e-6 * max(1.0, abs(g[m])) / len(y)
+
+
+def test_observed_loss_closed_forms():
+    """Huber with delta above every residual is half the squared loss; Huber
+    with a tiny delta is delta times the mean absolute residual (to first
+    order); the logistic loss is log 2 at y = 0 for either label and
+    symmetric under (y, t) -> (-y, -t)."""
+    rng = np.random.default_rng(72)
+    y, t = rng.standard_normal(50), rng.standard_normal(50)
+    Ls, gs = R.observed_loss(y, t, "squared")
+    Lh, gh = R.observed_loss(y, t, "huber", delta=100.0)
+    assert abs(Lh - 0.5 * Ls) <= 1e-15 and np.allclose(gh, 0.5 * gs, rtol=0, atol=1e-15)
+    d = 1e-6
+    Lt, _ = R.observed_loss(y, t, "huber", delta=d)
+    assert abs(Lt - d * np.mean(np.abs(y - t))) <= d * d
+    lab = np.sign(rng.standard_normal(50))
+    L0, _ = R.observed_loss(np.zeros(50), lab, "logistic")
+    assert abs(L0 - np.log(2.0)) <= 1e-15
+    La, ga = R.observed_loss(y, lab, "logistic")
+    Lb, gb = R.observed_loss(-y, -lab, "logistic")
+    assert abs(La - Lb) <= 1e-15 and np.allclose(ga, -gb, rtol=0, atol=1e-15)
+
+
+def test_riemannian_gradient_gives_the_directional_derivative():
+    """For tangent vectors xi at X, <P_X G, xi> equals the derivative of the
+    observed loss along xi (central differences of f(X + h xi), exact for
+    the squared loss since f is quadratic along a line): the defining
+    property of the Riemannian gradient; and P_X G of a sparse G is the
+    sparse projection."""
+    from oracle import core as K
+    rng = np.random.default_rng(73)
+    ns, ranks = [3, 4, 3, 2], [1, 2, 3, 2, 1]
+    X = [rng.standard_normal((ranks[k], ns[k], ranks[k + 1])) for k in range(4)]
+    M = 30
+    idx = np.stack([rng.integers(0, n, M) for n in ns]).astype(np.int32)
+    t = rng.standard_normal(M)
+    for kind in ("squared", "huber", "logistic"):
+        tk = np.sign(t) if kind == "logistic" else t
+        f = lambda cores: R.observed_loss(K.gather(cores, idx), tk, kind, 0.5)[0]
+        _, g = R.observed_loss(K.gather(X, idx), tk, kind, 0.5)
+        G = np.zeros(ns)
+        np.add.at(G, tuple(idx), g)
+        PG = R.riemannian_grad_dense(X, G)
+        Wsp = R.project_sparse(X, idx, g)[0]
+        assert np.abs(K.full(Wsp) - PG).max() <= 1e-12 * max(1.0, np.abs(PG).max())
+        U = R.orthogonalize_lr(X)
+        V = R.orthogonalize_rl(X)
+        for j in range(3):
+            H = [rng.standard_normal(c.shape) for c in X]
+            xi_cores = R.tangent_tt(U, V, R.tangent_cores(U, H), 1.0, 0.0)
+            xi = K.full(xi_cores)
+            h = 1e-5
+            Xp = K.add(X, K.scale(xi_cores, h))
+            Xm = K.add(X, K.scale(xi_cores, -h))
+            fd = (f(Xp) - f(Xm)) / (2 * h)
+            assert abs(fd - float(np.sum(PG * xi))) <= 1e-6 * max(1.0, abs(fd))
