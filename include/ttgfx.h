@@ -330,6 +330,38 @@ int64_t tt_tangent_gram_workspace(const tt_tensor *U, const tt_batch *A);
 int tt_tangent_gram(const tt_tensor *U, const tt_batch *A, float *G,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------ Riemannian gradients */
+/* Riemannian automatic differentiation in two bounded forms (Riemannian
+ * Geometry Operations: the Riemannian gradient is the projection of the
+ * Euclidean gradient onto the tangent space at X).
+ *
+ * tt_observed_loss: a per-entry loss over observed entries,
+ * L = (1/M) sum_m phi(y_m, t_m), and g_m = phi'(y_m, t_m) / M, for
+ *   TT_LOSS_SQUARED   phi = (y - t)^2;
+ *   TT_LOSS_HUBER     r = y - t, phi = r^2 / 2 for |r| <= delta, else
+ *                     delta (|r| - delta / 2)  (delta > 0);
+ *   TT_LOSS_LOGISTIC  t in {-1, +1}, phi = log(1 + exp(-t y)).
+ * y, t: (dev) [M]; g: (dev) [M] or NULL; loss: (dev) one float.  The loss
+ * is summed in a fixed order.  The Riemannian gradient of L at X is
+ * tt_project_sparse(U, V, idx, M, g, 1, 0, ...) with y = tt_gather(X).
+ *
+ * tt_riemannian_grad: the gauge-fixed tangent TT from per-core Euclidean
+ * gradients Zhat_k of f in the tangent parametrisation
+ * xi(dG) = sum_k U_<k dG_k V_>k at dG = 0 (what automatic differentiation
+ * of f(X + xi(dG)) with respect to the dG_k returns): dG_k = Zhat_k -
+ * U_k (U_k^T Zhat_k) for k < d, dG_d = Zhat_d, assembled as by
+ * tt_project_sparse into W = add_x X + alpha P_X(grad f) (ranks 2 r_k).
+ * Zhat: X's shape (U's ranks); U, V the two sweeps of X. */
+enum { TT_LOSS_SQUARED = 0, TT_LOSS_HUBER = 1, TT_LOSS_LOGISTIC = 2 };
+int64_t tt_observed_loss_workspace(int64_t M);
+int tt_observed_loss(const float *y, const float *t, int64_t M, int kind,
+                     float delta, float *g, float *loss, void *ws,
+                     size_t ws_bytes, void *stream);
+int64_t tt_riemannian_grad_workspace(const tt_tensor *U);
+int tt_riemannian_grad(const tt_tensor *U, const tt_tensor *V,
+                       const tt_tensor *Zhat, float alpha, int add_x,
+                       tt_tensor *W, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ A7 */
 /* TT rounding (t3f.round(x, max_tt_rank), Implementation Details): TT_RL
  * sweep, then left-to-right truncated SVDs of reshape(G^k, r_{k-1} n_k x r_k)

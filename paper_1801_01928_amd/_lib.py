@@ -18,6 +18,7 @@ TT_ERR_HIP = -5
 TT_ERR_INDEX = -6
 TT_LR = 0
 TT_RL = 1
+TT_LOSS = {"squared": 0, "huber": 1, "logistic": 2}
 TT_MAX_D = 32
 TT_MAX_RANK = 64
 
@@ -91,6 +92,10 @@ SIGNATURES = {
     "tt_tangent_combine": (C.c_int, [P_TT, P_TT, C.c_float, C.c_int, P_TT, VP]),
     "tt_tangent_combine_dev": (C.c_int, [P_TT, P_TT, VP, C.c_float, C.c_int, P_TT, VP]),
     "tt_cg_direction": (C.c_int, [P_TT, P_TT, P_TT, P_TT, VP, P_TT, VP, VP]),
+    "tt_observed_loss_workspace": (I64, [I64]),
+    "tt_observed_loss": (C.c_int, [VP, VP, I64, C.c_int, C.c_float, VP, VP, VP, SZ, VP]),
+    "tt_riemannian_grad_workspace": (I64, [P_TT]),
+    "tt_riemannian_grad": (C.c_int, [P_TT, P_TT, P_TT, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_project_tt_workspace": (I64, [P_TT, P_TT]),
     "tt_project_tt": (C.c_int, [P_TT, P_TT, P_TT, C.c_float, C.c_int, P_TT, VP, SZ, VP]),
     "tt_round_ranks": (C.c_int, [P_TT, I32, PI32]),

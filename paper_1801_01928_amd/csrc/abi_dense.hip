@@ -119,6 +119,32 @@ int tt_project_sparse(const tt_tensor *U, const tt_tensor *V, const int32_t *idx
   return tangent_assemble(U, V, &Z, W, alpha, add_x, base + zb + ab, ws_bytes - zb - ab, s);
 }
 
+int64_t tt_riemannian_grad_workspace(const tt_tensor *U) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  return (int64_t)tangent_ws(U);
+}
+
+int tt_riemannian_grad(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Zhat, float alpha, int add_x,
+                       tt_tensor *W, void *ws, size_t ws_bytes, void *stream) {
+  int rc = validate_tt(U, "U", TT_MAX_RANK);
+  if (rc) return rc;
+  if ((rc = validate_tt(V, "V", TT_MAX_RANK))) return rc;
+  if ((rc = validate_tt(Zhat, "Zhat", TT_MAX_RANK))) return rc;
+  if ((rc = validate_tt(W, "W", 2 * TT_MAX_RANK))) return rc;
+  if (U->d < 2) return set_error(TT_ERR_ARG, "riemannian_grad needs d >= 2");
+  if (!same_shape(U, V))
+    return set_error(TT_ERR_SHAPE, "U and V must have the same modes and ranks (X at feasible ranks)");
+  if (!same_shape(U, Zhat)) return set_error(TT_ERR_SHAPE, "Zhat must have the shape of U (X's cores)");
+  if (!same_modes(U, W)) return set_error(TT_ERR_SHAPE, "W must have U's mode sizes");
+  for (int k = 1; k < U->d; ++k)
+    if (W->r[k] != 2 * U->r[k])
+      return set_error(TT_ERR_SHAPE, "W rank r[%d] = %d, expected %d", k, W->r[k], 2 * U->r[k]);
+  if (add_x != 0 && add_x != 1) return set_error(TT_ERR_ARG, "add_x must be 0 or 1");
+  if ((rc = check_ws(ws, ws_bytes, tangent_ws(U), "riemannian_grad"))) return rc;
+  return tangent_assemble(U, V, Zhat, W, alpha, add_x, ws, ws_bytes, (hipStream_t)stream);
+}
+
 static int validate_project_tt(const tt_tensor *U, const tt_tensor *V, const tt_tensor *Y) {
   int rc = validate_tt(U, "U", TT_MAX_RANK);
   if (rc) return rc;

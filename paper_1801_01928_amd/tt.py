@@ -467,6 +467,49 @@ def tangent_axpby(U, a, A, b, B, out=None):
     return W
 
 
+def observed_loss(y, t, kind="squared", delta=1.0):
+    """Per-entry loss over the observed entries (tt_observed_loss): returns
+    (loss, g), L = mean(phi(y, t)) and g = phi'(y, t) / M as device tensors,
+    for kind 'squared', 'huber' (parameter delta) or 'logistic' (labels
+    t in {-1, +1})."""
+    lib = L.load()
+    y = torch.as_tensor(y).to(dtype=torch.float32).contiguous()
+    dev = y.device
+    M = y.numel()
+    t = _vec(t, M, dev)
+    g = torch.empty(M, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ws, nb = _workspace(L.check(lib.tt_observed_loss_workspace(M)), dev)
+    L.check(lib.tt_observed_loss(_ptr(y), _ptr(t), M, L.TT_LOSS[kind], C.c_float(delta), _ptr(g), _ptr(loss),
+                                 _ptr(ws), nb, _stream(dev)))
+    return loss, g
+
+
+def riemannian_grad_observed(X, idx, t, kind="squared", delta=1.0, UV=None):
+    """Riemannian gradient of an observed-entry loss at X: y = gather(X),
+    (L, g) = observed_loss(y, t), then P_X(sum_m g_m e_{i^m}) by the sparse
+    projection.  Returns (loss, W) with W the rank-2r tangent TT; UV may
+    pass the two sweeps of X."""
+    idx = _idx(idx, X.d, X.device)
+    y = gather(X, idx)
+    loss, g = observed_loss(y, t, kind, delta)
+    U, V = UV if UV is not None else orthogonalize_both(X)
+    return loss, project_sparse(U, V, idx, g, alpha=1.0, add_x=0)
+
+
+def riemannian_grad(U, V, zhat, alpha=1.0, add_x=0):
+    """Gauge-fixed tangent TT add_x X + alpha P_X(grad f) from the per-core
+    Euclidean gradients zhat (a TT of X's shape, or a list of cores) of f in
+    the tangent parametrisation at dG = 0 (tt_riemannian_grad)."""
+    lib = L.load()
+    Z = zhat if isinstance(zhat, TT) else TT.from_cores(zhat, device=U.device)
+    W = TT(U.ns, [1] + [2 * r for r in U.ranks[1:-1]] + [1], device=U.device)
+    ws, nb = _workspace(L.check(lib.tt_riemannian_grad_workspace(C.byref(U.desc()))), U.device)
+    L.check(lib.tt_riemannian_grad(C.byref(U.desc()), C.byref(V.desc()), C.byref(Z.desc()), C.c_float(alpha),
+                                   int(add_x), C.byref(W.desc()), _ptr(ws), nb, _stream(U.device)))
+    return W
+
+
 def line_search_terms(P, idx, y, t):
     """Line-search terms (tt_line_search) as a device tensor of 3 floats:
     sum_m P(i^m)^2, sum_m (y_m - t_m) P(i^m) and their quotient (the step
