@@ -507,48 +507,64 @@ def completion_leg(tt, W, iters=10, track=20):
     return out
 
 
-def matvec_leg(tt, W, reps=5):
-    """TT-matrix by TT-vector products in the TT format at Table 1's shape:
-    W of size 10^10 x 10^10 (d=10, modes 10 x 10, rank 10) times 100 TT
-    vectors of rank 10, giving 100 exact products of rank 100.  The outputs
-    are allocated before timing; HBM bandwidth counts the bytes written and
-    read once."""
+def table1_leg(tt, W, reps=5):
+    """The operations of the paper's Table 1 at its shapes, in float32 and
+    float64: TT-matrices 10^10 x 10^10 and TT vectors of size 10^10 (d=10,
+    mode size 10, rank 10), batches of 100 objects; times per object of the
+    batch, as the table reports them.  matvec: 100 products W x_j (outputs
+    of rank 100); matmul: W W2 (one product; the batch time is 100 of them);
+    norm: 100 TT vectors; gram: the 100 x 100 Gram matrix of 100 TT vectors
+    (per object = per vector); project: project_sum of 100 TT vectors onto
+    the tangent space at a rank-10 point (per object = per vector), and one
+    projection of a rank-10 TT.  The outputs are allocated before timing.
+    The HBM rate of the matvec counts its bytes read and written once."""
     import ctypes as C
     import numpy as np
     import torch
     from paper_1801_01928_amd import _lib as L
     from paper_1801_01928_amd.tt import _batch
     lib = L.load()
-    rng = np.random.default_rng(11)
     d, b = 10, 100
-    Wm = tt.TTMatrix.from_cores([rng.standard_normal((1 if k == 0 else 10, 10, 10, 1 if k == d - 1 else 10))
-                                 .astype(np.float32) * 0.3 for k in range(d)])
-    xs = [tt.TT.from_cores(W.random_cores(rng, [10] * d, W.uniform_ranks(d, 10), 0.3)) for _ in range(b)]
-    ys = tt.tt_matvec(Wm, xs)
-    xb, keepx = _batch(xs)
-    yb, keepy = _batch(ys)
+    out = {"workload": "d=10, modes 10 (x 10 for matrices), rank 10, batch 100; ms per object"}
     stream = torch.cuda.current_stream()
-    call = lambda: L.check(lib.tt_matvec(C.byref(Wm.desc()), C.byref(xb), C.byref(yb),
-                                         C.c_void_p(stream.cuda_stream)))
-    call()
-    torch.cuda.synchronize()
-    ms = _event_ms(call, reps)
-    nbytes = 4 * (sum(y.data.numel() for y in ys) + sum(x.data.numel() for x in xs) + Wm.data.numel())
-    gbs = nbytes / (ms * 1e-3) / 1e9
-    # one TT-matrix product W W2 at the same shape (output rank 100)
-    W2 = tt.TTMatrix.from_cores([rng.standard_normal((1 if k == 0 else 10, 10, 10, 1 if k == d - 1 else 10))
-                                 .astype(np.float32) * 0.3 for k in range(d)])
-    tt.tt_matmat(Wm, W2)
-    torch.cuda.synchronize()
-    mm_ms = _event_ms(lambda: tt.tt_matmat(Wm, W2), reps)
-    # norms of the 100 rank-10 vectors
-    tt.norms(xs)
-    torch.cuda.synchronize()
-    nrm_ms = _event_ms(lambda: tt.norms(xs), reps)
-    return {"workload": "y_j = W x_j in TT format, W 10^10 x 10^10 (d=10, modes 10x10, rank 10), 100 TT vectors "
-                        "of rank 10, outputs of rank 100", "ms": round(ms, 4), "bytes": nbytes,
-            "gb_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / 8000.0, 3),
-            "matmat_ms": round(mm_ms, 4), "norms_100_rank10_ms": round(nrm_ms, 4)}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        rng = np.random.default_rng(11)
+        mk = lambda: [rng.standard_normal((1 if k == 0 else 10, 10, 10, 1 if k == d - 1 else 10)) * 0.3
+                      for k in range(d)]
+        Wm = tt.TTMatrix.from_cores(mk(), dtype=dt)
+        W2 = tt.TTMatrix.from_cores(mk(), dtype=dt)
+        xs = [tt.TT.from_cores(W.random_cores(rng, [10] * d, W.uniform_ranks(d, 10), 0.3), dtype=dt)
+              for _ in range(b)]
+        ys = tt.tt_matvec(Wm, xs)
+        xb, keepx = _batch(xs)
+        yb, keepy = _batch(ys)
+        fn = lib.tt_matvec_f64 if dt == torch.float64 else lib.tt_matvec
+        call = lambda: L.check(fn(C.byref(Wm.desc()), C.byref(xb), C.byref(yb), C.c_void_p(stream.cuda_stream)))
+        call()
+        tt.tt_matmat(Wm, W2)
+        tt.norms(xs)
+        tt.gram(xs)
+        torch.cuda.synchronize()
+        mv = _event_ms(call, reps)
+        mm = _event_ms(lambda: tt.tt_matmat(Wm, W2), reps)
+        nr = _event_ms(lambda: tt.norms(xs), reps)
+        gr = _event_ms(lambda: tt.gram(xs), reps)
+        esize = 8 if dt == torch.float64 else 4
+        nbytes = esize * (sum(y.data.numel() for y in ys) + sum(x.data.numel() for x in xs) + Wm.data.numel())
+        rec = {"matvec_ms_per_object": round(mv / b, 5), "matvec_gb_per_s": round(nbytes / (mv * 1e-3) / 1e9, 1),
+               "matmul_ms_per_object": round(mm, 4), "norm_ms_per_object": round(nr / b, 5),
+               "gram_ms_per_object": round(gr / b, 5)}
+        if dt == torch.float32:
+            X10 = tt.TT.from_cores(W.random_cores(rng, [10] * d, W.canonical_ranks([10] * d, 10), 0.3))
+            U, V = tt.orthogonalize_both(X10)
+            cw = rng.standard_normal(b)
+            tt.project_sum(U, V, xs, cw)
+            tt.project_tt(U, V, xs[0])
+            torch.cuda.synchronize()
+            rec["project_sum_ms_per_object"] = round(_event_ms(lambda: tt.project_sum(U, V, xs, cw), reps) / b, 5)
+            rec["project_one_ms"] = round(_event_ms(lambda: tt.project_tt(U, V, xs[0]), reps), 4)
+        out[name] = rec
+    return out
 
 
 def ttm_leg(tt, W, reps=3):
@@ -671,7 +687,7 @@ def main():
         out["gram"] = gram_leg(tt, W)
         out["riemann_step"] = riemann_leg(tt, W)
         out["ttm_layer"] = ttm_leg(tt, W)
-        out["matvec"] = matvec_leg(tt, W)
+        out["table1"] = table1_leg(tt, W)
         out["completion_loop"] = completion_leg(tt, W)
     if not args.no_cpu_baseline and not args.no_oracle_workloads:
         out["cpu_baseline_workloads"] = oracle_workloads(W)

@@ -81,6 +81,20 @@ typedef struct {
   const tt_tensor *tt;    /* (host) [b]                                 */
 } tt_batch;
 
+/* The same descriptors with float64 cores, for the double-precision
+ * variants of Table 1's operations (the paper times them in double). */
+typedef struct {
+  int32_t d;
+  const int32_t *n;
+  const int32_t *r;
+  const int64_t *off;
+  double *data;           /* (dev) float64 core storage                 */
+} tt_tensor_f64;
+typedef struct {
+  int32_t b;
+  const tt_tensor_f64 *tt;
+} tt_batch_f64;
+
 /* ------------------------------------------------------------------ A1 */
 /* Gather (Introduction, entry formula): y[m] = G^1[i_1^m] ... G^d[i_d^m].
  * idx: (dev) int32 structure-of-arrays [d][M] (mode k of entry m at
@@ -388,6 +402,12 @@ int tt_round_status(const tt_tensor *Y, int32_t max_rank, tt_tensor *out,
 int64_t tt_gram_workspace(const tt_batch *A, const tt_batch *B);
 int tt_gram(const tt_batch *A, const tt_batch *B, float *G,
             void *ws, size_t ws_bytes, void *stream);
+/* Float64 variant (Table 1 times the Gram matrix in double): the same
+ * contraction on v_mfma_f64_16x16x4_f64, tt_batch_f64 members, G (dev)
+ * double [bA][bB]; same rules and workspace query. */
+int64_t tt_gram_f64_workspace(const tt_batch_f64 *A, const tt_batch_f64 *B);
+int tt_gram_f64(const tt_batch_f64 *A, const tt_batch_f64 *B, double *G,
+                void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ A9 */
 /* Batched persistent gather + MSE + adjoint over many TT tensors of uneven
@@ -485,6 +505,12 @@ int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *C, void *stream
  * interface matrices.  A: b >= 1 TTs of one shape and one set of core
  * offsets, ranks up to TT_MAX_RANK.  No workspace. */
 int tt_norms(const tt_batch *A, float *out, void *stream);
+/* Float64 variants of the three operations above, with the same layouts,
+ * shapes and rules: W, A, B, C as tt_matrix with float64 cores (data is a
+ * double pointer), TT vectors as tt_tensor_f64; arithmetic in float64. */
+int tt_matvec_f64(const tt_matrix *W, const tt_batch_f64 *X, tt_batch_f64 *Y, void *stream);
+int tt_matmat_f64(const tt_matrix *A, const tt_matrix *B, tt_matrix *C, void *stream);
+int tt_norms_f64(const tt_batch_f64 *A, double *out, void *stream);
 
 /* ---------------------------------------------------------------- misc */
 /* ---------------------------------------------------------- measurement */

@@ -44,6 +44,15 @@ class tt_batch(C.Structure):
     _fields_ = [("b", C.c_int32), ("tt", C.POINTER(tt_tensor))]
 
 
+class tt_tensor_f64(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.POINTER(C.c_int32)), ("r", C.POINTER(C.c_int32)),
+                ("off", C.POINTER(C.c_int64)), ("data", C.c_void_p)]
+
+
+class tt_batch_f64(C.Structure):
+    _fields_ = [("b", C.c_int32), ("tt", C.POINTER(tt_tensor_f64))]
+
+
 class tt_matrix(C.Structure):
     _fields_ = [("d", C.c_int32), ("m", C.POINTER(C.c_int32)), ("n", C.POINTER(C.c_int32)),
                 ("r", C.POINTER(C.c_int32)), ("off", C.POINTER(C.c_int64)), ("data", C.c_void_p)]
@@ -52,6 +61,7 @@ class tt_matrix(C.Structure):
 P_TT = C.POINTER(tt_tensor)
 P_BATCH = C.POINTER(tt_batch)
 P_TTM = C.POINTER(tt_matrix)
+P_BATCH64 = C.POINTER(tt_batch_f64)
 VP = C.c_void_p
 I64 = C.c_int64
 I32 = C.c_int32
@@ -117,6 +127,11 @@ SIGNATURES = {
     "tt_matvec": (C.c_int, [P_TTM, P_BATCH, P_BATCH, VP]),
     "tt_matmat": (C.c_int, [P_TTM, P_TTM, P_TTM, VP]),
     "tt_norms": (C.c_int, [P_BATCH, VP, VP]),
+    "tt_matvec_f64": (C.c_int, [P_TTM, P_BATCH64, P_BATCH64, VP]),
+    "tt_matmat_f64": (C.c_int, [P_TTM, P_TTM, P_TTM, VP]),
+    "tt_norms_f64": (C.c_int, [P_BATCH64, VP, VP]),
+    "tt_gram_f64_workspace": (I64, [P_BATCH64, P_BATCH64]),
+    "tt_gram_f64": (C.c_int, [P_BATCH64, P_BATCH64, VP, VP, SZ, VP]),
     "tt_matmul_backward": (C.c_int, [P_TTM, VP, I64, VP, VP, VP, C.c_int, VP, SZ, VP]),
     "tt_peak_work": (C.c_double, [C.c_int, I32, I32]),
     "tt_peak_launch": (C.c_int, [C.c_int, I32, I32, VP, VP]),

@@ -23,19 +23,45 @@ namespace ttgfx {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
+// Per scalar type: the 16 x 16 x 4 matrix-core product (the float64 one
+// has the float32 one's operand and result layout), 4-element accumulator
+// and 16-byte load vectors, and the pair tile (a float64 slice takes twice
+// the LDS, so its tiles are 2 x 2).
+template <class T>
+struct GramT;
+// Result layout (lane c + 16 q, register v): the float32 product holds row
+// 4 q + v, the float64 one row q + 4 v (measured).  A result used as the
+// next product's A operand therefore brings K chunk v as the K indices
+// {v, 4 + v, 8 + v, 12 + v} in float32 and {4 v .. 4 v + 3} in float64, and
+// the packed slices (the B operands) follow the same order (KCONTIG).
+template <>
+struct GramT<float> {
+  typedef v4f acc4;
+  typedef v4f vec16;
+  static constexpr int TILE = 4;
+  static constexpr bool KCONTIG = false;
+  __device__ static acc4 mfma(float a, float b, acc4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct GramT<double> {
+  typedef v4d acc4;
+  typedef v2d vec16;
+  static constexpr int TILE = 2;
+  static constexpr bool KCONTIG = true;
+  __device__ static acc4 mfma(double a, double b, acc4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
 
 constexpr int R = 32;
-constexpr int TILE = 4;                      // instances per side of a pair tile
-constexpr int THREADS = TILE * TILE * 64;    // one wave per pair
-constexpr int SLICE = R * R;                 // floats per padded slice
+constexpr int SLICE = R * R;                 // elements per padded slice
 
 // Per-instance metadata on the device.
 struct InstMeta {
-  const float *data;
+  const void *data;  // float or double cores
   long long off[TT_MAX_D];
   int r[TT_MAX_D + 1];
 };
@@ -47,10 +73,11 @@ struct Modes {
 };
 
 // Padded slice (k, i) of an instance in operand order: for lane (q, c),
-// comp tiles (ti, tc) and v < 4, the float at ((ti*2 + tc)*64 + lane)*4 + v
-// holds S[16 ti + 4 q + v][16 tc + c].
-__global__ void gram_pack_kernel(const InstMeta *__restrict__ meta, Modes md,
-                                 float *__restrict__ out) {
+// comp tiles (ti, tc) and v < 4, the element at ((ti*2 + tc)*64 + lane)*4 + v
+// holds S[16 ti + 4 q + v][16 tc + c] (float32) or S[16 ti + q + 4 v][16 tc + c]
+// (float64), the K order of the matching result layout.
+template <class T>
+__global__ void gram_pack_kernel(const InstMeta *__restrict__ meta, Modes md, T *__restrict__ out) {
   const int inst = blockIdx.y;
   const int slice = blockIdx.x;
   if (slice >= md.total) return;
@@ -61,52 +88,58 @@ __global__ void gram_pack_kernel(const InstMeta *__restrict__ meta, Modes md,
   }
   const int s = slice - base;
   const InstMeta &m = meta[inst];
+  const T *src = (const T *)m.data;
   const int r0 = m.r[k], r1 = m.r[k + 1], nk = md.n[k];
-  float *dst = out + ((long long)inst * md.total + slice) * SLICE;
+  T *dst = out + ((long long)inst * md.total + slice) * SLICE;
   for (int e = threadIdx.x; e < SLICE; e += blockDim.x) {
     const int v = e & 3, lane = (e >> 2) & 63, tile = e >> 8;
     const int ti = tile >> 1, tc = tile & 1;
-    const int row = 16 * ti + 4 * (lane >> 4) + v, col = 16 * tc + (lane & 15);
-    float x = 0.f;
-    if (row < r0 && col < r1) x = m.data[m.off[k] + ((long long)row * nk + s) * r1 + col];
+    const int q = lane >> 4;
+    const int row = 16 * ti + (GramT<T>::KCONTIG ? q + 4 * v : 4 * q + v), col = 16 * tc + (lane & 15);
+    T x = T(0);
+    if (row < r0 && col < r1) x = src[m.off[k] + ((long long)row * nk + s) * r1 + col];
     dst[e] = x;
   }
 }
 
 // Grid: one workgroup per pair tile (ta, tb), given by the tile list.
-__global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__ pa,
-                                                       const float *__restrict__ pb, int na, int nb,
-                                                       Modes md, int sym,
-                                                       const int2 *__restrict__ tiles,
-                                                       float *__restrict__ G) {
-  __shared__ __align__(16) float sa[2][TILE][SLICE];
-  __shared__ __align__(16) float sb[2][TILE][SLICE];
+template <class T>
+__global__ void __launch_bounds__(GramT<T>::TILE * GramT<T>::TILE * 64)
+    gram_kernel(const T *__restrict__ pa, const T *__restrict__ pb, int na, int nb, Modes md, int sym,
+                const int2 *__restrict__ tiles, T *__restrict__ G) {
+  constexpr int TILE = GramT<T>::TILE;
+  constexpr int THREADS = TILE * TILE * 64;  // one wave per pair
+  typedef typename GramT<T>::acc4 acc4;
+  typedef typename GramT<T>::vec16 vec16;
+  constexpr int VL = 16 / sizeof(T);        // elements per 16-byte vector
+  __shared__ __align__(16) T sa[2][TILE][SLICE];
+  __shared__ __align__(16) T sb[2][TILE][SLICE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave / TILE, wb = wave % TILE;
   const int2 tp = tiles[blockIdx.x];
   const int ta = tp.x, tb = tp.y;
   const int a = ta * TILE + wa, b = tb * TILE + wb;
 
-  // one slice of the 4 + 4 tensors: loaded into registers (kPer vectors
-  // per thread) while the current slice is multiplied, stored to the other
-  // LDS buffer after the products
-  constexpr int kPer = 2 * TILE * SLICE / 4 / THREADS;
-  static_assert(kPer * THREADS == 2 * TILE * SLICE / 4, "whole vectors per thread");
-  v4f pre[kPer];
+  // one slice of the TILE + TILE tensors: loaded into registers (kPer
+  // vectors per thread) while the current slice is multiplied, stored to
+  // the other LDS buffer after the products
+  constexpr int kPer = 2 * TILE * SLICE / VL / THREADS;
+  static_assert(kPer * THREADS == 2 * TILE * SLICE / VL, "whole vectors per thread");
+  vec16 pre[kPer];
   auto load = [&](int sl) {
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + u * THREADS;
-      const int side = e / (TILE * SLICE / 4);
-      const int rem = e % (TILE * SLICE / 4);
-      const int which = rem / (SLICE / 4), off = rem % (SLICE / 4);
-      pre[u] = v4f{0.f, 0.f, 0.f, 0.f};
+      const int side = e / (TILE * SLICE / VL);
+      const int rem = e % (TILE * SLICE / VL);
+      const int which = rem / (SLICE / VL), off = rem % (SLICE / VL);
+      pre[u] = vec16{};
       if (side == 0) {
         const int ia = ta * TILE + which;
-        if (ia < na) pre[u] = ((const v4f *)(pa + ((long long)ia * md.total + sl) * SLICE))[off];
+        if (ia < na) pre[u] = ((const vec16 *)(pa + ((long long)ia * md.total + sl) * SLICE))[off];
       } else {
         const int ib = tb * TILE + which;
-        if (ib < nb) pre[u] = ((const v4f *)(pb + ((long long)ib * md.total + sl) * SLICE))[off];
+        if (ib < nb) pre[u] = ((const vec16 *)(pb + ((long long)ib * md.total + sl) * SLICE))[off];
       }
     }
   };
@@ -114,22 +147,22 @@ __global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + u * THREADS;
-      const int side = e / (TILE * SLICE / 4);
-      const int rem = e % (TILE * SLICE / 4);
-      const int which = rem / (SLICE / 4), off = rem % (SLICE / 4);
-      if (side == 0) ((v4f *)sa[buf][which])[off] = pre[u];
-      else ((v4f *)sb[buf][which])[off] = pre[u];
+      const int side = e / (TILE * SLICE / VL);
+      const int rem = e % (TILE * SLICE / VL);
+      const int which = rem / (SLICE / VL), off = rem % (SLICE / VL);
+      if (side == 0) ((vec16 *)sa[buf][which])[off] = pre[u];
+      else ((vec16 *)sb[buf][which])[off] = pre[u];
     }
   };
 
   // Psi = Phi_0^T = e_0 e_0^T in D layout (tile (0,0), lane 0, v 0)
-  v4f psi[4], nxt[4];
+  acc4 psi[4], nxt[4];
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
-    psi[x] = v4f{0.f, 0.f, 0.f, 0.f};
-    nxt[x] = v4f{0.f, 0.f, 0.f, 0.f};
+    psi[x] = acc4{};
+    nxt[x] = acc4{};
   }
-  if (lane == 0) psi[0][0] = 1.f;
+  if (lane == 0) psi[0][0] = T(1);
 
   int sl = 0, buf = 0;
   load(0);
@@ -139,35 +172,36 @@ __global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__
     for (int i = 0; i < md.n[k]; ++i, ++sl) {
       const bool more = sl + 1 < md.total;
       if (more) load(sl + 1);  // in flight during this slice's products
-      v4f bo[4], ao[4];
+      acc4 bo[4], ao[4];
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        bo[x] = ((const v4f *)sb[buf][wb])[x * 64 + lane];
-        ao[x] = ((const v4f *)sa[buf][wa])[x * 64 + lane];
+        bo[x] = ((const acc4 *)sb[buf][wb])[x * 64 + lane];
+        ao[x] = ((const acc4 *)sa[buf][wa])[x * 64 + lane];
       }
-      // Y = Phi B_i; A operand Phi[16 to + c][16 ti + 4q + v] = Psi tile (ti, to)
-      v4f y[4];
+      // Y = Phi B_i; A operand Phi[16 to + c][16 ti + K(q, v)] = Psi tile (ti, to), with
+      // K(q, v) = 4q + v (float32) or q + 4v (float64)
+      acc4 y[4];
 #pragma unroll
       for (int to = 0; to < 2; ++to)
 #pragma unroll
         for (int tc = 0; tc < 2; ++tc) {
-          v4f acc = {0.f, 0.f, 0.f, 0.f};
+          acc4 acc = acc4{};
 #pragma unroll
           for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc = mfma4(psi[ti * 2 + to][v], bo[ti * 2 + tc][v], acc);
+            for (int v = 0; v < 4; ++v) acc = GramT<T>::mfma(psi[ti * 2 + to][v], bo[ti * 2 + tc][v], acc);
           y[to * 2 + tc] = acc;
         }
-      // Psi_next += Y^T A_i; A operand Y^T[16 to + c][16 ti + 4q + v] = Y tile (ti, to)
+      // Psi_next += Y^T A_i; A operand Y^T[16 to + c][16 ti + K(q, v)] = Y tile (ti, to)
 #pragma unroll
       for (int to = 0; to < 2; ++to)
 #pragma unroll
         for (int tc = 0; tc < 2; ++tc) {
-          v4f acc = nxt[to * 2 + tc];
+          acc4 acc = nxt[to * 2 + tc];
 #pragma unroll
           for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc = mfma4(y[ti * 2 + to][v], ao[ti * 2 + tc][v], acc);
+            for (int v = 0; v < 4; ++v) acc = GramT<T>::mfma(y[ti * 2 + to][v], ao[ti * 2 + tc][v], acc);
           nxt[to * 2 + tc] = acc;
         }
       if (more) store(buf ^ 1);
@@ -177,46 +211,48 @@ __global__ void __launch_bounds__(THREADS) gram_kernel(const float *__restrict__
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       psi[x] = nxt[x];
-      nxt[x] = v4f{0.f, 0.f, 0.f, 0.f};
+      nxt[x] = acc4{};
     }
   }
   // <A_a, B_b> = Phi_d[0][0] = Psi[0][0]
   // symmetric case: in diagonal tiles only the pairs with a <= b write, so
   // that G is exactly symmetric
   if (lane == 0 && a < na && b < nb && !(sym && a > b)) {
-    const float g = psi[0][0];
+    const T g = psi[0][0];
     G[(long long)a * nb + b] = g;
     if (sym && a != b) G[(long long)b * nb + a] = g;
   }
 }
 
-int pack(const tt_batch *X, const InstMeta *dmeta, const Modes &md, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(gram_pack_kernel, dim3(md.total, X->b), dim3(256), 0, s, dmeta, md, out);
-  return launch_check("gram pack");
+template <class T>
+int ntiles_of(int b) {
+  return (b + GramT<T>::TILE - 1) / GramT<T>::TILE;
 }
-
-int ntiles_of(int b) { return (b + TILE - 1) / TILE; }
 
 }  // namespace
 
-size_t gram_ws(const tt_batch *A, const tt_batch *B) {
-  const tt_tensor &t0 = A->tt[0];
+template <class T>
+size_t gram_ws_t(const tt_tensor *A, int na, const tt_tensor *B, int nb_in) {
+  const tt_tensor &t0 = A[0];
   long total = 0;
   for (int k = 0; k < t0.d; ++k) total += t0.n[k];
   const int sym = (B == nullptr);
-  const int nb = sym ? A->b : B->b;
-  const long nta = ntiles_of(A->b), ntb = ntiles_of(nb);
-  size_t bytes = arena_bytes<InstMeta>((size_t)A->b + (sym ? 0 : nb));
-  bytes += arena_bytes<float>((size_t)A->b * total * SLICE);
-  if (!sym) bytes += arena_bytes<float>((size_t)nb * total * SLICE);
+  const int nb = sym ? na : nb_in;
+  const long nta = ntiles_of<T>(na), ntb = ntiles_of<T>(nb);
+  size_t bytes = arena_bytes<InstMeta>((size_t)na + (sym ? 0 : nb));
+  bytes += arena_bytes<T>((size_t)na * total * SLICE);
+  if (!sym) bytes += arena_bytes<T>((size_t)nb * total * SLICE);
   bytes += arena_bytes<int2>((size_t)nta * ntb);
   return bytes;
 }
 
-int gram_run(const tt_batch *A, const tt_batch *B, float *G, void *ws, size_t bytes, hipStream_t s) {
+// A, B: shape views of the members; adata, bdata their core pointers.
+template <class T>
+int gram_run_t(const tt_tensor *A, int na, const T *const *adata, const tt_tensor *B, int nb_in,
+               const T *const *bdata, T *G, void *ws, size_t bytes, hipStream_t s) {
   const int sym = (B == nullptr);
-  const tt_batch *Bb = sym ? A : B;
-  const tt_tensor &t0 = A->tt[0];
+  const int nbb = sym ? na : nb_in;
+  const tt_tensor &t0 = A[0];
   Modes md = {};
   md.d = t0.d;
   md.total = 0;
@@ -225,10 +261,10 @@ int gram_run(const tt_batch *A, const tt_batch *B, float *G, void *ws, size_t by
     md.total += t0.n[k];
   }
   Arena ar(ws, bytes);
-  InstMeta *dmeta = ar.take<InstMeta>((size_t)A->b + (sym ? 0 : Bb->b));
-  float *packA = ar.take<float>((size_t)A->b * md.total * SLICE);
-  float *packB = sym ? packA : ar.take<float>((size_t)Bb->b * md.total * SLICE);
-  const int nta = ntiles_of(A->b), ntb = ntiles_of(Bb->b);
+  InstMeta *dmeta = ar.take<InstMeta>((size_t)na + (sym ? 0 : nbb));
+  T *packA = ar.take<T>((size_t)na * md.total * SLICE);
+  T *packB = sym ? packA : ar.take<T>((size_t)nbb * md.total * SLICE);
+  const int nta = ntiles_of<T>(na), ntb = ntiles_of<T>(nbb);
   int2 *dtiles = ar.take<int2>((size_t)nta * ntb);
   if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "gram: workspace too small");
 
@@ -236,15 +272,15 @@ int gram_run(const tt_batch *A, const tt_batch *B, float *G, void *ws, size_t by
   // per-thread buffers that only grow)
   static thread_local std::vector<InstMeta> hmeta_buf;
   static thread_local std::vector<int2> htile_buf;
-  const int nmeta = A->b + (sym ? 0 : Bb->b);
+  const int nmeta = na + (sym ? 0 : nbb);
   if ((int)hmeta_buf.size() < nmeta) hmeta_buf.resize(nmeta);
   if (htile_buf.size() < (size_t)nta * ntb) htile_buf.resize((size_t)nta * ntb);
   InstMeta *hmeta = hmeta_buf.data();
   for (int j = 0; j < nmeta; ++j) {
-    const tt_tensor *X = (j < A->b) ? &A->tt[j] : &Bb->tt[j - A->b];
+    const tt_tensor *X = (j < na) ? &A[j] : &B[j - na];
     InstMeta &m = hmeta[j];
     memset(&m, 0, sizeof m);
-    m.data = X->data;
+    m.data = (j < na) ? (const void *)adata[j] : (const void *)bdata[j - na];
     for (int k = 0; k < X->d; ++k) m.off[k] = core_off(X, k);
     for (int k = 0; k <= X->d; ++k) m.r[k] = X->r[k];
   }
@@ -258,13 +294,35 @@ int gram_run(const tt_batch *A, const tt_batch *B, float *G, void *ws, size_t by
     rc = hip_check(hipMemcpyAsync(dtiles, htiles, sizeof(int2) * ntile, hipMemcpyHostToDevice, s),
                    "gram tile copy");
   if (rc) return rc;
-  if ((rc = pack(A, dmeta, md, packA, s))) return rc;
-  if (!sym && (rc = pack(Bb, dmeta + A->b, md, packB, s))) return rc;
+  hipLaunchKernelGGL(gram_pack_kernel<T>, dim3(md.total, na), dim3(256), 0, s, dmeta, md, packA);
+  if ((rc = launch_check("gram pack"))) return rc;
+  if (!sym) {
+    hipLaunchKernelGGL(gram_pack_kernel<T>, dim3(md.total, nbb), dim3(256), 0, s, dmeta + na, md, packB);
+    if ((rc = launch_check("gram pack"))) return rc;
+  }
+  constexpr int THREADS = GramT<T>::TILE * GramT<T>::TILE * 64;
   timer_before(s);
-  hipLaunchKernelGGL(gram_kernel, dim3(ntile), dim3(THREADS), 0, s, packA, packB, A->b, Bb->b, md, sym,
-                     dtiles, G);
+  hipLaunchKernelGGL(gram_kernel<T>, dim3(ntile), dim3(THREADS), 0, s, packA, packB, na, nbb, md, sym, dtiles, G);
   timer_after(s);
   return launch_check("gram");
+}
+
+size_t gram_ws(const tt_batch *A, const tt_batch *B) {
+  return gram_ws_t<float>(A->tt, A->b, B ? B->tt : nullptr, B ? B->b : 0);
+}
+
+int gram_run(const tt_batch *A, const tt_batch *B, float *G, void *ws, size_t bytes, hipStream_t s) {
+  std::vector<const float *> ad(A->b), bd(B ? B->b : 0);
+  for (int j = 0; j < A->b; ++j) ad[j] = A->tt[j].data;
+  for (int j = 0; B && j < B->b; ++j) bd[j] = B->tt[j].data;
+  return gram_run_t<float>(A->tt, A->b, ad.data(), B ? B->tt : nullptr, B ? B->b : 0, bd.data(), G, ws, bytes, s);
+}
+
+size_t gram_ws_f64(const tt_tensor *A, int na, const tt_tensor *B, int nb) { return gram_ws_t<double>(A, na, B, nb); }
+
+int gram_run_f64(const tt_tensor *A, int na, const double *const *adata, const tt_tensor *B, int nb,
+                 const double *const *bdata, double *G, void *ws, size_t bytes, hipStream_t s) {
+  return gram_run_t<double>(A, na, adata, B, nb, bdata, G, ws, bytes, s);
 }
 
 }  // namespace ttgfx

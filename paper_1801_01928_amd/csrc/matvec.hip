@@ -11,6 +11,8 @@
 // the caches; the bytes that must move are those of y.  The LDS path stages
 // both factors' slices per workgroup; the grid-stride fallback gathers them
 // per lane.
+#include <vector>
+
 #include "common.h"
 
 namespace ttgfx {
@@ -20,11 +22,12 @@ constexpr int kMvBatch = 64;  // vectors per launch
 constexpr int kMvThreads = 256;
 constexpr int kMvPerThread = 8;  // fewer, fuller workgroups: dispatch is not the limit
 
+template <class T>
 struct MatDev {
   int d;
   int m[TT_MAX_D], n[TT_MAX_D], r[TT_MAX_D + 1];
   long long off[TT_MAX_D];
-  const float *data;
+  const T *data;
 };
 
 // The right factor: a TT vector (L_k = 1) or a TT-matrix with cores
@@ -37,16 +40,18 @@ struct OutDev {
   long long off[TT_MAX_D];
 };
 
+template <class T>
 struct MvIO {
-  const float *x[kMvBatch];
-  float *y[kMvBatch];
+  const T *x[kMvBatch];
+  T *y[kMvBatch];
 };
 
 // grid (g, d, members), grid-stride over the elements of y_k for member
 // blockIdx.z (g sized for about kMvPerThread elements per thread of the
 // largest core): element e = ((row m_k + i) L_k + l) R' + col, with
 // row = a s_k + b, col = a' s_{k+1} + b', R' = r_{k+1} s_{k+1}.
-__global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, RightDev X0, OutDev Y0, MvIO io) {
+template <class T>
+__global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
   const int k = blockIdx.y;
   const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
   const int mk = W.m[k], nk = W.n[k], lk = X0.L[k];
@@ -54,18 +59,18 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, RightDev X
   // arithmetic
   const unsigned R1 = (unsigned)(r1 * s1);
   const unsigned cnt = (unsigned)r0 * s0 * mk * lk * R1;
-  const float *xm = io.x[blockIdx.z] + X0.off[k];
-  float *yk = io.y[blockIdx.z] + Y0.off[k];
+  const T *xm = io.x[blockIdx.z] + X0.off[k];
+  T *yk = io.y[blockIdx.z] + Y0.off[k];
   const long long xs = (long long)lk * s1;  // x stride along j
   for (unsigned e = blockIdx.x * kMvThreads + threadIdx.x; e < cnt; e += gridDim.x * kMvThreads) {
     const unsigned t = e / R1, col = e - t * R1;
     const unsigned t2 = t / lk, l = t - t2 * lk;
     const unsigned row = t2 / mk, i = t2 - row * mk;
     const unsigned a = row / s0, b = row - a * s0, ap = col / s1, bp = col - ap * s1;
-    const float *wk = W.data + W.off[k] + (((long long)a * mk + i) * nk) * r1 + ap;
-    const float *xk = xm + ((long long)b * nk * lk + l) * s1 + bp;
-    float acc = 0.f;
-    for (int j = 0; j < nk; ++j) acc = fmaf(wk[(long long)j * r1], xk[j * xs], acc);
+    const T *wk = W.data + W.off[k] + (((long long)a * mk + i) * nk) * r1 + ap;
+    const T *xk = xm + ((long long)b * nk * lk + l) * s1 + bp;
+    T acc = T(0);
+    for (int j = 0; j < nk; ++j) acc = fma(wk[(long long)j * r1], xk[j * xs], acc);
     yk[e] = acc;
   }
 }
@@ -76,9 +81,11 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev W, RightDev X
 // writes the s_k rows (a, b) at (i, l), each a contiguous run of
 // r_{k+1} s_{k+1} elements.  The host takes this path when both slices fit
 // in kMvLdsFloats for every core.
-constexpr int kMvLdsFloats = 16384;  // 64 KB of dynamic LDS
-__global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev W, RightDev X0, OutDev Y0, MvIO io) {
-  extern __shared__ float lds[];
+constexpr int kMvLdsBytes = 65536;  // 64 KB of dynamic LDS
+template <class T>
+__global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
+  extern __shared__ __align__(16) char lds_raw[];
+  T *lds = (T *)lds_raw;
   const int k = blockIdx.y;
   const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
   const int mk = W.m[k], nk = W.n[k], lk = X0.L[k];
@@ -86,10 +93,10 @@ __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev W, RightD
   if (blockIdx.x >= pairs) return;  // uniform over the workgroup, before any barrier
   const unsigned t = blockIdx.x / lk, l = blockIdx.x - t * lk;
   const unsigned a = t / mk, i = t - a * mk;
-  float *ws = lds, *xs = lds + nk * r1;
-  const float *wsrc = W.data + W.off[k] + ((long long)a * mk + i) * nk * r1;
+  T *ws = lds, *xs = lds + nk * r1;
+  const T *wsrc = W.data + W.off[k] + ((long long)a * mk + i) * nk * r1;
   for (int e = threadIdx.x; e < nk * r1; e += kMvThreads) ws[e] = wsrc[e];
-  const float *xm = io.x[blockIdx.z] + X0.off[k];
+  const T *xm = io.x[blockIdx.z] + X0.off[k];
   const int xn = s0 * nk * s1;
   for (int e = threadIdx.x; e < xn; e += kMvThreads) {
     const int bp = e % s1, u = e / s1;  // u = b n_k + j
@@ -97,13 +104,13 @@ __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev W, RightD
   }
   __syncthreads();
   const int R1 = r1 * s1;
-  float *yk = io.y[blockIdx.z] + Y0.off[k];
+  T *yk = io.y[blockIdx.z] + Y0.off[k];
   for (int o = threadIdx.x; o < s0 * R1; o += kMvThreads) {
     const int b = o / R1, col = o - b * R1;
     const int ap = col / s1, bp = col - ap * s1;
-    const float *xb = xs + b * nk * s1 + bp;
-    float acc = 0.f;
-    for (int j = 0; j < nk; ++j) acc = fmaf(ws[j * r1 + ap], xb[j * s1], acc);
+    const T *xb = xs + b * nk * s1 + bp;
+    T acc = T(0);
+    for (int j = 0; j < nk; ++j) acc = fma(ws[j * r1 + ap], xb[j * s1], acc);
     const long long row = (long long)a * s0 + b;
     yk[((row * mk + i) * lk + l) * R1 + col] = acc;
   }
@@ -111,7 +118,8 @@ __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev W, RightD
 
 // Launches the product kernels for `members` right factors: the LDS path
 // when every core's two slices fit, else the grid-stride kernel.
-int launch_products(const MatDev &md, const RightDev &x0, const OutDev &y0, const MvIO &io, int members,
+template <class T>
+int launch_products(const MatDev<T> &md, const RightDev &x0, const OutDev &y0, const MvIO<T> &io, int members,
                     hipStream_t s) {
   long long maxcnt = 0, maxpairs = 0, maxlds = 0;
   for (int k = 0; k < md.d; ++k) {
@@ -124,18 +132,19 @@ int launch_products(const MatDev &md, const RightDev &x0, const OutDev &y0, cons
     maxlds = f > maxlds ? f : maxlds;
   }
   if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "product: an output core of 2^31 or more elements");
-  if (maxlds <= kMvLdsFloats && maxpairs <= 0x7fffffffLL) {
-    hipLaunchKernelGGL(matvec_lds_kernel, dim3((unsigned)maxpairs, (unsigned)md.d, (unsigned)members),
-                       dim3(kMvThreads), (size_t)maxlds * sizeof(float), s, md, x0, y0, io);
+  if (maxlds * (long long)sizeof(T) <= kMvLdsBytes && maxpairs <= 0x7fffffffLL) {
+    hipLaunchKernelGGL(matvec_lds_kernel<T>, dim3((unsigned)maxpairs, (unsigned)md.d, (unsigned)members),
+                       dim3(kMvThreads), (size_t)maxlds * sizeof(T), s, md, x0, y0, io);
   } else {
     const long long gx = (maxcnt + (long long)kMvThreads * kMvPerThread - 1) / ((long long)kMvThreads * kMvPerThread);
-    hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)gx, (unsigned)md.d, (unsigned)members), dim3(kMvThreads), 0,
+    hipLaunchKernelGGL(matvec_kernel<T>, dim3((unsigned)gx, (unsigned)md.d, (unsigned)members), dim3(kMvThreads), 0,
                        s, md, x0, y0, io);
   }
   return launch_check("TT-matrix product");
 }
 
-int validate_matrix(const tt_matrix *W, MatDev *md) {
+template <class T>
+int validate_matrix(const tt_matrix *W, MatDev<T> *md) {
   if (!W) return set_error(TT_ERR_ARG, "W: null descriptor");
   if (W->d < 1 || W->d > TT_MAX_D) return set_error(TT_ERR_ARG, "W: d = %d outside [1, %d]", W->d, TT_MAX_D);
   if (!W->m || !W->n || !W->r) return set_error(TT_ERR_ARG, "W: null m, n or r array");
@@ -143,7 +152,7 @@ int validate_matrix(const tt_matrix *W, MatDev *md) {
   if (W->r[0] != 1 || W->r[W->d] != 1)
     return set_error(TT_ERR_SHAPE, "W: boundary ranks must be 1 (got %d, %d)", W->r[0], W->r[W->d]);
   md->d = W->d;
-  md->data = (const float *)W->data;
+  md->data = (const T *)W->data;
   long long o = 0;
   for (int k = 0; k <= W->d; ++k) {
     if (W->r[k] < 1 || W->r[k] > TT_MAX_RANK)
@@ -163,14 +172,16 @@ int validate_matrix(const tt_matrix *W, MatDev *md) {
   return TT_OK;
 }
 
-int validate_matvec(const tt_matrix *W, const tt_batch *X, const tt_batch *Y, MatDev *md) {
+// X, Y: shape views of the b vectors and products (data only tested for NULL).
+template <class T>
+int validate_matvec(const tt_matrix *W, const tt_tensor *X, const tt_tensor *Y, int b, MatDev<T> *md) {
   int rc = validate_matrix(W, md);
   if (rc) return rc;
-  if (!X || X->b < 1 || !X->tt) return set_error(TT_ERR_ARG, "matvec: empty batch of vectors");
-  if (!Y || Y->b != X->b || !Y->tt) return set_error(TT_ERR_ARG, "matvec: Y must hold as many TTs as X");
-  const tt_tensor *x0 = &X->tt[0], *y0 = &Y->tt[0];
-  for (int j = 0; j < X->b; ++j) {
-    const tt_tensor *x = &X->tt[j], *y = &Y->tt[j];
+  if (b < 1 || !X) return set_error(TT_ERR_ARG, "matvec: empty batch of vectors");
+  if (!Y) return set_error(TT_ERR_ARG, "matvec: Y must hold as many TTs as X");
+  const tt_tensor *x0 = &X[0], *y0 = &Y[0];
+  for (int j = 0; j < b; ++j) {
+    const tt_tensor *x = &X[j], *y = &Y[j];
     if ((rc = validate_tt(x, "X[j]", TT_MAX_RANK))) return rc;
     if ((rc = validate_tt(y, "Y[j]", TT_MAX_RANK * TT_MAX_RANK))) return rc;
     if (x->d != W->d || y->d != W->d) return set_error(TT_ERR_SHAPE, "X[%d], Y[%d] must have W's d", j, j);
@@ -188,40 +199,38 @@ int validate_matvec(const tt_matrix *W, const tt_batch *X, const tt_batch *Y, Ma
   return TT_OK;
 }
 
-}  // namespace
-}  // namespace ttgfx
-
-using namespace ttgfx;
-
-extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, void *stream) {
-  MatDev md;
-  int rc = validate_matvec(W, X, Y, &md);
+template <class T>
+int run_matvec(const tt_matrix *W, const tt_tensor *X, const tt_tensor *Y, const T *const *xdata, T *const *ydata,
+               int b, hipStream_t s) {
+  MatDev<T> md;
+  int rc = validate_matvec(W, X, Y, b, &md);
   if (rc) return rc;
   RightDev x0{};
   OutDev y0{};
   for (int k = 0; k < md.d; ++k) {
-    x0.r[k] = X->tt[0].r[k];
+    x0.r[k] = X[0].r[k];
     x0.L[k] = 1;
-    x0.off[k] = core_off(&X->tt[0], k);
-    y0.off[k] = core_off(&Y->tt[0], k);
+    x0.off[k] = core_off(&X[0], k);
+    y0.off[k] = core_off(&Y[0], k);
   }
   x0.r[md.d] = 1;
-  for (int j0 = 0; j0 < X->b; j0 += kMvBatch) {
-    const int m = (X->b - j0) < kMvBatch ? (X->b - j0) : kMvBatch;
-    MvIO io{};
+  for (int j0 = 0; j0 < b; j0 += kMvBatch) {
+    const int m = (b - j0) < kMvBatch ? (b - j0) : kMvBatch;
+    MvIO<T> io{};
     for (int j = 0; j < m; ++j) {
-      io.x[j] = X->tt[j0 + j].data;
-      io.y[j] = Y->tt[j0 + j].data;
+      io.x[j] = xdata[j0 + j];
+      io.y[j] = ydata[j0 + j];
     }
-    if ((rc = launch_products(md, x0, y0, io, m, (hipStream_t)stream))) return rc;
+    if ((rc = launch_products(md, x0, y0, io, m, s))) return rc;
   }
   return TT_OK;
 }
 
 // C = A B for two TT-matrices (A: m x n modes, B: n x l modes): the cores
 // C_k[(a, b), i, l, (a', b')] = sum_j A_k[a, i, j, a'] B_k[b, j, l, b'].
-extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, void *stream) {
-  MatDev ma, mb;
+template <class T>
+int run_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, hipStream_t s) {
+  MatDev<T> ma, mb;
   int rc;
   if ((rc = validate_matrix(A, &ma)) || (rc = validate_matrix(B, &mb))) return rc;
   if (!Cm) return set_error(TT_ERR_ARG, "C: null descriptor");
@@ -248,8 +257,49 @@ extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, 
     oc += c;
   }
   x0.r[A->d] = 1;
-  MvIO io{};
+  MvIO<T> io{};
   io.x[0] = mb.data;
-  io.y[0] = (float *)Cm->data;
-  return launch_products(ma, x0, y0, io, 1, (hipStream_t)stream);
+  io.y[0] = (T *)Cm->data;
+  return launch_products(ma, x0, y0, io, 1, s);
+}
+
+}  // namespace
+}  // namespace ttgfx
+
+using namespace ttgfx;
+
+extern "C" int tt_matvec(const tt_matrix *W, const tt_batch *X, tt_batch *Y, void *stream) {
+  if (!X || X->b < 1 || !X->tt) return set_error(TT_ERR_ARG, "matvec: empty batch of vectors");
+  if (!Y || Y->b != X->b || !Y->tt) return set_error(TT_ERR_ARG, "matvec: Y must hold as many TTs as X");
+  std::vector<const float *> xd(X->b);
+  std::vector<float *> yd(X->b);
+  for (int j = 0; j < X->b; ++j) {
+    xd[j] = X->tt[j].data;
+    yd[j] = Y->tt[j].data;
+  }
+  return run_matvec<float>(W, X->tt, Y->tt, xd.data(), yd.data(), X->b, (hipStream_t)stream);
+}
+
+extern "C" int tt_matvec_f64(const tt_matrix *W, const tt_batch_f64 *X, tt_batch_f64 *Y, void *stream) {
+  if (!X || X->b < 1 || !X->tt) return set_error(TT_ERR_ARG, "matvec: empty batch of vectors");
+  if (!Y || Y->b != X->b || !Y->tt) return set_error(TT_ERR_ARG, "matvec: Y must hold as many TTs as X");
+  std::vector<tt_tensor> xv(X->b), yv(X->b);
+  std::vector<const double *> xd(X->b);
+  std::vector<double *> yd(X->b);
+  for (int j = 0; j < X->b; ++j) {
+    const tt_tensor_f64 &x = X->tt[j], &y = Y->tt[j];
+    xv[j] = tt_tensor{x.d, x.n, x.r, x.off, (float *)x.data};  // shape views
+    yv[j] = tt_tensor{y.d, y.n, y.r, y.off, (float *)y.data};
+    xd[j] = x.data;
+    yd[j] = y.data;
+  }
+  return run_matvec<double>(W, xv.data(), yv.data(), xd.data(), yd.data(), X->b, (hipStream_t)stream);
+}
+
+extern "C" int tt_matmat(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, void *stream) {
+  return run_matmat<float>(A, B, Cm, (hipStream_t)stream);
+}
+
+extern "C" int tt_matmat_f64(const tt_matrix *A, const tt_matrix *B, tt_matrix *Cm, void *stream) {
+  return run_matmat<double>(A, B, Cm, (hipStream_t)stream);
 }

@@ -30,9 +30,12 @@ def _workspace(nbytes, device):
 
 
 class TT:
-    """A TT tensor (Introduction: the TT format) with packed float32 cores."""
+    """A TT tensor (Introduction: the TT format) with packed float32 cores
+    (float64 for the double-precision Table 1 operations: tt_matvec,
+    tt_matmat, norms and gram take either; every other entry point takes
+    float32, and a float64 descriptor is refused by its argument types)."""
 
-    def __init__(self, ns, ranks, data=None, device="cuda"):
+    def __init__(self, ns, ranks, data=None, device="cuda", dtype=torch.float32):
         self.ns = [int(x) for x in ns]
         self.ranks = [int(x) for x in ranks]
         if len(self.ranks) != len(self.ns) + 1:
@@ -42,10 +45,10 @@ class TT:
         for s in self.sizes:
             self.offs.append(self.offs[-1] + s)
         if data is None:
-            data = torch.empty(self.offs[-1], dtype=torch.float32, device=device)
-        if data.dtype != torch.float32 or data.dim() != 1 or data.numel() != self.offs[-1] \
+            data = torch.empty(self.offs[-1], dtype=dtype, device=device)
+        if data.dtype not in (torch.float32, torch.float64) or data.dim() != 1 or data.numel() != self.offs[-1] \
                 or not data.is_contiguous():
-            raise ValueError("data must be a contiguous float32 vector of %d elements" % self.offs[-1])
+            raise ValueError("data must be a contiguous float32 or float64 vector of %d elements" % self.offs[-1])
         self.data = data
         self._desc = None
 
@@ -58,12 +61,17 @@ class TT:
         return self.data.device
 
     @classmethod
-    def from_cores(cls, cores, device="cuda"):
-        cores = [np.asarray(c, dtype=np.float32) if not torch.is_tensor(c) else c for c in cores]
+    def from_cores(cls, cores, device="cuda", dtype=torch.float32):
+        npdt = np.float64 if dtype == torch.float64 else np.float32
+        cores = [np.asarray(c, dtype=npdt) if not torch.is_tensor(c) else c for c in cores]
         ns = [int(c.shape[1]) for c in cores]
         ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
-        flat = torch.cat([torch.as_tensor(c, dtype=torch.float32).reshape(-1) for c in cores])
+        flat = torch.cat([torch.as_tensor(c, dtype=dtype).reshape(-1) for c in cores])
         return cls(ns, ranks, flat.to(device).contiguous(), device=device)
+
+    @property
+    def is_f64(self):
+        return self.data.dtype == torch.float64
 
     def core(self, k):
         return self.data[self.offs[k]:self.offs[k + 1]].view(self.ranks[k], self.ns[k], self.ranks[k + 1])
@@ -75,15 +83,17 @@ class TT:
         return [c.detach().cpu().numpy() for c in self.cores()]
 
     def empty_like(self):
-        return TT(self.ns, self.ranks, device=self.device)
+        return TT(self.ns, self.ranks, device=self.device, dtype=self.data.dtype)
 
     def desc(self):
-        """The ``tt_tensor`` descriptor (host arrays kept alive by this object)."""
+        """The ``tt_tensor`` descriptor (``tt_tensor_f64`` for float64 cores;
+        host arrays kept alive by this object)."""
         if self._desc is None or self._desc.data != self.data.data_ptr():
             d = self.d
             self._n = (C.c_int32 * d)(*self.ns)
             self._r = (C.c_int32 * (d + 1))(*self.ranks)
-            self._desc = L.tt_tensor(d, self._n, self._r, None, self.data.data_ptr())
+            kind = L.tt_tensor_f64 if self.is_f64 else L.tt_tensor
+            self._desc = kind(d, self._n, self._r, None, self.data.data_ptr())
         return self._desc
 
 
@@ -439,11 +449,13 @@ def tangent_inner(U, A, B):
 
 
 def norms(As):
-    """Frobenius norms of TT tensors of one shape (tt_norms), as a device
-    tensor of len(As) floats."""
+    """Frobenius norms of TT tensors of one shape (tt_norms; tt_norms_f64
+    for float64 TTs), as a device tensor of len(As) values."""
     A, keep = _batch(As)
-    out = torch.empty(len(As), dtype=torch.float32, device=As[0].device)
-    L.check(L.load().tt_norms(C.byref(A), _ptr(out), _stream(As[0].device)))
+    f64 = As[0].is_f64
+    out = torch.empty(len(As), dtype=torch.float64 if f64 else torch.float32, device=As[0].device)
+    fn = L.load().tt_norms_f64 if f64 else L.load().tt_norms
+    L.check(fn(C.byref(A), _ptr(out), _stream(As[0].device)))
     return out
 
 
@@ -655,24 +667,33 @@ def riemannian_cg(X0, idx, t, max_rank, iters, idx_test=None, t_test=None):
 
 
 def _batch(tts):
-    """A tt_batch descriptor over TT objects (kept alive by the returned tuple)."""
-    arr = (L.tt_tensor * len(tts))(*[t.desc() for t in tts])
-    return L.tt_batch(len(tts), arr), arr
+    """A tt_batch (tt_batch_f64 for float64) descriptor over TT objects of
+    one precision (kept alive by the returned tuple)."""
+    f64 = tts[0].is_f64
+    if any(t.is_f64 != f64 for t in tts):
+        raise ValueError("a batch holds TTs of one precision")
+    kind, bkind = (L.tt_tensor_f64, L.tt_batch_f64) if f64 else (L.tt_tensor, L.tt_batch)
+    arr = (kind * len(tts))(*[t.desc() for t in tts])
+    return bkind(len(tts), arr), arr
 
 
 def gram(As, Bs=None):
     """Gram matrix G[a][b] = <As[a], Bs[b]> (Bs = None: As with itself,
-    computed once per unordered pair).  Ranks up to 32; ranks may differ
-    between tensors."""
+    computed once per unordered pair; tt_gram_f64 for float64 TTs).  Ranks
+    up to 32; ranks may differ between tensors."""
     lib = L.load()
     dev = As[0].device
     A, keepA = _batch(As)
     B, keepB = _batch(Bs) if Bs is not None else (None, None)
     pB = C.byref(B) if B is not None else None
     nb = len(Bs) if Bs is not None else len(As)
-    G = torch.empty((len(As), nb), dtype=torch.float32, device=dev)
-    ws, n = _workspace(L.check(lib.tt_gram_workspace(C.byref(A), pB)), dev)
-    L.check(lib.tt_gram(C.byref(A), pB, _ptr(G), _ptr(ws), n, _stream(dev)))
+    f64 = As[0].is_f64
+    if Bs is not None and Bs[0].is_f64 != f64:
+        raise ValueError("gram takes two batches of one precision")
+    G = torch.empty((len(As), nb), dtype=torch.float64 if f64 else torch.float32, device=dev)
+    wsq, run = (lib.tt_gram_f64_workspace, lib.tt_gram_f64) if f64 else (lib.tt_gram_workspace, lib.tt_gram)
+    ws, n = _workspace(L.check(wsq(C.byref(A), pB)), dev)
+    L.check(run(C.byref(A), pB, _ptr(G), _ptr(ws), n, _stream(dev)))
     return G
 
 
@@ -762,9 +783,10 @@ class TTMatrix:
         self.offs = [0]
         for s in self.sizes:
             self.offs.append(self.offs[-1] + s)
-        if data.dtype not in (torch.float32, torch.bfloat16) or data.dim() != 1 \
+        if data.dtype not in (torch.float32, torch.bfloat16, torch.float64) or data.dim() != 1 \
                 or data.numel() != self.offs[-1] or not data.is_contiguous():
-            raise ValueError("data must be a contiguous float32 or bfloat16 vector of %d elements" % self.offs[-1])
+            raise ValueError("data must be a contiguous float32, bfloat16 or float64 vector of %d elements"
+                             % self.offs[-1])
         self.data = data
         self._desc = None
 
@@ -774,13 +796,15 @@ class TTMatrix:
 
     @property
     def dtype_code(self):
-        return 1 if self.data.dtype == torch.bfloat16 else 0
+        return {torch.float32: 0, torch.bfloat16: 1, torch.float64: 2}[self.data.dtype]
 
     @classmethod
     def from_cores(cls, cores, dtype=torch.float32, device="cuda"):
-        cores = [torch.as_tensor(np.asarray(c, dtype=np.float32)) if not torch.is_tensor(c) else c for c in cores]
+        npdt = np.float64 if dtype == torch.float64 else np.float32
+        cores = [torch.as_tensor(np.asarray(c, dtype=npdt)) if not torch.is_tensor(c) else c for c in cores]
         ranks = [int(cores[0].shape[0])] + [int(c.shape[3]) for c in cores]
-        flat = torch.cat([c.to(torch.float32).reshape(-1) for c in cores]).to(dtype)
+        mid = torch.float64 if dtype == torch.float64 else torch.float32
+        flat = torch.cat([c.to(mid).reshape(-1) for c in cores]).to(dtype)
         return cls([c.shape[1] for c in cores], [c.shape[2] for c in cores], ranks,
                    flat.to(device).contiguous())
 
@@ -789,7 +813,7 @@ class TTMatrix:
                                                              self.ranks[k + 1])
 
     def numpy_cores(self):
-        return [self.core(k).float().cpu().numpy() for k in range(self.d)]
+        return [(self.core(k) if self.dtype_code == 2 else self.core(k).float()).cpu().numpy() for k in range(self.d)]
 
     def desc(self):
         if self._desc is None or self._desc.data != self.data.data_ptr():
@@ -809,29 +833,33 @@ def _ttm_input(W, X, cols):
 
 
 def tt_matvec(W, xs):
-    """y_j = W x_j in the TT format (tt_matvec) for a float32 TTMatrix W and
-    TT vectors xs of one shape: exact products of ranks r_k s_k."""
-    if W.dtype_code != 0:
-        raise ValueError("tt_matvec takes a float32 TT-matrix")
+    """y_j = W x_j in the TT format (tt_matvec, tt_matvec_f64) for a float32
+    or float64 TTMatrix W and TT vectors xs of one shape and W's precision:
+    exact products of ranks r_k s_k."""
+    f64 = W.dtype_code == 2
+    if W.dtype_code == 1 or any(x.is_f64 != f64 for x in xs):
+        raise ValueError("tt_matvec takes float32 or float64 operands of one precision")
     lib = L.load()
     ranks = [a * b for a, b in zip(W.ranks, xs[0].ranks)]
-    ys = [TT(W.ms, ranks, device=xs[0].device) for _ in xs]
+    ys = [TT(W.ms, ranks, device=xs[0].device, dtype=xs[0].data.dtype) for _ in xs]
     X, keepx = _batch(xs)
     Y, keepy = _batch(ys)
-    L.check(lib.tt_matvec(C.byref(W.desc()), C.byref(X), C.byref(Y), _stream(xs[0].device)))
+    fn = lib.tt_matvec_f64 if f64 else lib.tt_matvec
+    L.check(fn(C.byref(W.desc()), C.byref(X), C.byref(Y), _stream(xs[0].device)))
     return ys
 
 
 def tt_matmat(A, B):
-    """C = A B in the TT format (tt_matmat) for float32 TTMatrix objects:
-    exact, modes A.ms x B.ns, ranks the products of A's and B's."""
-    if A.dtype_code != 0 or B.dtype_code != 0:
-        raise ValueError("tt_matmat takes float32 TT-matrices")
+    """C = A B in the TT format (tt_matmat, tt_matmat_f64) for float32 or
+    float64 TTMatrix objects of one precision: exact, modes A.ms x B.ns,
+    ranks the products of A's and B's."""
+    if A.dtype_code == 1 or A.dtype_code != B.dtype_code:
+        raise ValueError("tt_matmat takes float32 or float64 TT-matrices of one precision")
     ranks = [a * b for a, b in zip(A.ranks, B.ranks)]
     n = sum(ranks[k] * A.ms[k] * B.ns[k] * ranks[k + 1] for k in range(A.d))
-    Cm = TTMatrix(A.ms, B.ns, ranks, torch.empty(n, dtype=torch.float32, device=A.data.device))
-    L.check(L.load().tt_matmat(C.byref(A.desc()), C.byref(B.desc()), C.byref(Cm.desc()),
-                               _stream(A.data.device)))
+    Cm = TTMatrix(A.ms, B.ns, ranks, torch.empty(n, dtype=A.data.dtype, device=A.data.device))
+    fn = L.load().tt_matmat_f64 if A.dtype_code == 2 else L.load().tt_matmat
+    L.check(fn(C.byref(A.desc()), C.byref(B.desc()), C.byref(Cm.desc()), _stream(A.data.device)))
     return Cm
 
 
