@@ -158,6 +158,26 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
                            tt_tensor *gX, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* --------------------------------------------------- suffix tables */
+/* The slice-grouped kernels of the gather, its adjoint and the fused pass
+ * take the right partials rho of an entry's last l indices,
+ * G^{d-l}[i_{d-l}] .. G^{d-1}[i_{d-1}] e_0, from a table holding one row per
+ * value of those indices (n_{d-l} .. n_{d-1} rows), computed once per call
+ * beside the padded slices: entries that share their last l indices share
+ * these products (the entry formula of the Introduction, regrouped), so the
+ * right sweep starts l modes later and the adjoint reads those partials
+ * from the table instead of a per-entry stash.  Levels are taken while the
+ * table stays within 2 MiB and the entries outnumber the deepest level's
+ * rows 16 to 1; results differ from the table-free path only in rounding.
+ *   tt_set_suffix_depth: process-wide policy for later calls: -1 automatic
+ *     (the default), 0 never, k > 0 up to k levels whatever M is (within the
+ *     size cap and d-1).  Workspace sizes depend on it: query them after.
+ *   tt_suffix_depth: the levels a fused pass (tt_gather_mse_backward) over
+ *     X with M entries takes under the current policy (0 on the generic
+ *     kernels), or a negative error. */
+int tt_set_suffix_depth(int32_t depth);
+int32_t tt_suffix_depth(const tt_tensor *X, int64_t M);
+
 /* --------------------------------------- A1+A2+A3 without a workspace */
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

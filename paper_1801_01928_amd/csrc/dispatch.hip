@@ -84,3 +84,22 @@ int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const 
 }
 
 }  // namespace ttgfx
+
+using namespace ttgfx;
+
+extern "C" {
+
+int tt_set_suffix_depth(int32_t depth) {
+  mfma_set_suffix_depth(depth);
+  return TT_OK;
+}
+
+int32_t tt_suffix_depth(const tt_tensor *X, int64_t M) {
+  int rc = validate_tt(X, "X", TT_MAX_RANK);
+  if (rc) return rc;
+  if (M < 0) return set_error(TT_ERR_ARG, "M = %lld is negative", (long long)M);
+  if (!use_mfma(X, X)) return 0;
+  return mfma_suffix_depth_of(X, mfma_rank_class(X, X), M);
+}
+
+}  // extern "C"

@@ -42,6 +42,13 @@ struct MfInst {
   float inv_m2;            // 2 / M
   float inv_m;             // 1 / M
   int rclass;              // 16 or 32
+  // Suffix table: right partials rho_{d-l} of every value of the last l
+  // indices, l = 1..suf_depth (level l at rows suf_row0[l-1] .., R floats a
+  // row, row = C-ordered id of (i_{d-l}, .., i_{d-1})).  suf_depth = 0: none.
+  const float *suf;
+  int suf_depth;
+  int suf_row0[MF_MAX_D];
+  int suf_rows[MF_MAX_D];  // rows of level l: n_{d-l} * .. * n_{d-1}
 };
 
 // Tile shape of the batched kernel: entries per tile of rank classes 16
@@ -77,6 +84,10 @@ int mfma_batch_wgs_per_cu(int shape, int d, const int *n);
 int mfma_batch_prepare();
 int mfma_batch_launch(const MfBatchArgs &a, int shape, int nwg, size_t lds, hipStream_t s);
 int mfma_device_cus();
+// Suffix table depth of the single-tensor kernels: -1 automatic, 0 off, k > 0
+// at most k levels (within the table's byte cap and the LDS), whatever M is.
+void mfma_set_suffix_depth(int depth);
+int mfma_suffix_depth_of(const tt_tensor *X, int R, int64_t M);
 
 // True when every descriptor fits the MFMA kernels (2 <= d <= 16, ranks <= 32,
 // mode sizes within the rank class's limit).

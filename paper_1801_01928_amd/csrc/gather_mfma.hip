@@ -16,6 +16,17 @@
 // partials are stashed (in MFMA operand layout) in a per-workgroup global
 // buffer between the sweeps; left partials are recomputed by the left sweep.
 //
+// Suffix table: entries that share their last l indices share rho_{d-l+1}
+// (1-based).  When the entries outnumber the distinct suffixes, the rho of
+// every suffix of length l = 1..depth is computed once per call (beside the
+// padded slices) into a small table that stays in L2; the right sweep then
+// starts `depth` modes later from the table, and the left sweep reads those
+// modes' rho from the table instead of the stash.
+//
+// Each sweep runs a software pipeline over a wave's blocks: entry ids two
+// blocks ahead, entry rows one block ahead, slices and stash two blocks
+// ahead, with scheduling barriers so that the loads overlap the products.
+//
 // Layouts for a block of 16 entries (lane l, q = l / 16, c = l % 16):
 //   EL (entry on lane):     lane l holds components 16t + 4q + v of entry c
 //   CL (component on lane): lane l holds component 16t + c of entries 4q + v
@@ -51,7 +62,7 @@ enum { ACC_SLAB = 0, ACC_DIRECT = 1 };
 
 // Byte offsets of the LDS regions of one tile (see mf_layout).
 struct MfLayout {
-  int rows, slab, edges, sflag, wsum, perm, bslc, nblk, total, nmax;
+  int rows, slab, edges, sflag, wsum, sid, rid, perm, bslc, nblk, total, nmax;
 };
 
 namespace {
@@ -72,36 +83,28 @@ __device__ __forceinline__ void lds_barrier() {
 
 enum { MODE_GATHER = 0, MODE_ADJOINT = 1, MODE_MSE = 2 };
 
-template <int T>
-__device__ __forceinline__ int pbase_of(const MfInst &p, int k) {
-  int s = 0;
-  for (int j = 0; j < k; ++j) s += T + 16 * p.n[j];  // multiple of 16: aligned block reads
-  return s;
-}
-
-template <int T>
-__device__ __forceinline__ int bbase_of(const MfInst &p, int k) {
-  int s = 0;
-  for (int j = 0; j < k; ++j) s += (T + 16 * p.n[j]) / 16 + 1;
-  return s;
-}
-
 // LDS layout (bytes), in this order, sized for the tensor's d and mode sizes:
 //   rows   float [T + 2][R + 4]  (row T: zeros, row T+1: write sink)
 //   slab   float [nmax][R][R + 4]     (SLAB: per-slice sums)
 //   edges  float [waves][R][R + 4]    (SLAB: runs continuing the previous wave's slice)
 //   sflag  int   [nmax + 16]          (SLAB: slice has a stored run; edge slice ids)
 //   wsum   float [T + 2]              (per-entry weight g_e; [T] = 0)
+//   sid    int   [T + 2]              (suffix table of sd levels: id of the
+//                                      entry's last sd indices; [T] = 0)
+//   rid    uint16 [sum_{k=d-1-sd}^{d-2} (T + 16 n_k)]  (table row of each
+//                                      slot of perm, modes read from the table)
 //   perm   uint16 [sum_k (T + 16 n_k)]
 //   bslc   uint8  [sum_k ((T + 16 n_k) / 16 + 1)]
-//   nblk   int   [MF_MAX_D]
-__host__ __device__ inline MfLayout mf_layout(int R, int T, int NTHR, int ACC, int d, const int *n) {
+//   nblk   int   [4][MF_MAX_D]         (blocks of mode k; first slot of mode k in
+//                                      perm and in rid, first block in bslc)
+__host__ __device__ inline MfLayout mf_layout(int R, int T, int NTHR, int ACC, int d, const int *n, int sd) {
   const int W = NTHR / 64;
-  int nmax = 1, pcap = 0, bcap = 0;
+  int nmax = 1, pcap = 0, bcap = 0, rcap = 0;
   for (int k = 0; k < d; ++k) {
     nmax = n[k] > nmax ? n[k] : nmax;
     pcap += T + 16 * n[k];
     bcap += (T + 16 * n[k]) / 16 + 1;
+    if (k >= d - 1 - sd && k <= d - 2) rcap += T + 16 * n[k];
   }
   MfLayout L;
   int o = 0;
@@ -115,12 +118,16 @@ __host__ __device__ inline MfLayout mf_layout(int R, int T, int NTHR, int ACC, i
   if (ACC == ACC_SLAB) o += a16(4 * (nmax + 16));
   L.wsum = o;
   o += a16(4 * (T + 2));
+  L.sid = o;
+  if (sd > 0) o += a16(4 * (T + 2));
+  L.rid = o;
+  o += a16(2 * rcap);
   L.perm = o;
   o += a16(2 * pcap);
   L.bslc = o;
   o += a16(bcap + 16);
   L.nblk = o;
-  o += 4 * MF_MAX_D;
+  o += 4 * 4 * MF_MAX_D;
   L.total = o + 64;
   L.nmax = nmax;
   return L;
@@ -129,7 +136,8 @@ __host__ __device__ inline MfLayout mf_layout(int R, int T, int NTHR, int ACC, i
 // One tile of T entries starting at entry e0 (cnt of them valid): sort,
 // right sweep, residual, left sweep.  `accg` is the workgroup accumulator
 // (SLAB), `loss_part` collects this thread's squared residuals (MSE).
-template <int R, int T, int NTHR, int MODE, int ACC>
+// SUF: the suffix table may be in use (p.suf_depth levels).
+template <int R, int T, int NTHR, int MODE, int ACC, bool SUF>
 __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *smem, float *stash, int nb_max,
                          float *accg, bool first_tile, float &loss_part) {
   constexpr int NT = R / 16;      // comp tiles
@@ -138,16 +146,22 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   constexpr int SS = R + 4;       // slab/edge row stride (conflict-free D stores)
   constexpr int ZROW = T;         // LDS row of zeros (padding entries read it)
   constexpr int SROW = T + 1;     // LDS row that absorbs padding writes
-  const MfLayout L = mf_layout(R, T, NTHR, ACC, p.d, p.n);
+  const int SD = SUF ? p.suf_depth : 0;  // right partials of the last SD modes come from the suffix table
+  const MfLayout L = mf_layout(R, T, NTHR, ACC, p.d, p.n, SD);
   float *rows = (float *)(smem + L.rows);
   float *slab = (float *)(smem + L.slab);
   float *edges = (float *)(smem + L.edges);
   int *sflag = (int *)(smem + L.sflag);
   int *eslice = sflag + L.nmax;
   float *wsum = (float *)(smem + L.wsum);
+  int *sidv = (int *)(smem + L.sid);
+  uint16_t *ridv = (uint16_t *)(smem + L.rid);
   uint16_t *perm = (uint16_t *)(smem + L.perm);
   uint8_t *bslc = (uint8_t *)(smem + L.bslc);
   int *nblk = (int *)(smem + L.nblk);
+  int *pofs = nblk + MF_MAX_D;      // perm slots of mode k start at pofs[k] (multiple of 16)
+  int *rofs = nblk + 2 * MF_MAX_D;  // rid slots of mode k (modes read from the table)
+  int *bofs = nblk + 3 * MF_MAX_D;  // bslc entries of mode k
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -155,6 +169,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   const int q4 = lane >> 4;
   const int d = p.d;
   const long long M = p.M;
+  const int kstart = d - 1 - SD;    // first mode the right sweep computes
   (void)slab;
   (void)edges;
   (void)sflag;
@@ -162,8 +177,33 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   (void)accg;
   (void)first_tile;
 
+  if (wave == 0) {
+    // per-mode offsets of the slot arrays (lane k: sums over the modes before k)
+    const int nj = (lane < d) ? p.n[lane] : 0;
+    int ps = 0, bs = 0, rs = 0;
+#pragma unroll
+    for (int j = 0; j < MF_MAX_D; ++j) {
+      const int cap = T + 16 * __builtin_amdgcn_readlane(nj, j);
+      if (j < lane && j < d) {
+        ps += cap;
+        bs += cap / 16 + 1;
+        if (j >= kstart) rs += cap;
+      }
+    }
+    if (lane < MF_MAX_D) {
+      pofs[lane] = ps;
+      rofs[lane] = rs;
+      bofs[lane] = bs;
+    }
+  }
+  auto pbase = [&](int k) { return __builtin_amdgcn_readfirstlane(pofs[k]); };
+  auto rbase = [&](int k) { return __builtin_amdgcn_readfirstlane(rofs[k]); };
+  auto bbase = [&](int k) { return __builtin_amdgcn_readfirstlane(bofs[k]); };
   for (int c = tid; c < RS; c += NTHR) rows[ZROW * RS + c] = 0.f;
-  if (tid == 0) wsum[ZROW] = 0.f;
+  if (tid == 0) {
+    wsum[ZROW] = 0.f;
+    if (SD > 0) sidv[ZROW] = 0;
+  }
 
   // ---------------------------------------------------------------- sort
   // Stable counting sort of the tile's entries by slice index, every mode,
@@ -197,6 +237,12 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         const int e = 64 * (wave + W * c) + lane;
         iv[k][c] = (k < d && wave + W * c < CHUNKS && e < cnt_valid) ? p.idx[(long long)k * M + e0 + e] : -1;
       }
+    // C-ordered id of the entry's last SD indices (suffix table; an
+    // out-of-range index counts as 0, so table reads stay in bounds, and
+    // such entries are dropped from that mode's blocks)
+    int sfx[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) sfx[c] = 0;
 #pragma unroll
     for (int k = 0; k < MF_MAX_D; ++k) {
       if (k >= d) break;
@@ -207,6 +253,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         if (ch >= CHUNKS) break;
         const int v = iv[k][c];
         const bool ok = v >= 0 && v < nk;  // out-of-range indices are dropped
+        if (k >= d - SD) sfx[c] = sfx[c] * nk + (ok ? v : 0);
         // m: lanes of this chunk whose entry uses the same slice
         unsigned long long m = __ballot(ok);
 #pragma unroll
@@ -221,6 +268,14 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         int *crow = cnt + (k * CHUNKS + ch) * NSL;
         if (lane < NSL) crow[lane] = 0;
         if (ok && (m >> lane) == 1ull) crow[v] = rk + 1;
+      }
+    }
+    if (SD > 0) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int ch = wave + W * c;
+        if (ch >= CHUNKS) break;
+        sidv[64 * ch + lane] = sfx[c];
       }
     }
     lds_barrier();
@@ -255,26 +310,50 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           cnt[(k * CHUNKS + ch) * NSL + lane] = o;
           o += c[ch];
         }
-        uint16_t *pk = perm + pbase_of<T>(p, k);
+        uint16_t *pk = perm + pbase(k);
         for (int j = run; j < padded; ++j) pk[base + j] = (uint16_t)ZROW;
-        uint8_t *bk = bslc + bbase_of<T>(p, k) + base / 16;
+        if (k >= kstart && k < d - 1) {
+          uint16_t *rk = ridv + rbase(k);
+          for (int j = run; j < padded; ++j) rk[base + j] = 0;
+        }
+        uint8_t *bk = bslc + bbase(k) + base / 16;
         for (int j = 0; j < padded / 16; ++j) bk[j] = (uint8_t)lane;
       }
       if (lane == 0) nblk[k] = total / 16;
     }
     lds_barrier();
     for (int k = 0; k < d; ++k) {
-      uint16_t *pk = perm + pbase_of<T>(p, k);
+      uint16_t *pk = perm + pbase(k);
+      // modes whose right partial comes from the table also get, per slot,
+      // the entry's row in table level d-1-k (its suffix id reduced to the
+      // last d-1-k indices)
+      const bool tab = k >= kstart && k < d - 1;
+      uint16_t *rk = ridv + (tab ? rbase(k) : 0);
+      const unsigned nrow = tab ? (unsigned)p.suf_rows[d - 2 - k] : 1u;
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const int ch = wave + W * c;
         if (ch >= CHUNKS) break;
         const int kv = key[k * T + 64 * ch + lane];
-        if (kv != kNone) pk[cnt[(k * CHUNKS + ch) * NSL + (kv & 255)] + (kv >> 8)] = (uint16_t)(64 * ch + lane);
+        if (kv != kNone) {
+          const int pos = cnt[(k * CHUNKS + ch) * NSL + (kv & 255)] + (kv >> 8);
+          pk[pos] = (uint16_t)(64 * ch + lane);
+          if (tab) rk[pos] = (uint16_t)((unsigned)sfx[c] % nrow);
+        }
       }
     }
   }
   lds_barrier();
+
+  if (SD > 0) {
+    // rho_{kstart+1} of every entry from the deepest table level
+    const float *tab = p.suf + (long long)p.suf_row0[SD - 1] * R;
+    for (int x = tid; x < cnt_valid * (R / 4); x += NTHR) {
+      const int e = x / (R / 4), c4 = x - e * (R / 4);
+      *(v4f *)(rows + e * RS + 4 * c4) = *(const v4f *)(tab + (long long)sidv[e] * R + 4 * c4);
+    }
+    lds_barrier();
+  }
 
   // --------------------------------------------------------- right sweep
   // Each wave walks its blocks of mode k.  Loop bounds and slice ids are
@@ -285,19 +364,13 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   // it), so the compiler's memory-counter waits are exact: a block waits
   // for its own slices, not for the stash stores of the blocks before it.
   // Padding columns read the zero row.
-  for (int k = d - 1; k >= 0; --k) {
+  for (int k = kstart; k >= 0; --k) {
     const int nb = __builtin_amdgcn_readfirstlane(nblk[k]);
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
     if (jb < je) {
-      const uint16_t *pk = perm + pbase_of<T>(p, k);
+      const uint16_t *pk = perm + pbase(k);
       const float *gk = p.gp_right + (long long)p.sbase[k] * R * R;
-      const int mysl = (lane < je - jb) ? bslc[bbase_of<T>(p, k) + jb + lane] : 0;  // slice of block jb + lane
-      auto ld = [&](int j, v4f(&dst)[NT * NT]) {
-        const int jj = j < je ? j : je - 1;
-        const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, jj - jb) * R * R;
-#pragma unroll
-        for (int x = 0; x < NT * NT; ++x) dst[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-      };
+      const int mysl = (lane < je - jb) ? bslc[bbase(k) + jb + lane] : 0;  // slice of block jb + lane
       // mode kinds get their own loop bodies, free of runtime branches:
       // first step (k = d-1: input e_0, nothing to stash), middle steps, and
       // the last step (k = 0: writes y)
@@ -305,28 +378,65 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         constexpr bool ST = decltype(stash_tag)::value;
         constexpr bool last = decltype(last_tag)::value;
         constexpr bool END = decltype(end_tag)::value;
-        auto block = [&](int j, const v4f(&a)[NT * NT]) {
-          const int ent = pk[16 * j + c16];
+        // Software pipeline over the wave's blocks, two register sets per
+        // stage: the block's entry ids (LDS) are read two blocks ahead, its
+        // entry rows (LDS; EL layout for the product, CL layout for the
+        // stash) one block ahead, its slice (global) two blocks ahead.
+        // Blocks of one mode use disjoint entries, so a later block's rows
+        // may be read before this block writes its own (padding columns
+        // read and write the zero row, which stays zero).  Scheduling
+        // barriers keep the loads of later blocks ahead of this block's
+        // products, so their latency overlaps them.
+        struct Idx {
+          int ent;
+          uint2 q;  // the block's 16 entries, 4 per lane in CL order (stash)
+        };
+        struct Dat {
+          v4f bv[NT];
+          v4f cl[NT];
+          int ent;
+        };
+        auto ld_idx = [&](int j, Idx &x) {
+          const int jj = j < je ? j : je - 1;
+          x.ent = pk[16 * jj + c16];
+          if constexpr (ST) x.q = *(const uint2 *)(pk + 16 * jj + 4 * q4);
+        };
+        auto ld_dat = [&](const Idx &x, Dat &o) {
+          o.ent = x.ent;
+          if constexpr (!last) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) o.bv[t] = *(const v4f *)(rows + x.ent * RS + 16 * t + 4 * q4);
+          }
+          if constexpr (ST) {
+            const int ev[4] = {(int)(x.q.x & 0xFFFF), (int)(x.q.x >> 16), (int)(x.q.y & 0xFFFF),
+                               (int)(x.q.y >> 16)};
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) o.cl[t][v] = rows[ev[v] * RS + 16 * t + c16];
+          }
+        };
+        auto ld_glob = [&](int j, v4f(&a)[NT * NT]) {
+          const int jj = j < je ? j : je - 1;
+          const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, jj - jb) * R * R;
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) a[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+        };
+        auto compute = [&](int j, const Dat &o, const v4f(&a)[NT * NT]) {
+          const int ent = o.ent;
           v4f bv[NT];
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             if (last)
               bv[t] = v4f{(t == 0 && q4 == 0) ? 1.f : 0.f, 0.f, 0.f, 0.f};
             else
-              bv[t] = *(const v4f *)(rows + ent * RS + 16 * t + 4 * q4);
+              bv[t] = o.bv[t];
           }
           if constexpr (ST) {
             // stash rho_{k+1} of this block in CL layout
-            const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-            const int ev[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
-            v4f cl[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) cl[t][v] = rows[ev[v] * RS + 16 * t + c16];
             float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = cl[t];
+            for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = o.cl[t];
           }
           v4f out[NT];
 #pragma unroll
@@ -347,31 +457,40 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
             wsum[ent] = out[0][0];  // component 0 of rho_1 = y
           }
         };
-        constexpr int U = 2;  // blocks in flight (two and three measured best)
-        v4f ab[U][NT * NT];
-#pragma unroll
-        for (int u = 0; u < U; ++u) ld(jb + u, ab[u]);
-        auto grp = [&](int j) {
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            block(j + u, ab[u]);
-            ld(j + u + U, ab[u]);
-          }
+        Idx xi[2];
+        Dat xd[2];
+        v4f xa[2][NT * NT];
+        ld_idx(jb, xi[0]);
+        ld_idx(jb + 1, xi[1]);
+        ld_glob(jb, xa[0]);
+        ld_glob(jb + 1, xa[1]);
+        ld_dat(xi[0], xd[0]);
+        // block j uses register set s = (j - jb) % 2; set s of the index
+        // stage is free once block j's rows are loaded (the step before)
+        auto step = [&](int j, auto slot) {
+          constexpr int S = decltype(slot)::value, S1 = 1 - S;
+          ld_idx(j + 2, xi[S]);
+          ld_dat(xi[S1], xd[S1]);
+          __builtin_amdgcn_sched_barrier(0);
+          compute(j, xd[S], xa[S]);
+          __builtin_amdgcn_sched_barrier(0);
+          ld_glob(j + 2, xa[S]);
         };
-        int j = jb;
-        if (j + U - 1 < je) {
-          grp(j);
-          for (j += U; j + U - 1 < je; j += U) grp(j);
+        for (int j = jb; j < je; j += 2) {
+          step(j, std::integral_constant<int, 0>{});
+          if (j + 1 < je) step(j + 1, std::integral_constant<int, 1>{});
         }
-#pragma unroll
-        for (int u = 0; u < U - 1; ++u)
-          if (j + u < je) block(j + u, ab[u]);
       };
       using T1 = std::true_type;
       using F0 = std::false_type;
       constexpr bool STASH = MODE != MODE_GATHER;
-      if (k == d - 1)  // d >= 2, so this step is never the last
+      // the first computed step stashes nothing: its input is e_0 (no
+      // table; d >= 2, so this step is never the last) or rho_{kstart+1}
+      // from the table, which the left sweep reads there too
+      if (k == d - 1)
         sweep(F0{}, T1{}, F0{});
+      else if (SUF && k == kstart)
+        k > 0 ? sweep(F0{}, F0{}, F0{}) : sweep(F0{}, F0{}, T1{});
       else if (k > 0)
         sweep(std::bool_constant<STASH>{}, F0{}, F0{});
       else
@@ -427,8 +546,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
     }
     const int nb = __builtin_amdgcn_readfirstlane(nblk[k]);
     const int jb = (wave * nb) / W, je = ((wave + 1) * nb) / W;
-    const uint16_t *pk = perm + pbase_of<T>(p, k);
-    const uint8_t *bk = bslc + bbase_of<T>(p, k);
+    const uint16_t *pk = perm + pbase(k);
+    const uint8_t *bk = bslc + bbase(k);
     const int mysl = (lane < je - jb) ? bk[jb + lane] : 0;  // slice of block jb + lane
     const int prev_sl = __builtin_amdgcn_readfirstlane(jb > 0 ? (int)bk[jb - 1] : -1);
     const bool cont_first = (jb < je) && prev_sl == __builtin_amdgcn_readfirstlane(mysl);
@@ -472,45 +591,87 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
       }
     };
     // Two kinds of mode get their own loop bodies, free of runtime branches:
-    // k < d-1 (chain step, stashed rho_{k+1}) and k = d-1 (no chain step,
-    // rho_{d+1} = e_0, no global loads).  Operands of block j are rho_{k+1}
-    // in CL layout and slice G^k^T in A-operand layout, loaded U blocks
-    // ahead into U register sets used in turn, as in the right sweep.
-    auto sweep = [&](auto chain_tag) {
+    // k < d-1 (chain step; rho_{k+1} from the stash or the suffix table) and
+    // k = d-1 (no chain step, rho_{d+1} = e_0, no global loads).  The same
+    // software pipeline as the right sweep: entry ids (and table rows ids)
+    // two blocks ahead, the block's lambda rows (CL layout for the outer
+    // product, EL layout for the chain) and table rows one block ahead,
+    // slice G^k^T and stashed rho_{k+1} two blocks ahead.
+    auto sweep = [&](auto chain_tag, auto table_tag) {
       constexpr bool CHAIN = decltype(chain_tag)::value;
-      auto ld = [&](int j, v4f(&ga)[NT * NT], v4f(&rr)[NT]) {
-        if constexpr (CHAIN) {
-          const int jj = j < je ? j : je - 1;
-          const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) rr[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
-          const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) ga[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-        } else {
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
-            rr[t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
-          }
-        }
+      constexpr bool TAB = decltype(table_tag)::value;
+      struct Idx {
+        uint2 q;    // the block's 16 entries, 4 per lane in CL order
+        uint2 rid;  // their rows in the table level (TAB)
+        int ent;    // this lane's entry in EL order (CHAIN)
       };
-      auto block = [&](int j, const v4f(&a)[NT * NT], const v4f(&rcl)[NT]) {
-        const int sid = __builtin_amdgcn_readlane(mysl, j - jb);
-        const uint2 q = *(const uint2 *)(pk + 16 * j + 4 * q4);
-        const int ev[4] = {(int)(q.x & 0xFFFF), (int)(q.x >> 16), (int)(q.y & 0xFFFF), (int)(q.y >> 16)};
-        // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
+      struct Dat {
         v4f lcl[NT];
+        v4f bv[NT];
+        v4f rt[NT];  // rho_{k+1} from the table, CL layout (TAB)
+        int ent;
+      };
+      struct Glb {
+        v4f a[NT * NT];
+        v4f rs[NT];  // stashed rho_{k+1}, CL layout
+      };
+      const int lev = d - 1 - k;  // table level of rho_{k+1} (TAB)
+      const uint16_t *rk = TAB ? ridv + rbase(k) : nullptr;
+      const float *tab = TAB ? p.suf + (long long)p.suf_row0[lev - 1] * R : nullptr;
+      auto ld_idx = [&](int j, Idx &x) {
+        const int jj = j < je ? j : je - 1;
+        x.q = *(const uint2 *)(pk + 16 * jj + 4 * q4);
+        if constexpr (CHAIN) x.ent = pk[16 * jj + c16];
+        if constexpr (TAB) x.rid = *(const uint2 *)(rk + 16 * jj + 4 * q4);
+      };
+      auto ld_dat = [&](const Idx &x, Dat &o) {
+        const int ev[4] = {(int)(x.q.x & 0xFFFF), (int)(x.q.x >> 16), (int)(x.q.y & 0xFFFF), (int)(x.q.y >> 16)};
+        // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-          for (int t = 0; t < NT; ++t) lcl[t][v] = rows[ev[v] * RS + 16 * t + c16];
-        int ent = 0;
-        v4f bv[NT];
+          for (int t = 0; t < NT; ++t) o.lcl[t][v] = rows[ev[v] * RS + 16 * t + c16];
         if constexpr (CHAIN) {
-          ent = pk[16 * j + c16];
+          o.ent = x.ent;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) bv[t] = *(const v4f *)(rows + ent * RS + 16 * t + 4 * q4);
+          for (int t = 0; t < NT; ++t) o.bv[t] = *(const v4f *)(rows + x.ent * RS + 16 * t + 4 * q4);
+        }
+        if constexpr (TAB) {
+          // padding slots read row 0: their lambda is zero
+          const int rv[4] = {(int)(x.rid.x & 0xFFFF), (int)(x.rid.x >> 16), (int)(x.rid.y & 0xFFFF),
+                             (int)(x.rid.y >> 16)};
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) o.rt[t][v] = tab[(long long)rv[v] * R + 16 * t + c16];
+        }
+      };
+      auto ld_glob = [&](int j, Glb &g) {
+        if constexpr (CHAIN) {
+          const int jj = j < je ? j : je - 1;
+          if constexpr (!TAB) {
+            const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) g.rs[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+          }
+          const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
+#pragma unroll
+          for (int x = 0; x < NT * NT; ++x) g.a[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+        }
+      };
+      auto compute = [&](int j, const Dat &o, const Glb &g) {
+        const int sid = __builtin_amdgcn_readlane(mysl, j - jb);
+        v4f rcl[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if constexpr (!CHAIN) {
+            const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
+            rcl[t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
+          } else if constexpr (TAB) {
+            rcl[t] = o.rt[t];
+          } else {
+            rcl[t] = g.rs[t];
+          }
         }
         // outer products (NT * NT independent chains)
         v4f dg[NT * NT];
@@ -521,7 +682,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
 #pragma unroll
           for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-            for (int tb = 0; tb < NT; ++tb) dg[ta * NT + tb] = mfma4(lcl[ta][c], rcl[tb][c], dg[ta * NT + tb]);
+            for (int tb = 0; tb < NT; ++tb) dg[ta * NT + tb] = mfma4(o.lcl[ta][c], rcl[tb][c], dg[ta * NT + tb]);
         // chain lambda_{k+1}^T = G^T lambda_k^T
         if constexpr (CHAIN) {
           v4f out[NT];
@@ -532,10 +693,10 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-              for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
+              for (int to = 0; to < NT; ++to) out[to] = mfma4(g.a[to * NT + ti][c], o.bv[ti][c], out[to]);
           // a padding column reads the zero row and writes zeros back to it
 #pragma unroll
-          for (int t = 0; t < NT; ++t) *(v4f *)(rows + ent * RS + 16 * t + 4 * q4) = out[t];
+          for (int t = 0; t < NT; ++t) *(v4f *)(rows + o.ent * RS + 16 * t + 4 * q4) = out[t];
         }
         // merge the block's outer products into runs
         if (sid != rsid) {
@@ -551,31 +712,37 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           for (int x = 0; x < NT * NT; ++x) racc[x] += dg[x];
         }
       };
-      constexpr int U = 3;
-      v4f ab[U][NT * NT], rb[U][NT];
-#pragma unroll
-      for (int u = 0; u < U; ++u) ld(jb + u, ab[u], rb[u]);
-      auto grp = [&](int j) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          block(j + u, ab[u], rb[u]);
-          ld(j + u + U, ab[u], rb[u]);
-        }
+      Idx xi[2];
+      Dat xd[2];
+      Glb xg[2];
+      ld_idx(jb, xi[0]);
+      ld_idx(jb + 1, xi[1]);
+      ld_glob(jb, xg[0]);
+      ld_glob(jb + 1, xg[1]);
+      ld_dat(xi[0], xd[0]);
+      auto step = [&](int j, auto slot) {
+        constexpr int S = decltype(slot)::value, S1 = 1 - S;
+        ld_idx(j + 2, xi[S]);
+        ld_dat(xi[S1], xd[S1]);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(j, xd[S], xg[S]);
+        __builtin_amdgcn_sched_barrier(0);
+        ld_glob(j + 2, xg[S]);
       };
-      int j = jb;
-      if (j + U - 1 < je) {
-        grp(j);
-        for (j += U; j + U - 1 < je; j += U) grp(j);
+      for (int j = jb; j < je; j += 2) {
+        step(j, std::integral_constant<int, 0>{});
+        if (j + 1 < je) step(j + 1, std::integral_constant<int, 1>{});
       }
-#pragma unroll
-      for (int u = 0; u < U - 1; ++u)
-        if (j + u < je) block(j + u, ab[u], rb[u]);
     };
     if (jb < je) {
-      if (k < d - 1)
-        sweep(std::true_type{});
-      else
-        sweep(std::false_type{});
+      if (k < d - 1) {
+        if (SUF && k >= kstart)
+          sweep(std::true_type{}, std::bool_constant<SUF>{});
+        else
+          sweep(std::true_type{}, std::false_type{});
+      } else {
+        sweep(std::false_type{}, std::false_type{});
+      }
     }
     if (rsid >= 0) emit_run(rsid, first_run && cont_first);
     lds_barrier();
@@ -630,7 +797,7 @@ __global__ void __launch_bounds__(NTHR) fused_kernel(MfInst p, Grid g) {
   for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
     const long long e0 = (long long)tile * T;
     const int cnt = (int)((p.M - e0) < T ? (p.M - e0) : T);
-    run_tile<R, T, NTHR, MODE, ACC>(p, e0, cnt, smem, stash, g.nb_max, accg, first, loss_part);
+    run_tile<R, T, NTHR, MODE, ACC, true>(p, e0, cnt, smem, stash, g.nb_max, accg, first, loss_part);
     first = false;
   }
   if (MODE == MODE_MSE) {
@@ -674,11 +841,11 @@ __global__ void __launch_bounds__(NTHR) batched_kernel(MfBatchArgs a) {
       if (w.rclass == 16) {
         const long long e0 = (long long)(w.tile0 + t) * T16;
         const int cnt = (int)((p.M - e0) < T16 ? (p.M - e0) : T16);
-        run_tile<16, T16, NTHR, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb16, nullptr, false, lp);
+        run_tile<16, T16, NTHR, MODE_MSE, ACC_DIRECT, false>(p, e0, cnt, smem, stash, a.nb16, nullptr, false, lp);
       } else {
         const long long e0 = (long long)(w.tile0 + t) * T32;
         const int cnt = (int)((p.M - e0) < T32 ? (p.M - e0) : T32);
-        run_tile<32, T32, NTHR, MODE_MSE, ACC_DIRECT>(p, e0, cnt, smem, stash, a.nb32, nullptr, false, lp);
+        run_tile<32, T32, NTHR, MODE_MSE, ACC_DIRECT, false>(p, e0, cnt, smem, stash, a.nb32, nullptr, false, lp);
       }
       // this tile's share of the tensor's mean squared residual
       for (int off = 32; off > 0; off >>= 1) lp += __shfl_xor(lp, off);
@@ -694,14 +861,60 @@ __global__ void __launch_bounds__(NTHR) batched_kernel(MfBatchArgs a) {
   }
 }
 
+// Suffix table build: the right partial rho_{d-l} = G^{d-l}[i_{d-l}] ..
+// G^{d-1}[i_{d-1}] e_0 of every value of the last l indices, l = 1..depth.
+// A group of R lanes computes one suffix of length `depth` (lane a holds
+// component a), one mode at a time, and writes level l's row when the
+// suffix's leading depth-l indices are zero, so every row is written once.
+struct SufBuild {
+  float *tab;
+  int depth;
+  int row0[MF_MAX_D];
+  int rows[MF_MAX_D];
+  int blocks;  // workgroups of the build (after the slice workgroups)
+};
+
+__device__ void build_suffix_rows(const TTDev &X, int R, const SufBuild &sb, int blk) {
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / R, a = lane - grp * R;
+  const int groups = 64 / R;
+  const long long sfx = ((long long)blk * (blockDim.x >> 6) + (threadIdx.x >> 6)) * groups + grp;
+  const int D = sb.depth;
+  const bool live = sfx < sb.rows[D - 1];
+  int rem = live ? (int)sfx : 0;
+  float rho = 0.f;
+  for (int l = 1; l <= D; ++l) {
+    const int k = X.d - l;
+    const int nk = X.n[k], rk = X.r[k], rk1 = X.r[k + 1];
+    const int i = rem % nk;
+    rem /= nk;
+    const float *G = X.data + X.off[k] + (long long)i * rk1;  // G[a][i][b] at a * nk * rk1 + b
+    float acc = 0.f;
+    if (l == 1) {
+      if (a < rk) acc = G[(long long)a * nk * rk1];  // column 0 (r_d = 1)
+    } else {
+      for (int b = 0; b < rk1; ++b) {
+        const float rb = __shfl(rho, grp * R + b);
+        if (a < rk) acc = fmaf(G[(long long)a * nk * rk1 + b], rb, acc);
+      }
+    }
+    rho = acc;
+    if (live && sfx < sb.rows[l - 1]) sb.tab[((long long)sb.row0[l - 1] + sfx) * R + a] = rho;
+  }
+}
+
 // Padded slice copies in MFMA A-operand order: for slice G (R x R, zero
 // outside the true ranks) and comp tiles (to, ti), lane l's float4 holds
 // M[16 to + l%16][16 ti + 4 (l/16) + c], c < 4, with M = G for the right
-// sweep and M = G^T for the left sweep.
+// sweep and M = G^T for the left sweep.  Workgroups past the slices build
+// the suffix table of Xr.
 __global__ void pad_slices_kernel(TTDev Xr, TTDev Xl, int R, float *__restrict__ right,
-                                  float *__restrict__ left, int total_slices) {
+                                  float *__restrict__ left, int total_slices, SufBuild sb) {
   const int slice = blockIdx.x;
-  if (slice >= total_slices) return;
+  if (slice >= total_slices) {
+    if (sb.depth > 0 && slice - total_slices < sb.blocks) build_suffix_rows(Xr, R, sb, slice - total_slices);
+    return;
+  }
   int k = 0, base = 0;
   while (k < Xr.d && slice >= base + Xr.n[k]) {
     base += Xr.n[k];
@@ -831,10 +1044,20 @@ int device_id() {
   return hipGetDevice(&dev) == hipSuccess ? dev : -1;
 }
 
+// Suffix table levels of one launch (depth 0: none).
+struct SuffixPlan {
+  int depth;
+  int row0[MF_MAX_D];
+  int rows[MF_MAX_D];
+  long long total_rows;
+};
+
 struct Geometry {
   int R, T, threads, nb_max, total_slices, ntiles, nwg, lds;
   long long stash_stride, acc_stride;
+  SuffixPlan suf;
 };
+
 
 // Workgroups per CU the LDS allows (the kernels' register use admits at
 // least two 8-wave workgroups per CU).
@@ -843,6 +1066,37 @@ int wgs_per_cu(int lds, int threads) {
   int by_waves = 32 / (threads / 64);  // 8 waves per SIMD at most
   int w = by_lds < by_waves ? by_lds : by_waves;
   return w < 1 ? 1 : w;
+}
+
+// Suffix table policy.  Level l holds n_{d-l} .. n_{d-1} rows of R floats;
+// a level is taken while the whole table stays within kSuffixBytes (so it
+// stays in the L2 of every XCD beside the slices), while the entries
+// outnumber its rows 16 to 1 (the build costs one R x R step per row and
+// level, the sweep saves one per entry and level), at most d-1 levels, and
+// and only as deep as the suffix ids and per-slot row ids fit the LDS
+// without costing a workgroup per CU.
+constexpr long long kSuffixBytes = 2ll << 20;
+int g_suffix_mode = -1;  // -1 automatic, 0 off, k > 0: up to k levels, M aside
+
+SuffixPlan suffix_plan(const tt_tensor *X, int R, int64_t M, int T, int threads) {
+  SuffixPlan sf = {};
+  if (g_suffix_mode == 0) return sf;
+  const int l0 = mf_layout(R, T, threads, acc_of(R), X->d, X->n, 0).total;
+  long long N = 1, total = 0;
+  for (int l = 1; l <= X->d - 1; ++l) {
+    N *= X->n[X->d - l];
+    if ((total + N) * R * (long long)sizeof(float) > kSuffixBytes) break;
+    if (g_suffix_mode < 0 && N * 16 > M) break;
+    if (g_suffix_mode > 0 && l > g_suffix_mode) break;
+    const int l1 = mf_layout(R, T, threads, acc_of(R), X->d, X->n, l).total;
+    if (l1 > kLdsBytes || wgs_per_cu(l1, threads) < wgs_per_cu(l0, threads)) break;
+    sf.row0[l - 1] = (int)total;
+    sf.rows[l - 1] = (int)N;
+    total += N;
+    sf.depth = l;
+  }
+  sf.total_rows = total;
+  return sf;
 }
 
 Geometry geometry(const tt_tensor *X, int R, int64_t M) {
@@ -857,13 +1111,16 @@ Geometry geometry(const tt_tensor *X, int R, int64_t M) {
     nmax = X->n[k] > nmax ? X->n[k] : nmax;
     g.total_slices += X->n[k];
   }
-  g.lds = mf_layout(R, g.T, g.threads, acc_of(R), X->d, X->n).total;
+  g.suf = suffix_plan(X, R, M, g.T, g.threads);
+  g.lds = mf_layout(R, g.T, g.threads, acc_of(R), X->d, X->n, g.suf.depth).total;
   g.nb_max = g.T / 16 + nmax;
   g.ntiles = (int)((M + g.T - 1) / g.T);
   const int slots = device_cus() * wgs_per_cu(g.lds, g.threads);
   g.nwg = g.ntiles < slots ? g.ntiles : slots;
   if (g.nwg < 1) g.nwg = 1;
-  g.stash_stride = (long long)(X->d > 1 ? X->d - 1 : 1) * g.nb_max * 64 * (R / 4);
+  // modes 0 .. d-2-depth stash rho_{k+1}; the table serves the rest
+  const int stashed = X->d - 1 - g.suf.depth;
+  g.stash_stride = (long long)(stashed > 1 ? stashed : 1) * g.nb_max * 64 * (R / 4);
   g.acc_stride = (R == 16) ? (long long)g.total_slices * R * R : 0;
   return g;
 }
@@ -935,7 +1192,7 @@ static bool fits_class(const tt_tensor *X) {
   for (int i = 0; i < ns; ++i) {
     const int acc = (i < nsingle && R == 16) ? ACC_SLAB : ACC_DIRECT;
     const int cap = (i >= nsingle) ? kLdsBytes - kBatchStaticLds : kLdsBytes;
-    if (mf_layout(R, shapes[i].T, shapes[i].threads, acc, X->d, X->n).total > cap) return false;
+    if (mf_layout(R, shapes[i].T, shapes[i].threads, acc, X->d, X->n, 0).total > cap) return false;
   }
   return true;
 }
@@ -972,6 +1229,7 @@ int mfma_gather_class(const tt_tensor *X) {
 size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint) {
   const Geometry g = geometry(X, R, M);
   size_t b = 2 * arena_bytes<float>((size_t)g.total_slices * R * R);
+  if (g.suf.depth > 0) b += arena_bytes<float>((size_t)g.suf.total_rows * R);
   if (adjoint) {
     b += arena_bytes<float>((size_t)g.nwg * g.stash_stride);
     if (R == 16) {
@@ -985,12 +1243,18 @@ size_t mfma_ws(const tt_tensor *X, int R, int64_t M, bool adjoint) {
   return b;
 }
 
-int mfma_pad(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float *gpl, hipStream_t s) {
+static int pad_and_suffix(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float *gpl,
+                          const SufBuild &sb, hipStream_t s) {
   int total = 0;
   for (int k = 0; k < Rt->d; ++k) total += Rt->n[k];
-  hipLaunchKernelGGL(pad_slices_kernel, dim3(total), dim3(256), 0, s, make_dev(Rt), make_dev(Lt ? Lt : Rt), R,
-                     gpr, gpl, total);
+  hipLaunchKernelGGL(pad_slices_kernel, dim3(total + (sb.depth > 0 ? sb.blocks : 0)), dim3(256), 0, s,
+                     make_dev(Rt), make_dev(Lt ? Lt : Rt), R, gpr, gpl, total, sb);
   return launch_check("pad slices");
+}
+
+int mfma_pad(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float *gpl, hipStream_t s) {
+  SufBuild none = {};
+  return pad_and_suffix(Rt, Lt, R, gpr, gpl, none, s);
 }
 
 int mfma_unpad(const tt_tensor *O, int R, const float *padded, hipStream_t s) {
@@ -1010,6 +1274,7 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
   Arena ar(ws, ws_bytes);
   float *gpr = ar.take<float>((size_t)g.total_slices * R * R);
   float *gpl = ar.take<float>((size_t)g.total_slices * R * R);
+  float *suf = g.suf.depth > 0 ? ar.take<float>((size_t)g.suf.total_rows * R) : nullptr;
   float *stash = nullptr, *acc = nullptr, *lacc = nullptr, *rtmp = nullptr, *grad = nullptr;
   if (adjoint) {
     stash = ar.take<float>((size_t)g.nwg * g.stash_stride);
@@ -1022,7 +1287,18 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
     lacc = ar.take<float>((size_t)g.nwg);
   }
   if (!ar.ok()) return set_error(TT_ERR_WORKSPACE, "gather (MFMA): workspace too small");
-  int rc = mfma_pad(Rt, Lt, R, gpr, adjoint ? gpl : nullptr, s);
+  SufBuild sfb = {};
+  if (g.suf.depth > 0 && M > 0) {
+    sfb.tab = suf;
+    sfb.depth = g.suf.depth;
+    for (int l = 0; l < g.suf.depth; ++l) {
+      sfb.row0[l] = g.suf.row0[l];
+      sfb.rows[l] = g.suf.rows[l];
+    }
+    const int per_block = 4 * (64 / R);  // 256 threads: 4 waves of 64 / R suffixes
+    sfb.blocks = (g.suf.rows[g.suf.depth - 1] + per_block - 1) / per_block;
+  }
+  int rc = pad_and_suffix(Rt, Lt, R, gpr, adjoint ? gpl : nullptr, sfb, s);
   if (rc) return rc;
 
   MfInst p = {};
@@ -1045,6 +1321,12 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
   p.inv_m2 = M > 0 ? 2.0f / (float)M : 0.f;
   p.inv_m = M > 0 ? 1.0f / (float)M : 0.f;
   p.rclass = R;
+  p.suf = suf;
+  p.suf_depth = sfb.depth;
+  for (int l = 0; l < sfb.depth; ++l) {
+    p.suf_row0[l] = sfb.row0[l];
+    p.suf_rows[l] = sfb.rows[l];
+  }
   Grid gr = {};
   gr.ntiles = g.ntiles;
   gr.nb_max = g.nb_max;
@@ -1094,8 +1376,8 @@ MfBatchShape mfma_batch_shape(int shape) { return kBatchShapes[shape]; }
 
 size_t mfma_batch_lds(int shape, int d, const int *n) {
   const MfBatchShape &sh = kBatchShapes[shape];
-  const int a = mf_layout(16, sh.t16, sh.threads, ACC_DIRECT, d, n).total;
-  const int b = mf_layout(32, sh.t32, sh.threads, ACC_DIRECT, d, n).total;
+  const int a = mf_layout(16, sh.t16, sh.threads, ACC_DIRECT, d, n, 0).total;
+  const int b = mf_layout(32, sh.t32, sh.threads, ACC_DIRECT, d, n, 0).total;
   return (size_t)(a > b ? a : b);
 }
 
@@ -1147,5 +1429,9 @@ int mfma_batch_launch(const MfBatchArgs &a, int shape, int nwg, size_t lds, hipS
 }
 
 int mfma_device_cus() { return device_cus(); }
+
+void mfma_set_suffix_depth(int depth) { g_suffix_mode = depth < 0 ? -1 : depth; }
+
+int mfma_suffix_depth_of(const tt_tensor *X, int R, int64_t M) { return geometry(X, R, M).suf.depth; }
 
 }  // namespace ttgfx

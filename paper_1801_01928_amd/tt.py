@@ -197,6 +197,17 @@ def gather_backward(X, idx, gy):
     return gX
 
 
+def set_suffix_depth(depth):
+    """Suffix-table policy of the gather / adjoint / fused kernels for later
+    calls: -1 automatic (default), 0 never, k > 0 up to k levels."""
+    L.check(L.load().tt_set_suffix_depth(int(depth)))
+
+
+def suffix_depth(X, M):
+    """Suffix-table levels a fused pass over X with M entries takes now."""
+    return int(L.check(L.load().tt_suffix_depth(C.byref(X.desc()), int(M))))
+
+
 def gather_mse_workspace(X, M):
     """Workspace bytes of ``gather_mse_backward`` for M entries."""
     return int(L.check(L.load().tt_gather_mse_workspace(C.byref(X.desc()), int(M))))

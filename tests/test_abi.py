@@ -325,3 +325,30 @@ def test_noalloc_rejects_shapes_beyond_its_scratch(lib):
     B = _desc([3, 4], [2, 2, 1])
     assert lib.tt_gather_mse_backward_noalloc(C.byref(B), C.c_void_p(0x10), 5, C.c_void_p(0x10), None, None,
                                               None, C.byref(B), None) == L.TT_ERR_SHAPE
+
+
+def test_suffix_table_policy(lib):
+    """Suffix-table depth of the fused pass (host logic, no device work):
+    levels are taken while the entries outnumber the deepest level's rows 16
+    to 1 and the table stays within 2 MiB, at most d-1; the policy knob
+    forces a depth or turns the table off, and workspace sizes follow it."""
+    X = _desc([10] * 10, [1] + [16] * 9 + [1])
+    try:
+        assert lib.tt_suffix_depth(C.byref(X), 1 << 20) == 4      # 10^4 * 16 <= 2^20 < 10^5 * 16
+        assert lib.tt_suffix_depth(C.byref(X), 1000) == 1
+        assert lib.tt_suffix_depth(C.byref(X), 100) == 0
+        ws_auto = lib.tt_gather_mse_workspace(C.byref(X), 1 << 20)
+        lib.tt_set_suffix_depth(0)
+        assert lib.tt_suffix_depth(C.byref(X), 1 << 20) == 0
+        ws_off = lib.tt_gather_mse_workspace(C.byref(X), 1 << 20)
+        assert ws_off > ws_auto  # the table replaces 4 of 9 stashed modes
+        lib.tt_set_suffix_depth(9)
+        # 2 MiB cap at rank class 16: 11,110 rows (64 B each) fit, 111,110 do not
+        assert lib.tt_suffix_depth(C.byref(X), 100) == 4
+        Y = _desc([4, 5, 3], [1, 3, 2, 1])
+        assert lib.tt_suffix_depth(C.byref(Y), 7) == 2            # d-1 levels
+        Z = _desc([10] * 6, [1] + [32] * 5 + [1])
+        assert lib.tt_suffix_depth(C.byref(Z), 7) == 4            # 11,110 rows of 128 B
+    finally:
+        lib.tt_set_suffix_depth(-1)
+    assert lib.tt_suffix_depth(C.byref(X), 1 << 20) == 4
