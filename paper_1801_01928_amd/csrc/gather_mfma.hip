@@ -380,8 +380,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         constexpr bool END = decltype(end_tag)::value;
         // Software pipeline over the wave's blocks, two register sets per
         // stage: the block's entry ids (LDS) are read two blocks ahead, its
-        // entry rows (LDS; EL layout for the product, CL layout for the
-        // stash) one block ahead, its slice (global) two blocks ahead.
+        // slice (global) and entry rows (LDS; EL layout for the product, CL
+        // layout for the stash) one block ahead.
         // Blocks of one mode use disjoint entries, so a later block's rows
         // may be read before this block writes its own (padding columns
         // read and write the zero row, which stays zero).  Scheduling
@@ -389,19 +389,27 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         // products, so their latency overlaps them.
         struct Idx {
           int ent;
+          int jj;
           uint2 q;  // the block's 16 entries, 4 per lane in CL order (stash)
         };
         struct Dat {
+          v4f a[NT * NT];
           v4f bv[NT];
           v4f cl[NT];
           int ent;
         };
         auto ld_idx = [&](int j, Idx &x) {
           const int jj = j < je ? j : je - 1;
+          x.jj = jj;
           x.ent = pk[16 * jj + c16];
           if constexpr (ST) x.q = *(const uint2 *)(pk + 16 * jj + 4 * q4);
         };
         auto ld_dat = [&](const Idx &x, Dat &o) {
+          {
+            const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, x.jj - jb) * R * R;
+#pragma unroll
+            for (int xx = 0; xx < NT * NT; ++xx) o.a[xx] = *(const v4f *)(gs + (xx * 64 + lane) * 4);
+          }
           o.ent = x.ent;
           if constexpr (!last) {
 #pragma unroll
@@ -416,13 +424,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
               for (int v = 0; v < 4; ++v) o.cl[t][v] = rows[ev[v] * RS + 16 * t + c16];
           }
         };
-        auto ld_glob = [&](int j, v4f(&a)[NT * NT]) {
-          const int jj = j < je ? j : je - 1;
-          const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, jj - jb) * R * R;
-#pragma unroll
-          for (int x = 0; x < NT * NT; ++x) a[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
-        };
-        auto compute = [&](int j, const Dat &o, const v4f(&a)[NT * NT]) {
+        auto compute = [&](int j, const Dat &o) {
           const int ent = o.ent;
           v4f bv[NT];
 #pragma unroll
@@ -446,7 +448,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-              for (int to = 0; to < NT; ++to) out[to] = mfma4(a[to * NT + ti][c], bv[ti][c], out[to]);
+              for (int to = 0; to < NT; ++to) out[to] = mfma4(o.a[to * NT + ti][c], bv[ti][c], out[to]);
           if constexpr (!END) {
             // a padding column is zero (zero row in, zero out) except in the
             // first step, where the input is e_0: that one goes to the sink row
@@ -459,22 +461,18 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         };
         Idx xi[2];
         Dat xd[2];
-        v4f xa[2][NT * NT];
         ld_idx(jb, xi[0]);
         ld_idx(jb + 1, xi[1]);
-        ld_glob(jb, xa[0]);
-        ld_glob(jb + 1, xa[1]);
         ld_dat(xi[0], xd[0]);
         // block j uses register set s = (j - jb) % 2; set s of the index
-        // stage is free once block j's rows are loaded (the step before)
+        // stage is free once block j's operands are loaded (the step before)
         auto step = [&](int j, auto slot) {
           constexpr int S = decltype(slot)::value, S1 = 1 - S;
           ld_idx(j + 2, xi[S]);
           ld_dat(xi[S1], xd[S1]);
           __builtin_amdgcn_sched_barrier(0);
-          compute(j, xd[S], xa[S]);
+          compute(j, xd[S]);
           __builtin_amdgcn_sched_barrier(0);
-          ld_glob(j + 2, xa[S]);
         };
         for (int j = jb; j < je; j += 2) {
           step(j, std::integral_constant<int, 0>{});
@@ -593,10 +591,11 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
     // Two kinds of mode get their own loop bodies, free of runtime branches:
     // k < d-1 (chain step; rho_{k+1} from the stash or the suffix table) and
     // k = d-1 (no chain step, rho_{d+1} = e_0, no global loads).  The same
-    // software pipeline as the right sweep: entry ids (and table rows ids)
-    // two blocks ahead, the block's lambda rows (CL layout for the outer
-    // product, EL layout for the chain) and table rows one block ahead,
-    // slice G^k^T and stashed rho_{k+1} two blocks ahead.
+    // software pipeline as the right sweep: entry ids (and table row ids)
+    // two blocks ahead; the block's lambda rows (CL layout for the outer
+    // product, EL layout for the chain) and rho_{k+1} (stash or table) one
+    // block ahead; slice G^k^T two blocks ahead.  (Loads consumed one step
+    // after issue keep the compiler's memory-counter waits exact.)
     auto sweep = [&](auto chain_tag, auto table_tag) {
       constexpr bool CHAIN = decltype(chain_tag)::value;
       constexpr bool TAB = decltype(table_tag)::value;
@@ -604,27 +603,34 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         uint2 q;    // the block's 16 entries, 4 per lane in CL order
         uint2 rid;  // their rows in the table level (TAB)
         int ent;    // this lane's entry in EL order (CHAIN)
+        int jj;
       };
       struct Dat {
         v4f lcl[NT];
         v4f bv[NT];
-        v4f rt[NT];  // rho_{k+1} from the table, CL layout (TAB)
+        v4f rt[NT];  // rho_{k+1} (stash or table), CL layout
         int ent;
       };
       struct Glb {
         v4f a[NT * NT];
-        v4f rs[NT];  // stashed rho_{k+1}, CL layout
       };
       const int lev = d - 1 - k;  // table level of rho_{k+1} (TAB)
       const uint16_t *rk = TAB ? ridv + rbase(k) : nullptr;
       const float *tab = TAB ? p.suf + (long long)p.suf_row0[lev - 1] * R : nullptr;
       auto ld_idx = [&](int j, Idx &x) {
         const int jj = j < je ? j : je - 1;
+        x.jj = jj;
         x.q = *(const uint2 *)(pk + 16 * jj + 4 * q4);
         if constexpr (CHAIN) x.ent = pk[16 * jj + c16];
         if constexpr (TAB) x.rid = *(const uint2 *)(rk + 16 * jj + 4 * q4);
       };
       auto ld_dat = [&](const Idx &x, Dat &o) {
+        if constexpr (CHAIN && !TAB) {
+          const int jj = x.jj;
+          const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) o.rt[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+        }
         const int ev[4] = {(int)(x.q.x & 0xFFFF), (int)(x.q.x >> 16), (int)(x.q.y & 0xFFFF), (int)(x.q.y >> 16)};
         // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
 #pragma unroll
@@ -649,11 +655,6 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
       auto ld_glob = [&](int j, Glb &g) {
         if constexpr (CHAIN) {
           const int jj = j < je ? j : je - 1;
-          if constexpr (!TAB) {
-            const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) g.rs[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
-          }
           const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
 #pragma unroll
           for (int x = 0; x < NT * NT; ++x) g.a[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
@@ -667,10 +668,8 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           if constexpr (!CHAIN) {
             const float one = (t == 0 && c16 == 0) ? 1.f : 0.f;
             rcl[t] = v4f{one, one, one, one};  // rho_{d+1} = e_0
-          } else if constexpr (TAB) {
-            rcl[t] = o.rt[t];
           } else {
-            rcl[t] = g.rs[t];
+            rcl[t] = o.rt[t];
           }
         }
         // outer products (NT * NT independent chains)
