@@ -178,6 +178,28 @@ int tt_gather_mse_backward(const tt_tensor *X, const int32_t *idx, int64_t M,
 int tt_set_suffix_depth(int32_t depth);
 int32_t tt_suffix_depth(const tt_tensor *X, int64_t M);
 
+/* ------------------------------------------------ reduction policy */
+/* The adjoint sums, for each core slice, the outer products of every
+ * entry whose index in that mode selects the slice (the gradient of the
+ * entry formula of the Introduction with respect to one core).  The
+ * slice-grouped kernels of rank classes 16 and 32 sum in a fixed order
+ * (per-workgroup accumulators reduced in workgroup order), so their results
+ * repeat bitwise.  The batched plan's persistent kernel, the generic
+ * kernels (ranks above 32, d outside 2..16) and rank class 32 with mode
+ * sizes whose slice accumulator does not fit the LDS add with float
+ * atomics, so the last bits of their gradients may differ between runs.
+ *   tt_set_deterministic(1): later adjoint, fused-pass, projection and plan
+ *     calls sum in a fixed order: plans run tensor by tensor (tt_plan_run
+ *     then equals tt_plan_run_plain; a graph captured under the other
+ *     policy is not replayed), and shapes that only the atomic kernels
+ *     serve fail with TT_ERR_UNSUPPORTED before any device work.
+ *   tt_set_deterministic(0): the default.
+ *   tt_deterministic: the current policy (0 or 1).
+ * The policy is process-wide and not synchronised with calls in flight on
+ * other host threads. */
+int tt_set_deterministic(int32_t on);
+int32_t tt_deterministic(void);
+
 /* --------------------------------------- A1+A2+A3 without a workspace */
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -81,6 +81,8 @@ SIGNATURES = {
     "tt_gather_mse_backward_noalloc": (C.c_int, [P_TT, VP, I64, VP, VP, VP, VP, P_TT, VP]),
     "tt_check_indices": (C.c_int, [P_TT, VP, I64, VP, VP]),
     "tt_set_suffix_depth": (C.c_int, [I32]),
+    "tt_set_deterministic": (C.c_int, [I32]),
+    "tt_deterministic": (I32, []),
     "tt_suffix_depth": (I32, [P_TT, I64]),
     "tt_halves_split": (C.c_int32, [P_TT]),
     "tt_halves_bytes": (I64, [P_TT, C.c_int32]),

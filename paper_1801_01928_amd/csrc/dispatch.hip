@@ -20,6 +20,16 @@ static bool generic_forced() {
 
 static bool use_mfma(const tt_tensor *L, const tt_tensor *R) { return !generic_forced() && mfma_supported(L, R); }
 
+// Deterministic mode: the adjoint must run on a slice-grouped kernel with a
+// fixed-order accumulator (the generic kernels add with float atomics).
+static int check_deterministic(const tt_tensor *L, const tt_tensor *R, int64_t M) {
+  if (!mfma_deterministic()) return TT_OK;
+  if (use_mfma(L, R) && mfma_deterministic_fits(R, mfma_rank_class(L, R), M)) return TT_OK;
+  return set_error(TT_ERR_UNSUPPORTED,
+                   "deterministic mode: this shape runs on kernels that add with float atomics "
+                   "(ranks above 32, d outside 2..16, or mode sizes too large for the slice accumulator)");
+}
+
 // The gather alone also has a rank-64 class (0: generic kernel).
 static int gather_class(const tt_tensor *X) { return generic_forced() ? 0 : mfma_gather_class(X); }
 
@@ -47,6 +57,8 @@ size_t adjoint_dispatch_ws2(const tt_tensor *L, const tt_tensor *R, int64_t M) {
 
 int adjoint_dispatch(const tt_tensor *L, const tt_tensor *R, tt_tensor *O, const int32_t *idx,
                      int64_t M, const float *w, void *ws, size_t ws_bytes, hipStream_t s) {
+  int rc = check_deterministic(L, R, M);
+  if (rc) return rc;
   if (use_mfma(L, R))
     return mfma_run(1, L, R, O, idx, M, nullptr, w, nullptr, nullptr, nullptr, ws, ws_bytes, s);
   int mr = max_rank_of(L);
@@ -62,6 +74,8 @@ size_t fused_mse_ws(const tt_tensor *X, int64_t M) {
 
 int fused_mse_dispatch(const tt_tensor *X, const int32_t *idx, int64_t M, const float *t, float *y,
                        float *g, float *loss, tt_tensor *gX, void *ws, size_t ws_bytes, hipStream_t s) {
+  int rc0 = check_deterministic(X, X, M);
+  if (rc0) return rc0;
   if (use_mfma(X, X))
     return mfma_run(2, X, X, gX, idx, M, t, nullptr, y, g, loss, ws, ws_bytes, s);
   const size_t m = (size_t)(M > 0 ? M : 1);
@@ -93,6 +107,13 @@ int tt_set_suffix_depth(int32_t depth) {
   mfma_set_suffix_depth(depth);
   return TT_OK;
 }
+
+int tt_set_deterministic(int32_t on) {
+  mfma_set_deterministic(on != 0);
+  return TT_OK;
+}
+
+int32_t tt_deterministic(void) { return mfma_deterministic() ? 1 : 0; }
 
 int32_t tt_suffix_depth(const tt_tensor *X, int64_t M) {
   int rc = validate_tt(X, "X", TT_MAX_RANK);

@@ -87,6 +87,13 @@ int mfma_device_cus();
 // Suffix table depth of the single-tensor kernels: -1 automatic, 0 off, k > 0
 // at most k levels (within the table's byte cap and the LDS), whatever M is.
 void mfma_set_suffix_depth(int depth);
+// Deterministic mode: shapes whose adjoint would add with float atomics are
+// refused; the batched plan runs tensor by tensor.
+void mfma_set_deterministic(bool on);
+bool mfma_deterministic();
+// True when the adjoint of rank class R over X has a fixed-order accumulator
+// (class 16 always; class 32 when the slice slab fits the LDS).
+bool mfma_deterministic_fits(const tt_tensor *X, int R, int64_t M);
 int mfma_suffix_depth_of(const tt_tensor *X, int R, int64_t M);
 
 // True when every descriptor fits the MFMA kernels (2 <= d <= 16, ranks <= 32,

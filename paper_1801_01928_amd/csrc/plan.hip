@@ -138,6 +138,7 @@ struct tt_plan {
   size_t plain_ws_bytes = 0;
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
+  bool graph_det = false;  // reduction policy the graph was captured under
 };
 
 namespace {
@@ -212,6 +213,26 @@ int issue(tt_plan *P, hipStream_t s) {
   hipLaunchKernelGGL(unpad_batch_kernel, dim3(P->md.d, P->b), dim3(256), 0, s, P->dmeta, P->md, P->gp);
   return launch_check("plan: unpad gradients");
 }
+
+// One fused pass per tensor (no batched kernel).
+int run_plain(tt_plan *plan, hipStream_t s) {
+  const int d = plan->md.d;
+  for (int j = 0; j < plan->b; ++j) {
+    tt_tensor x = plan->X[j].desc();
+    tt_tensor g = plan->grads[j].desc();
+    const int64_t M = plan->entry_off[j + 1] - plan->entry_off[j];
+    const int32_t *ij = plan->idx ? plan->idx + (long long)d * plan->entry_off[j] : nullptr;
+    const float *tj = plan->t ? plan->t + plan->entry_off[j] : nullptr;
+    int rc = fused_mse_dispatch(&x, ij, M, tj, nullptr, nullptr, plan->loss + j, &g, plan->plain_ws,
+                                plan->plain_ws_bytes, s);
+    if (rc) return rc;
+  }
+  return TT_OK;
+}
+
+// In deterministic mode the plan runs tensor by tensor: the batched kernel
+// adds finished runs with float atomics.
+int issue_policy(tt_plan *P, hipStream_t s) { return mfma_deterministic() ? run_plain(P, s) : issue(P, s); }
 
 void drop_graph(tt_plan *P) {
   if (P->graph) (void)hipGraphExecDestroy(P->graph);
@@ -392,8 +413,9 @@ int tt_plan_create(const tt_batch *X, const int32_t *idx, const float *t, const 
 int tt_plan_run(tt_plan *plan, void *stream) {
   if (!plan) return set_error(TT_ERR_ARG, "null plan");
   hipStream_t s = (hipStream_t)stream;
-  if (plan->graph && plan->graph_stream == s) return hip_check(hipGraphLaunch(plan->graph, s), "plan: graph launch");
-  return issue(plan, s);
+  if (plan->graph && plan->graph_stream == s && plan->graph_det == mfma_deterministic())
+    return hip_check(hipGraphLaunch(plan->graph, s), "plan: graph launch");
+  return issue_policy(plan, s);
 }
 
 int tt_plan_capture(tt_plan *plan, void *stream) {
@@ -403,7 +425,7 @@ int tt_plan_capture(tt_plan *plan, void *stream) {
   drop_graph(plan);
   int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "plan: begin capture");
   if (rc) return rc;
-  rc = issue(plan, s);
+  rc = issue_policy(plan, s);
   hipGraph_t g = nullptr;
   int rc2 = hip_check(hipStreamEndCapture(s, &g), "plan: end capture");
   if (rc || rc2) {
@@ -414,24 +436,13 @@ int tt_plan_capture(tt_plan *plan, void *stream) {
   (void)hipGraphDestroy(g);
   if (rc) return rc;
   plan->graph_stream = s;
+  plan->graph_det = mfma_deterministic();
   return TT_OK;
 }
 
 int tt_plan_run_plain(tt_plan *plan, void *stream) {
   if (!plan) return set_error(TT_ERR_ARG, "null plan");
-  hipStream_t s = (hipStream_t)stream;
-  const int d = plan->md.d;
-  for (int j = 0; j < plan->b; ++j) {
-    tt_tensor x = plan->X[j].desc();
-    tt_tensor g = plan->grads[j].desc();
-    const int64_t M = plan->entry_off[j + 1] - plan->entry_off[j];
-    const int32_t *ij = plan->idx ? plan->idx + (long long)d * plan->entry_off[j] : nullptr;
-    const float *tj = plan->t ? plan->t + plan->entry_off[j] : nullptr;
-    int rc = fused_mse_dispatch(&x, ij, M, tj, nullptr, nullptr, plan->loss + j, &g, plan->plain_ws,
-                                plan->plain_ws_bytes, s);
-    if (rc) return rc;
-  }
-  return TT_OK;
+  return run_plain(plan, (hipStream_t)stream);
 }
 
 int tt_plan_autotune(tt_plan *plan, void *stream, int32_t *chosen) {

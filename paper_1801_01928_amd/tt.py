@@ -203,6 +203,19 @@ def set_suffix_depth(depth):
     L.check(L.load().tt_set_suffix_depth(int(depth)))
 
 
+def set_deterministic(on):
+    """Reduction policy for later adjoint, fused-pass, projection and plan
+    calls: True sums every gradient in a fixed order (bitwise repeatable),
+    False (default) lets rank class 32 and the batched plan add with float
+    atomics."""
+    L.check(L.load().tt_set_deterministic(1 if on else 0))
+
+
+def deterministic():
+    """The current reduction policy."""
+    return bool(L.load().tt_deterministic())
+
+
 def suffix_depth(X, M):
     """Suffix-table levels a fused pass over X with M entries takes now."""
     return int(L.check(L.load().tt_suffix_depth(C.byref(X.desc()), int(M))))

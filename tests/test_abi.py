@@ -352,3 +352,28 @@ def test_suffix_table_policy(lib):
     finally:
         lib.tt_set_suffix_depth(-1)
     assert lib.tt_suffix_depth(C.byref(X), 1 << 20) == 4
+
+
+def test_deterministic_policy(lib):
+    """Reduction policy (host logic, no device work): workspaces do not
+    depend on it, and shapes without a fixed-order accumulator (ranks above
+    32) are refused before any device work while it is on."""
+    from paper_1801_01928_amd import _lib as L
+    X16 = _desc([10] * 10, [1] + [16] * 9 + [1])
+    X32 = _desc([10] * 10, [1, 10] + [32] * 7 + [10, 1])
+    X64 = _desc([6, 6, 6], [1, 40, 40, 1])
+    M = 1 << 16
+    assert lib.tt_deterministic() == 0
+    w16, w32 = lib.tt_gather_backward_workspace(C.byref(X16), M), lib.tt_gather_backward_workspace(C.byref(X32), M)
+    try:
+        assert lib.tt_set_deterministic(1) == 0 and lib.tt_deterministic() == 1
+        assert lib.tt_gather_backward_workspace(C.byref(X16), M) == w16
+        assert lib.tt_gather_backward_workspace(C.byref(X32), M) == w32
+        ws = lib.tt_gather_backward_workspace(C.byref(X64), 3001)
+        rc = lib.tt_gather_backward(C.byref(X64), C.c_void_p(0x10), 3001, C.c_void_p(0x10), C.byref(X64),
+                                    C.c_void_p(0x1000), ws, None)
+        assert rc == L.TT_ERR_UNSUPPORTED
+        assert "deterministic" in L.last_error()
+    finally:
+        lib.tt_set_deterministic(0)
+    assert lib.tt_deterministic() == 0

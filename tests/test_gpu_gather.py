@@ -45,6 +45,10 @@ CASES = [
     (12, [2] * 32, [1] + [3] * 31 + [1], 5000),   # d = TT_MAX_D (generic kernels)
     (13, [4096, 3], [1, 5, 1], 20000),            # n = TT_MAX_N
     (14, [40, 50, 30], [1, 8, 8, 1], 10000),      # modes above the MFMA classes' sizes
+    # rank class 32 with slices that span several waves of a tile (the
+    # slice sums of later waves are merged in rounds), one-slice modes
+    (15, [2] * 6, [1] + [32] * 5 + [1], 40000),
+    (16, [1, 5, 2, 1, 3], [1, 32, 32, 32, 32, 1], 30011),
 ]
 
 
