@@ -159,51 +159,109 @@ __device__ void blk_form_q(const float *W, int m, int c, const float *tau, float
   }
 }
 
-// Householder QR plus thin Q of a column-major m x c matrix (m <= 640,
-// c <= 64) held in registers: wave w owns columns w, w + 8, ..., lane l
-// rows l, l + 64, ...  For each column the owner wave forms the reflector
-// and broadcasts it through LDS (double-buffered, one barrier per column);
-// every wave applies it to its own columns.  Q is accumulated backwards in
-// registers the same way.  On return Wm holds R in its upper triangle (the
-// reflectors below it) and Q (m x p, column-major, ld = m) is written.
-// Same arithmetic as blk_qr / blk_form_q (diag(R) >= 0); only the data
-// placement differs.
-constexpr int kRegRows = 10;               // rows per lane
+// Sum over the 16 lanes of a DPP row; every lane of the row gets it.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Sums over the 64 lanes of N values at once, returned wave-uniform: each
+// butterfly stage of wave_sum runs on all N values before the next, so the
+// N dependent chains overlap instead of running back to back.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_f<0xB1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_f<0x4E>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_f<0x141>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_f<0x140>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 48));
+    v[i] = (r0 + r1) + (r2 + r3);
+  }
+}
+
+// Householder QR plus thin Q of an m x c matrix (m <= 64 RR, c <= 64) held
+// in registers: wave w owns columns w, w + 8, ..., lane l rows l, l + 64, ...
+// Element (i, j) is read through load(i, j).  For each column the owner
+// wave forms the reflector and broadcasts it through LDS (double-buffered,
+// one barrier per column); every wave applies it to its own trailing
+// columns, with the dot products of all its columns reduced together.  Q is
+// then accumulated backwards, each column on its own (it is
+// H_0 .. H_{p-1} e_col) with no barriers, the reflectors read back from Wm.
+// On return Wm (column-major, ld = m) holds R in its upper triangle and the
+// reflectors below it, and Q (m x p) went through storeq(i, j, value).  Same
+// arithmetic as blk_qr / blk_form_q (diag(R) >= 0); only the data placement
+// and the summation order differ.
+constexpr int kRegRows = 10;               // rows per lane at the largest size (m <= 640)
 constexpr int kRegCols = kJac / kWaves;    // columns per wave
 static_assert(kRegCols * kWaves == kJac, "columns must split over the waves");
 
 __device__ bool reg_qr_fits(int m, int c) { return m <= 64 * kRegRows && c <= kJac; }
 
-__device__ void reg_qr(float *Wm, int m, int c, float *Q, Shared &sh) {
+// wave_sum_n over the eight column sums of a wave; the first four are
+// skipped when none of those columns is still live (first_live false).
+__device__ __forceinline__ void reduce_live(float (&sp)[kRegCols], bool first_live) {
+  float lo[kRegCols / 2], hi[kRegCols / 2];
+#pragma unroll
+  for (int i = 0; i < kRegCols / 2; ++i) {
+    lo[i] = sp[i];
+    hi[i] = sp[kRegCols / 2 + i];
+  }
+  if (first_live) wave_sum_n<kRegCols / 2>(lo);
+  wave_sum_n<kRegCols / 2>(hi);
+#pragma unroll
+  for (int i = 0; i < kRegCols / 2; ++i) {
+    sp[i] = lo[i];
+    sp[kRegCols / 2 + i] = hi[i];
+  }
+}
+
+template <int RR, class Load, class StoreQ>
+__device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared &sh) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p = m < c ? m : c;
-  float x[kRegCols][kRegRows];
+  float x[kRegCols][RR];
 #pragma unroll
   for (int cc = 0; cc < kRegCols; ++cc)
 #pragma unroll
-    for (int rr = 0; rr < kRegRows; ++rr) {
+    for (int rr = 0; rr < RR; ++rr) {
       const int col = wave + kWaves * cc, row = lane + 64 * rr;
-      x[cc][rr] = (col < c && row < m) ? Wm[(long)col * m + row] : 0.f;
+      x[cc][rr] = (col < c && row < m) ? load(row, col) : 0.f;
     }
   // ---- factorization
   for (int j = 0; j < p; ++j) {
     const int owner = j % kWaves, cj = j / kWaves;
     float *hv = sh.hv[j & 1];
     if (wave == owner) {
-      float part = 0.f, x0l = 0.f;
+      float y[RR];  // column j
 #pragma unroll
-      for (int cc = 0; cc < kRegCols; ++cc) {
-        if (cc != cj) continue;
+      for (int rr = 0; rr < RR; ++rr) {
+        float t = x[0][rr];
 #pragma unroll
-        for (int rr = 0; rr < kRegRows; ++rr) {
-          const int row = lane + 64 * rr;
-          if (row > j) part = fmaf(x[cc][rr], x[cc][rr], part);
-          if (row == j) x0l = x[cc][rr];
-        }
+        for (int cc = 1; cc < kRegCols; ++cc) t = (cc == cj) ? x[cc][rr] : t;
+        y[rr] = t;
       }
-      const float sigma = wave_sum(part);
-      const float x0 = wave_sum(x0l);  // only lane j % 64 holds a non-zero
+      float sx[2] = {0.f, 0.f};  // sigma = |x(j+1:)|^2, x0 = x(j)
+#pragma unroll
+      for (int rr = 0; rr < RR; ++rr) {
+        const int row = lane + 64 * rr;
+        if (row > j && row < m) sx[0] = fmaf(y[rr], y[rr], sx[0]);
+        if (row == j) sx[1] = y[rr];
+      }
+      wave_sum_n<2>(sx);
+      const float sigma = sx[0], x0 = sx[1];
       float beta, v0, rjj;
       if (sigma == 0.f) {
         v0 = 1.f;
@@ -220,124 +278,144 @@ __device__ void reg_qr(float *Wm, int m, int c, float *Q, Shared &sh) {
       }
       const float inv = (sigma != 0.f) ? __builtin_amdgcn_rcpf(v0) : 1.f;
 #pragma unroll
-      for (int cc = 0; cc < kRegCols; ++cc) {
-        if (cc != cj) continue;
-#pragma unroll
-        for (int rr = 0; rr < kRegRows; ++rr) {
-          const int row = lane + 64 * rr;
-          float v = 0.f;
-          if (row > j) {
-            x[cc][rr] *= inv;      // reflector below the diagonal
-            v = x[cc][rr];
-          } else if (row == j) {
-            x[cc][rr] = rjj;       // R(j, j)
-            v = 1.f;
-          }
-          if (row < m) hv[row] = v;
+      for (int rr = 0; rr < RR; ++rr) {
+        const int row = lane + 64 * rr;
+        float v = 0.f;
+        if (row > j) {
+          y[rr] *= inv;  // reflector below the diagonal
+          v = y[rr];
+        } else if (row == j) {
+          y[rr] = rjj;   // R(j, j)
+          v = 1.f;
         }
+        if (row < m) hv[row] = v;
       }
+#pragma unroll
+      for (int cc = 0; cc < kRegCols; ++cc)
+        if (cc == cj) {
+#pragma unroll
+          for (int rr = 0; rr < RR; ++rr) x[cc][rr] = y[rr];
+        }
       if (lane == 0) sh.hb[j] = beta;
     }
     __syncthreads();
     const float beta = sh.hb[j];
-    float v[kRegRows];
+    float v[RR];
 #pragma unroll
-    for (int rr = 0; rr < kRegRows; ++rr) {
+    for (int rr = 0; rr < RR; ++rr) {
       const int row = lane + 64 * rr;
       v[rr] = (row < m) ? hv[row] : 0.f;
     }
+    // trailing columns of this wave: col > j, col < c (a wave-uniform
+    // range); finished columns take no dot products, and a half of the
+    // columns with none left takes no reduction
+    float sp[kRegCols];
+#pragma unroll
+    for (int cc = 0; cc < kRegCols; ++cc) {
+      sp[cc] = 0.f;
+      const int col = wave + kWaves * cc;
+      if (col <= j || col >= c) continue;
+#pragma unroll
+      for (int rr = 0; rr < RR; ++rr) sp[cc] = fmaf(v[rr], x[cc][rr], sp[cc]);
+    }
+    reduce_live(sp, wave + kWaves * (kRegCols / 2 - 1) > j);
 #pragma unroll
     for (int cc = 0; cc < kRegCols; ++cc) {
       const int col = wave + kWaves * cc;
       if (col <= j || col >= c) continue;
-      float sp = 0.f;
+      const float w = beta * sp[cc];
 #pragma unroll
-      for (int rr = 0; rr < kRegRows; ++rr) sp = fmaf(v[rr], x[cc][rr], sp);
-      const float w = beta * wave_sum(sp);
-#pragma unroll
-      for (int rr = 0; rr < kRegRows; ++rr) x[cc][rr] = fmaf(-w, v[rr], x[cc][rr]);
+      for (int rr = 0; rr < RR; ++rr) x[cc][rr] = fmaf(-w, v[rr], x[cc][rr]);
     }
   }
-  // R (and the reflectors) back to Wm
+  // R (upper triangle) and the reflectors (below it) to Wm; the register
+  // tile is dead from here on, which leaves its registers to Q
 #pragma unroll
   for (int cc = 0; cc < kRegCols; ++cc)
 #pragma unroll
-    for (int rr = 0; rr < kRegRows; ++rr) {
+    for (int rr = 0; rr < RR; ++rr) {
       const int col = wave + kWaves * cc, row = lane + 64 * rr;
       if (col < c && row < m) Wm[(long)col * m + row] = x[cc][rr];
     }
-  // ---- thin Q by backward accumulation, columns owned as above
-  float q[kRegCols][kRegRows];
+  // ---- thin Q by backward accumulation (no barriers: each column of Q
+  // is H_0 .. H_{p-1} e_col on its own); the next reflector is loaded from
+  // Wm while the current one is applied
+  float q[kRegCols][RR];
 #pragma unroll
   for (int cc = 0; cc < kRegCols; ++cc)
 #pragma unroll
-    for (int rr = 0; rr < kRegRows; ++rr) {
+    for (int rr = 0; rr < RR; ++rr) {
       const int col = wave + kWaves * cc, row = lane + 64 * rr;
       q[cc][rr] = (row == col) ? 1.f : 0.f;
     }
-  for (int j = p - 1; j >= 0; --j) {
-    const int owner = j % kWaves, cj = j / kWaves;
-    float *hv = sh.hv[j & 1];
-    if (wave == owner) {
+  __syncthreads();  // Wm's reflectors are visible to every wave
+  float nxt[RR];
+  auto fetch = [&](int j) {
 #pragma unroll
-      for (int cc = 0; cc < kRegCols; ++cc) {
-        if (cc != cj) continue;
-#pragma unroll
-        for (int rr = 0; rr < kRegRows; ++rr) {
-          const int row = lane + 64 * rr;
-          const float vv = (row > j) ? x[cc][rr] : (row == j ? 1.f : 0.f);
-          if (row < m) hv[row] = vv;
-        }
-      }
-    }
-    __syncthreads();
-    const float beta = sh.hb[j];
-    float v[kRegRows];
-#pragma unroll
-    for (int rr = 0; rr < kRegRows; ++rr) {
+    for (int rr = 0; rr < RR; ++rr) {
       const int row = lane + 64 * rr;
-      v[rr] = (row < m) ? hv[row] : 0.f;
+      nxt[rr] = (row > j && row < m) ? Wm[(long)j * m + row] : (row == j ? 1.f : 0.f);
     }
+  };
+  fetch(p - 1);
+  for (int j = p - 1; j >= 0; --j) {
+    const float beta = sh.hb[j];
+    float v[RR];
+#pragma unroll
+    for (int rr = 0; rr < RR; ++rr) v[rr] = nxt[rr];
+    if (j > 0) fetch(j - 1);
+    float sp[kRegCols];
+#pragma unroll
+    for (int cc = 0; cc < kRegCols; ++cc) {
+      sp[cc] = 0.f;
+      const int col = wave + kWaves * cc;
+      if (col < j || col >= p) continue;
+#pragma unroll
+      for (int rr = 0; rr < RR; ++rr) sp[cc] = fmaf(v[rr], q[cc][rr], sp[cc]);
+    }
+    reduce_live(sp, wave + kWaves * (kRegCols / 2 - 1) >= j);
 #pragma unroll
     for (int cc = 0; cc < kRegCols; ++cc) {
       const int col = wave + kWaves * cc;
       if (col < j || col >= p) continue;
-      float sp = 0.f;
+      const float w = beta * sp[cc];
 #pragma unroll
-      for (int rr = 0; rr < kRegRows; ++rr) sp = fmaf(v[rr], q[cc][rr], sp);
-      const float w = beta * wave_sum(sp);
-#pragma unroll
-      for (int rr = 0; rr < kRegRows; ++rr) q[cc][rr] = fmaf(-w, v[rr], q[cc][rr]);
+      for (int rr = 0; rr < RR; ++rr) q[cc][rr] = fmaf(-w, v[rr], q[cc][rr]);
     }
   }
+  __syncthreads();  // every load and LDS read precedes the stores below
 #pragma unroll
   for (int cc = 0; cc < kRegCols; ++cc)
 #pragma unroll
-    for (int rr = 0; rr < kRegRows; ++rr) {
+    for (int rr = 0; rr < RR; ++rr) {
       const int col = wave + kWaves * cc, row = lane + 64 * rr;
-      if (col < p && row < m) Q[(long)col * m + row] = q[cc][rr];
+      if (col < p && row < m) storeq(row, col, q[cc][rr]);
     }
   __syncthreads();
 }
 
-// QR with thin Q: registers when the matrix fits, the global-memory
-// kernels otherwise.
-__device__ void qr_thin(float *Wm, int m, int c, float *tau, float *Q, Shared &sh) {
+// QR with thin Q of the m x c matrix read through load(i, j): registers
+// when the matrix fits, else the global-memory kernels on a column-major
+// copy in Wm (ld = m) with Q built in Qg.  On return R is in Wm's upper
+// triangle and Q went through storeq(i, j, value) (which may write over the
+// source that load reads).
+template <class Load, class StoreQ>
+__device__ void qr_thin(Load load, int m, int c, float *Wm, float *tau, float *Qg, StoreQ storeq, Shared &sh) {
   if (reg_qr_fits(m, c)) {
-    reg_qr(Wm, m, c, Q, sh);
-  } else {
-    blk_qr(Wm, m, c, tau, sh);
-    blk_form_q(Wm, m, c, tau, Q, sh);
+    // rows per lane: the smallest of 2, 5 and 10 that holds the m rows
+    if (m <= 128) reg_qr<2>(load, m, c, Wm, storeq, sh);
+    else if (m <= 320) reg_qr<5>(load, m, c, Wm, storeq, sh);
+    else reg_qr<kRegRows>(load, m, c, Wm, storeq, sh);
+    return;
   }
-}
-
-// Sum over the 16 lanes of a DPP row; every lane of the row gets it.
-__device__ __forceinline__ float row16_sum(float v) {
-  v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2)
-  v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1)
-  v += dpp_f<0x141>(v);  // row_half_mirror
-  v += dpp_f<0x140>(v);  // row_mirror
-  return v;
+  const int p = m < c ? m : c;
+  for (long e = threadIdx.x; e < (long)m * c; e += kThreads) Wm[e] = load((int)(e % m), (int)(e / m));
+  __syncthreads();
+  blk_qr(Wm, m, c, tau, sh);
+  blk_form_q(Wm, m, c, tau, Qg, sh);
+  __syncthreads();
+  for (long e = threadIdx.x; e < (long)m * p; e += kThreads) storeq((int)(e % m), (int)(e / m), Qg[e]);
+  __syncthreads();
 }
 
 // One-sided Jacobi on the columns of sh.jb (rows x cols, ld = kJac); sh.jv
@@ -459,24 +537,40 @@ __device__ __forceinline__ void mfma_block(const float *ta, const float *tb, int
 // C (M x N) = A (M x K) * B (K x N) for K <= 64, the small factor A read
 // through aop(i, l) (consecutive l on consecutive lanes when staged), B in
 // global memory (element (l, j) at B[l*br + j*bc]), staged in chunks of 64
-// columns.  C may alias B: a chunk's columns are written only after the
-// whole chunk was staged (element (i, j) of C at C[i*cr + j*cc]).
+// columns; each thread loads its part of the next chunk into registers
+// while the current one is multiplied.  C may alias B: a chunk's columns
+// are written only after the whole chunk was staged, and the next chunk's
+// columns were read before (element (i, j) of C at C[i*cr + j*cc]).
 template <class AOp>
 __device__ void gemm_lds_a(int M, int N, int K, AOp aop, const float *B, long br, long bc, float *C, long cr,
                            long cc, Shared &sh) {
+  constexpr int PER = 64 * 64 / kThreads;
+  auto fetch = [&](int j0, float (&r)[PER]) {
+    const int nc = (N - j0) < 64 ? (N - j0) : 64;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      const int l = e >> 6, jj = e & 63;
+      r[u] = (jj < nc && l < K) ? B[(long)l * br + (long)(j0 + jj) * bc] : 0.f;
+    }
+  };
   for (int i0 = 0; i0 < M; i0 += 64) {
     const int mr = (M - i0) < 64 ? (M - i0) : 64;
     for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
       const int i = e >> 6, l = e & 63;
       sh.sm[i * 65 + l] = (i < mr && l < K) ? aop(i0 + i, l) : 0.f;
     }
+    float cur[PER];
+    fetch(0, cur);
     for (int j0 = 0; j0 < N; j0 += 64) {
       const int nc = (N - j0) < 64 ? (N - j0) : 64;
-      for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
-        const int l = e >> 6, jj = e & 63;
-        sh.stg[l * 65 + jj] = (jj < nc && l < K) ? B[(long)l * br + (long)(j0 + jj) * bc] : 0.f;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        sh.stg[(e >> 6) * 65 + (e & 63)] = cur[u];
       }
       __syncthreads();
+      if (j0 + 64 < N) fetch(j0 + 64, cur);
       mfma_block(sh.sm, sh.stg, K, [&](int i, int jj, float v) {
         if (i < mr && jj < nc) C[(long)(i0 + i) * cr + (long)(j0 + jj) * cc] = v;
       });
@@ -486,27 +580,44 @@ __device__ void gemm_lds_a(int M, int N, int K, AOp aop, const float *B, long br
 }
 
 // C (M x N) = A (M x K) * B (K x N) for K <= 64 and N <= 64, A in global
-// memory (element (i, l) at A[i*ar + l*ac]) staged in chunks of 64 rows,
-// the small factor B read through bop(l, j).  ROWS_ON_LANES: bop is read
-// with consecutive l on consecutive lanes (for factors whose elements of
-// one row l are 64 floats apart), else with consecutive j.  C may alias A
-// when row i of C (C[i*ldc + j]) never reaches past row i of A, i.e. ldc <=
-// A's row stride: a chunk's rows are written after the chunk was staged.
+// memory (element (i, l) at A[i*ar + l*ac]) staged in chunks of 64 rows
+// (the next chunk loaded into registers while the current one is
+// multiplied), the small factor B read through bop(l, j).  ROWS_ON_LANES:
+// bop is read with consecutive l on consecutive lanes (for factors whose
+// elements of one row l are 64 floats apart), else with consecutive j.  C
+// may alias A when row i of C (C[i*ldc + j]) never reaches past row i of
+// A, i.e. ldc <= A's row stride: a chunk's rows are written after the chunk
+// and the next one were read.
 template <bool ROWS_ON_LANES = false, class BOp>
 __device__ void gemm_lds_b(int M, int N, int K, const float *A, long ar, long ac, BOp bop, float *C, long ldc,
                            Shared &sh) {
+  constexpr int PER = 64 * 64 / kThreads;
   for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
     const int l = ROWS_ON_LANES ? (e & 63) : (e >> 6), j = ROWS_ON_LANES ? (e >> 6) : (e & 63);
     sh.sm[l * 65 + j] = (l < K && j < N) ? bop(l, j) : 0.f;
   }
+  // consecutive threads walk the unit-stride index of A (coalesced loads)
+  auto fetch = [&](int i0, float (&r)[PER]) {
+    const int mr = (M - i0) < 64 ? (M - i0) : 64;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      const int ii = (ar == 1) ? (e & 63) : (e >> 6), l = (ar == 1) ? (e >> 6) : (e & 63);
+      r[u] = (ii < mr && l < K) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
+    }
+  };
+  float cur[PER];
+  fetch(0, cur);
   for (int i0 = 0; i0 < M; i0 += 64) {
     const int mr = (M - i0) < 64 ? (M - i0) : 64;
-    // consecutive threads walk the unit-stride index of A (coalesced loads)
-    for (int e = threadIdx.x; e < 64 * 64; e += kThreads) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * kThreads;
       const int ii = (ar == 1) ? (e & 63) : (e >> 6), l = (ar == 1) ? (e >> 6) : (e & 63);
-      sh.stg[ii * 65 + l] = (ii < mr && l < K) ? A[(long)(i0 + ii) * ar + (long)l * ac] : 0.f;
+      sh.stg[ii * 65 + l] = cur[u];
     }
     __syncthreads();
+    if (i0 + 64 < M) fetch(i0 + 64, cur);
     mfma_block(sh.stg, sh.sm, K, [&](int ii, int j, float v) {
       if (ii < mr && j < N) C[(long)(i0 + ii) * ldc + j] = v;
     });
@@ -540,19 +651,10 @@ __device__ void sweep_lr(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
     const int m = r[k] * n[k], c = r[k + 1];
     const int p = m < c ? m : c;
     float *G = w.core(k);
-    // column-major copy of the left unfolding (row-major m x c)
-    for (long e = threadIdx.x; e < (long)m * c; e += kThreads) {
-      const int i = (int)(e % m), j = (int)(e / m);
-      Wm[e] = G[(long)i * c + j];
-    }
-    __syncthreads();
-    qr_thin(Wm, m, c, tau, Q, sh);
-    // core k <- Q (row-major m x p)
-    for (long e = threadIdx.x; e < (long)m * p; e += kThreads) {
-      const int i = (int)(e / p), j = (int)(e % p);
-      G[e] = Q[(long)j * m + i];
-    }
-    __syncthreads();  // Q's buffer is reused below
+    // QR of the left unfolding (row-major m x c); core k <- Q (row-major
+    // m x p), written over the unfolding once it was read
+    qr_thin([&](int i, int j) { return G[(long)i * c + j]; }, m, c, Wm, tau, Q,
+            [&](int i, int j, float v) { G[(long)i * p + j] = v; }, sh);
     // next core <- R (p x c, upper triangle of Wm) * next (c x n r'), in place
     const int nn = n[k + 1] * r[k + 2];
     float *Gn = w.core(k + 1);
@@ -575,14 +677,11 @@ __device__ void sweep_rl(WorkTT &w, int d, const int *n, int *r, float *Wm, floa
     const int rows = r[k], mm = n[k] * r[k + 1];  // unfolding rows x mm; QR of its transpose
     const int p = mm < rows ? mm : rows;
     float *G = w.core(k);
-    // transpose of the right unfolding, column-major (mm x rows): the
-    // row-major core already has that layout
-    for (long e = threadIdx.x; e < (long)mm * rows; e += kThreads) Wm[e] = G[e];
-    __syncthreads();
-    qr_thin(Wm, mm, rows, tau, Q, sh);
-    // core k <- Q^T (p x mm row-major) = Q column-major
-    for (long e = threadIdx.x; e < (long)p * mm; e += kThreads) G[e] = Q[e];
-    __syncthreads();  // Q's buffer is reused below
+    // QR of the transposed right unfolding (mm x rows; the row-major core
+    // holds it column-major); core k <- Q^T (p x mm row-major = Q
+    // column-major), written over the core once it was read
+    qr_thin([&](int i, int j) { return G[(long)j * mm + i]; }, mm, rows, Wm, tau, Q,
+            [&](int i, int j, float v) { G[(long)j * mm + i] = v; }, sh);
     // previous core (r[k-1] n[k-1] x rows) <- prev * L, L = R^T (rows x p),
     // in place (the output row stride p does not exceed rows)
     const int mp = r[k - 1] * n[k - 1];
@@ -667,12 +766,9 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
     const int m = r[k] * n[k], c = r[k + 1];
     const int p = m < c ? m : c;
     float *G = w.core(k);
-    for (long e = threadIdx.x; e < (long)m * c; e += kThreads) {
-      const int i = (int)(e % m), j = (int)(e / m);
-      b.wm[e] = G[(long)i * c + j];
-    }
-    __syncthreads();
-    qr_thin(b.wm, m, c, b.tau, b.q, sh);
+    float *bq = b.q;
+    qr_thin([&](int i, int j) { return G[(long)i * c + j]; }, m, c, b.wm, b.tau, bq,
+            [&](int i, int j, float v) { bq[(long)j * m + i] = v; }, sh);
     // Jacobi on B = R^T (c x p): jb[row l][col j] = R[j][l]
     for (int e = threadIdx.x; e < kJac * kJac; e += kThreads) {
       const int l = e % kJac, j = e / kJac;
