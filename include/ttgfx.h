@@ -524,6 +524,22 @@ int tt_matmul(const tt_matrix *W, const void *X, int64_t B, float *Y, int dtype,
 int tt_matmul_backward(const tt_matrix *W, const void *X, int64_t B,
                        const void *dY, float *dX, float *dWdata, int dtype,
                        void *ws, size_t ws_bytes, void *stream);
+/* Evaluation path of tt_matmul and tt_matmul_backward.  The chain contracts
+ * one core per step against every row (intermediates B prod m_<k
+ * prod n_>=k r_k); the dense path builds W from the left partial products
+ * of the cores, runs Y = X W^T, dX = dY W and dW_dense = dY^T X on the
+ * matrix cores, and takes dG^k from dW_dense by contracting it with the
+ * partial products on either side of core k.  Both compute the same linear
+ * map and its exact gradients (results differ in rounding; in bf16 the
+ * dense path rounds W once where the chain rounds each intermediate).
+ *   tt_matmul_set_path: 0 automatic (the default: dense when prod m prod n
+ *     <= 2^28 and 2 B prod m prod n is below the chain's forward flops), 1
+ *     chain, 2 dense (falls back to the chain when W exceeds 2^28
+ *     elements).  Process-wide; workspace sizes follow it.
+ *   tt_matmul_path: the path a call with this W and B takes now (1 or 2),
+ *     or a negative error. */
+int tt_matmul_set_path(int32_t path);
+int32_t tt_matmul_path(const tt_matrix *W, int64_t B, int dtype);
 
 /* TT-matrix by TT-vector product in the TT format (Implementation Details:
  * matrix-by-vector products of TT objects; Table 1 times it as matvec).

@@ -127,6 +127,8 @@ SIGNATURES = {
     "tt_plan_set_config": (C.c_int, [VP, PI32]),
     "tt_plan_destroy": (None, [VP]),
     "tt_matmul_workspace": (I64, [P_TTM, I64, C.c_int]),
+    "tt_matmul_set_path": (C.c_int, [I32]),
+    "tt_matmul_path": (I32, [P_TTM, I64, C.c_int]),
     "tt_matmul": (C.c_int, [P_TTM, VP, I64, VP, C.c_int, VP, SZ, VP]),
     "tt_matvec": (C.c_int, [P_TTM, P_BATCH, P_BATCH, VP]),
     "tt_matmat": (C.c_int, [P_TTM, P_TTM, P_TTM, VP]),

@@ -6,6 +6,20 @@ using namespace ttgfx;
 
 extern "C" {
 
+int tt_matmul_set_path(int32_t path) {
+  if (path < TTM_PATH_AUTO || path > TTM_PATH_DENSE)
+    return set_error(TT_ERR_ARG, "tt_matmul_set_path: %d is not 0 (automatic), 1 (chain) or 2 (dense)", path);
+  ttm_set_path(path);
+  return TT_OK;
+}
+
+int32_t tt_matmul_path(const tt_matrix *W, int64_t B, int dtype) {
+  TTMDims D;
+  const int rc = ttm_validate(W, B, dtype, &D);
+  if (rc) return rc;
+  return ttm_path_of(D, B);
+}
+
 int64_t tt_matmul_workspace(const tt_matrix *W, int64_t B, int dtype) {
   TTMDims D;
   const int rc = ttm_validate(W, B, dtype, &D);

@@ -545,7 +545,7 @@ int ttm_validate(const tt_matrix *W, long long B, int dtype, TTMDims *D) {
   return TT_OK;
 }
 
-size_t ttm_ws(const TTMDims &D, long long B, int dtype, int backward) {
+static size_t chain_ws(const TTMDims &D, long long B, int dtype, int backward) {
   const size_t e = esz(dtype);
   size_t bytes = 2 * arena_bytes<char>(e * (size_t)max_pingpong(D, B, backward));
   if (backward) {
@@ -557,8 +557,8 @@ size_t ttm_ws(const TTMDims &D, long long B, int dtype, int backward) {
   return bytes;
 }
 
-int ttm_forward(const TTMDims &D, const void *cores, const void *X, long long B, float *Y, int dtype, void *ws,
-                size_t bytes, hipStream_t st) {
+static int chain_forward(const TTMDims &D, const void *cores, const void *X, long long B, float *Y, int dtype,
+                         void *ws, size_t bytes, hipStream_t st) {
   Arena ar(ws, bytes);
   const size_t pp = esz(dtype) * (size_t)max_pingpong(D, B, 0);
   void *buf[2] = {ar.take<char>(pp), ar.take<char>(pp)};
@@ -576,8 +576,8 @@ int ttm_forward(const TTMDims &D, const void *cores, const void *X, long long B,
   return TT_OK;
 }
 
-int ttm_backward(const TTMDims &D, const void *cores, const void *X, long long B, const void *dY, float *dX,
-                 float *dW, int dtype, void *ws, size_t bytes, hipStream_t st) {
+static int chain_backward(const TTMDims &D, const void *cores, const void *X, long long B, const void *dY,
+                          float *dX, float *dW, int dtype, void *ws, size_t bytes, hipStream_t st) {
   const size_t e = esz(dtype);
   const int d = D.d;
   Arena ar(ws, bytes);
@@ -681,6 +681,44 @@ int ttm_backward(const TTMDims &D, const void *cores, const void *X, long long B
   }
   timer_after(st);
   return TT_OK;
+}
+
+// ---------------------------------------------------------------- dispatch
+
+static int g_ttm_path = TTM_PATH_AUTO;
+
+void ttm_set_path(int path) { g_ttm_path = path; }
+
+// Flops of the core-by-core forward chain: step k contracts (j_k, r_k) and
+// produces (i_k, r_{k+1}) for B prod m_<k prod n_>k rows.
+long long ttm_chain_flops(const TTMDims &D, long long B) {
+  long long f = 0;
+  for (int k = 0; k < D.d; ++k)
+    f += 2 * B * prod(D.m, 0, k) * prod(D.n, k + 1, D.d) * D.n[k] * D.r[k] * D.m[k] * D.r[k + 1];
+  return f;
+}
+
+int ttm_path_of(const TTMDims &D, long long B) {
+  if (g_ttm_path == TTM_PATH_CHAIN) return TTM_PATH_CHAIN;
+  if (!ttm_dense_fits(D)) return TTM_PATH_CHAIN;
+  if (g_ttm_path == TTM_PATH_DENSE) return TTM_PATH_DENSE;
+  return ttm_dense_flops(D, B) < ttm_chain_flops(D, B) ? TTM_PATH_DENSE : TTM_PATH_CHAIN;
+}
+
+size_t ttm_ws(const TTMDims &D, long long B, int dtype, int backward) {
+  return ttm_path_of(D, B) == TTM_PATH_DENSE ? ttm_dense_ws(D, B, dtype, backward) : chain_ws(D, B, dtype, backward);
+}
+
+int ttm_forward(const TTMDims &D, const void *cores, const void *X, long long B, float *Y, int dtype, void *ws,
+                size_t bytes, hipStream_t st) {
+  if (ttm_path_of(D, B) == TTM_PATH_DENSE) return ttm_dense_forward(D, cores, X, B, Y, dtype, ws, bytes, st);
+  return chain_forward(D, cores, X, B, Y, dtype, ws, bytes, st);
+}
+
+int ttm_backward(const TTMDims &D, const void *cores, const void *X, long long B, const void *dY, float *dX,
+                 float *dW, int dtype, void *ws, size_t bytes, hipStream_t st) {
+  if (ttm_path_of(D, B) == TTM_PATH_DENSE) return ttm_dense_backward(D, cores, X, B, dY, dX, dW, dtype, ws, bytes, st);
+  return chain_backward(D, cores, X, B, dY, dX, dW, dtype, ws, bytes, st);
 }
 
 }  // namespace ttgfx

@@ -887,6 +887,20 @@ def tt_matmat(A, B):
     return Cm
 
 
+def ttm_set_path(path):
+    """Evaluation path of the TT-matrix layer for later calls: "auto"
+    (default), "chain" (one core per step) or "dense" (W built once, GEMMs
+    on the matrix cores)."""
+    codes = {"auto": 0, "chain": 1, "dense": 2}
+    L.check(L.load().tt_matmul_set_path(codes[path]))
+
+
+def ttm_path(W, B):
+    """The path ("chain" or "dense") a layer call on B rows takes now."""
+    code = L.check(L.load().tt_matmul_path(C.byref(W.desc()), int(B), W.dtype_code))
+    return {1: "chain", 2: "dense"}[code]
+
+
 def ttm_matmul(W, X):
     """Y = X W^T (float32) for a batch of rows X (B x prod n), X in W's dtype."""
     lib = L.load()

@@ -93,8 +93,13 @@ def test_matmul_validation_before_device(lib):
     from paper_1801_01928_amd import _lib as L
     W = _mdesc([4, 4], [4, 4], [1, 8, 1])
     assert lib.tt_matmul_workspace(C.byref(W), 16, 0) > 0
-    # bf16 intermediates need half the bytes of float32 ones (plus fixed parts)
-    assert lib.tt_matmul_workspace(C.byref(W), 4096, 1) < lib.tt_matmul_workspace(C.byref(W), 4096, 0)
+    # on the chain, bf16 intermediates need half the bytes of float32 ones
+    # (plus fixed parts)
+    try:
+        assert lib.tt_matmul_set_path(1) == 0
+        assert lib.tt_matmul_workspace(C.byref(W), 4096, 1) < lib.tt_matmul_workspace(C.byref(W), 4096, 0)
+    finally:
+        lib.tt_matmul_set_path(0)
     assert lib.tt_matmul_workspace(C.byref(W), 16, 2) == L.TT_ERR_ARG
     assert lib.tt_matmul_workspace(C.byref(W), -1, 0) == L.TT_ERR_ARG
     # a mode size times a rank above the fused step limit of 128
@@ -377,3 +382,33 @@ def test_deterministic_policy(lib):
     finally:
         lib.tt_set_deterministic(0)
     assert lib.tt_deterministic() == 0
+
+
+def test_matmul_path_policy(lib):
+    """Path choice of the TT-matrix layer (host logic, no device work): the
+    automatic policy takes the dense matrix when its GEMM flops, 2 B prod m
+    prod n, are below the core-by-core chain's; the knob forces either path;
+    W above 2^28 elements always takes the chain; workspaces follow the
+    path, including an empty batch."""
+    from paper_1801_01928_amd import _lib as L
+    layer = _mdesc([4] * 5, [4] * 5, [1, 32, 32, 32, 32, 1])   # chain 105 GFLOP, dense 8.6 at B = 4096
+    thin = _mdesc([4, 4], [4, 4], [1, 1, 1])                    # rank 1: the chain is cheaper
+    huge = _mdesc([128] * 3, [128] * 3, [1, 1, 1, 1])           # W of 2^42 elements
+    try:
+        assert lib.tt_matmul_path(C.byref(layer), 4096, 0) == 2
+        assert lib.tt_matmul_path(C.byref(thin), 4096, 0) == 1
+        assert lib.tt_matmul_path(C.byref(huge), 4, 0) == 1
+        w_dense = lib.tt_matmul_workspace(C.byref(layer), 4096, 0)
+        assert lib.tt_matmul_set_path(1) == 0
+        assert lib.tt_matmul_path(C.byref(layer), 4096, 0) == 1
+        w_chain = lib.tt_matmul_workspace(C.byref(layer), 4096, 0)
+        assert w_chain > w_dense  # the chain keeps B-sized intermediates
+        assert lib.tt_matmul_set_path(2) == 0
+        assert lib.tt_matmul_path(C.byref(thin), 4096, 0) == 2
+        assert lib.tt_matmul_path(C.byref(huge), 4, 0) == 1
+        for B in (0, 1, 255, 256, 4096):
+            assert lib.tt_matmul_workspace(C.byref(layer), B, 0) > 0
+            assert lib.tt_matmul_workspace(C.byref(layer), B, 1) > 0
+        assert lib.tt_matmul_set_path(3) == L.TT_ERR_ARG
+    finally:
+        lib.tt_matmul_set_path(0)

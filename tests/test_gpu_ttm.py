@@ -39,6 +39,16 @@ def _bf16(a):
     return torch.as_tensor(a).to(torch.bfloat16)
 
 
+@pytest.fixture(params=["chain", "dense"])
+def ttm_path(gpu_lib, request):
+    """Each layer test runs on both evaluation paths (one core per step;
+    W built once and multiplied on the matrix cores)."""
+    tt = gpu_lib
+    tt.ttm_set_path(request.param)
+    yield tt
+    tt.ttm_set_path("auto")
+
+
 CASES = [
     ([4, 4, 4], [4, 4, 4], [1, 8, 8, 1], 64),
     ([2, 3, 5], [4, 2, 3], [1, 3, 7, 1], 37),          # ragged batch, odd sizes
@@ -51,8 +61,8 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_fp32_forward_backward(gpu_lib, case):
-    tt = gpu_lib
+def test_fp32_forward_backward(ttm_path, case):
+    tt = ttm_path
     ms, ns, ranks, B = CASES[case]
     print("ttm fp32", ms, ns, ranks, B, flush=True)
     cores, X, dY = _case(500 + case, ms, ns, ranks, B)
@@ -75,8 +85,8 @@ def test_fp32_forward_backward(gpu_lib, case):
 
 
 @pytest.mark.parametrize("case", [0, 1, 3, 4])
-def test_bf16_forward_backward(gpu_lib, case):
-    tt = gpu_lib
+def test_bf16_forward_backward(ttm_path, case):
+    tt = ttm_path
     ms, ns, ranks, B = CASES[case]
     print("ttm bf16", ms, ns, ranks, B, flush=True)
     cores, X, dY = _case(600 + case, ms, ns, ranks, B)
@@ -97,8 +107,8 @@ def test_bf16_forward_backward(gpu_lib, case):
         assert rel(g, r) <= tol
 
 
-def test_empty_batch(gpu_lib):
-    tt = gpu_lib
+def test_empty_batch(ttm_path):
+    tt = ttm_path
     cores, X, dY = _case(700, [4, 4], [4, 4], [1, 4, 1], 0)
     Wm = tt.TTMatrix.from_cores(cores)
     Y = tt.ttm_matmul(Wm, torch.zeros((0, 16), device="cuda"))
@@ -108,11 +118,11 @@ def test_empty_batch(gpu_lib):
     assert float(dG.abs().max()) == 0.0
 
 
-def test_autograd_and_finite_differences(gpu_lib):
+def test_autograd_and_finite_differences(ttm_path):
     """tt_linear through torch.autograd; L = <dY, Y> is linear in every core
     entry, so a central difference with a large step is exact up to fp32
     rounding of the forward."""
-    tt = gpu_lib
+    tt = ttm_path
     ms, ns, ranks, B = [4, 4, 4], [4, 4, 4], [1, 8, 8, 1], 96
     cores, X, dY = _case(800, ms, ns, ranks, B)
     Wm = tt.TTMatrix.from_cores(cores)
@@ -140,11 +150,11 @@ def test_autograd_and_finite_differences(gpu_lib):
         assert abs(fd - float(flat.grad[e])) <= 1e-5 * scale
 
 
-def test_ttm_layer_full_size(gpu_lib):
+def test_ttm_layer_full_size(ttm_path):
     """The 1024 x 1024 layer (modes 4^5, r = 32) on a batch of 4096 rows,
     float32, against the full oracle; the Euler identity <dG^k, G^k> = <dY, Y>
     holds for every core."""
-    tt = gpu_lib
+    tt = ttm_path
     p = W.ttm_layer()
     print("ttm layer 4096 x 1024, r = 32", flush=True)
     Wm = tt.TTMatrix.from_cores(p.cores)
@@ -171,8 +181,8 @@ def test_ttm_layer_full_size(gpu_lib):
         assert abs(euler - L0) <= 1e-5 * np.linalg.norm(g) * np.linalg.norm(p.cores[k])
 
 
-def test_ttm_layer_full_size_bf16(gpu_lib):
-    tt = gpu_lib
+def test_ttm_layer_full_size_bf16(ttm_path):
+    tt = ttm_path
     p = W.ttm_layer()
     print("ttm layer bf16", flush=True)
     cb = [_bf16(c) for c in p.cores]
