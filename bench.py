@@ -567,34 +567,69 @@ def table1_leg(tt, W, reps=5):
     return out
 
 
+def ttm_dense_flops(ms_, ns_, rk, B):
+    """Flops the dense path executes: W from the left partial products, the
+    three GEMMs (Y, dX, dW_dense) and the core gradients (right partial sums
+    and the contractions with the left partial products)."""
+    import numpy as np
+    d = len(ms_)
+    U = lambda k: int(np.prod(ms_[:k])) if k else 1
+    V = lambda k: int(np.prod(ns_[:k])) if k else 1
+    build = sum(2 * U(k) * V(k) * rk[k] * ms_[k] * ns_[k] * rk[k + 1] for k in range(d))
+    M, N = int(np.prod(ms_)), int(np.prod(ns_))
+    right = sum(2 * U(k + 1) * V(k + 1) * rk[k + 1] * ms_[k + 1] * ns_[k + 1] * rk[k + 2] for k in range(d - 1))
+    grads = sum(2 * rk[k] * ms_[k] * ns_[k] * rk[k + 1] * U(k) * V(k) for k in range(d))
+    fwd = build + 2 * B * M * N
+    bwd = build + 4 * B * M * N + right + grads
+    return fwd, bwd
+
+
 def ttm_leg(tt, W, reps=3):
     """TT-matrix layer 1024 x 1024 (modes 4^5, r=32) on a batch of 4096 rows:
-    forward and adjoint, float32 and bf16 (float32 accumulation)."""
+    forward and adjoint, float32 and bf16 (float32 accumulation), on the
+    path the library picks (the dense matrix) and on the core-by-core
+    chain."""
     import numpy as np
     import torch
     p = W.ttm_layer()
     ms_, ns_, rk, B = p.row_modes, p.col_modes, p.ranks, p.X.shape[0]
     fwd_flop = sum(2.0 * B * np.prod(ms_[:k]) * np.prod(ns_[k + 1:]) * ns_[k] * rk[k] * ms_[k] * rk[k + 1]
                    for k in range(len(ms_)))
+    dfwd, dbwd = ttm_dense_flops(ms_, ns_, rk, B)
     out = {"workload": "Y = X W^T, W 1024x1024 TT-matrix d=5 modes 4x4 r=32, batch 4096",
-           "chain_fwd_gflop": round(fwd_flop / 1e9, 2)}
+           "chain_fwd_gflop": round(fwd_flop / 1e9, 2),
+           "dense_gflop": {"fwd": round(dfwd / 1e9, 3), "bwd": round(dbwd / 1e9, 3)}}
     for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
         Wm = tt.TTMatrix.from_cores([torch.as_tensor(c).to(dt) for c in p.cores], dtype=dt)
         X = torch.as_tensor(p.X).to(dt).cuda()
         dY = torch.as_tensor(p.dY).to(dt).cuda()
-        tt.ttm_matmul(Wm, X)
-        tt.ttm_matmul_backward(Wm, X, dY)
-        torch.cuda.synchronize()
-        f = _event_ms(lambda: tt.ttm_matmul(Wm, X), reps)
-        b = _event_ms(lambda: tt.ttm_matmul_backward(Wm, X, dY), reps)
         peak = PEAK_MFMA_F32_TFLOPS if name == "f32" else PEAK_MFMA_BF16_TFLOPS
-        # forward + backward: the backward is dX (one chain) and every dG^k
-        # (the chain of T_k and V_{k+1} contractions): 3x the forward chain
-        tf = 3 * fwd_flop / ((f + b) * 1e-3) / 1e12
-        out[name] = {"fwd_ms": round(f, 3), "bwd_ms": round(b, 3),
-                     "fwd_chain_tflops": round(fwd_flop / (f * 1e-3) / 1e12, 2),
-                     "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
-                                  "frac": round(tf / peak, 4), "flop_fwd_bwd": round(3 * fwd_flop / 1e9, 1)}}
+        rec = {"path": tt.ttm_path(Wm, B)}
+        for path in ("auto", "chain"):
+            tt.ttm_set_path(path)
+            tt.ttm_matmul(Wm, X)
+            tt.ttm_matmul_backward(Wm, X, dY)
+            torch.cuda.synchronize()
+            f = _event_ms(lambda: tt.ttm_matmul(Wm, X), reps)
+            b = _event_ms(lambda: tt.ttm_matmul_backward(Wm, X, dY), reps)
+            if path == "auto":
+                # executed flops of the dense path against the matrix-core peak
+                tf = (dfwd + dbwd) / ((f + b) * 1e-3) / 1e12
+                rec.update({"fwd_ms": round(f, 3), "bwd_ms": round(b, 3),
+                            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": peak,
+                                         "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                                         "flop_fwd_bwd": round((dfwd + dbwd) / 1e9, 2)}})
+            else:
+                # the backward is dX (one chain) and every dG^k (the chain of
+                # T_k and V_{k+1} contractions): 3x the forward chain
+                tf = 3 * fwd_flop / ((f + b) * 1e-3) / 1e12
+                rec["chain"] = {"fwd_ms": round(f, 3), "bwd_ms": round(b, 3),
+                                "fwd_chain_tflops": round(fwd_flop / (f * 1e-3) / 1e12, 2),
+                                "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": peak,
+                                             "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                                             "flop_fwd_bwd": round(3 * fwd_flop / 1e9, 1)}}
+        tt.ttm_set_path("auto")
+        out[name] = rec
     return out
 
 

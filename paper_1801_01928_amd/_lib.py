@@ -8,6 +8,9 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libttgfx.so")
+# The host-AddressSanitizer build of the same sources (build.py --asan), for
+# the validation and bookkeeping tests of the C ABI on the CPU.
+ASAN_LIB_PATH = os.path.join(_HERE, "libttgfx_asan.so")
 
 TT_OK = 0
 TT_ERR_ARG = -1
@@ -155,7 +158,7 @@ def load(path=None):
     global _lib
     if _lib is not None:
         return _lib
-    path = path or LIB_PATH
+    path = path or os.environ.get("TTGFX_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError("libttgfx.so not found at %s: run __graft_entry__.build() "
                            "(or python paper_1801_01928_amd/build.py) first" % path)

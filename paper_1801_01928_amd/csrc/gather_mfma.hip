@@ -950,10 +950,11 @@ struct SufBuild {
   int blocks;  // workgroups of the build (after the slice workgroups)
 };
 
-__device__ void build_suffix_rows(const TTDev &X, int R, const SufBuild &sb, int blk) {
+template <int R>
+__device__ void build_suffix_rows(const TTDev &X, const SufBuild &sb, int blk) {
   const int lane = threadIdx.x & 63;
   const int grp = lane / R, a = lane - grp * R;
-  const int groups = 64 / R;
+  constexpr int groups = 64 / R;
   const long long sfx = ((long long)blk * (blockDim.x >> 6) + (threadIdx.x >> 6)) * groups + grp;
   const int D = sb.depth;
   const bool live = sfx < sb.rows[D - 1];
@@ -964,15 +965,21 @@ __device__ void build_suffix_rows(const TTDev &X, int R, const SufBuild &sb, int
     const int nk = X.n[k], rk = X.r[k], rk1 = X.r[k + 1];
     const int i = rem % nk;
     rem /= nk;
-    const float *G = X.data + X.off[k] + (long long)i * rk1;  // G[a][i][b] at a * nk * rk1 + b
+    const float *G = X.data + X.off[k] + (long long)i * rk1 + (long long)a * nk * rk1;  // G[a][i][:]
     float acc = 0.f;
     if (l == 1) {
-      if (a < rk) acc = G[(long long)a * nk * rk1];  // column 0 (r_d = 1)
+      if (a < rk) acc = G[0];  // column 0 (r_d = 1)
     } else {
-      for (int b = 0; b < rk1; ++b) {
-        const float rb = __shfl(rho, grp * R + b);
-        if (a < rk) acc = fmaf(G[(long long)a * nk * rk1 + b], rb, acc);
+      // the row of G and the partner values are read before the sum, so
+      // the R loads of a level are in flight together
+      float gv[R], rv[R];
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        gv[b] = (a < rk && b < rk1) ? G[b] : 0.f;
+        rv[b] = __shfl(rho, grp * R + b);
       }
+#pragma unroll
+      for (int b = 0; b < R; ++b) acc = fmaf(gv[b], rv[b], acc);
     }
     rho = acc;
     if (live && sfx < sb.rows[l - 1]) sb.tab[((long long)sb.row0[l - 1] + sfx) * R + a] = rho;
@@ -988,7 +995,10 @@ __global__ void pad_slices_kernel(TTDev Xr, TTDev Xl, int R, float *__restrict__
                                   float *__restrict__ left, int total_slices, SufBuild sb) {
   const int slice = blockIdx.x;
   if (slice >= total_slices) {
-    if (sb.depth > 0 && slice - total_slices < sb.blocks) build_suffix_rows(Xr, R, sb, slice - total_slices);
+    if (sb.depth > 0 && slice - total_slices < sb.blocks) {
+      if (R == 16) build_suffix_rows<16>(Xr, sb, slice - total_slices);
+      else build_suffix_rows<32>(Xr, sb, slice - total_slices);
+    }
     return;
   }
   int k = 0, base = 0;
@@ -1031,11 +1041,23 @@ __global__ void reduce_acc_stage1(const float *__restrict__ acc, long long acc_s
 }
 
 // Stage 2: out core k (a, s, b) = sum over groups (increasing) of the padded
-// element (slice(k, s), a, b).
+// element (slice(k, s), a, b).  With loss set, the blocks of row d instead
+// form loss = (fixed-order sum of the per-workgroup squared residuals) / M
+// (one wave).
 __global__ void reduce_acc_stage2(TTDev O, int R, const float *__restrict__ tmp, long long E,
-                                  int ngroups) {
+                                  int ngroups, const float *__restrict__ lpart, int nwg, long long M,
+                                  float *__restrict__ loss) {
   const int k = blockIdx.y;
-  if (k >= O.d) return;
+  if (k == O.d) {
+    if (!loss || blockIdx.x != 0 || threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    float v = 0.f;
+    for (int w = lane; w < nwg; w += 64) v += lpart[w];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) *loss = (M > 0) ? v / (float)M : 0.f;
+    return;
+  }
+  if (k > O.d) return;
   int sbase = 0;
   for (int j = 0; j < k; ++j) sbase += O.n[j];
   const int rk = O.r[k], nk = O.n[k], rk1 = O.r[k + 1];
@@ -1359,7 +1381,8 @@ int mfma_pad(const tt_tensor *Rt, const tt_tensor *Lt, int R, float *gpr, float 
 int mfma_unpad(const tt_tensor *O, int R, const float *padded, hipStream_t s) {
   long long E = 0;
   for (int k = 0; k < O->d; ++k) E += (long long)O->n[k] * R * R;
-  hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, make_dev(O), R, padded, E, 1);
+  hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, make_dev(O), R, padded, E, 1, nullptr, 0,
+                     0LL, nullptr);
   return launch_check("unpad gradients");
 }
 
@@ -1462,8 +1485,12 @@ int mfma_run(int mode, const tt_tensor *Lt, const tt_tensor *Rt, tt_tensor *O, c
     hipLaunchKernelGGL(reduce_acc_stage1, dim3((unsigned)((E + 255) / 256), ngroups), dim3(256), 0, s,
                        acc, g.acc_stride, g.nwg, E, rtmp);
     if ((rc = launch_check("reduce partial gradients"))) return rc;
-    hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d), dim3(256), 0, s, od, R, rtmp, E, ngroups);
+    // the MSE loss rides along as an extra row of blocks
+    const bool with_loss = mode == MODE_MSE && loss;
+    hipLaunchKernelGGL(reduce_acc_stage2, dim3(64, O->d + (with_loss ? 1 : 0)), dim3(256), 0, s, od, R, rtmp, E,
+                       ngroups, lacc, g.nwg, (long long)M, with_loss ? loss : nullptr);
     if ((rc = launch_check("reduce partial gradients (2)"))) return rc;
+    if (with_loss) return TT_OK;
   } else {
     if ((rc = mfma_unpad(O, R, grad, s))) return rc;
   }
