@@ -970,16 +970,19 @@ __device__ void build_suffix_rows(const TTDev &X, const SufBuild &sb, int blk) {
     if (l == 1) {
       if (a < rk) acc = G[0];  // column 0 (r_d = 1)
     } else {
-      // the row of G and the partner values are read before the sum, so
-      // the R loads of a level are in flight together
-      float gv[R], rv[R];
+      // the row of G and the partner values are read 16 at a time before
+      // their sum, so the loads of a chunk are in flight together
 #pragma unroll
-      for (int b = 0; b < R; ++b) {
-        gv[b] = (a < rk && b < rk1) ? G[b] : 0.f;
-        rv[b] = __shfl(rho, grp * R + b);
+      for (int b0 = 0; b0 < R; b0 += 16) {
+        float gv[16], rv[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          gv[b] = (a < rk && b0 + b < rk1) ? G[b0 + b] : 0.f;
+          rv[b] = __shfl(rho, grp * R + b0 + b);
+        }
+#pragma unroll
+        for (int b = 0; b < 16; ++b) acc = fmaf(gv[b], rv[b], acc);
       }
-#pragma unroll
-      for (int b = 0; b < R; ++b) acc = fmaf(gv[b], rv[b], acc);
     }
     rho = acc;
     if (live && sfx < sb.rows[l - 1]) sb.tab[((long long)sb.row0[l - 1] + sfx) * R + a] = rho;
@@ -997,7 +1000,8 @@ __global__ void pad_slices_kernel(TTDev Xr, TTDev Xl, int R, float *__restrict__
   if (slice >= total_slices) {
     if (sb.depth > 0 && slice - total_slices < sb.blocks) {
       if (R == 16) build_suffix_rows<16>(Xr, sb, slice - total_slices);
-      else build_suffix_rows<32>(Xr, sb, slice - total_slices);
+      else if (R == 32) build_suffix_rows<32>(Xr, sb, slice - total_slices);
+      else build_suffix_rows<64>(Xr, sb, slice - total_slices);
     }
     return;
   }
