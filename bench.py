@@ -73,6 +73,8 @@ def parse():
                     help="run only a plain device copy of known size (for HBM counter scaling)")
     ap.add_argument("--tables-only", action="store_true",
                     help="run only the table gather leg (for its kernel trace and HBM counters)")
+    ap.add_argument("--leg", choices=["batched", "tables", "gram", "riemann", "ttm", "table1", "completion"],
+                    help="run only this secondary measurement (for its kernel trace and counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (batched plan, Riemannian step, Gram, TT-matrix)")
     return ap.parse_args()
@@ -656,6 +658,13 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.leg:
+        torch.cuda.set_device(0)
+        tt.load()
+        legs = {"batched": batched_leg, "tables": tables_leg, "gram": gram_leg, "riemann": riemann_leg,
+                "ttm": ttm_leg, "table1": table1_leg, "completion": completion_leg}
+        print(json.dumps({args.leg: legs[args.leg](tt, W)}), flush=True)
         return
 
     torch.cuda.set_device(0)

@@ -81,6 +81,22 @@ def stats_markdown(path, top=12):
     return "\n".join(lines)
 
 
+def counters_markdown(dirs, kernels):
+    """Average per-dispatch value of every counter in the runs under dirs,
+    for each kernel whose name contains one of the substrings."""
+    lines = ["| kernel | counter | avg per dispatch | dispatches |", "|---|---|---|---|"]
+    merged = {}
+    for d in dirs:
+        for key, vs in counter_values(d).items():
+            merged.setdefault(key, []).extend(vs)
+    for sub in kernels:
+        for (name, ctr), vs in sorted(merged.items(), key=lambda kv: (kv[0][1], kv[0][0])):
+            if sub in name:
+                short = sub
+                lines.append("| %s | %s | %.4g | %d |" % (short, ctr, sum(vs) / len(vs), len(vs)))
+    return "\n".join(lines)
+
+
 def main(argv=None):
     import argparse
     import json
@@ -99,9 +115,14 @@ def main(argv=None):
     tr.add_argument("--copy-bytes", type=int, default=1 << 29)
     tr.add_argument("--sources", nargs="+", required=True)
     tr.add_argument("--alg-bytes", type=float, required=True)
+    ct = sub.add_parser("counters", help="markdown table of counter averages per kernel")
+    ct.add_argument("dirs", nargs="+")
+    ct.add_argument("--kernel", action="append", required=True, help="substring of a kernel name")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_markdown(a.dir, a.top))
+    elif a.cmd == "counters":
+        print(counters_markdown(a.dirs, a.kernel))
     else:
         rec = traffic_record(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes,
                              a.sources, a.alg_bytes, a.label)
