@@ -35,6 +35,7 @@ struct Shared {
   float sig[kJac];
   int perm[kJac];
   int rotated;
+  int wide;                 // Jacobi: some pair of the sweep had cos^2 above 1e-8
   float hv[2][64 * 10];     // register QR: broadcast Householder vector (double-buffered)
   float stg[64 * 65];       // staging chunk of the large GEMM operand
   float sm[64 * 65];        // the small GEMM factor, staged (row stride 65)
@@ -437,7 +438,11 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
   const int pr = wave + kWaves * slot;  // pair position of this row of lanes
   const bool live = pr < P / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (threadIdx.x == 0) sh.rotated = 0;
+    if (threadIdx.x == 0) {
+      sh.rotated = 0;
+      sh.wide = 0;
+    }
+    bool wide = false;  // this row met a pair with ga^2 > 1e-8 al be in the sweep
     __syncthreads();
     // position qa = pr pairs with qb = P-1-pr; every position other than 0
     // advances by one column per round
@@ -469,6 +474,7 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
       // 1 ulp each, so cs^2 + sn^2 = 1 to a few ulp), which shortens the
       // dependent chain of every round.  A rotating pair has ga^2 > 0, so
       // 1 / (2 ga) is finite and zeta is never 0 * inf.
+      wide |= on && ga * ga > 1e-8f * (al * be);
       if (on && ga * ga > 1e-12f * (al * be) && ga != 0.f) {
         const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
         const float tn = copysignf(1.f, zeta) *
@@ -493,9 +499,16 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
       pb = (pb == P - 1) ? 1 : pb + 1;
       __syncthreads();
     }
-    const int any = sh.rotated;
+    if ((lane & 15) == 0 && wide) sh.wide = 1;
+    __syncthreads();
+    const int any = sh.rotated, w = sh.wide;
     __syncthreads();
     if (!any) return sweep + 1;
+    // Cyclic Jacobi converges quadratically: after a sweep whose pairs were
+    // all within |cos| <= 1e-4 of orthogonal, the next sweep's pairs are
+    // within about 1e-8, below the 1e-6 rotation threshold, so that sweep
+    // would only confirm convergence.
+    if (!w) return sweep + 1;
   }
   return -1;  // not converged within 40 sweeps
 }
