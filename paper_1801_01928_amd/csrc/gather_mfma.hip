@@ -1040,7 +1040,16 @@ __global__ void reduce_acc_stage1(const float *__restrict__ acc, long long acc_s
   const int w0 = blockIdx.y * 32;
   const int w1 = (w0 + 32 < nwg) ? w0 + 32 : nwg;
   float v = 0.f;
-  for (int w = w0; w < w1; ++w) v += acc[(long long)w * acc_stride + e];
+  int w = w0;
+  // eight loads in flight at a time; the additions keep workgroup order
+  for (; w + 8 <= w1; w += 8) {
+    float x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = acc[(long long)(w + u) * acc_stride + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += x[u];
+  }
+  for (; w < w1; ++w) v += acc[(long long)w * acc_stride + e];
   tmp[(long long)blockIdx.y * E + e] = v;
 }
 
