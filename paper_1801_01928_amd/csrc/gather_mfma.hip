@@ -960,6 +960,52 @@ __device__ void build_suffix_rows(const TTDev &X, const SufBuild &sb, int blk) {
   const bool live = sfx < sb.rows[D - 1];
   int rem = live ? (int)sfx : 0;
   float rho = 0.f;
+  if constexpr (R <= 32) {
+    // Up to four levels, with coalesced loads: lane b of the group holds
+    // component b of rho and reads column b of the slice (rows a = 0..R-1 of
+    // G[:, i, :], R consecutive floats per row across the group), forms the
+    // products G[a][i][b] rho_b for every a, and a recursive-halving
+    // exchange over the group sums them so that lane a ends with
+    // sum_b G[a][i][b] rho_b.  Every level's loads are issued before the
+    // first product.  Level 1 starts from rho = e_0 (r_d = 1).
+    constexpr int DMAX = 4;
+    if (D <= DMAX) {
+      const int b = a;  // this lane's column
+      float gv[DMAX][R];
+#pragma unroll
+      for (int l = 1; l <= DMAX; ++l) {
+        if (l > D) break;
+        const int k = X.d - l;
+        const int nk = X.n[k], rk = X.r[k], rk1 = X.r[k + 1];
+        const int i = rem % nk;
+        rem /= nk;
+        const float *G = X.data + X.off[k] + (long long)i * rk1 + b;  // G[0][i][b]
+#pragma unroll
+        for (int r = 0; r < R; ++r) gv[l - 1][r] = (r < rk && b < rk1) ? G[(long long)r * nk * rk1] : 0.f;
+      }
+      float x = (b == 0) ? 1.f : 0.f;  // rho_b
+#pragma unroll
+      for (int l = 1; l <= DMAX; ++l) {
+        if (l > D) break;
+        float pv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) pv[r] = gv[l - 1][r] * x;
+#pragma unroll
+        for (int h = R / 2; h >= 1; h >>= 1) {
+          const bool upper = (b & h) != 0;  // keeps indices [h, 2h) of the live range
+#pragma unroll
+          for (int j = 0; j < h; ++j) {
+            const float keep = upper ? pv[j + h] : pv[j];
+            const float give = upper ? pv[j] : pv[j + h];
+            pv[j] = keep + __shfl_xor(give, h);
+          }
+        }
+        x = pv[0];  // component b of the new rho
+        if (live && sfx < sb.rows[l - 1]) sb.tab[((long long)sb.row0[l - 1] + sfx) * R + b] = x;
+      }
+      return;
+    }
+  }
   for (int l = 1; l <= D; ++l) {
     const int k = X.d - l;
     const int nk = X.n[k], rk = X.r[k], rk1 = X.r[k + 1];
@@ -994,8 +1040,8 @@ __device__ void build_suffix_rows(const TTDev &X, const SufBuild &sb, int blk) {
 // M[16 to + l%16][16 ti + 4 (l/16) + c], c < 4, with M = G for the right
 // sweep and M = G^T for the left sweep.  Workgroups past the slices build
 // the suffix table of Xr.
-__global__ void pad_slices_kernel(TTDev Xr, TTDev Xl, int R, float *__restrict__ right,
-                                  float *__restrict__ left, int total_slices, SufBuild sb) {
+__global__ void __launch_bounds__(256) pad_slices_kernel(TTDev Xr, TTDev Xl, int R, float *__restrict__ right,
+                                                        float *__restrict__ left, int total_slices, SufBuild sb) {
   const int slice = blockIdx.x;
   if (slice >= total_slices) {
     if (sb.depth > 0 && slice - total_slices < sb.blocks) {
