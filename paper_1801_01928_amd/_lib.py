@@ -160,8 +160,8 @@ def load(path=None):
         return _lib
     path = path or os.environ.get("TTGFX_LIB") or LIB_PATH
     if not os.path.exists(path):
-        raise RuntimeError("libttgfx.so not found at %s: run __graft_entry__.build() "
-                           "(or python paper_1801_01928_amd/build.py) first" % path)
+        raise RuntimeError("libttgfx.so not found at %s: build it first "
+                           "(python paper_1801_01928_amd/build.py)" % path)
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
