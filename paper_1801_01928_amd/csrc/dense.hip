@@ -23,6 +23,17 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
+
+// Elementwise work over a row-major rows x cols block: rows by wave (a
+// wave-uniform index, so per-row index arithmetic stays scalar), columns by
+// lane; no per-element division.
+template <class F>
+__device__ __forceinline__ void for_rows(int rows, int cols, F f) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int row = wave; row < rows; row += kWaves)
+    for (int c = lane; c < cols; c += 64) f(row, c);
+}
 constexpr int kJac = DENSE_MAX_RANK;  // Jacobi matrices are at most 64 x 64
 constexpr int kProjBatch = 64;        // tensors per launch of a batched projection
 
@@ -837,7 +848,11 @@ __global__ void __launch_bounds__(kThreads) round_kernel(TTDev Y, TTDev O, int m
       if (lane == 0) sh.sig[j] = (val < 0.f) ? -1.f : 1.f;  // reuse as the sign of column j
     }
     __syncthreads();
-    for (long e = threadIdx.x; e < (long)m * keep; e += kThreads) G[e] *= sh.sig[(int)(e % keep)];
+    {
+      const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      for (int i = wv; i < m; i += kWaves)
+        for (int j = lane; j < keep; j += 64) G[(long)i * keep + j] *= sh.sig[j];
+    }
     // next core <- (Sigma V^T)[kept] (keep x c) * next (c x n r'');
     // (Sigma V^T) row j = sign_j * column perm[j] of B V, transposed
     const int nn = n[k + 1] * r[k + 2];
@@ -879,11 +894,18 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
         const int ti = tile / nt, tj = tile % nt;
         const int ci = 16 * ti + c16, cj = 16 * tj + c16;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < m; k0 += 4) {
-          const int kr = k0 + q4;
-          const float av = (kr < m && ci < r1) ? Uk[(long)kr * r1 + ci] : 0.f;
-          const float bv = (kr < m && cj < r1) ? Zk[(long)kr * r1 + cj] : 0.f;
-          acc = mfma4(av, bv, acc);
+        // eight k-steps' operands are loaded before their products, so the
+        // loads of a group are in flight together
+        for (int k0 = 0; k0 < m; k0 += 32) {
+          float av[8], bv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int kr = k0 + 4 * u + q4;
+            av[u] = (kr < m && ci < r1) ? Uk[(long)kr * r1 + ci] : 0.f;
+            bv[u] = (kr < m && cj < r1) ? Zk[(long)kr * r1 + cj] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = mfma4(av[u], bv[u], acc);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -903,8 +925,9 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
   float *Wk = W.data + W.off[k];
   const int w0 = W.r[k], w1 = W.r[k + 1];
   const float *Vk = V.data + V.off[k];
-  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
-    const int b = (int)(e % w1), s = (int)((e / w1) % nk), a = (int)(e / ((long)w1 * nk));
+  for_rows(w0 * nk, w1, [&](int row, int b) {
+    const int a = row / nk, s = row - a * nk;
+    const long e = (long)row * w1 + b;
     float v = 0.f;
     if (k == 0) {  // [alpha dG, U]
       v = (b < r1) ? alpha * dG[(long)s * r1 + b] : Uk[(long)s * r1 + (b - r1)];
@@ -917,7 +940,7 @@ __global__ void __launch_bounds__(kThreads) tangent_kernel(TTDev U, TTDev V, TTD
       else v = Uk[((long)(a - r0) * nk + s) * r1 + (b - r1)];
     }
     Wk[e] = v;
-  }
+  });
 }
 
 // add_x X + alpha P_X(Z) from the tangent TT P = P_X(Z) that
@@ -935,8 +958,9 @@ __global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDe
   const float *Pk = P.data + P.off[k];
   float *Wk = W.data + W.off[k];
   const int w0 = W.r[k], w1 = W.r[k + 1];
-  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
-    const int b = (int)(e % w1), s = (int)((e / w1) % nk), a = (int)(e / ((long)w1 * nk));
+  for_rows(w0 * nk, w1, [&](int row, int b) {
+    const int a = row / nk, s = row - a * nk;
+    const long e = (long)row * w1 + b;
     float v = Pk[e];
     if (k == 0) {  // [dG, U]
       if (b < r1) v *= alpha;
@@ -946,7 +970,7 @@ __global__ void __launch_bounds__(kThreads) tangent_combine_kernel(TTDev U, TTDe
       if (a >= r0 && b < r1) v *= alpha;
     }
     Wk[e] = v;
-  }
+  });
 }
 
 // z[e] = (acc ? z[e] : 0) + sum_{i < nb} c[i] zp[i * stride + e], in order.
@@ -984,11 +1008,11 @@ __global__ void __launch_bounds__(kThreads) tangent_inner_kernel(TTDev U, TTDev 
     const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1], w1 = A.r[k + 1];
     const float *Ak = A.data + A.off[k];
     const float *Bk = B.data + B.off[k];
-    for (long e = threadIdx.x; e < (long)r0 * nk * r1; e += kThreads) {
-      const int b = (int)(e % r1), sl = (int)((e / r1) % nk), a = (int)(e / ((long)r1 * nk));
+    for_rows(r0 * nk, r1, [&](int row, int b) {
+      const int a = row / nk, sl = row - a * nk;
       const long o = dg_offset(k, r0, nk, w1, a, sl, b);
       acc = fmaf(Ak[o], Bk[o], acc);
-    }
+    });
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) out[0] = acc;
@@ -1006,8 +1030,9 @@ __global__ void __launch_bounds__(kThreads) tangent_axpby_kernel(TTDev U, TTDev 
   const float *Bk = B.data + B.off[k];
   float *Wk = W.data + W.off[k];
   const int w0 = W.r[k], w1 = W.r[k + 1];
-  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
-    const int b = (int)(e % w1), a = (int)(e / ((long)w1 * nk));
+  for_rows(w0 * nk, w1, [&](int row, int b) {
+    const int a = row / nk;
+    const long e = (long)row * w1 + b;
     bool dg;
     if (k == 0)
       dg = b < r1;
@@ -1017,7 +1042,7 @@ __global__ void __launch_bounds__(kThreads) tangent_axpby_kernel(TTDev U, TTDev 
       dg = a >= r0 && b < r1;
     const float va = Ak[e];
     Wk[e] = dg ? fmaf(ca, va, cb * Bk[e]) : va;
-  }
+  });
 }
 
 // Nonlinear conjugate gradients on tangent vectors (the Riemannian CG of
@@ -1047,8 +1072,9 @@ __global__ void __launch_bounds__(kThreads) cg_axpby_kernel(TTDev U, TTDev A, TT
   const float *Tk = T.data + T.off[k];
   float *Wk = W.data + W.off[k];
   const int w0 = W.r[k], w1 = W.r[k + 1];
-  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
-    const int bb = (int)(e % w1), a = (int)(e / ((long)w1 * nk));
+  for_rows(w0 * nk, w1, [&](int row, int bb) {
+    const int a = row / nk;
+    const long e = (long)row * w1 + bb;
     bool dg;
     if (k == 0)
       dg = bb < r1;
@@ -1058,7 +1084,7 @@ __global__ void __launch_bounds__(kThreads) cg_axpby_kernel(TTDev U, TTDev A, TT
       dg = a >= r0 && bb < r1;
     const float va = Ak[e];
     Wk[e] = dg ? fmaf(-1.f, va, b * Tk[e]) : va;
-  }
+  });
 }
 
 // When eta is not a descent direction (<xi, eta> >= 0), reset it to -xi:
@@ -1071,8 +1097,9 @@ __global__ void __launch_bounds__(kThreads) cg_restart_kernel(TTDev U, TTDev A, 
   const float *Ak = A.data + A.off[k];
   float *Wk = W.data + W.off[k];
   const int w0 = W.r[k], w1 = W.r[k + 1];
-  for (long e = threadIdx.x; e < (long)w0 * nk * w1; e += kThreads) {
-    const int bb = (int)(e % w1), a = (int)(e / ((long)w1 * nk));
+  for_rows(w0 * nk, w1, [&](int row, int bb) {
+    const int a = row / nk;
+    const long e = (long)row * w1 + bb;
     bool dg;
     if (k == 0)
       dg = bb < r1;
@@ -1082,7 +1109,7 @@ __global__ void __launch_bounds__(kThreads) cg_restart_kernel(TTDev U, TTDev A, 
       dg = a >= r0 && bb < r1;
     const float va = Ak[e];
     Wk[e] = dg ? -va : va;
-  }
+  });
   if (k == 0 && threadIdx.x == 0) {
     sc[1] = 0.f;
     sc[2] = 1.f;
@@ -1116,8 +1143,8 @@ __global__ void __launch_bounds__(256) tangent_pack_kernel(TTDev U, TTDev A0, Me
     base += sz;
   }
   const int r0 = U.r[k], nk = U.n[k], r1 = U.r[k + 1];
-  const long long l = e - base;
-  const int b = (int)(l % r1), sl = (int)((l / r1) % nk), a = (int)(l / ((long long)r1 * nk));
+  const int l = (int)(e - base);  // within one core
+  const int b = l % r1, sl = (l / r1) % nk, a = l / (r1 * nk);
   D[(long long)(i0 + blockIdx.y) * S + e] = src[A0.off[k] + dg_offset(k, r0, nk, A0.r[k + 1], a, sl, b)];
 }
 
