@@ -73,6 +73,36 @@ def test_suffix_table_gather_adjoint_fused(gpu_lib, depth_policy, case, depth):
     assert_adjoint(gF.numpy_cores(), grr, cores, cores, idx, gl, TOL, "fused depth %d" % depth)
 
 
+DEEP = [
+    # (seed, ns, ranks, M): small modes, so the table reaches past four levels
+    (27, [2] * 12, [1, 2, 4, 8, 16, 16, 16, 16, 16, 8, 4, 2, 1], 40000),
+    (28, [2] * 10, [1, 2, 4, 8, 16, 32, 16, 8, 4, 2, 1], 30000),   # rank class 32
+]
+
+
+@pytest.mark.parametrize("case", DEEP, ids=lambda c: "seed%d" % c[0])
+def test_suffix_table_deep(gpu_lib, depth_policy, case):
+    """Tables deeper than four levels (built one level at a time) against
+    the oracle: gather, adjoint and fused pass."""
+    tt = gpu_lib
+    seed, ns, ranks, M = case
+    depth_policy(15)
+    cores, idx, g = _case(seed, ns, ranks, M)
+    X = tt.TT.from_cores(cores)
+    depth = tt.suffix_depth(X, M)
+    print("deep suffix case", seed, "depth", depth, flush=True)
+    assert depth > 4
+    yr = oracle.gather(cores, idx)
+    assert_gather(tt.gather(X, idx).cpu().numpy(), yr, cores, idx, TOL)
+    gX = tt.gather_backward(X, idx, torch.from_numpy(g))
+    assert_adjoint(gX.numpy_cores(), oracle.gather_backward(cores, idx, g), cores, cores, idx, g, TOL, "adjoint")
+    t = (yr + 0.1 * g).astype(np.float32)
+    y2, loss, gF = tt.gather_mse_backward(X, idx, t)
+    lr, gl = oracle.mse_loss_and_grad(yr, t)
+    assert abs(float(loss.item()) - lr) <= TOL * lr
+    assert_adjoint(gF.numpy_cores(), oracle.gather_backward(cores, idx, gl), cores, cores, idx, gl, TOL, "fused")
+
+
 def test_suffix_table_projection(gpu_lib, depth_policy):
     """The sparse tangent projection (left sweep over U, right sweep and
     table over V) at the deepest table: element-wise against the oracle."""
