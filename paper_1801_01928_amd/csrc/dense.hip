@@ -24,15 +24,23 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 
-// Elementwise work over a row-major rows x cols block: rows by wave (a
-// wave-uniform index, so per-row index arithmetic stays scalar), columns by
-// lane; no per-element division.
+// Elementwise work over a row-major rows x cols block with no 64-bit
+// index division: at 64 columns or more, rows by wave (a wave-uniform
+// index) and columns by lane; below, each wave takes 64 / cols rows at a
+// time, every lane a fixed (row offset, column) pair computed once.
 template <class F>
 __device__ __forceinline__ void for_rows(int rows, int cols, F f) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int row = wave; row < rows; row += kWaves)
-    for (int c = lane; c < cols; c += 64) f(row, c);
+  if (cols >= 64) {
+    for (int row = wave; row < rows; row += kWaves)
+      for (int c = lane; c < cols; c += 64) f(row, c);
+  } else if (cols > 0) {
+    const int rpw = 64 / cols;  // rows per wave and step
+    const int sub = lane / cols, c = lane - sub * cols;
+    if (sub < rpw)
+      for (int row = wave * rpw + sub; row < rows; row += kWaves * rpw) f(row, c);
+  }
 }
 constexpr int kJac = DENSE_MAX_RANK;  // Jacobi matrices are at most 64 x 64
 constexpr int kProjBatch = 64;        // tensors per launch of a batched projection
