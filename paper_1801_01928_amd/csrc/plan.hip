@@ -45,28 +45,30 @@ struct ModeInfo {
   int total;
 };
 
-// padded operand-order slices of every tensor: grid (total slices, b)
+// padded operand-order slices of every tensor: grid (d, b), one block per
+// core, looping over its slices (one block per slice made the launch
+// dispatch-bound)
 __global__ void pad_batch_kernel(const PadMeta *__restrict__ meta, ModeInfo md, float *__restrict__ gp) {
   const PadMeta &m = meta[blockIdx.y];
-  const int slice = blockIdx.x;
-  int k = 0, base = 0;
-  while (k < md.d && slice >= base + md.n[k]) {
-    base += md.n[k];
-    ++k;
-  }
-  const int s = slice - base, R = m.R, NT = R / 16, nk = md.n[k];
+  const int k = blockIdx.x;
+  int base = 0;
+  for (int j = 0; j < k; ++j) base += md.n[j];
+  const int R = m.R, NT = R / 16, nk = md.n[k];
   const int r0 = m.r[k], r1 = m.r[k + 1];
-  float *right = gp + m.right + (long long)slice * R * R;
-  float *left = gp + m.left + (long long)slice * R * R;
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-    const int c = e & 3, lane = (e >> 2) & 63, x = e >> 8;
-    const int to = x / NT, ti = x % NT;
-    const int row = 16 * to + (lane & 15), col = 16 * ti + 4 * (lane >> 4) + c;
-    float vr = 0.f, vl = 0.f;
-    if (row < r0 && col < r1) vr = m.data[m.off[k] + ((long long)row * nk + s) * r1 + col];
-    if (col < r0 && row < r1) vl = m.data[m.off[k] + ((long long)col * nk + s) * r1 + row];
-    right[e] = vr;
-    left[e] = vl;
+  const float *G = m.data + m.off[k];
+  for (int s = 0; s < nk; ++s) {
+    float *right = gp + m.right + (long long)(base + s) * R * R;
+    float *left = gp + m.left + (long long)(base + s) * R * R;
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+      const int c = e & 3, lane = (e >> 2) & 63, x = e >> 8;
+      const int to = x / NT, ti = x % NT;
+      const int row = 16 * to + (lane & 15), col = 16 * ti + 4 * (lane >> 4) + c;
+      float vr = 0.f, vl = 0.f;
+      if (row < r0 && col < r1) vr = G[(row * nk + s) * r1 + col];
+      if (col < r0 && row < r1) vl = G[(col * nk + s) * r1 + row];
+      right[e] = vr;
+      left[e] = vl;
+    }
   }
 }
 
@@ -77,12 +79,11 @@ __global__ void unpad_batch_kernel(const PadMeta *__restrict__ meta, ModeInfo md
   int sbase = 0;
   for (int j = 0; j < k; ++j) sbase += md.n[j];
   const int rk = m.r[k], nk = md.n[k], rk1 = m.r[k + 1];
-  const long long total = (long long)rk * nk * rk1;
+  const int total = rk * nk * rk1;  // one core: ranks and mode sizes of a plan are at most 32
   const float *g = gp + m.grad;
-  for (long long e = threadIdx.x; e < total; e += blockDim.x) {
-    const int b = (int)(e % rk1);
-    const int s = (int)((e / rk1) % nk);
-    const int a = (int)(e / ((long long)rk1 * nk));
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int b = e % rk1, t = e / rk1;
+    const int s = t % nk, a = t / nk;
     m.out[m.out_off[k] + e] = g[((long long)(sbase + s) * R + a) * R + b];
   }
 }
@@ -191,7 +192,7 @@ int build_items(tt_plan *P) {
 }
 
 int issue(tt_plan *P, hipStream_t s) {
-  hipLaunchKernelGGL(pad_batch_kernel, dim3(P->md.total, P->b), dim3(256), 0, s, P->dmeta, P->md, P->gp);
+  hipLaunchKernelGGL(pad_batch_kernel, dim3(P->md.d, P->b), dim3(256), 0, s, P->dmeta, P->md, P->gp);
   int rc = launch_check("plan: pad slices");
   if (rc) return rc;
   if ((rc = fill_zero(P->gp + P->grad_begin, P->grad_floats, s))) return rc;
