@@ -484,10 +484,15 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           compute(j, xd[S]);
           __builtin_amdgcn_sched_barrier(0);
         };
-        for (int j = jb; j < je; j += 2) {
+        // whole pairs in the loop and an odd last block after it: no exit
+        // between the two steps of a pair, so the memory-counter waits at
+        // the loop head see the same outstanding loads on every path
+        int j = jb;
+        for (; j + 1 < je; j += 2) {
           step(j, std::integral_constant<int, 0>{});
-          if (j + 1 < je) step(j + 1, std::integral_constant<int, 1>{});
+          step(j + 1, std::integral_constant<int, 1>{});
         }
+        if (j < je) step(j, std::integral_constant<int, 0>{});
       };
       using T1 = std::true_type;
       using F0 = std::false_type;
@@ -757,10 +762,12 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
         __builtin_amdgcn_sched_barrier(0);
         ld_glob(j + 2, xg[S]);
       };
-      for (int j = jb; j < je; j += 2) {
+      int j = jb;  // whole pairs, then an odd last block (as in the right sweep)
+      for (; j + 1 < je; j += 2) {
         step(j, std::integral_constant<int, 0>{});
-        if (j + 1 < je) step(j + 1, std::integral_constant<int, 1>{});
+        step(j + 1, std::integral_constant<int, 1>{});
       }
+      if (j < je) step(j, std::integral_constant<int, 0>{});
     };
     if (jb < je) {
       if (k < d - 1) {
