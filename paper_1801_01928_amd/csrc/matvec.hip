@@ -82,6 +82,7 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev<T> W, RightDe
 // r_{k+1} s_{k+1} elements.  The host takes this path when both slices fit
 // in kMvLdsFloats for every core.
 constexpr int kMvLdsBytes = 65536;  // 64 KB of dynamic LDS
+constexpr long long kMvMinRowBlocks = 2048;  // about eight workgroups per CU of a 256-CU device
 template <class T>
 __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -116,23 +117,83 @@ __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, Rig
   }
 }
 
-// Launches the product kernels for `members` right factors: the LDS path
-// when every core's two slices fit, else the grid-stride kernel.
+// Row-block LDS path: one workgroup per (core, member, a, l) stages all of
+// W_k[a, :, :, :] and the l-slice of x_k once and writes the m_k s_k output
+// rows (i, b) of that (a, l), each a contiguous run of r_{k+1} s_{k+1}
+// elements: a tenth of the workgroups of the per-(a, i) path at Table 1's
+// shape, and one staging of the x slice per m_k rows.  Threads take fixed
+// output columns (col = t mod R', computed once) and walk the rows.
+template <class T>
+__global__ void __launch_bounds__(kMvThreads) matvec_rows_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
+  extern __shared__ __align__(16) char lds_raw[];
+  T *lds = (T *)lds_raw;
+  const int k = blockIdx.y;
+  const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
+  const int mk = W.m[k], nk = W.n[k], lk = X0.L[k];
+  const unsigned groups = (unsigned)r0 * lk;
+  if (blockIdx.x >= groups) return;  // uniform over the workgroup, before any barrier
+  const unsigned a = blockIdx.x / lk, l = blockIdx.x - a * lk;
+  const int wn = mk * nk * r1;
+  T *ws = lds, *xs = lds + wn;
+  const T *wsrc = W.data + W.off[k] + (long long)a * wn;
+  for (int e = threadIdx.x; e < wn; e += kMvThreads) ws[e] = wsrc[e];
+  const T *xm = io.x[blockIdx.z] + X0.off[k];
+  const int xn = s0 * nk * s1;
+  for (int e = threadIdx.x; e < xn; e += kMvThreads) {
+    const int bp = e % s1, u = e / s1;  // u = b n_k + j
+    xs[e] = xm[((long long)u * lk + l) * s1 + bp];
+  }
+  __syncthreads();
+  const int R1 = r1 * s1;
+  const int rows = mk * s0;  // (i, b) pairs of this (a, l)
+  const int per = kMvThreads / R1;  // rows per pass (R1 <= kMvThreads on this path)
+  const int t = threadIdx.x;
+  const int col = t % R1, ib0 = t / R1;
+  if (ib0 >= per) return;  // after the only barrier
+  const int ap = col / s1, bp = col - ap * s1;
+  T *yk = io.y[blockIdx.z] + Y0.off[k];
+  for (int ib = ib0; ib < rows; ib += per) {
+    const int i = ib / s0, b = ib - i * s0;
+    const T *wi = ws + i * nk * r1 + ap;
+    const T *xb = xs + b * nk * s1 + bp;
+    T acc = T(0);
+    for (int j = 0; j < nk; ++j) acc = fma(wi[j * r1], xb[j * s1], acc);
+    const long long row = (long long)a * s0 + b;
+    yk[((row * mk + i) * lk + l) * R1 + col] = acc;
+  }
+}
+
+// Launches the product kernels for `members` right factors: the row-block
+// LDS path when every core's staged slices fit, its output rows fit a
+// workgroup's threads and its grid fills the chip, else the per-(a, i) LDS
+// path when its two slices fit, else the grid-stride kernel.
 template <class T>
 int launch_products(const MatDev<T> &md, const RightDev &x0, const OutDev &y0, const MvIO<T> &io, int members,
                     hipStream_t s) {
-  long long maxcnt = 0, maxpairs = 0, maxlds = 0;
+  long long maxcnt = 0, maxpairs = 0, maxlds = 0, maxgroups = 0, maxrowlds = 0, maxR1 = 0;
   for (int k = 0; k < md.d; ++k) {
     const long long r0 = md.r[k], r1 = md.r[k + 1], s0 = x0.r[k], s1 = x0.r[k + 1];
     const long long c = r0 * s0 * md.m[k] * x0.L[k] * r1 * s1;
     const long long p = r0 * md.m[k] * x0.L[k];
     const long long f = (long long)md.n[k] * r1 + s0 * md.n[k] * s1;
+    const long long g = r0 * x0.L[k];
+    const long long fr = (long long)md.m[k] * md.n[k] * r1 + s0 * md.n[k] * s1;
     maxcnt = c > maxcnt ? c : maxcnt;
     maxpairs = p > maxpairs ? p : maxpairs;
     maxlds = f > maxlds ? f : maxlds;
+    maxgroups = g > maxgroups ? g : maxgroups;
+    maxrowlds = fr > maxrowlds ? fr : maxrowlds;
+    maxR1 = r1 * s1 > maxR1 ? r1 * s1 : maxR1;
   }
   if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "product: an output core of 2^31 or more elements");
-  if (maxlds * (long long)sizeof(T) <= kMvLdsBytes && maxpairs <= 0x7fffffffLL) {
+  // the row-block grid is m_k times coarser: it needs enough workgroups to
+  // fill the chip (a single TT-matrix product does not have them)
+  const bool rows_fill = maxgroups * md.d * members >= kMvMinRowBlocks;
+  if (rows_fill && maxrowlds * (long long)sizeof(T) <= kMvLdsBytes && maxR1 <= kMvThreads &&
+      maxgroups <= 0x7fffffffLL) {
+    hipLaunchKernelGGL(matvec_rows_kernel<T>, dim3((unsigned)maxgroups, (unsigned)md.d, (unsigned)members),
+                       dim3(kMvThreads), (size_t)maxrowlds * sizeof(T), s, md, x0, y0, io);
+  } else if (maxlds * (long long)sizeof(T) <= kMvLdsBytes && maxpairs <= 0x7fffffffLL) {
     hipLaunchKernelGGL(matvec_lds_kernel<T>, dim3((unsigned)maxpairs, (unsigned)md.d, (unsigned)members),
                        dim3(kMvThreads), (size_t)maxlds * sizeof(T), s, md, x0, y0, io);
   } else {

@@ -206,8 +206,9 @@ MATVEC_CASES = [
     (40, [2, 3, 5], [3, 4, 2], [1, 3, 4, 1], [1, 2, 5, 1], 3),     # ragged modes and ranks
     (41, [7], [5], [1, 1], [1, 1], 2),                              # d = 1: a dense matvec
     (42, [3, 2, 2], [2, 2, 3], [1, 2, 2, 1], [1, 2, 3, 1], 65),     # two launches of 64 + 1
-    (43, [10] * 10, [10] * 10, [1] + [10] * 9 + [1], [1] + [10] * 9 + [1], 2),  # d=10, rank 10 x 10
+    (43, [10] * 10, [10] * 10, [1] + [10] * 9 + [1], [1] + [10] * 9 + [1], 21),  # d=10, rank 10 x 10: row-block path
     (46, [3, 3, 3], [8, 8, 8], [1, 2, 2, 1], [1, 64, 64, 1], 2),   # x core 64x8x64: beyond LDS, grid-stride path
+    (47, [4, 3], [3, 4], [1, 20, 1], [1, 16, 1], 2),            # output rows of 320: the per-(a, i) LDS path
 ]
 
 
