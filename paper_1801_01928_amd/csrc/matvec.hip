@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev<T> W, RightDe
 // in kMvLdsFloats for every core.
 constexpr int kMvLdsBytes = 65536;  // 64 KB of dynamic LDS
 constexpr long long kMvMinRowBlocks = 2048;  // about eight workgroups per CU of a 256-CU device
+constexpr int kMvMaxN = 16;  // row-block path: W columns of up to this many n_k held in registers
 template <class T>
 __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -145,14 +146,33 @@ __global__ void __launch_bounds__(kMvThreads) matvec_rows_kernel(MatDev<T> W, Ri
   }
   __syncthreads();
   const int R1 = r1 * s1;
-  const int rows = mk * s0;  // (i, b) pairs of this (a, l)
-  const int per = kMvThreads / R1;  // rows per pass (R1 <= kMvThreads on this path)
+  const int per = kMvThreads / R1;  // row offsets per pass (R1 <= kMvThreads on this path)
   const int t = threadIdx.x;
-  const int col = t % R1, ib0 = t / R1;
-  if (ib0 >= per) return;  // after the only barrier
+  const int col = t % R1, q0 = t / R1;
+  if (q0 >= per) return;  // after the only barrier
   const int ap = col / s1, bp = col - ap * s1;
   T *yk = io.y[blockIdx.z] + Y0.off[k];
-  for (int ib = ib0; ib < rows; ib += per) {
+  if (nk <= kMvMaxN) {
+    // rows by i, then b = q0, q0 + per, ...: the thread's W column of each
+    // i sits in registers and serves all of its rows b
+    for (int i = 0; i < mk; ++i) {
+      T wcol[kMvMaxN];
+      const T *wi = ws + i * nk * r1 + ap;
+#pragma unroll
+      for (int j = 0; j < kMvMaxN; ++j) wcol[j] = (j < nk) ? wi[j * r1] : T(0);
+      for (int b = q0; b < s0; b += per) {
+        const T *xb = xs + b * nk * s1 + bp;
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < kMvMaxN; ++j)
+          if (j < nk) acc = fma(wcol[j], xb[j * s1], acc);
+        const long long row = (long long)a * s0 + b;
+        yk[((row * mk + i) * lk + l) * R1 + col] = acc;
+      }
+    }
+    return;
+  }
+  for (int ib = q0; ib < mk * s0; ib += per) {
     const int i = ib / s0, b = ib - i * s0;
     const T *wi = ws + i * nk * r1 + ap;
     const T *xb = xs + b * nk * s1 + bp;
