@@ -31,7 +31,7 @@ struct NormLds {
 template <class T>
 __global__ void __launch_bounds__(kNormThreads) norm_kernel(TTDev A0, NormPtrs<T> np, int j0, T *__restrict__ out) {
   constexpr int TN = NormLds<T>::TN;
-  __shared__ T M[kNormRank * kNormRank], N[kNormRank * kNormRank], Tq[TN];
+  __shared__ T M[kNormRank * kNormRank], N[kNormRank * kNormRank], Tq[TN], Gs[TN];
   const T *src = np.p[blockIdx.x];
   if (threadIdx.x == 0) M[0] = T(1);
   __syncthreads();
@@ -42,11 +42,20 @@ __global__ void __launch_bounds__(kNormThreads) norm_kernel(TTDev A0, NormPtrs<T
     for (int e = threadIdx.x; e < r1 * r1; e += kNormThreads) N[e] = T(0);
     for (int i0 = 0; i0 < nk; i0 += g) {
       const int gi = (nk - i0) < g ? (nk - i0) : g;
+      // the group's slices G_k[:, i0 .. i0 + gi, :] staged once (r0 runs of
+      // gi r1 contiguous elements), Gs[(b gi + q) r1 + c]; both products
+      // below then read LDS only
+      const int run = gi * r1;
+      for (int e = threadIdx.x; e < r0 * run; e += kNormThreads) {
+        const int b = e / run, w = e - b * run;
+        Gs[e] = G[((long long)b * nk + i0) * r1 + w];
+      }
+      __syncthreads();
       // T_q (r0 x r1) = M (r0 x r0) G_k[i0 + q] (r0 x r1)
       for (int e = threadIdx.x; e < gi * rr; e += kNormThreads) {
         const int q = e / rr, rem = e - q * rr, a = rem / r1, c = rem - a * r1;
         T acc = T(0);
-        for (int b = 0; b < r0; ++b) acc = fma(M[a * r0 + b], G[((long long)b * nk + i0 + q) * r1 + c], acc);
+        for (int b = 0; b < r0; ++b) acc = fma(M[a * r0 + b], Gs[(b * gi + q) * r1 + c], acc);
         Tq[e] = acc;
       }
       __syncthreads();
@@ -55,8 +64,7 @@ __global__ void __launch_bounds__(kNormThreads) norm_kernel(TTDev A0, NormPtrs<T
         const int c = e / r1, f = e - c * r1;
         T acc = N[e];
         for (int q = 0; q < gi; ++q)
-          for (int a = 0; a < r0; ++a)
-            acc = fma(G[((long long)a * nk + i0 + q) * r1 + c], Tq[q * rr + a * r1 + f], acc);
+          for (int a = 0; a < r0; ++a) acc = fma(Gs[(a * gi + q) * r1 + c], Tq[q * rr + a * r1 + f], acc);
         N[e] = acc;
       }
       __syncthreads();
