@@ -188,6 +188,23 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
+// Three row sums at once, their steps interleaved so that no DPP read waits
+// on the add just before it.
+__device__ __forceinline__ void row16_sum3(float &x, float &y, float &z) {
+  x += dpp_f<0xB1>(x);
+  y += dpp_f<0xB1>(y);
+  z += dpp_f<0xB1>(z);
+  x += dpp_f<0x4E>(x);
+  y += dpp_f<0x4E>(y);
+  z += dpp_f<0x4E>(z);
+  x += dpp_f<0x141>(x);
+  y += dpp_f<0x141>(y);
+  z += dpp_f<0x141>(z);
+  x += dpp_f<0x140>(x);
+  y += dpp_f<0x140>(y);
+  z += dpp_f<0x140>(z);
+}
+
 // Sums over the 64 lanes of N values at once, returned wave-uniform: each
 // butterfly stage of wave_sum runs on all N values before the next, so the
 // N dependent chains overlap instead of running back to back.
@@ -440,10 +457,17 @@ __device__ void qr_thin(Load load, int m, int c, float *Wm, float *tau, float *Q
 
 // One-sided Jacobi on the columns of sh.jb (rows x cols, ld = kJac); sh.jv
 // accumulates the rotations (cols x cols).  On return the columns of jb are
-// mutually orthogonal (jb = B V) and V is orthogonal.  Round-robin pairing:
-// every round rotates up to 32 disjoint column pairs, 4 per wave, one pair
-// per row of 16 lanes with 4 matrix rows per lane (jb and jv are zero beyond
-// rows and cols, so whole columns of 64 are rotated).
+// mutually orthogonal (jb = B V) and V is orthogonal.  Block-cyclic order:
+// the columns form nb blocks of 4 (nb even).  In each of a sweep's nb - 1
+// super-rounds a round-robin tournament hands wave w one pair of blocks, and
+// the wave rotates the 16 column pairs between them in 4 rounds of 4
+// disjoint pairs (in the first super-round also the 6 pairs inside each of
+// its two blocks, in 3 more rounds).  A row of 16 lanes takes one pair, with
+// 4 matrix rows per lane (jb and jv are zero beyond rows and cols, so whole
+// columns of 64 are rotated).  Inside a super-round no other wave touches
+// the wave's blocks and a wave's LDS accesses complete in issue order, so
+// only the super-rounds end with a workgroup barrier: nb - 1 barriers per
+// sweep instead of one per round.
 __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
   (void)rows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -452,10 +476,10 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
     sh.jv[e] = (i == j) ? 1.f : 0.f;
   }
   __syncthreads();
-  const int P = (cols + 1) & ~1;
+  int nb = (cols + 3) >> 2;
+  nb += nb & 1;  // at most kJac / 4 = 2 kWaves blocks
   const int slot = lane >> 4, c4 = 4 * (lane & 15);
-  const int pr = wave + kWaves * slot;  // pair position of this row of lanes
-  const bool live = pr < P / 2;
+  const bool live = wave < nb / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) {
       sh.rotated = 0;
@@ -463,59 +487,78 @@ __device__ int blk_jacobi(int rows, int cols, Shared &sh) {
     }
     bool wide = false;  // this row met a pair with ga^2 > 1e-8 al be in the sweep
     __syncthreads();
-    // position qa = pr pairs with qb = P-1-pr; every position other than 0
-    // advances by one column per round
-    int pa = pr, pb = P - 1 - pr;
-    for (int round = 0; round < P - 1; ++round) {
-      const bool on = live && pa < cols && pb < cols;
-      const int ca = on ? pa : 0, cb = on ? pb : 0;
-      const v4f xa = *(const v4f *)(sh.jb + ca * kJac + c4);
-      const v4f xb = *(const v4f *)(sh.jb + cb * kJac + c4);
-      const v4f ya = *(const v4f *)(sh.jv + ca * kJac + c4);
-      const v4f yb = *(const v4f *)(sh.jv + cb * kJac + c4);
-      float al = 0.f, be = 0.f, ga = 0.f;
+    // block position ba = w pairs with bb = nb-1-w; every position other
+    // than 0 advances by one block per super-round
+    int ba = wave, bb = nb - 1 - wave;
+    for (int sr = 0; sr < nb - 1; ++sr) {
+      if (live) {
+        const int nloc = sr == 0 ? 7 : 4;
+        for (int t = 0; t < nloc; ++t) {
+          int pa, pb;
+          if (sr == 0 && t < 3) {
+            // inside a block: rows 0, 1 of lanes in block ba, rows 2, 3 in
+            // bb; pairs (0,1)(2,3), then (0,2)(1,3), then (0,3)(1,2)
+            const int blk = slot < 2 ? ba : bb, h = slot & 1;
+            const int i = t == 0 ? 2 * h : h;
+            const int j = t == 0 ? 2 * h + 1 : (t == 1 ? h + 2 : 3 - h);
+            pa = 4 * blk + i;
+            pb = 4 * blk + j;
+          } else {
+            const int sh4 = sr == 0 ? t - 3 : t;
+            pa = 4 * ba + slot;
+            pb = 4 * bb + ((slot + sh4) & 3);
+          }
+          const bool on = pa < cols && pb < cols;
+          const v4f xa = *(const v4f *)(sh.jb + pa * kJac + c4);
+          const v4f xb = *(const v4f *)(sh.jb + pb * kJac + c4);
+          const v4f ya = *(const v4f *)(sh.jv + pa * kJac + c4);
+          const v4f yb = *(const v4f *)(sh.jv + pb * kJac + c4);
+          float al = 0.f, be = 0.f, ga = 0.f;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        al = fmaf(xa[v], xa[v], al);
-        be = fmaf(xb[v], xb[v], be);
-        ga = fmaf(xa[v], xb[v], ga);
-      }
-      // the rotation's V columns were read with the B columns; this empty
-      // use keeps the compiler from sinking those reads into the branch
-      // below, which would add a second LDS round trip to every round
-      asm volatile("" ::"v"(ya), "v"(yb));
-      al = row16_sum(al);
-      be = row16_sum(be);
-      ga = row16_sum(ga);
-      // every lane of the row takes the same decision
-      // |ga| > 1e-6 sqrt(al be), compared squared; the rotation uses the
-      // hardware reciprocal, square root and reciprocal square root (about
-      // 1 ulp each, so cs^2 + sn^2 = 1 to a few ulp), which shortens the
-      // dependent chain of every round.  A rotating pair has ga^2 > 0, so
-      // 1 / (2 ga) is finite and zeta is never 0 * inf.
-      wide |= on && ga * ga > 1e-8f * (al * be);
-      if (on && ga * ga > 1e-12f * (al * be) && ga != 0.f) {
-        const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
-        const float tn = copysignf(1.f, zeta) *
-                         __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.f)));
-        const float cs = __builtin_amdgcn_rsqf(fmaf(tn, tn, 1.f));
-        const float sn = cs * tn;
-        v4f na, nb, ma, mb;
+          for (int v = 0; v < 4; ++v) {
+            al = fmaf(xa[v], xa[v], al);
+            be = fmaf(xb[v], xb[v], be);
+            ga = fmaf(xa[v], xb[v], ga);
+          }
+          // the rotation's V columns were read with the B columns; this
+          // empty use keeps the compiler from sinking those reads into the
+          // branch below, which would add a second LDS round trip
+          asm volatile("" ::"v"(ya), "v"(yb));
+          row16_sum3(al, be, ga);
+          // every lane of the row takes the same decision
+          // |ga| > 1e-6 sqrt(al be), compared squared; the rotation uses the
+          // hardware reciprocal, square root and reciprocal square root
+          // (about 1 ulp each, so cs^2 + sn^2 = 1 to a few ulp), which
+          // shortens the dependent chain of every round.  A rotating pair
+          // has ga^2 > 0, so 1 / (2 ga) is finite and zeta is never 0 * inf.
+          wide |= on && ga * ga > 1e-8f * (al * be);
+          if (on && ga * ga > 1e-12f * (al * be) && ga != 0.f) {
+            const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
+            const float tn = copysignf(1.f, zeta) *
+                             __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.f)));
+            const float cs = __builtin_amdgcn_rsqf(fmaf(tn, tn, 1.f));
+            const float sn = cs * tn;
+            v4f na, nb4, ma, mb;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          na[v] = cs * xa[v] - sn * xb[v];
-          nb[v] = sn * xa[v] + cs * xb[v];
-          ma[v] = cs * ya[v] - sn * yb[v];
-          mb[v] = sn * ya[v] + cs * yb[v];
+            for (int v = 0; v < 4; ++v) {
+              na[v] = cs * xa[v] - sn * xb[v];
+              nb4[v] = sn * xa[v] + cs * xb[v];
+              ma[v] = cs * ya[v] - sn * yb[v];
+              mb[v] = sn * ya[v] + cs * yb[v];
+            }
+            *(v4f *)(sh.jb + pa * kJac + c4) = na;
+            *(v4f *)(sh.jb + pb * kJac + c4) = nb4;
+            *(v4f *)(sh.jv + pa * kJac + c4) = ma;
+            *(v4f *)(sh.jv + pb * kJac + c4) = mb;
+            if ((lane & 15) == 0) sh.rotated = 1;
+          }
+          // the next round reads columns that other rows of this wave just
+          // wrote: keep the compiler from moving LDS accesses across rounds
+          asm volatile("" ::: "memory");
         }
-        *(v4f *)(sh.jb + pa * kJac + c4) = na;
-        *(v4f *)(sh.jb + pb * kJac + c4) = nb;
-        *(v4f *)(sh.jv + pa * kJac + c4) = ma;
-        *(v4f *)(sh.jv + pb * kJac + c4) = mb;
-        if ((lane & 15) == 0) sh.rotated = 1;
       }
-      if (pa != 0) pa = (pa == P - 1) ? 1 : pa + 1;
-      pb = (pb == P - 1) ? 1 : pb + 1;
+      if (ba != 0) ba = (ba == nb - 1) ? 1 : ba + 1;
+      bb = (bb == nb - 1) ? 1 : bb + 1;
       __syncthreads();
     }
     if ((lane & 15) == 0 && wide) sh.wide = 1;
