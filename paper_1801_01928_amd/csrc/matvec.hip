@@ -80,10 +80,60 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev<T> W, RightDe
 // core (s_k x n_k x s_{k+1}) are staged in LDS once; the workgroup then
 // writes the s_k rows (a, b) at (i, l), each a contiguous run of
 // r_{k+1} s_{k+1} elements.  The host takes this path when both slices fit
-// in kMvLdsFloats for every core.
+// in kMvLdsBytes for every core.
 constexpr int kMvLdsBytes = 65536;  // 64 KB of dynamic LDS
 constexpr long long kMvMinRowBlocks = 2048;  // about eight workgroups per CU of a 256-CU device
 constexpr int kMvMaxN = 16;  // row-block path: W columns of up to this many n_k held in registers
+
+// Stages the l-slice of a right-factor core, s_k n_k runs of s_{k+1}
+// elements (run u = b n_k + j starts at (u L_k + l) s_{k+1}), into xs: each
+// thread keeps one position in the run, so no division per element.
+// Up to kMvStage loads per thread are issued before their LDS stores, so a
+// workgroup waits for one round trip to memory per kMvStage elements.
+constexpr int kMvStage = 8;
+template <class T>
+__device__ __forceinline__ void stage_x_slice(T *xs, const T *xm, int runs, int s1, int lk, int l) {
+  if (s1 <= kMvThreads) {
+    const int rpp = kMvThreads / s1;  // runs per pass
+    const int u0 = threadIdx.x / s1, bp = threadIdx.x - u0 * s1;
+    if (u0 < rpp)
+      for (int ub = u0; ub < runs; ub += rpp * kMvStage) {
+        T v[kMvStage];
+#pragma unroll
+        for (int q = 0; q < kMvStage; ++q) {
+          const int u = ub + q * rpp;
+          v[q] = (u < runs) ? xm[((long long)u * lk + l) * s1 + bp] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kMvStage; ++q) {
+          const int u = ub + q * rpp;
+          if (u < runs) xs[u * s1 + bp] = v[q];
+        }
+      }
+  } else {
+    for (int u = 0; u < runs; ++u)
+      for (int bp = threadIdx.x; bp < s1; bp += kMvThreads) xs[u * s1 + bp] = xm[((long long)u * lk + l) * s1 + bp];
+  }
+}
+
+// Contiguous staging of n elements (W slices), kMvStage loads in flight.
+template <class T>
+__device__ __forceinline__ void stage_run(T *dst, const T *src, int n) {
+  for (int eb = threadIdx.x; eb < n; eb += kMvThreads * kMvStage) {
+    T v[kMvStage];
+#pragma unroll
+    for (int q = 0; q < kMvStage; ++q) {
+      const int e = eb + q * kMvThreads;
+      v[q] = (e < n) ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kMvStage; ++q) {
+      const int e = eb + q * kMvThreads;
+      if (e < n) dst[e] = v[q];
+    }
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -97,53 +147,71 @@ __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, Rig
   const unsigned a = t / mk, i = t - a * mk;
   T *ws = lds, *xs = lds + nk * r1;
   const T *wsrc = W.data + W.off[k] + ((long long)a * mk + i) * nk * r1;
-  for (int e = threadIdx.x; e < nk * r1; e += kMvThreads) ws[e] = wsrc[e];
-  const T *xm = io.x[blockIdx.z] + X0.off[k];
-  const int xn = s0 * nk * s1;
-  for (int e = threadIdx.x; e < xn; e += kMvThreads) {
-    const int bp = e % s1, u = e / s1;  // u = b n_k + j
-    xs[e] = xm[((long long)u * lk + l) * s1 + bp];
-  }
+  stage_run(ws, wsrc, nk * r1);
+  stage_x_slice(xs, io.x[blockIdx.z] + X0.off[k], s0 * nk, s1, lk, (int)l);
   __syncthreads();
   const int R1 = r1 * s1;
-  T *yk = io.y[blockIdx.z] + Y0.off[k];
+  // row b of this (a, i, l) starts at ((((a s_k + b) m_k + i) L_k + l) R'
+  const long long rstride = (long long)mk * lk * R1;
+  T *yb0 = io.y[blockIdx.z] + Y0.off[k] + (((long long)a * s0 * mk + i) * lk + l) * R1;
+  if (R1 <= kMvThreads && nk <= kMvMaxN) {
+    // fixed output column per thread: its W column sits in registers and
+    // serves rows b = q0, q0 + per, ...
+    const int per = kMvThreads / R1;
+    const int col = threadIdx.x % R1, q0 = threadIdx.x / R1;
+    if (q0 >= per) return;  // after the only barrier
+    const int ap = col / s1, bp = col - ap * s1;
+    T wcol[kMvMaxN];
+#pragma unroll
+    for (int j = 0; j < kMvMaxN; ++j) wcol[j] = (j < nk) ? ws[j * r1 + ap] : T(0);
+    for (int b = q0; b < s0; b += per) {
+      const T *xb = xs + b * nk * s1 + bp;
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < kMvMaxN; ++j)
+        if (j < nk) acc = fma(wcol[j], xb[j * s1], acc);
+      yb0[b * rstride + col] = acc;
+    }
+    return;
+  }
   for (int o = threadIdx.x; o < s0 * R1; o += kMvThreads) {
     const int b = o / R1, col = o - b * R1;
     const int ap = col / s1, bp = col - ap * s1;
     const T *xb = xs + b * nk * s1 + bp;
     T acc = T(0);
     for (int j = 0; j < nk; ++j) acc = fma(ws[j * r1 + ap], xb[j * s1], acc);
-    const long long row = (long long)a * s0 + b;
-    yk[((row * mk + i) * lk + l) * R1 + col] = acc;
+    yb0[b * rstride + col] = acc;
   }
 }
 
-// Row-block LDS path: one workgroup per (core, member, a, l) stages all of
-// W_k[a, :, :, :] and the l-slice of x_k once and writes the m_k s_k output
-// rows (i, b) of that (a, l), each a contiguous run of r_{k+1} s_{k+1}
-// elements: a tenth of the workgroups of the per-(a, i) path at Table 1's
-// shape, and one staging of the x slice per m_k rows.  Threads take fixed
-// output columns (col = t mod R', computed once) and walk the rows.
+// Row-block LDS path: one workgroup per (core, member, a, l, chunk of ib
+// row modes i) stages W_k[a, i0 : i0 + ib, :, :] and the l-slice of x_k
+// once and writes the ib s_k output rows (i, b) of that (a, l), each a
+// contiguous run of r_{k+1} s_{k+1} elements.  With ib = m_k (launches that
+// fill the chip that way, such as Table 1's batch of matvecs) a tenth of
+// the workgroups of one per (a, i) at Table 1's shape, and one staging of
+// the x slice per m_k rows; a single product takes smaller chunks.
+// Threads take fixed output columns (col = t mod R', computed once) and
+// walk the rows.
 template <class T>
-__global__ void __launch_bounds__(kMvThreads) matvec_rows_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io) {
+__global__ void __launch_bounds__(kMvThreads) matvec_rows_kernel(MatDev<T> W, RightDev X0, OutDev Y0, MvIO<T> io,
+                                                                  int ib, int nchunk) {
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = (T *)lds_raw;
   const int k = blockIdx.y;
   const int r0 = W.r[k], r1 = W.r[k + 1], s0 = X0.r[k], s1 = X0.r[k + 1];
-  const int mk = W.m[k], nk = W.n[k], lk = X0.L[k];
+  const int mk0 = W.m[k], nk = W.n[k], lk = X0.L[k];
   const unsigned groups = (unsigned)r0 * lk;
-  if (blockIdx.x >= groups) return;  // uniform over the workgroup, before any barrier
-  const unsigned a = blockIdx.x / lk, l = blockIdx.x - a * lk;
+  const unsigned g = blockIdx.x / (unsigned)nchunk;
+  const int i0 = (int)(blockIdx.x - g * (unsigned)nchunk) * ib;
+  if (g >= groups || i0 >= mk0) return;  // uniform over the workgroup, before any barrier
+  const int mk = (mk0 - i0) < ib ? (mk0 - i0) : ib;  // rows i0 .. i0 + mk - 1 of this workgroup
+  const unsigned a = g / lk, l = g - a * lk;
   const int wn = mk * nk * r1;
   T *ws = lds, *xs = lds + wn;
-  const T *wsrc = W.data + W.off[k] + (long long)a * wn;
-  for (int e = threadIdx.x; e < wn; e += kMvThreads) ws[e] = wsrc[e];
-  const T *xm = io.x[blockIdx.z] + X0.off[k];
-  const int xn = s0 * nk * s1;
-  for (int e = threadIdx.x; e < xn; e += kMvThreads) {
-    const int bp = e % s1, u = e / s1;  // u = b n_k + j
-    xs[e] = xm[((long long)u * lk + l) * s1 + bp];
-  }
+  const T *wsrc = W.data + W.off[k] + ((long long)a * mk0 + i0) * nk * r1;
+  stage_run(ws, wsrc, wn);
+  stage_x_slice(xs, io.x[blockIdx.z] + X0.off[k], s0 * nk, s1, lk, (int)l);
   __syncthreads();
   const int R1 = r1 * s1;
   const int per = kMvThreads / R1;  // row offsets per pass (R1 <= kMvThreads on this path)
@@ -167,52 +235,67 @@ __global__ void __launch_bounds__(kMvThreads) matvec_rows_kernel(MatDev<T> W, Ri
         for (int j = 0; j < kMvMaxN; ++j)
           if (j < nk) acc = fma(wcol[j], xb[j * s1], acc);
         const long long row = (long long)a * s0 + b;
-        yk[((row * mk + i) * lk + l) * R1 + col] = acc;
+        yk[((row * mk0 + i0 + i) * lk + l) * R1 + col] = acc;
       }
     }
     return;
   }
-  for (int ib = q0; ib < mk * s0; ib += per) {
-    const int i = ib / s0, b = ib - i * s0;
+  for (int ix = q0; ix < mk * s0; ix += per) {
+    const int i = ix / s0, b = ix - i * s0;
     const T *wi = ws + i * nk * r1 + ap;
     const T *xb = xs + b * nk * s1 + bp;
     T acc = T(0);
     for (int j = 0; j < nk; ++j) acc = fma(wi[j * r1], xb[j * s1], acc);
     const long long row = (long long)a * s0 + b;
-    yk[((row * mk + i) * lk + l) * R1 + col] = acc;
+    yk[((row * mk0 + i0 + i) * lk + l) * R1 + col] = acc;
   }
 }
 
 // Launches the product kernels for `members` right factors: the row-block
-// LDS path when every core's staged slices fit, its output rows fit a
-// workgroup's threads and its grid fills the chip, else the per-(a, i) LDS
+// LDS path when every core's output rows fit a workgroup's threads and its
+// staged slices fit (at some chunk of row modes), else the per-(a, i) LDS
 // path when its two slices fit, else the grid-stride kernel.
 template <class T>
 int launch_products(const MatDev<T> &md, const RightDev &x0, const OutDev &y0, const MvIO<T> &io, int members,
                     hipStream_t s) {
-  long long maxcnt = 0, maxpairs = 0, maxlds = 0, maxgroups = 0, maxrowlds = 0, maxR1 = 0;
+  long long maxcnt = 0, maxpairs = 0, maxlds = 0, maxgroups = 0, maxR1 = 0;
   for (int k = 0; k < md.d; ++k) {
     const long long r0 = md.r[k], r1 = md.r[k + 1], s0 = x0.r[k], s1 = x0.r[k + 1];
     const long long c = r0 * s0 * md.m[k] * x0.L[k] * r1 * s1;
     const long long p = r0 * md.m[k] * x0.L[k];
     const long long f = (long long)md.n[k] * r1 + s0 * md.n[k] * s1;
     const long long g = r0 * x0.L[k];
-    const long long fr = (long long)md.m[k] * md.n[k] * r1 + s0 * md.n[k] * s1;
     maxcnt = c > maxcnt ? c : maxcnt;
     maxpairs = p > maxpairs ? p : maxpairs;
     maxlds = f > maxlds ? f : maxlds;
     maxgroups = g > maxgroups ? g : maxgroups;
-    maxrowlds = fr > maxrowlds ? fr : maxrowlds;
     maxR1 = r1 * s1 > maxR1 ? r1 * s1 : maxR1;
   }
   if (maxcnt >= (1LL << 31)) return set_error(TT_ERR_UNSUPPORTED, "product: an output core of 2^31 or more elements");
-  // the row-block grid is m_k times coarser: it needs enough workgroups to
-  // fill the chip (a single TT-matrix product does not have them)
-  const bool rows_fill = maxgroups * md.d * members >= kMvMinRowBlocks;
-  if (rows_fill && maxrowlds * (long long)sizeof(T) <= kMvLdsBytes && maxR1 <= kMvThreads &&
-      maxgroups <= 0x7fffffffLL) {
-    hipLaunchKernelGGL(matvec_rows_kernel<T>, dim3((unsigned)maxgroups, (unsigned)md.d, (unsigned)members),
-                       dim3(kMvThreads), (size_t)maxrowlds * sizeof(T), s, md, x0, y0, io);
+  // Row-block chunk: the whole row mode when that grid fills the chip, else
+  // smaller chunks (down to one i per workgroup) until it does and the
+  // staged slices fit the LDS.
+  int maxmk = 1;
+  for (int k = 0; k < md.d; ++k) maxmk = md.m[k] > maxmk ? md.m[k] : maxmk;
+  auto rows_lds = [&](int ib) {
+    long long mx = 0;
+    for (int k = 0; k < md.d; ++k) {
+      const long long mi = md.m[k] < ib ? md.m[k] : ib;
+      const long long fr = mi * md.n[k] * md.r[k + 1] + (long long)x0.r[k] * md.n[k] * x0.r[k + 1];
+      mx = fr > mx ? fr : mx;
+    }
+    return mx;
+  };
+  int ib = maxmk, nchunk = 1;
+  while (ib > 1 && (maxgroups * nchunk * md.d * members < kMvMinRowBlocks ||
+                    rows_lds(ib) * (long long)sizeof(T) > kMvLdsBytes)) {
+    --ib;
+    nchunk = (maxmk + ib - 1) / ib;
+  }
+  const long long rowlds = rows_lds(ib);
+  if (maxR1 <= kMvThreads && rowlds * (long long)sizeof(T) <= kMvLdsBytes && maxgroups * nchunk <= 0x7fffffffLL) {
+    hipLaunchKernelGGL(matvec_rows_kernel<T>, dim3((unsigned)(maxgroups * nchunk), (unsigned)md.d, (unsigned)members),
+                       dim3(kMvThreads), (size_t)rowlds * sizeof(T), s, md, x0, y0, io, ib, nchunk);
   } else if (maxlds * (long long)sizeof(T) <= kMvLdsBytes && maxpairs <= 0x7fffffffLL) {
     hipLaunchKernelGGL(matvec_lds_kernel<T>, dim3((unsigned)maxpairs, (unsigned)md.d, (unsigned)members),
                        dim3(kMvThreads), (size_t)maxlds * sizeof(T), s, md, x0, y0, io);

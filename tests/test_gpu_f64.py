@@ -47,11 +47,13 @@ def test_tt_matvec_f64(gpu_lib, case):
             assert np.all(np.abs(g - w) <= TOL * bd + 1e-300)
 
 
-@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("case", [0, 1, 2])
 def test_tt_matmat_f64(gpu_lib, case):
     tt = gpu_lib
     seed, ms, ns, ls, ra, rb = [(44, [2, 3, 5], [3, 4, 2], [2, 1, 3], [1, 3, 4, 1], [1, 2, 5, 1]),
-                                (45, [10] * 4, [10] * 4, [10] * 4, [1, 10, 10, 10, 1], [1, 10, 10, 10, 1])][case]
+                                (45, [10] * 4, [10] * 4, [10] * 4, [1, 10, 10, 10, 1], [1, 10, 10, 10, 1]),
+                                (48, [10] * 10, [10] * 10, [10] * 10, [1] + [10] * 9 + [1],
+                                 [1] + [10] * 9 + [1])][case]
     rng = np.random.default_rng(seed)
     d = len(ms)
     A = [rng.standard_normal((ra[k], ms[k], ns[k], ra[k + 1])) for k in range(d)]

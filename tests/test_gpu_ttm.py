@@ -239,6 +239,8 @@ MATMAT_CASES = [
     # (seed, row modes, inner modes, column modes, A ranks, B ranks)
     (44, [2, 3, 5], [3, 4, 2], [2, 1, 3], [1, 3, 4, 1], [1, 2, 5, 1]),
     (45, [10] * 4, [10] * 4, [10] * 4, [1, 10, 10, 10, 1], [1, 10, 10, 10, 1]),
+    # Table 1's shape (d=10, modes 10, ranks 10): row chunks of 4, 4 and 2
+    (48, [10] * 10, [10] * 10, [10] * 10, [1] + [10] * 9 + [1], [1] + [10] * 9 + [1]),
 ]
 
 
