@@ -386,21 +386,23 @@ __device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared
       q[cc][rr] = (row == col) ? 1.f : 0.f;
     }
   __syncthreads();  // Wm's reflectors are visible to every wave
-  float nxt[RR];
-  auto fetch = [&](int j) {
+  // Reflector j from Wm through global-memory loads (a flat load would also
+  // hold up the LDS counter), every lane loading unconditionally (rows past
+  // m read row m - 1, rows at or above j are replaced), so that the
+  // compiler's memory-counter waits stay exact: two register sets used in
+  // turn, each loaded one step before its use.
+  const __attribute__((address_space(1))) float *Wg = (const __attribute__((address_space(1))) float *)Wm;
+  auto fetch = [&](int j, float(&dst)[RR]) __attribute__((always_inline)) {
+    const __attribute__((address_space(1))) float *wc = Wg + (long)j * m;
 #pragma unroll
     for (int rr = 0; rr < RR; ++rr) {
       const int row = lane + 64 * rr;
-      nxt[rr] = (row > j && row < m) ? Wm[(long)j * m + row] : (row == j ? 1.f : 0.f);
+      const float t = wc[row < m ? row : m - 1];
+      dst[rr] = (row > j && row < m) ? t : (row == j ? 1.f : 0.f);
     }
   };
-  fetch(p - 1);
-  for (int j = p - 1; j >= 0; --j) {
+  auto apply = [&](int j, const float(&v)[RR]) __attribute__((always_inline)) {
     const float beta = sh.hb[j];
-    float v[RR];
-#pragma unroll
-    for (int rr = 0; rr < RR; ++rr) v[rr] = nxt[rr];
-    if (j > 0) fetch(j - 1);
     float sp[kRegCols];
 #pragma unroll
     for (int cc = 0; cc < kRegCols; ++cc) {
@@ -419,7 +421,17 @@ __device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared
 #pragma unroll
       for (int rr = 0; rr < RR; ++rr) q[cc][rr] = fmaf(-w, v[rr], q[cc][rr]);
     }
+  };
+  float va[RR], vb[RR];
+  fetch(p - 1, va);
+  int j = p - 1;
+  for (; j >= 1; j -= 2) {
+    fetch(j - 1, vb);
+    apply(j, va);
+    fetch(j >= 2 ? j - 2 : 0, va);  // j = 1: a spare load of reflector 0
+    apply(j - 1, vb);
   }
+  if (j == 0) apply(0, va);
   __syncthreads();  // every load and LDS read precedes the stores below
 #pragma unroll
   for (int cc = 0; cc < kRegCols; ++cc)
