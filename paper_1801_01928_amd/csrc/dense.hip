@@ -246,9 +246,10 @@ static_assert(kRegCols * kWaves == kJac, "columns must split over the waves");
 
 __device__ bool reg_qr_fits(int m, int c) { return m <= 64 * kRegRows && c <= kJac; }
 
-// wave_sum_n over the eight column sums of a wave; the first four are
-// skipped when none of those columns is still live (first_live false).
-__device__ __forceinline__ void reduce_live(float (&sp)[kRegCols], bool first_live) {
+// wave_sum_n over the eight column sums of a wave; either half is skipped
+// when none of its columns is still live (first_live, second_live false;
+// the second half has no columns at all when the matrix has at most 32).
+__device__ __forceinline__ void reduce_live(float (&sp)[kRegCols], bool first_live, bool second_live) {
   float lo[kRegCols / 2], hi[kRegCols / 2];
 #pragma unroll
   for (int i = 0; i < kRegCols / 2; ++i) {
@@ -256,7 +257,7 @@ __device__ __forceinline__ void reduce_live(float (&sp)[kRegCols], bool first_li
     hi[i] = sp[kRegCols / 2 + i];
   }
   if (first_live) wave_sum_n<kRegCols / 2>(lo);
-  wave_sum_n<kRegCols / 2>(hi);
+  if (second_live) wave_sum_n<kRegCols / 2>(hi);
 #pragma unroll
   for (int i = 0; i < kRegCols / 2; ++i) {
     sp[i] = lo[i];
@@ -355,7 +356,8 @@ __device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared
 #pragma unroll
       for (int rr = 0; rr < RR; ++rr) sp[cc] = fmaf(v[rr], x[cc][rr], sp[cc]);
     }
-    reduce_live(sp, wave + kWaves * (kRegCols / 2 - 1) > j);
+    reduce_live(sp, wave + kWaves * (kRegCols / 2 - 1) > j,
+                wave + kWaves * (kRegCols / 2) < c && wave + kWaves * (kRegCols - 1) > j);
 #pragma unroll
     for (int cc = 0; cc < kRegCols; ++cc) {
       const int col = wave + kWaves * cc;
@@ -412,7 +414,8 @@ __device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared
 #pragma unroll
       for (int rr = 0; rr < RR; ++rr) sp[cc] = fmaf(v[rr], q[cc][rr], sp[cc]);
     }
-    reduce_live(sp, wave + kWaves * (kRegCols / 2 - 1) >= j);
+    reduce_live(sp, wave + kWaves * (kRegCols / 2 - 1) >= j,
+                wave + kWaves * (kRegCols / 2) < p && wave + kWaves * (kRegCols - 1) >= j);
 #pragma unroll
     for (int cc = 0; cc < kRegCols; ++cc) {
       const int col = wave + kWaves * cc;
