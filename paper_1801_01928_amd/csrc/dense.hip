@@ -72,18 +72,16 @@ __device__ __forceinline__ float dpp_f(float v) {
 
 // Sum over the 64 lanes (all lanes active), returned wave-uniform: DPP
 // butterflies inside each row of 16 (quad swaps, half-row and row
-// mirrors), then the four row sums read as scalars.  VALU only, no LDS
-// round trips.
+// mirrors), two row broadcasts that gather the four row sums in lane 63,
+// and one read of that lane as a scalar.  VALU only, no LDS round trips.
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2)
   v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1)
   v += dpp_f<0x141>(v);  // row_half_mirror
-  v += dpp_f<0x140>(v);  // row_mirror
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+  v += dpp_f<0x140>(v);  // row_mirror: every lane holds its row's sum
+  v += dpp_f<0x142>(v);  // row_bcast:15: rows 1 and 3 add rows 0 and 2
+  v += dpp_f<0x143>(v);  // row_bcast:31: row 3 adds lane 31 (rows 0 + 1)
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Sum over the block; every thread gets the result.
@@ -218,14 +216,16 @@ __device__ __forceinline__ void wave_sum_n(float (&v)[N]) {
   for (int i = 0; i < N; ++i) v[i] += dpp_f<0x141>(v[i]);
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] += dpp_f<0x140>(v[i]);
+  // every lane of a row now holds the row's sum: row_bcast:15 adds row 0's
+  // into row 1 and row 2's into row 3, row_bcast:31 then adds lane 31
+  // (rows 0 + 1) into row 3, and lane 63 holds the total (rows 0 and 2,
+  // whatever they receive, are not read)
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 48));
-    v[i] = (r0 + r1) + (r2 + r3);
-  }
+  for (int i = 0; i < N; ++i) v[i] += dpp_f<0x142>(v[i]);  // row_bcast:15
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_f<0x143>(v[i]);  // row_bcast:31
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), 63));
 }
 
 // Householder QR plus thin Q of an m x c matrix (m <= 64 RR, c <= 64) held
