@@ -265,6 +265,13 @@ __device__ __forceinline__ void reduce_live(float (&sp)[kRegCols], bool first_li
   }
 }
 
+template <int C, int RR>
+__device__ __forceinline__ void take_col(const float (&x)[kRegCols][RR], float (&y)[RR]) {
+  static_assert(C < kRegCols, "column slot out of range");
+#pragma unroll
+  for (int rr = 0; rr < RR; ++rr) y[rr] = x[C][rr];
+}
+
 template <int RR, class Load, class StoreQ>
 __device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared &sh) {
   const int lane = threadIdx.x & 63;
@@ -283,13 +290,16 @@ __device__ void reg_qr(Load load, int m, int c, float *Wm, StoreQ storeq, Shared
     const int owner = j % kWaves, cj = j / kWaves;
     float *hv = sh.hv[j & 1];
     if (wave == owner) {
-      float y[RR];  // column j
-#pragma unroll
-      for (int rr = 0; rr < RR; ++rr) {
-        float t = x[0][rr];
-#pragma unroll
-        for (int cc = 1; cc < kRegCols; ++cc) t = (cc == cj) ? x[cc][rr] : t;
-        y[rr] = t;
+      float y[RR];  // column j: a uniform branch on cj, constant register indices
+      switch (cj) {
+        case 0: take_col<0>(x, y); break;
+        case 1: take_col<1>(x, y); break;
+        case 2: take_col<2>(x, y); break;
+        case 3: take_col<3>(x, y); break;
+        case 4: take_col<4>(x, y); break;
+        case 5: take_col<5>(x, y); break;
+        case 6: take_col<6>(x, y); break;
+        default: take_col<7>(x, y); break;
       }
       float sx[2] = {0.f, 0.f};  // sigma = |x(j+1:)|^2, x0 = x(j)
 #pragma unroll
