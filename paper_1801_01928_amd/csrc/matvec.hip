@@ -79,8 +79,11 @@ __global__ void __launch_bounds__(kMvThreads) matvec_kernel(MatDev<T> W, RightDe
 // W_k[a, i, :, :] (n_k x r_{k+1}) and the l-slice of the right factor's
 // core (s_k x n_k x s_{k+1}) are staged in LDS once; the workgroup then
 // writes the s_k rows (a, b) at (i, l), each a contiguous run of
-// r_{k+1} s_{k+1} elements.  The host takes this path when both slices fit
-// in kMvLdsBytes for every core.
+// r_{k+1} s_{k+1} elements.  The host takes this path when some core's
+// output rows are longer than a workgroup's threads (the row-block path's
+// limit) and both slices fit in kMvLdsBytes for every core; cores with
+// shorter rows use fixed output columns per thread as the row-block path
+// does.
 constexpr int kMvLdsBytes = 65536;  // 64 KB of dynamic LDS
 constexpr long long kMvMinRowBlocks = 2048;  // about eight workgroups per CU of a 256-CU device
 constexpr int kMvMaxN = 16;  // row-block path: W columns of up to this many n_k held in registers
