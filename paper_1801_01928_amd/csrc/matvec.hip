@@ -11,6 +11,7 @@
 // the caches; the bytes that must move are those of y.  The LDS path stages
 // both factors' slices per workgroup; the grid-stride fallback gathers them
 // per lane.
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -119,6 +120,52 @@ __device__ __forceinline__ void stage_x_slice(T *xs, const T *xm, int runs, int 
   }
 }
 
+// The thread's W column w[j * r1], j < N = n_k, and its n_k-term sum with
+// an x column, N a compile-time constant (every n_k up to kMvMaxN has its
+// own copy): all loads are issued before the first use, with no branch
+// between them.
+template <int N, class T>
+__device__ __forceinline__ void load_wcol(T (&wcol)[N], const T *w, int r1) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) wcol[j] = w[j * r1];
+}
+
+template <int N, class T>
+__device__ __forceinline__ T dot_wcol(const T (&wcol)[N], const T *x, int s1) {
+  T xv[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) xv[j] = x[j * s1];
+  T acc = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) acc = fma(wcol[j], xv[j], acc);
+  return acc;
+}
+
+// Calls f(std::integral_constant<int, n_k>) for 1 <= n_k <= kMvMaxN.
+template <class F>
+__device__ __forceinline__ void with_nk(int nk, F &&f) {
+  static_assert(kMvMaxN == 16, "one case per n_k up to kMvMaxN");
+  switch (nk) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    case 11: f(std::integral_constant<int, 11>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
+    case 13: f(std::integral_constant<int, 13>{}); break;
+    case 14: f(std::integral_constant<int, 14>{}); break;
+    case 15: f(std::integral_constant<int, 15>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: break;
+  }
+}
+
 // Contiguous staging of n elements (W slices), kMvStage loads in flight.
 template <class T>
 __device__ __forceinline__ void stage_run(T *dst, const T *src, int n) {
@@ -164,17 +211,12 @@ __global__ void __launch_bounds__(kMvThreads) matvec_lds_kernel(MatDev<T> W, Rig
     const int col = threadIdx.x % R1, q0 = threadIdx.x / R1;
     if (q0 >= per) return;  // after the only barrier
     const int ap = col / s1, bp = col - ap * s1;
-    T wcol[kMvMaxN];
-#pragma unroll
-    for (int j = 0; j < kMvMaxN; ++j) wcol[j] = (j < nk) ? ws[j * r1 + ap] : T(0);
-    for (int b = q0; b < s0; b += per) {
-      const T *xb = xs + b * nk * s1 + bp;
-      T acc = T(0);
-#pragma unroll
-      for (int j = 0; j < kMvMaxN; ++j)
-        if (j < nk) acc = fma(wcol[j], xb[j * s1], acc);
-      yb0[b * rstride + col] = acc;
-    }
+    with_nk(nk, [&](auto nc) __attribute__((always_inline)) {
+      constexpr int N = decltype(nc)::value;
+      T wcol[N];
+      load_wcol<N>(wcol, ws + ap, r1);
+      for (int b = q0; b < s0; b += per) yb0[b * rstride + col] = dot_wcol<N>(wcol, xs + b * nk * s1 + bp, s1);
+    });
     return;
   }
   for (int o = threadIdx.x; o < s0 * R1; o += kMvThreads) {
@@ -226,21 +268,17 @@ __global__ void __launch_bounds__(kMvThreads) matvec_rows_kernel(MatDev<T> W, Ri
   if (nk <= kMvMaxN) {
     // rows by i, then b = q0, q0 + per, ...: the thread's W column of each
     // i sits in registers and serves all of its rows b
-    for (int i = 0; i < mk; ++i) {
-      T wcol[kMvMaxN];
-      const T *wi = ws + i * nk * r1 + ap;
-#pragma unroll
-      for (int j = 0; j < kMvMaxN; ++j) wcol[j] = (j < nk) ? wi[j * r1] : T(0);
-      for (int b = q0; b < s0; b += per) {
-        const T *xb = xs + b * nk * s1 + bp;
-        T acc = T(0);
-#pragma unroll
-        for (int j = 0; j < kMvMaxN; ++j)
-          if (j < nk) acc = fma(wcol[j], xb[j * s1], acc);
-        const long long row = (long long)a * s0 + b;
-        yk[((row * mk0 + i0 + i) * lk + l) * R1 + col] = acc;
+    with_nk(nk, [&](auto nc) __attribute__((always_inline)) {
+      constexpr int N = decltype(nc)::value;
+      for (int i = 0; i < mk; ++i) {
+        T wcol[N];
+        load_wcol<N>(wcol, ws + i * nk * r1 + ap, r1);
+        for (int b = q0; b < s0; b += per) {
+          const long long row = (long long)a * s0 + b;
+          yk[((row * mk0 + i0 + i) * lk + l) * R1 + col] = dot_wcol<N>(wcol, xs + b * nk * s1 + bp, s1);
+        }
       }
-    }
+    });
     return;
   }
   for (int ix = q0; ix < mk * s0; ix += per) {
