@@ -1167,7 +1167,7 @@ int device_cus() {
 // the larger tile pads fewer entries (slice groups round up to 16 entries)
 // while the smaller one keeps a tile's LDS under half of a CU's 160 KiB, so
 // two workgroups share a CU.  Measured at d=10, n=10, r=16, 2^20 entries:
-// 0.41 ms and 0.43 ms; at rank class 32 (projection, d=10, rank 32):
+// 0.34 ms and 0.50 ms; at rank class 32 (projection, d=10, rank 32):
 // 1.41 ms and 2.10 ms.
 struct TileShape {
   int T, threads;
