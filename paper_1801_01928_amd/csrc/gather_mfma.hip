@@ -67,6 +67,24 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr int a16(int x) { return (x + 15) & ~15; }
 
+// Global-memory views of pointers.  The batched kernel reads its instances'
+// pointers from memory, where the compiler cannot tell their address space
+// and would use flat instructions, which also count on the LDS counter:
+// every LDS wait in the sweeps would then wait for the prefetched global
+// loads and the stash stores too.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gmem(const T *q) {
+  return (const __attribute__((address_space(1))) T *)q;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem_w(T *q) {
+  return (__attribute__((address_space(1))) T *)q;
+}
+// No-return float atomic add to global memory.
+__device__ __forceinline__ void global_add(float *q, float v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f32(gmem_w(q), v);
+}
+
 enum { ACC_SLAB = 0, ACC_DIRECT = 1, ACC_MERGE = 2 };
 
 // Byte offsets of the LDS regions of one tile (see mf_layout).
@@ -245,7 +263,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const int e = 64 * (wave + W * c) + lane;
-        iv[k][c] = (k < d && wave + W * c < CHUNKS && e < cnt_valid) ? p.idx[(long long)k * M + e0 + e] : -1;
+        iv[k][c] = (k < d && wave + W * c < CHUNKS && e < cnt_valid) ? gmem(p.idx)[(long long)k * M + e0 + e] : -1;
       }
     // C-ordered id of the entry's last SD indices (suffix table; an
     // out-of-range index counts as 0, so table reads stay in bounds, and
@@ -360,7 +378,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
     const float *tab = p.suf + (long long)p.suf_row0[SD - 1] * R;
     for (int x = tid; x < cnt_valid * (R / 4); x += NTHR) {
       const int e = x / (R / 4), c4 = x - e * (R / 4);
-      *(v4f *)(rows + e * RS + 4 * c4) = *(const v4f *)(tab + (long long)sidv[e] * R + 4 * c4);
+      *(v4f *)(rows + e * RS + 4 * c4) = *gmem((const v4f *)(tab + (long long)sidv[e] * R + 4 * c4));
     }
     lds_barrier();
   }
@@ -418,7 +436,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           {
             const float *gs = gk + (long long)__builtin_amdgcn_readlane(mysl, x.jj - jb) * R * R;
 #pragma unroll
-            for (int xx = 0; xx < NT * NT; ++xx) o.a[xx] = *(const v4f *)(gs + (xx * 64 + lane) * 4);
+            for (int xx = 0; xx < NT * NT; ++xx) o.a[xx] = *gmem((const v4f *)(gs + (xx * 64 + lane) * 4));
           }
           o.ent = x.ent;
           if constexpr (!last) {
@@ -448,7 +466,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
             // stash rho_{k+1} of this block in CL layout
             float *st = stash + ((long long)k * nb_max + j) * (64 * R / 4);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) *(v4f *)(st + (t * 64 + lane) * 4) = o.cl[t];
+            for (int t = 0; t < NT; ++t) *gmem_w((v4f *)(st + (t * 64 + lane) * 4)) = o.cl[t];
           }
           v4f out[NT];
 #pragma unroll
@@ -515,15 +533,15 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
   // ------------------------------------------------------------ residual
   for (int e = tid; e < cnt_valid; e += NTHR) {
     const float yv = wsum[e];
-    if (p.y) p.y[e0 + e] = yv;
+    if (p.y) gmem_w(p.y)[e0 + e] = yv;
     float w = 0.f;
     if (MODE == MODE_MSE) {
-      const float rho = yv - p.t[e0 + e];
+      const float rho = yv - gmem(p.t)[e0 + e];
       w = p.inv_m2 * rho;
       loss_part += rho * rho;
-      if (p.gout) p.gout[e0 + e] = w;
+      if (p.gout) gmem_w(p.gout)[e0 + e] = w;
     } else if (MODE == MODE_ADJOINT) {
-      w = p.gy[e0 + e];
+      w = gmem(p.gy)[e0 + e];
     }
     wsum[e] = w;
   }
@@ -619,7 +637,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              unsafeAtomicAdd(dst + (16 * ta + 4 * q4 + v) * R + 16 * tb + c16, racc[ta * NT + tb][v]);
+              global_add(dst + (16 * ta + 4 * q4 + v) * R + 16 * tb + c16, racc[ta * NT + tb][v]);
       }
     };
     // Two kinds of mode get their own loop bodies, free of runtime branches:
@@ -663,7 +681,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           const int jj = x.jj;
           const float *st = stash + ((long long)k * nb_max + jj) * (64 * R / 4);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) o.rt[t] = *(const v4f *)(st + (t * 64 + lane) * 4);
+          for (int t = 0; t < NT; ++t) o.rt[t] = *gmem((const v4f *)(st + (t * 64 + lane) * 4));
         }
         const int ev[4] = {(int)(x.q.x & 0xFFFF), (int)(x.q.x >> 16), (int)(x.q.y & 0xFFFF), (int)(x.q.y >> 16)};
         // lambda_k (weighted): CL (A operand of the outer product) and EL (chain)
@@ -683,7 +701,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
 #pragma unroll
           for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) o.rt[t][v] = tab[(long long)rv[v] * R + 16 * t + c16];
+            for (int t = 0; t < NT; ++t) o.rt[t][v] = gmem(tab)[(long long)rv[v] * R + 16 * t + c16];
         }
       };
       auto ld_glob = [&](int j, Glb &g) {
@@ -691,7 +709,7 @@ __device__ void run_tile(const MfInst &p, long long e0, int cnt_valid, char *sme
           const int jj = j < je ? j : je - 1;
           const float *gs = p.gp_left + ((long long)p.sbase[k] + __builtin_amdgcn_readlane(mysl, jj - jb)) * R * R;
 #pragma unroll
-          for (int x = 0; x < NT * NT; ++x) g.a[x] = *(const v4f *)(gs + (x * 64 + lane) * 4);
+          for (int x = 0; x < NT * NT; ++x) g.a[x] = *gmem((const v4f *)(gs + (x * 64 + lane) * 4));
         }
       };
       auto compute = [&](int j, const Dat &o, const Glb &g) {
@@ -937,7 +955,7 @@ __global__ void __launch_bounds__(NTHR) batched_kernel(MfBatchArgs a) {
       if (threadIdx.x == 0) {
         float s = 0.f;
         for (int wv = 0; wv < NTHR / 64; ++wv) s += red[wv];
-        unsafeAtomicAdd(p.loss, s * p.inv_m);
+        global_add(p.loss, s * p.inv_m);
       }
       __syncthreads();
     }
